@@ -1,0 +1,128 @@
+"""Pins of the oracle's gas model and generator against what the paper and
+mathematics fix (no GPU).  Each test names the passage it follows."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import usp_workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+KB = 1.380649e-23
+
+
+def _printed():
+    out = {}
+    for line in open(os.path.join(GOLD, "paper_printed_values.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        name, val, tol = line.split()[:3]
+        out[name] = (float(val), float(tol))
+    return out
+
+
+def test_philox_known_answers():
+    """Philox4x32-10 against the generator's published known-answer vectors."""
+    rows = [l.split() for l in open(os.path.join(GOLD, "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(t, 16) for t in r]
+        out = oracle.philox(v[0:4], v[4:6])
+        assert list(out) == v[6:10]
+
+
+def test_tau_c_printed_values():
+    """tau_c of the VSS model (Sec. IV.A) reproduces the mean collision times
+    printed in Secs. V.A.1 and V.A.2 with m = 4.65e-26 kg."""
+    pv = _printed()
+    g = oracle.Gas(W.Gas())
+    for name, T in (("tau_c_6000K_1e24", 6000.0), ("tau_c_4000K_1e24", 4000.0)):
+        val, tol = pv[name]
+        assert abs(g.tau_c(T, 1e24) / val - 1) < tol, name
+
+
+def test_mean_free_path_poiseuille():
+    """lambda = cbar tau_c at the Poiseuille state of Sec. V.B is 1e-8 m."""
+    val, tol = _printed()["lambda_poiseuille"]
+    g = oracle.Gas(W.Gas())
+    cbar = math.sqrt(8 * KB * 273.15 / (math.pi * W.M_N2))
+    assert abs(cbar * g.tau_c(273.15, 1.33245e26) / val - 1) < tol
+
+
+def test_mach_cylinder():
+    """U = 2883 m/s at 200 K is Mach 10 with R = k_B/m (Sec. V.C)."""
+    val, tol = _printed()["mach_cylinder"]
+    g = oracle.Gas(W.Gas())
+    assert abs(2883.0 / math.sqrt(1.4 * g.R() * 200.0) / val - 1) < tol
+
+
+def test_mu_ref_constants_follow_vss_formula():
+    """The workload reference viscosities are the VSS formula of Sec. IV.A
+    evaluated at d_ref = 4.11e-10 m; with them tau_c no longer depends on
+    the scattering parameter (alpha cancels)."""
+    for T_ref, w, a, mu in ((273.15, 0.74, 1.36, W.MU_REF_VSS), (290.0, 0.70, 1.0, W.MU_REF_VHS),
+                            (273.15, 0.74, 1.0, W.MU_REF_VHS074)):
+        g = oracle.Gas(W.Gas(T_ref=T_ref, omega=w, alpha_vss=a, mu_ref=mu))
+        # alpha-free form of tau_c * n k T at T_ref: sqrt(m k T_ref/pi) / (4 d^2)
+        want = math.sqrt(W.M_N2 * KB * T_ref / math.pi) / (4 * 4.11e-10 ** 2)
+        assert abs(g.tau_c(T_ref, 1.0) * KB * T_ref / want - 1) < 1e-12
+
+
+def test_cv_vib_is_derivative_of_e_vib():
+    """c_v,vib = d e_vib/dT (Sec. II.A): central differences of e_vib agree,
+    which fixes the sinh^2 reading of the printed heat capacity."""
+    g = oracle.Gas(W.Gas())
+    for T in (200.0, 800.0, 3371.0, 10000.0, 40000.0):
+        h = T * 1e-5
+        fd = (g.e_vib(T + h) - g.e_vib(T - h)) / (2 * h)
+        assert abs(g.cv_vib(T) / fd - 1) < 1e-8
+
+
+def test_e_vib_special_values():
+    g = oracle.Gas(W.Gas())
+    R = g.R()
+    # exp(theta/T) = 2  ->  e_vib = R theta
+    assert abs(g.e_vib(W.THETA_VIB_N2 / math.log(2.0)) / (R * W.THETA_VIB_N2) - 1) < 1e-14
+    # high-T expansion: R theta/(e^x - 1) = R T - R theta/2 + R theta x/12 + O(x^3)
+    T = 1e7
+    th = W.THETA_VIB_N2
+    assert abs(g.e_vib(T) - (R * T - 0.5 * R * th + R * th * (th / T) / 12)) / (R * T) < 1e-12
+    assert g.e_vib(0.0) == 0.0
+
+
+def test_eucken_limits():
+    """Eucken Pr (Sec. IV.B): 14/19 as T -> 0; printed xi -> 1 as T -> inf."""
+    g = oracle.Gas(W.Gas())
+    assert abs(g.prandtl(1.0) - 14 / 19) < 1e-15
+    assert abs(g.prandtl(1e9) - 16 / 21) < 1e-5
+    gs = oracle.Gas(W.Gas(pr_model=W.PR_EUCKEN_STANDARD))
+    assert abs(gs.prandtl(1e9) - 18 / 23) < 1e-5
+
+
+def test_collision_number_limits():
+    """Parker Z_rot tends to Z_rot_inf at high T; Millikan-White + HT is
+    dominated by the exponential at low T (Sec. V.C)."""
+    gas = W.Gas(zrot_model=W.ZROT_PARKER, zvib_model=W.ZVIB_MW_HT, T_ref=290.0, omega=0.7)
+    g = oracle.Gas(gas)
+    assert abs(g.zrot(91.5e12) / 23.0 - 1) < 1e-5
+    assert g.zrot(200.0) < g.zrot(2000.0) < 23.0
+    T = 300.0
+    mw = 9.1 / T ** 0.7 * math.exp(220.0 * T ** (-1 / 3))
+    assert abs(g.zvib(T) / mw - 1) < 1e-6
+    # high-T term alone: (pi d^2/sigma)(T_ref/T)^(omega-1/2)
+    T = 1e8
+    ht = math.pi * 4.11e-10 ** 2 / 5.81e-21 * (290.0 / T) ** 0.2
+    assert abs(g.zvib(T) - ht - 9.1 / T ** 0.7 * math.exp(220.0 * T ** (-1 / 3))) < 1e-9 * ht
+
+
+def test_eigvals_match_library():
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        A = rng.standard_normal((3, 3))
+        S = A @ A.T + rng.standard_normal() * np.eye(3)
+        P = [S[0, 0], S[1, 1], S[2, 2], S[0, 1], S[0, 2], S[1, 2]]
+        assert np.allclose(oracle.eigvals_sym3(P), np.linalg.eigvalsh(S), rtol=1e-10, atol=1e-10)
+    assert np.allclose(oracle.eigvals_sym3([3, 1, 2, 0, 0, 0]), [1, 2, 3])

@@ -1,0 +1,398 @@
+"""Seeded synthetic inputs for the USP-FPM step.
+
+This module only *describes* problems and *samples* initial particle states
+(Maxwellian velocities, Boltzmann rotational energies and vibrational
+levels, uniform positions).  It holds none of the method's arithmetic; both
+the GPU library's tests/benchmark and the CPU oracle take their inputs from
+here, so the two sides always start from identical arrays.
+
+The workloads stand in for the paper's test cases (arXiv 2508.05642, Sec. V):
+  * ``relax0d``   -- homogeneous thermal relaxation of N2 in one cell
+                     (Sec. V.A.2 is its model; initial T_tr = 10,000 K,
+                     T_rot = T_vib = 300 K, n = 1e23 m^-3, 100,000 particles).
+  * ``poiseuille`` -- force-driven Poiseuille flow between diffuse walls
+                     (Sec. V.B is its model; 1 mm gap, 200 cells x 1000
+                     particles, Kn = 0.05 or 0.01).
+  * ``cylinder``  -- Mach-10 N2 flow over a cylinder, half body with a
+                     symmetry plane (Sec. V.C is its model; 600 x 300 cells of
+                     1 mm on a 0.6 m x 0.3 m domain, r = 0.1 m, about 220
+                     particles per free-stream cell, ~36M particles).
+No dataset is used: every array is drawn from a seeded numpy generator.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+KB = 1.380649e-23
+# N2.  The paper prints 6.63e-26 kg (argon's mass); 4.65e-26 kg is the N2
+# mass that reproduces the paper's printed mean collision times and Mach 10
+# at U = 2883 m/s, T = 200 K.
+M_N2 = 4.65e-26
+THETA_VIB_N2 = 3371.0
+
+# reference viscosities for d_ref = 4.11e-10 m (VSS reference-viscosity
+# formula of Sec. IV.A evaluated once; the oracle tests check these numbers)
+MU_REF_VSS = 1.6590167999226515e-05   # T_ref 273.15 K, omega 0.74, alpha 1.36
+MU_REF_VHS = 1.695427691582835e-05    # T_ref 290 K,    omega 0.70, alpha 1.0
+MU_REF_VHS074 = 1.7072206778865052e-05  # T_ref 273.15 K, omega 0.74, alpha 1.0
+
+ZROT_CONST, ZROT_PARKER = 0, 1
+ZVIB_CONST, ZVIB_MW_HT = 0, 1
+PR_EUCKEN_PRINTED, PR_EUCKEN_STANDARD, PR_CONST = 0, 1, 2
+BC_PERIODIC, BC_DIFFUSE, BC_SPECULAR, BC_FREESTREAM, BC_OUTFLOW = 0, 1, 2, 3, 4
+SIDE_XLO, SIDE_XHI, SIDE_YLO, SIDE_YHI = 0, 1, 2, 3
+FLAG_SOLID, FLAG_CUT = 1, 2
+
+
+@dataclass
+class Gas:
+    m: float = M_N2
+    theta_vib: float = THETA_VIB_N2
+    T_ref: float = 273.15
+    mu_ref: float = MU_REF_VSS
+    omega: float = 0.74
+    alpha_vss: float = 1.36
+    zrot_model: int = ZROT_CONST
+    Z_rot: float = 5.0
+    Z_rot_inf: float = 23.0
+    T_star: float = 91.5
+    zvib_model: int = ZVIB_CONST
+    Z_vib: float = 50.0
+    C1: float = 9.1
+    C2: float = 220.0
+    sigma_vib: float = 5.81e-21
+    d_ref: float = 4.11e-10
+    pr_model: int = PR_EUCKEN_PRINTED
+    Pr_const: float = 2.0 / 3.0
+
+    @property
+    def R(self) -> float:
+        return KB / self.m
+
+
+@dataclass
+class Grid:
+    dim: int
+    nx: int
+    ny: int
+    x0: float = 0.0
+    y0: float = 0.0
+    dx: float = 1.0
+    dy: float = 1.0
+    fnum: float = 1.0
+    volume: np.ndarray = None   # [M] float64
+    flags: np.ndarray = None    # [M] uint8
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * self.ny
+
+
+@dataclass
+class BC:
+    kind: tuple = (BC_PERIODIC, BC_PERIODIC, BC_PERIODIC, BC_PERIODIC)
+    Tw: tuple = (0.0, 0.0, 0.0, 0.0)
+    fs_n: float = 0.0
+    fs_T: float = 0.0
+    fs_U: tuple = (0.0, 0.0, 0.0)
+    depth: float = 1.0
+    cyl: int = 0
+    cyl_xc: float = 0.0
+    cyl_yc: float = 0.0
+    cyl_r: float = 0.0
+    cyl_Tw: float = 0.0
+    g: tuple = (0.0, 0.0, 0.0)
+
+
+@dataclass
+class Problem:
+    name: str
+    gas: Gas
+    grid: Grid
+    bc: BC
+    dt: float
+    seed: int
+    f32: bool
+    dt_cell: np.ndarray = None
+    steps: int = 1
+    capacity_factor: float = 1.0
+    notes: dict = field(default_factory=dict)
+
+
+# --------------------------------------------------------------------------
+# samplers
+# --------------------------------------------------------------------------
+def _boltzmann_levels(rng, T, size):
+    """Harmonic-oscillator Boltzmann levels P(I) = (1-q) q^I, q = exp(-Theta/T)."""
+    if T <= 0:
+        return np.zeros(size, np.int32)
+    q = math.exp(-THETA_VIB_N2 / T)
+    # numpy's geometric counts trials to the first success (>= 1)
+    return (rng.geometric(1.0 - q, size=size) - 1).astype(np.int32)
+
+
+def _fill_species(rng, n, R, T_tr, T_rot, T_vib, U=(0.0, 0.0, 0.0), anis=(1.0, 1.0, 1.0)):
+    s = math.sqrt(R * T_tr)
+    c = rng.standard_normal((3, n))
+    cx = U[0] + s * math.sqrt(anis[0]) * c[0]
+    cy = U[1] + s * math.sqrt(anis[1]) * c[1]
+    cz = U[2] + s * math.sqrt(anis[2]) * c[2]
+    erot = rng.exponential(R * T_rot, size=n) if T_rot > 0 else np.zeros(n)
+    vib = _boltzmann_levels(rng, T_vib, n)
+    return cx, cy, cz, erot, vib
+
+
+def _pack(prob: Problem, x, y, cx, cy, cz, erot, vib, cell):
+    n = len(cx)
+    dt = np.float32 if prob.f32 else np.float64
+    cap = max(n, int(math.ceil(n * prob.capacity_factor)) + 64)
+
+    def arr(v):
+        out = np.zeros(cap, dt)
+        if v is not None:
+            out[:n] = v
+        return out
+
+    parts = dict(
+        n=n, cap=cap,
+        x=arr(x) if x is not None else None,
+        y=arr(y) if y is not None else None,
+        cx=arr(cx), cy=arr(cy), cz=arr(cz), erot=arr(erot),
+        vib=np.zeros(cap, np.int32), cell=np.full(cap, -1, np.int32),
+        pid=np.zeros(cap, np.uint32), next_pid=n,
+    )
+    parts["vib"][:n] = vib
+    parts["cell"][:n] = cell
+    parts["pid"][:n] = np.arange(n, dtype=np.uint32)
+    return parts
+
+
+# --------------------------------------------------------------------------
+# 0D: independent cells
+# --------------------------------------------------------------------------
+def relax0d(n_particles=100_000, f32=False, seed=1234, steps=200):
+    """Homogeneous relaxation of N2 in one cell (T_tr 10,000 K, T_rot = T_vib
+    = 300 K, n = 1e23 m^-3, VHS omega = 0.74, Z_rot = 5, Z_vib = 50, dt =
+    half the initial mean collision time)."""
+    gas = Gas(T_ref=273.15, mu_ref=MU_REF_VHS074, omega=0.74, alpha_vss=1.0,
+              Z_rot=5.0, Z_vib=50.0)
+    vol = 1e-9
+    n = 1e23
+    grid = Grid(dim=0, nx=1, ny=1, fnum=n * vol / n_particles,
+                volume=np.array([vol]), flags=np.zeros(1, np.uint8))
+    prob = Problem("relax0d", gas, grid, BC(), dt=5.749101535703162e-09, seed=seed,
+                   f32=f32, steps=steps)
+    prob.notes = dict(T_tr=10000.0, T_rot=300.0, T_vib=300.0, n=n)
+    return prob
+
+
+def relax0d_particles(prob: Problem, init_seed=None, anis=(1.0, 1.0, 1.0)):
+    rng = np.random.default_rng(prob.seed if init_seed is None else init_seed)
+    N = int(round(prob.notes["n"] * prob.grid.volume[0] / prob.grid.fnum))
+    cx, cy, cz, erot, vib = _fill_species(rng, N, prob.gas.R, prob.notes["T_tr"],
+                                          prob.notes["T_rot"], prob.notes["T_vib"], anis=anis)
+    return _pack(prob, None, None, cx, cy, cz, erot, vib, np.zeros(N, np.int32))
+
+
+def batch0d(counts, T_tr, T_rot, T_vib, dens, gas=None, dt=None, dt_cell=None, f32=True,
+            seed=42, U=None, anis=None):
+    """Several independent 0D cells, cell c holding counts[c] particles."""
+    counts = np.asarray(counts, np.int64)
+    M = len(counts)
+    gas = gas or Gas()
+    vol = np.full(M, 1e-9)
+    # one particle weight for all cells; cell volumes carry the densities
+    fnum = 1e9
+    vol = counts * fnum / np.asarray(dens, float)
+    grid = Grid(dim=0, nx=M, ny=1, fnum=fnum, volume=vol, flags=np.zeros(M, np.uint8))
+    prob = Problem("batch0d", gas, grid, BC(), dt=dt if dt is not None else 1e-9, seed=seed,
+                   f32=f32, dt_cell=dt_cell)
+    rng = np.random.default_rng(seed)
+    cols = [[], [], [], [], []]
+    cells = []
+    for c in range(M):
+        u = (0.0, 0.0, 0.0) if U is None else U[c]
+        a = (1.0, 1.0, 1.0) if anis is None else anis[c]
+        vals = _fill_species(rng, int(counts[c]), gas.R, T_tr[c], T_rot[c], T_vib[c], U=u, anis=a)
+        for k in range(5):
+            cols[k].append(vals[k])
+        cells.append(np.full(int(counts[c]), c, np.int32))
+    cx, cy, cz, erot, vib = (np.concatenate(v) for v in cols)
+    parts = _pack(prob, None, None, cx, cy, cz, erot, vib, np.concatenate(cells))
+    return prob, parts
+
+
+# --------------------------------------------------------------------------
+# 1D: Poiseuille channel (y between two diffuse walls, x periodic)
+# --------------------------------------------------------------------------
+_POIS = {
+    0.05: dict(n=2.7256e22, g=3.964e6, dt=2.0e-8),
+    0.01: dict(n=1.3628e23, g=7.928e5, dt=4.0e-8),
+}
+
+
+def poiseuille(kn=0.05, cells=200, ppc=1000, f32=True, seed=7, steps=20_000, Tw=300.0,
+               gap=1e-3, g=None, dt=None, n=None):
+    p = _POIS[kn]
+    gas = Gas()  # VSS row, Z_rot = 5
+    gas.Z_vib = 1e14
+    dy = gap / cells
+    area = 1.0
+    dens = p["n"] if n is None else n
+    fnum = dens * dy * area / ppc
+    grid = Grid(dim=1, nx=1, ny=cells, x0=0.0, y0=0.0, dx=1.0, dy=dy, fnum=fnum,
+                volume=np.full(cells, dy * area), flags=np.zeros(cells, np.uint8))
+    bc = BC(kind=(BC_PERIODIC, BC_PERIODIC, BC_DIFFUSE, BC_DIFFUSE), Tw=(0, 0, Tw, Tw),
+            g=(p["g"] if g is None else g, 0.0, 0.0))
+    prob = Problem(f"poiseuille_kn{kn}", gas, grid, bc, dt=p["dt"] if dt is None else dt,
+                   seed=seed, f32=f32, steps=steps, capacity_factor=1.0)
+    prob.notes = dict(T=Tw, n=dens, ppc=ppc, gap=gap)
+    return prob
+
+
+def poiseuille_particles(prob: Problem, init_seed=None):
+    rng = np.random.default_rng(prob.seed if init_seed is None else init_seed)
+    g = prob.grid
+    ppc = prob.notes["ppc"]
+    N = ppc * g.ny
+    y = g.y0 + rng.random(N) * (g.ny * g.dy)
+    y = np.minimum(y, g.y0 + g.ny * g.dy * (1 - 1e-7))
+    T = prob.notes["T"]
+    cx, cy, cz, erot, vib = _fill_species(rng, N, prob.gas.R, T, T, T)
+    return _pack(prob, None, y, cx, cy, cz, erot, vib, np.zeros(N, np.int32))
+
+
+# --------------------------------------------------------------------------
+# 2D: hypersonic cylinder (half body, symmetry plane y = 0)
+# --------------------------------------------------------------------------
+def _disk_rect_area(xc, yc, r, x1, x2, y1, y2, nq=64):
+    """Area of {|p - c| < r} inside [x1,x2]x[y1,y2] (Gauss-Legendre per
+    piece between the x-breakpoints where the circle meets y1 or y2)."""
+    a, b = max(x1, xc - r), min(x2, xc + r)
+    if a >= b:
+        return 0.0
+    pts = {a, b}
+    for yy in (y1, y2):
+        d = r * r - (yy - yc) ** 2
+        if d > 0:
+            for xx in (xc - math.sqrt(d), xc + math.sqrt(d)):
+                if a < xx < b:
+                    pts.add(xx)
+    pts = sorted(pts)
+    gx, gw = np.polynomial.legendre.leggauss(nq)
+    total = 0.0
+    for lo, hi in zip(pts[:-1], pts[1:]):
+        xs = 0.5 * (hi - lo) * gx + 0.5 * (hi + lo)
+        h = np.sqrt(np.maximum(r * r - (xs - xc) ** 2, 0.0))
+        top = np.clip(yc + h, y1, y2)
+        bot = np.clip(yc - h, y1, y2)
+        total += 0.5 * (hi - lo) * np.dot(gw, top - bot)
+    return float(total)
+
+
+def cylinder(scale=1.0, f32=True, seed=99, steps=20_000, ppc=220.0, nx=600, ny=300,
+             Lx=0.6, Ly=0.3, r=0.1, xc=0.25, capacity_factor=1.3, dt=1.25e-7):
+    """Mach-10 N2 over a cylinder (free stream n = 1e22 m^-3, T = 200 K in all
+    modes, U = 2883.3 m/s; diffuse isothermal wall at 500 K; VHS gas, Parker
+    Z_rot, Millikan-White + high-T Z_vib).  ``scale`` < 1 shrinks the grid
+    (same cell size, same physics) for tests."""
+    if scale != 1.0:
+        nx = max(8, int(round(nx * scale)))
+        ny = max(4, int(round(ny * scale)))
+        Lx, Ly, r, xc = Lx * scale, Ly * scale, r * scale, xc * scale
+    dx = Lx / nx
+    dy = Ly / ny
+    gas = Gas(T_ref=290.0, mu_ref=MU_REF_VHS, omega=0.70, alpha_vss=1.0,
+              zrot_model=ZROT_PARKER, zvib_model=ZVIB_MW_HT)
+    n_inf, T_inf = 1e22, 200.0
+    U_inf = 10.0 * math.sqrt(1.4 * gas.R * T_inf)
+    depth = 1.0
+    fnum = n_inf * dx * dy * depth / ppc
+    M = nx * ny
+    vol = np.full(M, dx * dy * depth)
+    flags = np.zeros(M, np.uint8)
+    yc = 0.0
+    for j in range(ny):
+        y1, y2 = j * dy, (j + 1) * dy
+        if y1 >= yc + r:
+            break
+        for i in range(nx):
+            x1, x2 = i * dx, (i + 1) * dx
+            if x2 <= xc - r or x1 >= xc + r:
+                continue
+            corners_in = [(cx_ - xc) ** 2 + (cy_ - yc) ** 2 < r * r
+                          for cx_ in (x1, x2) for cy_ in (y1, y2)]
+            # nearest point of the cell to the centre decides any overlap
+            nxp = min(max(xc, x1), x2)
+            nyp = min(max(yc, y1), y2)
+            touches = (nxp - xc) ** 2 + (nyp - yc) ** 2 < r * r
+            c = j * nx + i
+            if all(corners_in):
+                flags[c] = FLAG_SOLID
+                vol[c] = 0.0
+            elif touches:
+                flags[c] = FLAG_CUT
+                vol[c] = (dx * dy - _disk_rect_area(xc, yc, r, x1, x2, y1, y2)) * depth
+    grid = Grid(dim=2, nx=nx, ny=ny, x0=0.0, y0=0.0, dx=dx, dy=dy, fnum=fnum,
+                volume=vol, flags=flags)
+    bc = BC(kind=(BC_FREESTREAM, BC_FREESTREAM, BC_SPECULAR, BC_FREESTREAM),
+            fs_n=n_inf, fs_T=T_inf, fs_U=(U_inf, 0.0, 0.0), depth=depth,
+            cyl=1, cyl_xc=xc, cyl_yc=yc, cyl_r=r, cyl_Tw=500.0)
+    prob = Problem("cylinder" if scale == 1.0 else f"cylinder_s{scale}", gas, grid, bc, dt=dt,
+                   seed=seed, f32=f32, steps=steps, capacity_factor=capacity_factor)
+    prob.notes = dict(n=n_inf, T=T_inf, U=U_inf, ppc=ppc)
+    return prob
+
+
+def cylinder_particles(prob: Problem, init_seed=None):
+    rng = np.random.default_rng(prob.seed if init_seed is None else init_seed)
+    g, bc = prob.grid, prob.bc
+    M = g.ncells
+    expect = prob.notes["n"] * g.volume / g.fnum
+    counts = np.floor(expect + rng.random(M)).astype(np.int64)
+    counts[(g.flags & FLAG_SOLID) != 0] = 0
+    N = int(counts.sum())
+    cell = np.repeat(np.arange(M, dtype=np.int64), counts)
+    ix = cell % g.nx
+    iy = cell // g.nx
+    x = g.x0 + (ix + rng.random(N)) * g.dx
+    y = g.y0 + (iy + rng.random(N)) * g.dy
+    # cut cells: redraw points that fell inside the body
+    for _ in range(200):
+        bad = (x - bc.cyl_xc) ** 2 + (y - bc.cyl_yc) ** 2 < bc.cyl_r ** 2
+        nb = int(bad.sum())
+        if nb == 0:
+            break
+        x[bad] = g.x0 + (ix[bad] + rng.random(nb)) * g.dx
+        y[bad] = g.y0 + (iy[bad] + rng.random(nb)) * g.dy
+    keep = ~((x - bc.cyl_xc) ** 2 + (y - bc.cyl_yc) ** 2 < bc.cyl_r ** 2)
+    x, y, cell = x[keep], y[keep], cell[keep]
+    N = len(x)
+    # keep positions strictly inside the domain after rounding to storage
+    xhi = g.x0 + g.nx * g.dx
+    yhi = g.y0 + g.ny * g.dy
+    x = np.minimum(x, xhi * (1 - 1e-7))
+    y = np.minimum(y, yhi * (1 - 1e-7))
+    T = prob.notes["T"]
+    cx, cy, cz, erot, vib = _fill_species(rng, N, prob.gas.R, T, T, T, U=(prob.notes["U"], 0, 0))
+    return _pack(prob, x, y, cx, cy, cz, erot, vib, cell.astype(np.int32))
+
+
+def particles_for(prob: Problem, **kw):
+    if prob.grid.dim == 0:
+        return relax0d_particles(prob, **kw)
+    if prob.grid.dim == 1:
+        return poiseuille_particles(prob, **kw)
+    return cylinder_particles(prob, **kw)
+
+
+def copy_parts(parts):
+    return {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in parts.items()}
+
+
+def replace(obj, **kw):
+    return dataclasses.replace(obj, **kw)

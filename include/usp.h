@@ -1,0 +1,248 @@
+/*
+ * usp.h -- C ABI of libusp, the MI355X (gfx950) implementation of one time
+ * step of the unified stochastic particle Fokker-Planck-Master (USP-FPM)
+ * method for a diatomic gas (Kim & Jun, arXiv 2508.05642).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Arrays named in usp_particles, usp_grid and the plane buffers are DEVICE
+ *   pointers owned by the caller; the library allocates nothing.  Scratch
+ *   space is a caller buffer of usp_workspace_bytes() bytes.
+ * - Structs themselves (usp_gas, usp_grid, usp_bc, usp_particles) live in
+ *   HOST memory and are read during the call only.
+ * - `stream` is a hipStream_t (passed as void*).  Every call enqueues work
+ *   on it and returns without synchronising.  Nothing is copied between host
+ *   and device, so calls may be captured in a HIP graph.
+ * - The live particle count and the next free particle id are device
+ *   scalars (usp_particles.count[0], count[1]); kernels read them on the
+ *   device, so no step needs a host round trip.
+ * - Return value: USP_OK, or a negative usp_status detected on the host
+ *   before anything is enqueued (USP_EINVAL), or a HIP launch error
+ *   (USP_EDEVICE).  Non-fatal physics events are counted on the device in
+ *   the caller's int64 counters[USP_NCOUNTERS] (see enum below).
+ * - Cells are numbered c = j*nx + i (dim 2), c = j (dim 1, nx = 1), or are
+ *   independent boxes c = 0..nx-1 (dim 0, ny = 1).  M = nx*ny.
+ * - Plane buffers are FP64, plane-major: buf[k*M + c].
+ */
+#ifndef USP_H
+#define USP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t usp_status;
+#define USP_OK 0
+#define USP_EINVAL -1      /* null pointer, bad size or dimension, dt <= 0 */
+#define USP_EDEVICE -2     /* a HIP launch or runtime error */
+#define USP_ECAPACITY -3   /* reserved: capacity problems are counted instead */
+#define USP_EUNSUPPORTED -5
+
+#define USP_F32 0
+#define USP_F64 1
+
+/* model switches (Sec. V.C for the temperature-dependent collision numbers,
+   Sec. IV.B for the Eucken Prandtl number) */
+#define USP_ZROT_CONST 0
+#define USP_ZROT_PARKER 1
+#define USP_ZVIB_CONST 0
+#define USP_ZVIB_MW_HT 1
+#define USP_PR_EUCKEN_PRINTED 0   /* xi_vib = x/(e^x - 1) as printed */
+#define USP_PR_EUCKEN_STANDARD 1  /* xi_vib = 2x/(e^x - 1) */
+#define USP_PR_CONST 2
+
+/* boundary kinds, per domain side */
+#define USP_BC_PERIODIC 0
+#define USP_BC_DIFFUSE 1     /* isothermal wall, full accommodation */
+#define USP_BC_SPECULAR 2    /* symmetry plane */
+#define USP_BC_FREESTREAM 3  /* particles leaving are removed; free stream injected */
+#define USP_BC_OUTFLOW 4     /* particles leaving are removed */
+#define USP_SIDE_XLO 0
+#define USP_SIDE_XHI 1
+#define USP_SIDE_YLO 2
+#define USP_SIDE_YHI 3
+
+/* cell flags */
+#define USP_FLAG_SOLID 1u  /* inside the body: particles found there are removed */
+#define USP_FLAG_CUT 2u    /* cut by the body: collides, but is not a stencil neighbour */
+
+/* device event counters (int64 each) */
+enum {
+  USP_CNT_PB_CLAMP = 0,      /* binomial p_B > 1 clamped to 1 (Sec. III.A.2 caveat) */
+  USP_CNT_CHOL_FALLBACK = 1, /* Cholesky test failed; nu/alpha refit (Sec. III.A.3) */
+  USP_CNT_NU_ZERO = 2,       /* refit still not positive definite; nu = 0 */
+  USP_CNT_TREL_SKIP = 3,     /* T_tr^rel <= 0: particle not updated */
+  USP_CNT_TREL_CLAMP = 4,    /* T_rot^rel < 0 or mean level m* < 0 set to 0 */
+  USP_CNT_VIB_SAT = 5,       /* level clamped at 255 */
+  USP_CNT_INTERP_CLAMP = 6,  /* interpolated temperature raised to 5% of the cell's */
+  USP_CNT_CONS_SKIP = 7,     /* a conservation scaling was skipped */
+  USP_CNT_PICK_FAIL = 8,     /* vibrational correction stopped early */
+  USP_CNT_CELL_SKIP = 9,     /* occupied cell skipped (fewer than 2 particles, T <= 0) */
+  USP_CNT_INJECTED = 10,     /* particles created at free-stream faces */
+  USP_CNT_DELETED = 11,      /* particles removed at free-stream/outflow faces */
+  USP_CNT_WALL_HITS = 12,    /* diffuse re-emissions */
+  USP_CNT_BOUNCE_LIMIT = 13, /* flight stopped at the re-emission limit */
+  USP_CNT_CAPACITY = 14,     /* injections dropped: capacity reached */
+  USP_CNT_SOLID_DROP = 15,   /* particles found in a solid cell and removed */
+  USP_NCOUNTERS = 16
+};
+
+/* Gas model.  Sec. II.A (harmonic oscillator, Landau-Teller relaxation
+   times tau_rot = Z_rot tau_c, tau_vib = Z_vib tau_c), Sec. IV.A (viscosity
+   mu = mu_ref (T/T_ref)^omega and mean collision time tau_c = K mu/p with the
+   VSS factor K(alpha_vss, omega)), Sec. IV.B (Prandtl number), Sec. V.C
+   (Parker and Millikan-White + high-temperature collision numbers). */
+typedef struct {
+  double m;          /* molecular mass [kg]; R = k_B/m */
+  double theta_vib;  /* characteristic vibrational temperature [K] */
+  double T_ref;      /* viscosity reference temperature [K] */
+  double mu_ref;     /* viscosity at T_ref [Pa s] */
+  double omega;      /* viscosity index */
+  double alpha_vss;  /* VSS scattering parameter (1 = VHS) */
+  int32_t zrot_model;
+  double Z_rot, Z_rot_inf, T_star;
+  int32_t zvib_model;
+  double Z_vib, C1, C2, sigma_vib, d_ref;
+  int32_t pr_model;
+  double Pr_const;
+} usp_gas;
+
+/* Uniform Cartesian grid (the uniform grid of Sec. III.B).  volume and flags
+   are DEVICE arrays of M entries; flags may be NULL. */
+typedef struct {
+  int32_t dim;       /* 0: independent boxes, 1: y only, 2: x and y */
+  int32_t nx, ny;
+  double x0, y0, dx, dy;
+  double fnum;       /* real molecules per simulated particle */
+  const double* volume;
+  const uint8_t* flags;
+} usp_grid;
+
+/* Boundaries (host struct).  The paper names diffuse isothermal walls, a
+   symmetry plane and a free stream (Secs. V.B, V.C); kinds per side. */
+typedef struct {
+  int32_t kind[4];   /* USP_BC_* for xlo, xhi, ylo, yhi */
+  double Tw[4];      /* diffuse-wall temperature per side [K] */
+  double fs_n;       /* free-stream number density [1/m^3] */
+  double fs_T;       /* free-stream temperature, all modes [K] */
+  double fs_U[3];    /* free-stream velocity [m/s] */
+  double depth;      /* z extent [m] used for injection face areas */
+  int32_t cyl;       /* 1: a cylinder (a circle in x,y) is present */
+  double cyl_xc, cyl_yc, cyl_r, cyl_Tw;
+  double g[3];       /* body acceleration [m/s^2], applied before the flight */
+} usp_bc;
+
+/* Particle state (Sec. II.A: position, velocity, rotational energy,
+   vibrational level), structure of arrays in DEVICE memory, `capacity`
+   entries each.  x is unused (may be NULL) unless dim = 2; y unused unless
+   dim >= 1.  Floating arrays hold float (USP_F32) or double (USP_F64).
+   count is a device int64[2]: live particle count, next particle id. */
+typedef struct {
+  int32_t prec;
+  int64_t capacity;
+  void* x;
+  void* y;
+  void* cx;
+  void* cy;
+  void* cz;
+  void* erot;        /* rotational energy per unit mass [J/kg] */
+  uint8_t* vib;      /* vibrational level I (energy I R theta_vib) */
+  int32_t* cell;     /* cell index; -1 marks a removed particle */
+  uint32_t* pid;     /* particle id: the random-stream key */
+  int64_t* count;
+} usp_particles;
+
+/* ---- plane layouts ------------------------------------------------------ */
+/* Moment planes (Sec. II.A, per unit mass, central about U):
+   N, U(3), Pi(6: xx yy zz xy xz yz), e_rot, mean level, q_tr(3) =
+   (1/2)<C^2 C>, q_rot(3) = <C eps_rot>, <C I>(3) (times R theta = q_vib). */
+#define USP_NMOM 21
+/* Cell-state planes: see usp_cs_name(k). */
+#define USP_NCS 35
+
+const char* usp_status_str(usp_status s);
+const char* usp_mom_name(int32_t k);
+const char* usp_cs_name(int32_t k);
+const char* usp_counter_name(int32_t k);
+const char* usp_version(void);
+
+/* Bytes of scratch the caller passes as `ws` to usp_bin, usp_advect and
+   usp_step for this grid and particle capacity. */
+size_t usp_workspace_bytes(const usp_grid* grid, int64_t capacity);
+
+/* Bin (the per-cell organisation the collision step of Sec. IV.D loops
+   over): cell of each live particle from its position (dim >= 1; cell =
+   number of cell edges, in the stored precision, at or below the
+   coordinate) or from in->cell (dim 0); particles marked -1 or in a solid
+   cell are dropped; the rest are written to `out` sorted by cell, stable in
+   input order.  offsets: device int64[M+1], cell c owns [offsets[c],
+   offsets[c+1]).  out->count[0] becomes the kept count, out->count[1] =
+   in->count[1].  in and out must not alias. */
+usp_status usp_bin(const usp_grid* grid, const usp_particles* in, usp_particles* out,
+                   int64_t* offsets, void* ws, size_t ws_bytes, int64_t* counters, void* stream);
+
+/* Moments (Sec. II.A) of every cell from a binned state: mom = device
+   double[USP_NMOM*M].  Two passes per cell (U, then central moments),
+   accumulated in FP64 in a fixed order (deterministic). */
+usp_status usp_moments(const usp_grid* grid, const usp_particles* p, const int64_t* offsets,
+                       double* mom, void* stream);
+
+/* Cell state (Secs. II.A, III.A.1, III.A.2, IV.A, IV.B): temperatures,
+   viscosity, tau_c, Z's, Pr, the USP-FPM coefficients alpha (eq.
+   USP-FPM_alpha_tr), nu (eq. USP-FPM_nu), a = dt/(dt + 2 tau_rot), b =
+   dt/(dt + 2 tau_vib), the cell energy targets of eqs. e_rot/e_vib_relax and
+   the stencil usability flag used by the reconstruction (Sec. III.B).
+   cs = device double[USP_NCS*M].  dt_cell (device, M) overrides dt per cell
+   when not NULL (independent 0D boxes). */
+usp_status usp_reconstruct(const usp_grid* grid, const usp_gas* gas, const double* mom,
+                           double dt, const double* dt_cell, double* cs, int64_t* counters,
+                           void* stream);
+
+/* Collision (Secs. III.A.2, III.A.3, flow chart of Sec. IV.D): for every
+   particle of a colliding cell, the first-order polynomial reconstruction of
+   U, T_tr, T_rot, T_vib, Pi at its position, the relaxation temperatures
+   (eqs. T_tr_USP, T_rot_USP, T_vib_USP), the diffusion tensor (eq. D_tr)
+   with its Cholesky test and positivity fallback, and the velocity (eq.
+   update_ci), rotational (eq. update_erot) and vibrational (eq.
+   update_evib) updates.  Random numbers: Philox4x32-10 keyed by `seed`,
+   counter (pid, step, 0, block).  In-place on p (binned). */
+usp_status usp_collide(const usp_grid* grid, const usp_gas* gas, const double* cs,
+                       const int64_t* offsets, usp_particles* p, uint64_t seed, uint64_t step,
+                       int64_t* counters, void* stream);
+
+/* Conservation (Sec. IV.C), per colliding cell: integer vibrational
+   correction by random level moves, rotational scaling to the cell target,
+   velocity scaling conserving momentum and total energy.  Picks draw from
+   Philox counter (cell, step, 2, j).  In-place on p (binned). */
+usp_status usp_conserve(const usp_grid* grid, const usp_gas* gas, const double* cs,
+                        const int64_t* offsets, usp_particles* p, uint64_t seed, uint64_t step,
+                        int64_t* counters, void* stream);
+
+/* Advection (free flight x += c dt, Sec. II.C) with body force and the
+   boundaries of usp_bc; diffuse re-emissions draw from counter (pid, step,
+   1, block).  Removed particles get cell -1; survivors get their new cell.
+   Free-stream faces then inject new particles after the live ones (ids
+   count[1], count[1]+1, ...; draws from (face, step, 5, 0) and (pid, step, 3,
+   block)); count[] is advanced on the device.  No-op for dim 0. */
+usp_status usp_advect(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
+                      usp_particles* p, uint64_t seed, uint64_t step, void* ws, size_t ws_bytes,
+                      int64_t* counters, void* stream);
+
+/* nsteps full steps (bin, moments, reconstruct, collide, conserve, advect)
+   starting at step index `step`.  p and p_alt are the two particle buffers;
+   on return *p describes the buffer that holds the state (the two structs
+   are swapped as needed).  offsets, mom, cs as above (they describe the last
+   step's pre-collision state on return). */
+usp_status usp_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
+                    const double* dt_cell, usp_particles* p, usp_particles* p_alt,
+                    int64_t* offsets, double* mom, double* cs, void* ws, size_t ws_bytes,
+                    uint64_t seed, uint64_t step, int32_t nsteps, int64_t* counters,
+                    void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,43 @@
+"""Build libusp.so (hand-written HIP for gfx950) in-tree with hipcc."""
+import glob
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libusp.so")
+SRC = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
+HDR = sorted(glob.glob(os.path.join(HERE, "csrc", "*.h"))) + [
+    os.path.join(os.path.dirname(HERE), "include", "usp.h")]
+
+HIPCC_FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # no packed FP32 instructions (v_pk_*_f32)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+]
+
+
+def stale():
+    if not os.path.exists(LIB):
+        return True
+    t = os.path.getmtime(LIB)
+    return any(os.path.getmtime(f) > t for f in SRC + HDR)
+
+
+def build(force=True, verbose=False):
+    """Compile every .hip source into one shared library (always, unless
+    force=False and the library is newer than all sources)."""
+    if not force and not stale():
+        return LIB
+    tmp = LIB + ".tmp"
+    cmd = ["hipcc"] + HIPCC_FLAGS + ["-o", tmp] + SRC
+    r = subprocess.run(cmd, cwd=HERE, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
+    if verbose:
+        print(r.stderr)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,277 @@
+// usp_api.hip -- C ABI of libusp: argument checks, workspace layout,
+// dispatch on the state precision, and the full step.
+#include <string.h>
+
+#include "usp_internal.h"
+
+namespace usp {
+
+GasP make_gas(const usp_gas* g) {
+  GasP p;
+  p.R = KB / g->m;
+  p.theta = g->theta_vib;
+  p.T_ref = g->T_ref;
+  p.mu_ref = g->mu_ref;
+  p.omega = g->omega;
+  const double a = g->alpha_vss, w = g->omega;
+  p.K = a * (5.0 - 2.0 * w) * (7.0 - 2.0 * w) / (5.0 * (a + 1.0) * (a + 2.0));
+  p.zrot_model = g->zrot_model; p.Z_rot = g->Z_rot; p.Z_rot_inf = g->Z_rot_inf; p.T_star = g->T_star;
+  p.zvib_model = g->zvib_model; p.Z_vib = g->Z_vib; p.C1 = g->C1; p.C2 = g->C2;
+  p.sigma_vib = g->sigma_vib; p.d_ref = g->d_ref;
+  p.pr_model = g->pr_model; p.Pr_const = g->Pr_const;
+  return p;
+}
+
+GridP make_grid(const usp_grid* g) {
+  GridP p;
+  p.dim = g->dim; p.nx = g->nx; p.ny = g->ny;
+  p.M = (int64_t)g->nx * g->ny;
+  p.x0 = g->x0; p.y0 = g->y0; p.dx = g->dx; p.dy = g->dy; p.fnum = g->fnum;
+  p.volume = g->volume; p.flags = g->flags;
+  return p;
+}
+
+BcP make_bc(const usp_bc* b) {
+  BcP p;
+  memset(&p, 0, sizeof(p));
+  if (!b) {
+    for (int k = 0; k < 4; ++k) p.kind[k] = USP_BC_PERIODIC;
+    return p;
+  }
+  for (int k = 0; k < 4; ++k) { p.kind[k] = b->kind[k]; p.Tw[k] = b->Tw[k]; }
+  p.fs_n = b->fs_n; p.fs_T = b->fs_T;
+  for (int k = 0; k < 3; ++k) { p.fs_U[k] = b->fs_U[k]; p.g[k] = b->g[k]; }
+  p.depth = b->depth;
+  p.cyl = b->cyl; p.cyl_xc = b->cyl_xc; p.cyl_yc = b->cyl_yc; p.cyl_r = b->cyl_r; p.cyl_Tw = b->cyl_Tw;
+  return p;
+}
+
+template <typename S>
+PartP<S> make_parts(const usp_particles* q) {
+  PartP<S> p;
+  p.x = (S*)q->x; p.y = (S*)q->y; p.cx = (S*)q->cx; p.cy = (S*)q->cy; p.cz = (S*)q->cz;
+  p.erot = (S*)q->erot; p.vib = q->vib; p.cell = q->cell; p.pid = q->pid; p.count = q->count;
+  p.capacity = q->capacity;
+  return p;
+}
+template PartP<float> make_parts<float>(const usp_particles*);
+template PartP<double> make_parts<double>(const usp_particles*);
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+WsLayout ws_layout(int64_t M, int64_t capacity, int nfaces) {
+  WsLayout L;
+  size_t o = 0;
+  L.key = o; o = align256(o + sizeof(int32_t) * (size_t)capacity);
+  L.cursor = o; o = align256(o + sizeof(int32_t) * (size_t)M);
+  L.perm = o; o = align256(o + sizeof(uint32_t) * (size_t)capacity);
+  L.blocksums = o; o = align256(o + sizeof(int64_t) * (size_t)(cdiv(M, 1024) + 1));
+  L.face_cnt = o; o = align256(o + sizeof(int32_t) * (size_t)(nfaces + 1));
+  L.face_off = o; o = align256(o + sizeof(int64_t) * (size_t)(nfaces + 1));
+  L.misc = o; o = align256(o + sizeof(int64_t) * 8);
+  L.total = o;
+  return L;
+}
+
+}  // namespace usp
+
+using namespace usp;
+
+namespace {
+
+bool grid_ok(const usp_grid* g) {
+  if (!g || g->nx <= 0 || g->ny <= 0 || !g->volume) return false;
+  if (g->dim < 0 || g->dim > 2) return false;
+  if (g->dim == 0 && g->ny != 1) return false;
+  if (g->dim == 1 && g->nx != 1) return false;
+  if (g->dim >= 1 && !(g->dy > 0.0)) return false;
+  if (g->dim == 2 && !(g->dx > 0.0)) return false;
+  if (!(g->fnum > 0.0)) return false;
+  if ((int64_t)g->nx * g->ny > (int64_t)INT32_MAX) return false;
+  return true;
+}
+
+bool parts_ok(const usp_particles* p, const usp_grid* g) {
+  if (!p || !p->cx || !p->cy || !p->cz || !p->erot || !p->vib || !p->cell || !p->pid || !p->count)
+    return false;
+  if (p->prec != USP_F32 && p->prec != USP_F64) return false;
+  if (p->capacity <= 0 || p->capacity > (int64_t)UINT32_MAX) return false;
+  if (g->dim >= 1 && !p->y) return false;
+  if (g->dim == 2 && !p->x) return false;
+  return true;
+}
+
+bool gas_ok(const usp_gas* g) {
+  return g && g->m > 0.0 && g->theta_vib > 0.0 && g->T_ref > 0.0 && g->mu_ref > 0.0 &&
+         g->alpha_vss > 0.0;
+}
+
+usp_status hip_status(hipError_t e) { return e == hipSuccess ? USP_OK : USP_EDEVICE; }
+
+template <typename S>
+usp_status do_bin(const usp_grid* grid, const usp_particles* in, usp_particles* out,
+                  int64_t* offsets, void* ws, int64_t* counters, hipStream_t st) {
+  const GridP g = make_grid(grid);
+  const WsLayout L = ws_layout(g.M, in->capacity, n_faces(g));
+  return hip_status(launch_bin<S>(g, make_parts<S>(in), make_parts<S>(out), offsets, (char*)ws, L,
+                                  counters, st));
+}
+
+template <typename S>
+usp_status do_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
+                   const double* dt_cell, usp_particles* p, usp_particles* p_alt,
+                   int64_t* offsets, double* mom, double* cs, void* ws, uint64_t seed,
+                   uint64_t step, int32_t nsteps, int64_t* counters, hipStream_t st) {
+  const GridP g = make_grid(grid);
+  const GasP gp = make_gas(gas);
+  const BcP bp = make_bc(bc);
+  const WsLayout L = ws_layout(g.M, p->capacity, n_faces(g));
+  char* w = (char*)ws;
+  for (int32_t s = 0; s < nsteps; ++s) {
+    const uint64_t sn = step + (uint64_t)s;
+    hipError_t e = launch_bin<S>(g, make_parts<S>(p), make_parts<S>(p_alt), offsets, w, L, counters, st);
+    if (e != hipSuccess) return USP_EDEVICE;
+    const usp_particles tmp = *p;
+    *p = *p_alt;
+    *p_alt = tmp;
+    const PartP<S> q = make_parts<S>(p);
+    if ((e = launch_moments<S>(g, q, offsets, mom, st)) != hipSuccess) return USP_EDEVICE;
+    if ((e = launch_reconstruct(g, gp, mom, dt, dt_cell, cs, counters, st)) != hipSuccess) return USP_EDEVICE;
+    if ((e = launch_collide<S>(g, gp, cs, offsets, q, seed, sn, counters, st)) != hipSuccess) return USP_EDEVICE;
+    if ((e = launch_conserve<S>(g, gp, cs, offsets, q, seed, sn, counters, st)) != hipSuccess) return USP_EDEVICE;
+    if ((e = launch_advect<S>(g, gp, bp, dt, q, seed, sn, w, L, counters, st)) != hipSuccess) return USP_EDEVICE;
+  }
+  return USP_OK;
+}
+
+const char* kMomNames[USP_NMOM] = {"N", "UX", "UY", "UZ", "PXX", "PYY", "PZZ", "PXY", "PXZ",
+                                   "PYZ", "EROT", "IBAR", "QTRX", "QTRY", "QTRZ", "QROTX",
+                                   "QROTY", "QROTZ", "QIX", "QIY", "QIZ"};
+const char* kCsNames[USP_NCS] = {
+    "NP", "NDENS", "UX", "UY", "UZ", "TTR", "TROT", "TVIB", "PXX", "PYY", "PZZ", "PXY",
+    "PXZ", "PYZ", "ETR", "EROT", "EVIB", "MU", "MUP", "TAUC", "ZROT", "ZVIB", "PR", "DT",
+    "A", "B", "R2", "R3", "ALPHA", "OMA2", "NU", "EROT_NEW", "EVIB_NEW", "COLLIDE", "NBR_OK"};
+const char* kCntNames[USP_NCOUNTERS] = {
+    "PB_CLAMP", "CHOL_FALLBACK", "NU_ZERO", "TREL_SKIP", "TREL_CLAMP", "VIB_SAT",
+    "INTERP_CLAMP", "CONS_SKIP", "PICK_FAIL", "CELL_SKIP", "INJECTED", "DELETED",
+    "WALL_HITS", "BOUNCE_LIMIT", "CAPACITY", "SOLID_DROP"};
+
+}  // namespace
+
+extern "C" {
+
+const char* usp_status_str(usp_status s) {
+  switch (s) {
+    case USP_OK: return "ok";
+    case USP_EINVAL: return "invalid argument";
+    case USP_EDEVICE: return "HIP device error";
+    case USP_ECAPACITY: return "particle capacity exceeded";
+    case USP_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* usp_mom_name(int32_t k) { return (k >= 0 && k < USP_NMOM) ? kMomNames[k] : ""; }
+const char* usp_cs_name(int32_t k) { return (k >= 0 && k < USP_NCS) ? kCsNames[k] : ""; }
+const char* usp_counter_name(int32_t k) {
+  return (k >= 0 && k < USP_NCOUNTERS) ? kCntNames[k] : "";
+}
+const char* usp_version(void) { return "libusp 0.1 (gfx950)"; }
+
+size_t usp_workspace_bytes(const usp_grid* grid, int64_t capacity) {
+  if (!grid_ok(grid) || capacity <= 0) return 0;
+  const GridP g = make_grid(grid);
+  return ws_layout(g.M, capacity, n_faces(g)).total;
+}
+
+usp_status usp_bin(const usp_grid* grid, const usp_particles* in, usp_particles* out,
+                   int64_t* offsets, void* ws, size_t ws_bytes, int64_t* counters, void* stream) {
+  if (!grid_ok(grid) || !parts_ok(in, grid) || !parts_ok(out, grid) || !offsets || !ws) return USP_EINVAL;
+  if (in->prec != out->prec || out->capacity < in->capacity) return USP_EINVAL;
+  if (in->cx == out->cx || in->count == out->count) return USP_EINVAL;
+  if (ws_bytes < usp_workspace_bytes(grid, in->capacity)) return USP_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  return in->prec == USP_F32 ? do_bin<float>(grid, in, out, offsets, ws, counters, st)
+                             : do_bin<double>(grid, in, out, offsets, ws, counters, st);
+}
+
+usp_status usp_moments(const usp_grid* grid, const usp_particles* p, const int64_t* offsets,
+                       double* mom, void* stream) {
+  if (!grid_ok(grid) || !parts_ok(p, grid) || !offsets || !mom) return USP_EINVAL;
+  const GridP g = make_grid(grid);
+  hipStream_t st = (hipStream_t)stream;
+  return hip_status(p->prec == USP_F32 ? launch_moments<float>(g, make_parts<float>(p), offsets, mom, st)
+                                       : launch_moments<double>(g, make_parts<double>(p), offsets, mom, st));
+}
+
+usp_status usp_reconstruct(const usp_grid* grid, const usp_gas* gas, const double* mom,
+                           double dt, const double* dt_cell, double* cs, int64_t* counters,
+                           void* stream) {
+  if (!grid_ok(grid) || !gas_ok(gas) || !mom || !cs) return USP_EINVAL;
+  if (!dt_cell && !(dt > 0.0)) return USP_EINVAL;
+  return hip_status(launch_reconstruct(make_grid(grid), make_gas(gas), mom, dt, dt_cell, cs,
+                                       counters, (hipStream_t)stream));
+}
+
+usp_status usp_collide(const usp_grid* grid, const usp_gas* gas, const double* cs,
+                       const int64_t* offsets, usp_particles* p, uint64_t seed, uint64_t step,
+                       int64_t* counters, void* stream) {
+  if (!grid_ok(grid) || !gas_ok(gas) || !cs || !offsets || !parts_ok(p, grid)) return USP_EINVAL;
+  const GridP g = make_grid(grid);
+  const GasP gp = make_gas(gas);
+  hipStream_t st = (hipStream_t)stream;
+  return hip_status(p->prec == USP_F32
+                        ? launch_collide<float>(g, gp, cs, offsets, make_parts<float>(p), seed, step, counters, st)
+                        : launch_collide<double>(g, gp, cs, offsets, make_parts<double>(p), seed, step, counters, st));
+}
+
+usp_status usp_conserve(const usp_grid* grid, const usp_gas* gas, const double* cs,
+                        const int64_t* offsets, usp_particles* p, uint64_t seed, uint64_t step,
+                        int64_t* counters, void* stream) {
+  if (!grid_ok(grid) || !gas_ok(gas) || !cs || !offsets || !parts_ok(p, grid)) return USP_EINVAL;
+  const GridP g = make_grid(grid);
+  const GasP gp = make_gas(gas);
+  hipStream_t st = (hipStream_t)stream;
+  return hip_status(p->prec == USP_F32
+                        ? launch_conserve<float>(g, gp, cs, offsets, make_parts<float>(p), seed, step, counters, st)
+                        : launch_conserve<double>(g, gp, cs, offsets, make_parts<double>(p), seed, step, counters, st));
+}
+
+usp_status usp_advect(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
+                      usp_particles* p, uint64_t seed, uint64_t step, void* ws, size_t ws_bytes,
+                      int64_t* counters, void* stream) {
+  if (!grid_ok(grid) || !gas_ok(gas) || !bc || !parts_ok(p, grid) || !ws) return USP_EINVAL;
+  if (!(dt > 0.0)) return USP_EINVAL;
+  if (ws_bytes < usp_workspace_bytes(grid, p->capacity)) return USP_EINVAL;
+  const GridP g = make_grid(grid);
+  const GasP gp = make_gas(gas);
+  const BcP bp = make_bc(bc);
+  if (g.dim == 2) {
+    for (int k = 0; k < 4; ++k)
+      if (bp.kind[k] == USP_BC_FREESTREAM && !(bp.fs_T > 0.0 && bp.depth > 0.0)) return USP_EINVAL;
+  }
+  const WsLayout L = ws_layout(g.M, p->capacity, n_faces(g));
+  hipStream_t st = (hipStream_t)stream;
+  return hip_status(p->prec == USP_F32
+                        ? launch_advect<float>(g, gp, bp, dt, make_parts<float>(p), seed, step, (char*)ws, L, counters, st)
+                        : launch_advect<double>(g, gp, bp, dt, make_parts<double>(p), seed, step, (char*)ws, L, counters, st));
+}
+
+usp_status usp_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
+                    const double* dt_cell, usp_particles* p, usp_particles* p_alt,
+                    int64_t* offsets, double* mom, double* cs, void* ws, size_t ws_bytes,
+                    uint64_t seed, uint64_t step, int32_t nsteps, int64_t* counters,
+                    void* stream) {
+  if (!grid_ok(grid) || !gas_ok(gas) || !parts_ok(p, grid) || !parts_ok(p_alt, grid)) return USP_EINVAL;
+  if (!offsets || !mom || !cs || !ws || nsteps < 0) return USP_EINVAL;
+  if (p->prec != p_alt->prec || p_alt->capacity < p->capacity || p->cx == p_alt->cx) return USP_EINVAL;
+  if (grid->dim >= 1 && (!bc || !(dt > 0.0))) return USP_EINVAL;
+  if (!dt_cell && !(dt > 0.0)) return USP_EINVAL;
+  if (ws_bytes < usp_workspace_bytes(grid, p->capacity)) return USP_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  return p->prec == USP_F32
+             ? do_step<float>(grid, gas, bc, dt, dt_cell, p, p_alt, offsets, mom, cs, ws, seed, step, nsteps, counters, st)
+             : do_step<double>(grid, gas, bc, dt, dt_cell, p, p_alt, offsets, mom, cs, ws, seed, step, nsteps, counters, st);
+}
+
+}  // extern "C"

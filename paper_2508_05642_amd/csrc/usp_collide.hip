@@ -1,0 +1,476 @@
+// usp_collide.hip -- the per-particle USP-FPM update and the per-cell
+// conservation scheme.
+//
+// Precision: the particle update runs in the state precision S (float for
+// FP32 states, double for FP64 states); reconstruction weights, all cell
+// quantities and the discrete vibrational decisions are FP64.
+#include "usp_device.h"
+
+namespace usp {
+
+constexpr int PART_BLOCK = 256;
+constexpr int CONS_BLOCK = 256;
+
+// Negative-binomial NB(r, p) (failures before the r-th success) and
+// binomial B(n, p) draws by sequential CDF inversion: the smallest k with
+// u < F(k).  The pmf recurrences and the order of every FP64 operation are
+// fixed (no contraction) so that decisions are reproducible.
+__device__ __noinline__ int sample_nb(double u, int r, double p) {
+#pragma clang fp contract(off)
+  const double q = 1.0 - p;
+  double pk = 1.0;
+  for (int i = 0; i < r; ++i) pk = pk * p;
+  double F = pk;
+  int k = 0;
+  while (u >= F && k < NB_KMAX) {
+    double t = q * (double)(r + k);
+    t = t / (double)(k + 1);
+    pk = pk * t;
+    F = F + pk;
+    k = k + 1;
+  }
+  return k;
+}
+
+__device__ __noinline__ int sample_b(double u, int n, double p) {
+#pragma clang fp contract(off)
+  if (n <= 0 || p <= 0.0) return 0;
+  if (p >= 1.0) return n;
+  const double q = 1.0 - p;
+  double pk = 1.0;
+  for (int i = 0; i < n; ++i) pk = pk * q;
+  const double ratio = p / q;
+  double F = pk;
+  int k = 0;
+  while (u >= F && k < n) {
+    double t = ratio * (double)(n - k);
+    t = t / (double)(k + 1);
+    pk = pk * t;
+    F = F + pk;
+    k = k + 1;
+  }
+  return k;
+}
+
+// smallest and largest eigenvalue of a symmetric 3x3 (trigonometric form)
+template <typename T>
+__device__ __forceinline__ void eig_minmax(const T P[6], T* lmin, T* lmax) {
+  const T p1 = P[3] * P[3] + P[4] * P[4] + P[5] * P[5];
+  if (p1 == T(0)) {
+    *lmin = fmin(P[0], fmin(P[1], P[2]));
+    *lmax = fmax(P[0], fmax(P[1], P[2]));
+    return;
+  }
+  const T q = (P[0] + P[1] + P[2]) / T(3);
+  const T a = P[0] - q, b = P[1] - q, c = P[2] - q;
+  const T p2 = a * a + b * b + c * c + T(2) * p1;
+  const T p = sqrt(p2 / T(6));
+  const T ip = T(1) / p;
+  const T b11 = a * ip, b22 = b * ip, b33 = c * ip, b12 = P[3] * ip, b13 = P[4] * ip,
+          b23 = P[5] * ip;
+  const T det = b11 * (b22 * b33 - b23 * b23) - b12 * (b12 * b33 - b23 * b13) +
+                b13 * (b12 * b23 - b22 * b13);
+  T r = det / T(2);
+  r = fmin(T(1), fmax(T(-1), r));
+  const T phi = acos(r) / T(3);
+  *lmax = q + T(2) * p * cos(phi);
+  *lmin = q + T(2) * p * cos(phi + T(2.0943951023931954923));
+}
+
+// Cell-level coefficients (FP64, from the cell state).
+struct CellCoef {
+  double a, b, al, oma2, nu, r2, A2, Pr, dt;
+};
+
+// Per-particle coefficients of the update.
+template <typename T>
+struct PartCoef {
+  T L[6];          // Cholesky factor of Lambda = tau D_tr
+  T al;            // alpha_tr = alpha_rot = alpha_vib
+  double oma2;     // 1 - alpha^2 (FP64: it feeds the discrete decisions)
+  T Trot_rel, mstar;
+  T margin;        // smallest relative pivot of the accepted factor
+  bool skip, fallback, nu_zero, clamp_rot, clamp_m;
+};
+
+// Cholesky with the smallest relative pivot min(d2/S_yy, d3/S_zz) returned.
+template <typename T>
+__device__ __forceinline__ bool chol3m(const T S[6], T L[6], T* margin) {
+  if (!(S[0] > T(0))) return false;
+  const T l11 = sqrt(S[0]);
+  const T l21 = S[3] / l11, l31 = S[4] / l11;
+  const T d2 = S[1] - l21 * l21;
+  if (!(d2 > T(0))) return false;
+  const T l22 = sqrt(d2);
+  const T l32 = (S[5] - l31 * l21) / l22;
+  const T d3 = S[2] - l31 * l31 - l32 * l32;
+  if (!(d3 > T(0))) return false;
+  L[0] = l11; L[1] = l21; L[2] = l22; L[3] = l31; L[4] = l32; L[5] = sqrt(d3);
+  *margin = fmin(d2 / S[1], d3 / S[2]);
+  return true;
+}
+
+// The chain of Secs. III.A.1-III.A.3 for one particle: rescaled
+// temperature and gamma coefficients from the interpolated temperatures,
+// relaxation temperatures (eqs. T_tr_USP, T_rot_USP, T_vib_USP), the
+// diffusion tensor (eq. D_tr) and its Cholesky test, and on failure the nu
+// clamp and alpha refit (eqs. nu_USP_positivity, alpha_USP_positivity_1..4).
+template <typename T>
+__device__ PartCoef<T> particle_coef(T R, T Th, T Ttr, T Trot, T Tvib, const T P[6],
+                                     const CellCoef& cc) {
+  PartCoef<T> r;
+  r.skip = r.fallback = r.nu_zero = r.clamp_rot = r.clamp_m = false;
+  r.margin = T(1);
+  const T a = (T)cc.a, b = (T)cc.b;
+  T al = (T)cc.al;
+  double oma2d = cc.oma2;
+  T nu = (T)cc.nu;
+  const T Tc = tcheck<T>(Th, Ttr, Trot, Tvib, a, b);
+  const T cb = cbar_R<T>(Th, Tc, Tvib);
+  const T D = T(1.5) + a + b * cb;
+  const T g1 = T(3) * a / D, g2 = T(3) * b * cb / D, g3 = T(2) * a * b * cb / D;
+  const T Xtr = g1 * (Ttr - Trot) + g2 * (Ttr - Tvib);
+  const T Xrot = g1 * (Ttr - Trot) - g3 * (Trot - Tvib);
+  const T Xvib = g2 * (Ttr - Tvib) + g3 * (Trot - Tvib);
+  const T mvib = mlevel<T>(Th, Tvib);
+  T oma2 = (T)oma2d;
+  T Ttr_rel = Ttr - Xtr / (T(1.5) * oma2);
+  T Trot_rel = Trot + Xrot / oma2;
+  T mstar = mvib + Xvib / (oma2 * Th);
+  const T RT = R * Ttr;
+  T Lam[6];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) Lam[k] = R * Ttr_rel + nu * (P[k] - RT);
+#pragma unroll
+  for (int k = 3; k < 6; ++k) Lam[k] = nu * P[k];
+  bool ok = chol3m<T>(Lam, r.L, &r.margin);
+  if (!ok) {
+    r.fallback = true;
+    if (!(Ttr_rel > T(0))) {
+      r.skip = true;
+      return r;
+    }
+    T lmin, lmax;
+    eig_minmax<T>(P, &lmin, &lmax);
+    const T RTr = R * Ttr_rel;
+    const T shrink = T(1) - T(1.0 / 1048576.0);
+    if (nu <= T(0)) {
+      if (lmax > RT) nu = fmax(nu, -RTr / (lmax - RT) * shrink);
+    } else {
+      if (lmin < RT) nu = fmin(nu, RTr / (RT - lmin) * shrink);
+    }
+    double a2 = ((double)nu - cc.r2) / ((double)nu - 1.0);
+    a2 = fmin(1.0, fmax(0.0, a2));
+    const double ap = sqrt(a2), am = -ap;
+    const double Prp = cc.A2 * (1.0 - ap * ap * ap) / (cc.dt * (1.0 + ap * ap * ap));
+    const double Prm = cc.A2 * (1.0 - am * am * am) / (cc.dt * (1.0 + am * am * am));
+    al = (T)((fabs(Prm - cc.Pr) < fabs(Prp - cc.Pr)) ? am : ap);
+    oma2d = 1.0 - a2;
+    if (!(oma2d > 0.0)) {
+      r.skip = true;
+      return r;
+    }
+    oma2 = (T)oma2d;
+    Ttr_rel = Ttr - Xtr / (T(1.5) * oma2);
+    Trot_rel = Trot + Xrot / oma2;
+    mstar = mvib + Xvib / (oma2 * Th);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Lam[k] = R * Ttr_rel + nu * (P[k] - RT);
+#pragma unroll
+    for (int k = 3; k < 6; ++k) Lam[k] = nu * P[k];
+    ok = chol3m<T>(Lam, r.L, &r.margin);
+    if (!ok) {
+      r.nu_zero = true;
+      if (Ttr_rel > T(0)) {
+        const T s0 = sqrt(R * Ttr_rel);
+        r.L[0] = s0; r.L[1] = T(0); r.L[2] = s0; r.L[3] = T(0); r.L[4] = T(0); r.L[5] = s0;
+      } else {
+        r.skip = true;
+        return r;
+      }
+    }
+  }
+  if (Trot_rel < T(0)) { Trot_rel = T(0); r.clamp_rot = true; }
+  if (mstar < T(0)) { mstar = T(0); r.clamp_m = true; }
+  r.al = al;
+  r.oma2 = oma2d;
+  r.Trot_rel = Trot_rel;
+  r.mstar = mstar;
+  return r;
+}
+
+template <typename S>
+__global__ __launch_bounds__(PART_BLOCK) void k_collide(GridP g, GasP gas, const double* __restrict__ cs,
+                                                        PartP<S> p, uint64_t seed, uint32_t step,
+                                                        int64_t* counters) {
+  using T = S;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.count[0]) return;
+  const int32_t c = p.cell[i];
+  if (c < 0) return;
+  const int64_t M = g.M;
+  if (cs[CS_COLLIDE * M + c] == 0.0) return;
+
+  // ---- first-order polynomial reconstruction (Sec. III.B), FP64 --------
+  int64_t c10 = c, c01 = c, c11 = c;
+  double wx = 0.0, wy = 0.0;
+  bool hx = false, hy = false, hxy = false;
+  if (g.dim >= 1) {
+    const int nx = g.nx;
+    const int ci = g.dim == 2 ? c % nx : 0;
+    const int cj = g.dim == 2 ? c / nx : c;
+    auto ok = [&](int ii, int jj) -> bool {
+      if (ii < 0 || jj < 0 || ii >= g.nx || jj >= g.ny) return false;
+      return cs[CS_NBR_OK * M + (int64_t)jj * nx + ii] != 0.0;
+    };
+    // cell centre with explicitly rounded operations (no contraction)
+    const double yc = __dadd_rn(g.y0, __dmul_rn(cj + 0.5, g.dy));
+    const double dyv = (double)p.y[i] - yc;
+    const int sy = dyv >= 0.0 ? 1 : -1;
+    int ty = 0;
+    if (ok(ci, cj + sy)) ty = sy;
+    else if (ok(ci, cj - sy)) ty = -sy;
+    if (ty) { hy = true; wy = dyv / (ty * g.dy); c01 = (int64_t)(cj + ty) * nx + ci; }
+    if (g.dim == 2) {
+      const double xc = __dadd_rn(g.x0, __dmul_rn(ci + 0.5, g.dx));
+      const double dxv = (double)p.x[i] - xc;
+      const int sx = dxv >= 0.0 ? 1 : -1;
+      int tx = 0;
+      if (ok(ci + sx, cj)) tx = sx;
+      else if (ok(ci - sx, cj)) tx = -sx;
+      if (tx) { hx = true; wx = dxv / (tx * g.dx); c10 = (int64_t)cj * nx + ci + tx; }
+      if (tx && ty && ok(ci + tx, cj + ty)) { hxy = true; c11 = (int64_t)(cj + ty) * nx + ci + tx; }
+    }
+  }
+  auto interp = [&](int f) -> double {
+    const double* F = cs + (int64_t)f * M;
+    const double f00 = F[c];
+    double phi = f00;
+    const double f10 = F[c10], f01 = F[c01];
+    if (hx) phi += (f10 - f00) * wx;
+    if (hy) phi += (f01 - f00) * wy;
+    if (hxy) phi += (f00 - f10 - f01 + F[c11]) * wx * wy;
+    return phi;
+  };
+  T U[3], P[6];
+  double Pd[6], Tk[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) U[k] = (T)interp(CS_UX + k);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) { Pd[k] = interp(CS_PXX + k); P[k] = (T)Pd[k]; }
+  bool clamped = false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    Tk[k] = interp(CS_TTR + k);
+    const double fl = 0.05 * cs[(CS_TTR + k) * M + c];
+    if (Tk[k] < fl) { Tk[k] = fl; clamped = true; }
+  }
+  if (clamped) count_event(counters, USP_CNT_INTERP_CLAMP);
+
+  // ---- per-particle coefficients -----------------------------------------
+  CellCoef cc;
+  cc.a = cs[CS_A * M + c]; cc.b = cs[CS_B * M + c]; cc.al = cs[CS_ALPHA * M + c];
+  cc.oma2 = cs[CS_OMA2 * M + c]; cc.nu = cs[CS_NU * M + c]; cc.r2 = cs[CS_R2 * M + c];
+  cc.A2 = 2.0 * cs[CS_MUP * M + c]; cc.Pr = cs[CS_PR * M + c]; cc.dt = cs[CS_DT * M + c];
+  PartCoef<T> pc = particle_coef<T>((T)gas.R, (T)gas.theta, (T)Tk[0], (T)Tk[1], (T)Tk[2], P, cc);
+  if constexpr (sizeof(T) == 4) {
+    // The Cholesky test is a branch: near the positive-definiteness
+    // boundary it is taken in FP64, from the FP64 interpolated values.
+    if (pc.fallback || pc.margin < T(1e-4)) {
+      const PartCoef<double> pd = particle_coef<double>(gas.R, gas.theta, Tk[0], Tk[1], Tk[2], Pd, cc);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) pc.L[k] = (T)pd.L[k];
+      pc.al = (T)pd.al; pc.oma2 = pd.oma2; pc.Trot_rel = (T)pd.Trot_rel; pc.mstar = (T)pd.mstar;
+      pc.skip = pd.skip; pc.fallback = pd.fallback; pc.nu_zero = pd.nu_zero;
+      pc.clamp_rot = pd.clamp_rot; pc.clamp_m = pd.clamp_m;
+    }
+  }
+  if (pc.fallback) count_event(counters, USP_CNT_CHOL_FALLBACK);
+  if (pc.nu_zero) count_event(counters, USP_CNT_NU_ZERO);
+  if (pc.skip) {
+    count_event(counters, USP_CNT_TREL_SKIP);
+    return;
+  }
+  if (pc.clamp_rot) count_event(counters, USP_CNT_TREL_CLAMP);
+  if (pc.clamp_m) count_event(counters, USP_CNT_TREL_CLAMP);
+  const T R = (T)gas.R;
+  const T al = pc.al;
+  const T oma2 = (T)pc.oma2;
+  const double oma2d = pc.oma2;
+  const T* L = pc.L;
+  const T Trot_rel = pc.Trot_rel, mstar = pc.mstar;
+
+  // ---- draws: Philox blocks (pid, step, 0, 0) and (pid, step, 0, 1) ----
+  const uint32_t id = p.pid[i];
+  const U4 w0 = philox(id, step, TAG_COLLIDE, 0u, seed);
+  const U4 w1 = philox(id, step, TAG_COLLIDE, 1u, seed);
+  T G1, G2, G3, G4;
+  box_muller<T>(w0.w[0], w0.w[1], &G1, &G2);
+  box_muller<T>(w0.w[2], w0.w[3], &G3, &G4);
+
+  // ---- velocity (eq. update_ci), rotation (eq. update_erot) -------------
+  const T sq = sqrt(oma2);
+  const T Cx = (T)p.cx[i] - U[0], Cy = (T)p.cy[i] - U[1], Cz = (T)p.cz[i] - U[2];
+  p.cx[i] = (S)(U[0] + al * Cx + sq * (L[0] * G1));
+  p.cy[i] = (S)(U[1] + al * Cy + sq * (L[1] * G1 + L[2] * G2));
+  p.cz[i] = (S)(U[2] + al * Cz + sq * (L[3] * G1 + L[4] * G2 + L[5] * G3));
+  const T half = T(0.5) * R * Trot_rel * oma2;
+  const T root = sqrt((T)p.erot[i]) * al + sqrt(half) * G4;
+  p.erot[i] = (S)(half + root * root);
+
+  // ---- vibrational level (eq. update_evib), decisions in FP64 ----------
+  const int I = p.vib[i];
+  const double ms = (double)mstar;
+  const double pNB = 1.0 / (1.0 + ms * oma2d);
+  double pB = (1.0 + ms) * oma2d;
+  if (pB > 1.0) { pB = 1.0; count_event(counters, USP_CNT_PB_CLAMP); }
+  int nI = I + sample_nb(u01d(w1.w[0]), I + 1, pNB) - sample_b(u01d(w1.w[1]), I, pB);
+  if (nI > VIB_MAX) { nI = VIB_MAX; count_event(counters, USP_CNT_VIB_SAT); }
+  p.vib[i] = (uint8_t)nI;
+}
+
+// ---------------------------------------------------------------------------
+// Conservation (Sec. IV.C): one block per cell.
+// ---------------------------------------------------------------------------
+template <int NV>
+__device__ __forceinline__ void cons_block_sum(double (&v)[NV], double* lds) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lds[wid * NV + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = lds[k];
+#pragma unroll
+    for (int w = 1; w < CONS_BLOCK / 64; ++w) s += lds[w * NV + k];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+template <typename S>
+__global__ __launch_bounds__(CONS_BLOCK) void k_conserve(GridP g, GasP gas, const double* __restrict__ cs,
+                                                         const int64_t* offsets, PartP<S> p,
+                                                         uint64_t seed, uint32_t step,
+                                                         int64_t* counters) {
+  __shared__ double lds[(CONS_BLOCK / 64) * 6];
+  __shared__ double fac[6];  // rot factor, vel scale, U* (3), flags
+  const int64_t M = g.M, c = blockIdx.x;
+  const int64_t o0 = offsets[c], o1 = offsets[c + 1], N = o1 - o0;
+  if (N == 0 || cs[CS_COLLIDE * M + c] == 0.0) return;
+  const double Un[3] = {cs[CS_UX * M + c], cs[CS_UY * M + c], cs[CS_UZ * M + c]};
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t i = o0 + threadIdx.x; i < o1; i += CONS_BLOCK) {
+    const double d0 = (double)p.cx[i] - Un[0], d1 = (double)p.cy[i] - Un[1],
+                 d2 = (double)p.cz[i] - Un[2];
+    s[0] += d0; s[1] += d1; s[2] += d2;
+    s[3] += d0 * d0 + d1 * d1 + d2 * d2;
+    s[4] += (double)p.erot[i];
+    s[5] += (double)p.vib[i];
+  }
+  cons_block_sum<6>(s, lds);
+  if (threadIdx.x == 0) {
+    const double Nd = (double)N;
+    const double RTh = gas.R * gas.theta;
+    const double m1[3] = {s[0] / Nd, s[1] / Nd, s[2] / Nd};
+    const double etr_s = 0.5 * (s[3] / Nd - (m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2]));
+    int64_t SI = (int64_t)s[5];
+    // (i) vibrational levels: I_delta = floor(N (e_target - e*)/(R theta) + U)
+    const double X = Nd * cs[CS_EVIB_NEW * M + c] / RTh - (double)SI;
+    U4 w = philox((uint32_t)c, step, TAG_CONSERVE, 0u, seed);
+    int64_t Id = (int64_t)floor(X + u01d(w.w[0]));
+    int64_t att = 0;
+    const int64_t maxatt = 64 * N;
+    uint32_t j = 1;
+    uint32_t blk = 0;
+    while (Id != 0) {
+      if (att >= maxatt || (Id < 0 && SI == 0)) {
+        count_event(counters, USP_CNT_PICK_FAIL);
+        break;
+      }
+      if ((j >> 2) != blk) { blk = j >> 2; w = philox((uint32_t)c, step, TAG_CONSERVE, blk, seed); }
+      const double uu = u01d(w.w[j & 3]);
+      ++j;
+      ++att;
+      int64_t k = (int64_t)floor(uu * Nd);
+      if (k >= N) k = N - 1;
+      uint8_t* lv = &p.vib[o0 + k];
+      const int cur = *lv;
+      if (Id > 0) {
+        if (cur < VIB_MAX) { *lv = (uint8_t)(cur + 1); ++SI; --Id; }
+      } else {
+        if (cur > 0) { *lv = (uint8_t)(cur - 1); --SI; ++Id; }
+      }
+    }
+    // (ii) rotational scaling to the cell target
+    const double erot_s = s[4] / Nd, erot_t = cs[CS_EROT_NEW * M + c];
+    double erot_a = erot_s, frot = 1.0, do_rot = 0.0;
+    if (erot_s > 0.0 && erot_t > 0.0) {
+      frot = erot_t / erot_s;
+      erot_a = erot_t;
+      do_rot = 1.0;
+    } else {
+      count_event(counters, USP_CNT_CONS_SKIP);
+    }
+    // (iii) velocity scaling about U*, toward U^n (momentum and energy)
+    const double evib_a = (double)SI * RTh / Nd;
+    const double E0 = cs[CS_ETR * M + c] + cs[CS_EROT * M + c] + cs[CS_EVIB * M + c];
+    const double s2 = (E0 - erot_a - evib_a) / etr_s;
+    double sc = 0.0;
+    if (etr_s > 0.0 && s2 > 0.0) sc = sqrt(s2);
+    else count_event(counters, USP_CNT_CONS_SKIP);
+    fac[0] = do_rot > 0.0 ? frot : 0.0;
+    fac[1] = sc;
+    fac[2] = Un[0] + m1[0];
+    fac[3] = Un[1] + m1[1];
+    fac[4] = Un[2] + m1[2];
+  }
+  __syncthreads();
+  const double frot = fac[0], sc = fac[1];
+  const double Us0 = fac[2], Us1 = fac[3], Us2 = fac[4];
+  for (int64_t i = o0 + threadIdx.x; i < o1; i += CONS_BLOCK) {
+    if (frot > 0.0) p.erot[i] = (S)((double)p.erot[i] * frot);
+    if (sc > 0.0) {
+      p.cx[i] = (S)(Un[0] + sc * ((double)p.cx[i] - Us0));
+      p.cy[i] = (S)(Un[1] + sc * ((double)p.cy[i] - Us1));
+      p.cz[i] = (S)(Un[2] + sc * ((double)p.cz[i] - Us2));
+    }
+  }
+}
+
+template <typename S>
+hipError_t launch_collide(const GridP& g, const GasP& gas, const double* cs, const int64_t* offsets,
+                          const PartP<S>& p, uint64_t seed, uint64_t step, int64_t* counters,
+                          hipStream_t st) {
+  (void)offsets;
+  k_collide<S><<<cdiv(p.capacity, PART_BLOCK), PART_BLOCK, 0, st>>>(g, gas, cs, p, seed,
+                                                                    (uint32_t)step, counters);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_conserve(const GridP& g, const GasP& gas, const double* cs,
+                           const int64_t* offsets, const PartP<S>& p, uint64_t seed, uint64_t step,
+                           int64_t* counters, hipStream_t st) {
+  k_conserve<S><<<g.M, CONS_BLOCK, 0, st>>>(g, gas, cs, offsets, p, seed, (uint32_t)step, counters);
+  return hipGetLastError();
+}
+
+template hipError_t launch_collide<float>(const GridP&, const GasP&, const double*, const int64_t*,
+                                          const PartP<float>&, uint64_t, uint64_t, int64_t*,
+                                          hipStream_t);
+template hipError_t launch_collide<double>(const GridP&, const GasP&, const double*, const int64_t*,
+                                           const PartP<double>&, uint64_t, uint64_t, int64_t*,
+                                           hipStream_t);
+template hipError_t launch_conserve<float>(const GridP&, const GasP&, const double*,
+                                           const int64_t*, const PartP<float>&, uint64_t, uint64_t,
+                                           int64_t*, hipStream_t);
+template hipError_t launch_conserve<double>(const GridP&, const GasP&, const double*,
+                                            const int64_t*, const PartP<double>&, uint64_t,
+                                            uint64_t, int64_t*, hipStream_t);
+
+}  // namespace usp

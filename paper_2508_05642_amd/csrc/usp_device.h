@@ -1,0 +1,201 @@
+// usp_device.h -- device-side building blocks of libusp (gfx950).
+#pragma once
+
+#include <math.h>
+
+#include "usp_internal.h"
+
+namespace usp {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11):
+// ten rounds of two 32x32->64 products; the key advances by two Weyl
+// constants between rounds.  Key = seed, counter = (c0, c1, c2, c3).
+// ---------------------------------------------------------------------------
+struct U4 {
+  uint32_t w[4];
+};
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint64_t seed) {
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return U4{{c0, c1, c2, c3}};
+}
+
+// uniform (w + 1/2) 2^-32 in (0,1), exact in double
+__device__ __forceinline__ double u01d(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
+
+// ln u for the same u, with full relative accuracy in single precision
+// (near u = 1 through log1p of the exactly formed 1 - u)
+__device__ __forceinline__ float logu(uint32_t w, float) {
+  if (w < 0x80000000u) return logf(((float)w + 0.5f) * 0x1p-32f);
+  return log1pf(-(((float)(~w) + 0.5f) * 0x1p-32f));
+}
+__device__ __forceinline__ double logu(uint32_t w, double) { return log(u01d(w)); }
+
+// (sin, cos)(2 pi u) for the same u
+__device__ __forceinline__ void sincos2pi(uint32_t w, float* s, float* c) {
+  sincospif(((float)w + 0.5f) * 0x1p-31f, s, c);
+}
+__device__ __forceinline__ void sincos2pi(uint32_t w, double* s, double* c) {
+  sincospi(u01d(w) * 2.0, s, c);
+}
+
+// two standard normals from two words (Box-Muller)
+template <typename T>
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, T* g1, T* g2) {
+  T r = sqrt(T(-2) * logu(wa, T()));
+  T s, c;
+  sincos2pi(wb, &s, &c);
+  *g1 = r * c;
+  *g2 = r * s;
+}
+
+// ---------------------------------------------------------------------------
+// Gas model in reduced units (temperatures in K, energies per R).
+// ---------------------------------------------------------------------------
+// mean harmonic-oscillator level 1/(e^{theta/T} - 1) = e_vib/(R theta)
+template <typename T>
+__device__ __forceinline__ T mlevel(T theta, T Temp) {
+  if (!(Temp > T(0))) return T(0);
+  const T x = theta / Temp;
+  if (x > T(700)) return T(0);
+  return T(1) / expm1(x);
+}
+
+// c_v,vib / R = x^2 e^{-x} / (1 - e^{-x})^2, x = theta/T
+template <typename T>
+__device__ __forceinline__ T cv_vib_R(T x) {
+  if (x > T(700)) return T(0);
+  const T e = exp(-x), d = -expm1(-x);
+  return x * x * e / (d * d);
+}
+
+// Rescaled translational temperature: root of
+//   (3/2 + a) T + b theta m(T) = 3/2 T_tr + a T_rot + b theta m(T_vib)
+// (the energy balance behind the gamma coefficients of Sec. III.A.1),
+// safeguarded Newton on [0, rhs/(3/2 + a)].
+template <typename T>
+__device__ __forceinline__ T tcheck(T theta, T Ttr, T Trot, T Tvib, T a, T b) {
+  const T ca = T(1.5) + a;
+  const T rhs = T(1.5) * Ttr + a * Trot + b * theta * mlevel(theta, Tvib);
+  T hi = rhs / ca, lo = T(0);
+  if (!(hi > T(0))) return T(0);
+  T t = (T(1.5) * Ttr + a * Trot) / ca;
+  if (!(t > T(0) && t <= hi)) t = hi;
+  const T tol = sizeof(T) == 4 ? T(3e-7) : T(1e-14);
+  for (int it = 0; it < 40; ++it) {
+    const T f = ca * t + b * theta * mlevel(theta, t) - rhs;
+    if (f > T(0)) hi = t; else lo = t;
+    const T fp = ca + b * cv_vib_R(theta / t);
+    T tn = t - f / fp;
+    if (!(tn > lo && tn < hi)) tn = T(0.5) * (lo + hi);
+    const T dt = fabs(tn - t);
+    t = tn;
+    if (dt <= tol * t) break;
+  }
+  return t;
+}
+
+// Secant heat capacity c_v,vib(T_1)/R between T_c and T_v (Sec. III.A.1),
+// evaluated without cancellation:
+//   xa xb e^{-xa} ((1 - e^{-d})/d) / ((1 - e^{-xa})(1 - e^{-xb})),
+// xa <= xb the two values of theta/T, d = xb - xa.
+template <typename T>
+__device__ __forceinline__ T cbar_R(T theta, T Tc, T Tv) {
+  if (!(Tc > T(0))) return T(0);
+  if (!(Tv > T(0))) {
+    const T xa = theta / Tc;
+    return xa > T(700) ? T(0) : xa / expm1(xa);
+  }
+  const T x1 = theta / Tc, x2 = theta / Tv;
+  const T xa = fmin(x1, x2), xb = fmax(x1, x2);
+  if (xa > T(700)) return T(0);
+  const T d = theta * fabs(Tc - Tv) / (Tc * Tv);
+  const T h = d < T(1e-3) ? T(1) - d * (T(0.5) - d * (T(1) / T(6) - d * T(1) / T(24)))
+                          : -expm1(-d) / d;
+  const T ea = exp(-xa);
+  const T oa = -expm1(-xa), ob = -expm1(-xb);
+  return xa * (xb * h) * ea / (oa * ob);
+}
+
+// Eucken Prandtl number (Sec. IV.B)
+__device__ __forceinline__ double prandtl(const GasP& g, double T) {
+  if (g.pr_model == USP_PR_CONST) return g.Pr_const;
+  double xi = 0.0;
+  if (T > 0.0) {
+    const double x = g.theta / T;
+    xi = x > 700.0 ? 0.0 : x / expm1(x);
+    if (g.pr_model == USP_PR_EUCKEN_STANDARD) xi *= 2.0;
+  }
+  return (14.0 + 2.0 * xi) / (19.0 + 2.0 * xi);
+}
+
+__device__ __forceinline__ double zrot(const GasP& g, double T) {
+  if (g.zrot_model == USP_ZROT_CONST) return g.Z_rot;
+  const double r = g.T_star / T;
+  return g.Z_rot_inf / (1.0 + 0.5 * pow(PI, 1.5) * sqrt(r) + (PI + 0.25 * PI * PI) * r);
+}
+
+__device__ __forceinline__ double zvib(const GasP& g, double T) {
+  if (g.zvib_model == USP_ZVIB_CONST) return g.Z_vib;
+  const double mw = (g.C1 / pow(T, g.omega)) * exp(g.C2 * pow(T, -1.0 / 3.0));
+  const double ht = (PI * g.d_ref * g.d_ref / g.sigma_vib) * pow(g.T_ref / T, g.omega - 0.5);
+  return mw + ht;
+}
+
+// ---------------------------------------------------------------------------
+// Grid: edge k of an axis in the stored precision S, formed with explicitly
+// rounded FP64 operations (no contraction), so host and device agree bit
+// for bit.  The index along an axis is the number of interior edges at or
+// below v; -1 outside [e_0, e_n).
+// ---------------------------------------------------------------------------
+template <typename S>
+__device__ __forceinline__ S edge(double o, double d, int k) {
+  return (S)__dadd_rn(o, __dmul_rn((double)k, d));
+}
+
+template <typename S>
+__device__ __forceinline__ int axis_index(S v, double o, double d, int n) {
+  if (!(v >= edge<S>(o, d, 0)) || v >= edge<S>(o, d, n)) return -1;
+  int k = (int)floor(((double)v - o) / d);
+  k = k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
+  while (k > 0 && edge<S>(o, d, k) > v) --k;
+  while (k < n - 1 && edge<S>(o, d, k + 1) <= v) ++k;
+  return k;
+}
+
+template <typename S>
+__device__ __forceinline__ int32_t cell_of(const GridP& g, S x, S y) {
+  if (g.dim == 1) return axis_index<S>(y, g.y0, g.dy, g.ny);
+  const int ix = axis_index<S>(x, g.x0, g.dx, g.nx);
+  const int iy = axis_index<S>(y, g.y0, g.dy, g.ny);
+  if (ix < 0 || iy < 0) return -1;
+  return iy * g.nx + ix;
+}
+
+// 64-bit event counter
+__device__ __forceinline__ void count_event(int64_t* counters, int k, int64_t v = 1) {
+  if (counters) atomicAdd((unsigned long long*)&counters[k], (unsigned long long)v);
+}
+
+// ---------------------------------------------------------------------------
+// wave64 / block reductions in a fixed order (deterministic)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+}  // namespace usp

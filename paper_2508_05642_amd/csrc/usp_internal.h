@@ -1,0 +1,107 @@
+// usp_internal.h -- shared declarations of libusp's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/usp.h"
+
+namespace usp {
+
+// moment planes, mom[k*M + c] (per unit mass, central about U)
+enum Mom {
+  M_N = 0, M_UX, M_UY, M_UZ, M_PXX, M_PYY, M_PZZ, M_PXY, M_PXZ, M_PYZ, M_EROT, M_IBAR,
+  M_QTRX, M_QTRY, M_QTRZ, M_QROTX, M_QROTY, M_QROTZ, M_QIX, M_QIY, M_QIZ, NMOM
+};
+static_assert(NMOM == USP_NMOM, "moment plane count");
+
+// cell-state planes, cs[k*M + c]
+enum Cs {
+  CS_NP = 0, CS_NDENS, CS_UX, CS_UY, CS_UZ, CS_TTR, CS_TROT, CS_TVIB,
+  CS_PXX, CS_PYY, CS_PZZ, CS_PXY, CS_PXZ, CS_PYZ, CS_ETR, CS_EROT, CS_EVIB,
+  CS_MU, CS_MUP, CS_TAUC, CS_ZROT, CS_ZVIB, CS_PR, CS_DT, CS_A, CS_B, CS_R2, CS_R3,
+  CS_ALPHA, CS_OMA2, CS_NU, CS_EROT_NEW, CS_EVIB_NEW, CS_COLLIDE, CS_NBR_OK, NCS
+};
+static_assert(NCS == USP_NCS, "cell-state plane count");
+
+constexpr int VIB_MAX = 255;
+constexpr int MAX_BOUNCE = 8;
+constexpr int NB_KMAX = 512;
+constexpr double KB = 1.380649e-23;
+constexpr double PI = 3.14159265358979323846;
+
+// stream tags of the counter-based generator
+enum Tag : uint32_t { TAG_COLLIDE = 0, TAG_WALL = 1, TAG_CONSERVE = 2, TAG_INJECT = 3, TAG_FACE = 5 };
+
+// Scalars the kernels need, passed by value (one copy per launch).
+struct GasP {
+  double R, theta, T_ref, mu_ref, omega, K;  // K = tau_c / (mu/p)
+  int zrot_model; double Z_rot, Z_rot_inf, T_star;
+  int zvib_model; double Z_vib, C1, C2, sigma_vib, d_ref;
+  int pr_model; double Pr_const;
+};
+
+struct GridP {
+  int dim, nx, ny;
+  int64_t M;
+  double x0, y0, dx, dy, fnum;
+  const double* volume;
+  const uint8_t* flags;
+};
+
+struct BcP {
+  int kind[4];
+  double Tw[4];
+  double fs_n, fs_T, fs_U[3], depth;
+  int cyl;
+  double cyl_xc, cyl_yc, cyl_r, cyl_Tw;
+  double g[3];
+};
+
+template <typename S>
+struct PartP {
+  S *x, *y, *cx, *cy, *cz, *erot;
+  uint8_t* vib;
+  int32_t* cell;
+  uint32_t* pid;
+  int64_t* count;
+  int64_t capacity;
+};
+
+GasP make_gas(const usp_gas* g);
+GridP make_grid(const usp_grid* g);
+BcP make_bc(const usp_bc* b);
+template <typename S> PartP<S> make_parts(const usp_particles* p);
+
+// workspace layout (byte offsets into the caller's scratch buffer)
+struct WsLayout {
+  size_t key, cursor, perm, blocksums, face_cnt, face_off, misc, total;
+};
+WsLayout ws_layout(int64_t M, int64_t capacity, int nfaces);
+int n_faces(const GridP& g);
+
+// launchers (return hipError_t of the last launch)
+template <typename S>
+hipError_t launch_bin(const GridP& g, const PartP<S>& in, const PartP<S>& out, int64_t* offsets,
+                      char* ws, const WsLayout& L, int64_t* counters, hipStream_t st);
+template <typename S>
+hipError_t launch_moments(const GridP& g, const PartP<S>& p, const int64_t* offsets, double* mom,
+                          hipStream_t st);
+hipError_t launch_reconstruct(const GridP& g, const GasP& gas, const double* mom, double dt,
+                              const double* dt_cell, double* cs, int64_t* counters, hipStream_t st);
+template <typename S>
+hipError_t launch_collide(const GridP& g, const GasP& gas, const double* cs, const int64_t* offsets,
+                          const PartP<S>& p, uint64_t seed, uint64_t step, int64_t* counters,
+                          hipStream_t st);
+template <typename S>
+hipError_t launch_conserve(const GridP& g, const GasP& gas, const double* cs,
+                           const int64_t* offsets, const PartP<S>& p, uint64_t seed, uint64_t step,
+                           int64_t* counters, hipStream_t st);
+template <typename S>
+hipError_t launch_advect(const GridP& g, const GasP& gas, const BcP& bc, double dt,
+                         const PartP<S>& p, uint64_t seed, uint64_t step, char* ws,
+                         const WsLayout& L, int64_t* counters, hipStream_t st);
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace usp

@@ -1,0 +1,164 @@
+// usp_moments.hip -- per-cell moments and the per-cell USP-FPM state.
+#include "usp_device.h"
+
+namespace usp {
+
+constexpr int CELL_BLOCK = 256;
+constexpr int CELL_WAVES = CELL_BLOCK / 64;
+
+// Sum NV values over the block in a fixed order: wave butterflies, then the
+// four wave partials in wave order.  Every thread receives the totals.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lds[wid * NV + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = lds[k];
+#pragma unroll
+    for (int w = 1; w < CELL_WAVES; ++w) s += lds[w * NV + k];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+// Moments of one cell (Sec. II.A): U = <c>, then central second and third
+// moments about U, per unit mass.
+template <typename S>
+__global__ __launch_bounds__(CELL_BLOCK) void k_moments(GridP g, PartP<S> p, const int64_t* offsets,
+                                                        double* mom) {
+  __shared__ double lds[CELL_WAVES * 17];
+  const int64_t M = g.M, c = blockIdx.x;
+  const int64_t o0 = offsets[c], o1 = offsets[c + 1], N = o1 - o0;
+  if (N == 0) {
+    if (threadIdx.x < NMOM) mom[threadIdx.x * M + c] = 0.0;
+    return;
+  }
+  double s1[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = o0 + threadIdx.x; i < o1; i += CELL_BLOCK) {
+    s1[0] += (double)p.cx[i];
+    s1[1] += (double)p.cy[i];
+    s1[2] += (double)p.cz[i];
+  }
+  block_sum<3>(s1, lds);
+  const double invN = 1.0 / (double)N;
+  const double Ux = s1[0] * invN, Uy = s1[1] * invN, Uz = s1[2] * invN;
+  double s[17];
+#pragma unroll
+  for (int k = 0; k < 17; ++k) s[k] = 0.0;
+  for (int64_t i = o0 + threadIdx.x; i < o1; i += CELL_BLOCK) {
+    const double Cx = (double)p.cx[i] - Ux, Cy = (double)p.cy[i] - Uy, Cz = (double)p.cz[i] - Uz;
+    const double e = (double)p.erot[i], I = (double)p.vib[i];
+    const double hC2 = 0.5 * (Cx * Cx + Cy * Cy + Cz * Cz);
+    s[0] += Cx * Cx; s[1] += Cy * Cy; s[2] += Cz * Cz;
+    s[3] += Cx * Cy; s[4] += Cx * Cz; s[5] += Cy * Cz;
+    s[6] += e; s[7] += I;
+    s[8] += hC2 * Cx; s[9] += hC2 * Cy; s[10] += hC2 * Cz;
+    s[11] += Cx * e; s[12] += Cy * e; s[13] += Cz * e;
+    s[14] += Cx * I; s[15] += Cy * I; s[16] += Cz * I;
+  }
+  block_sum<17>(s, lds);
+  if (threadIdx.x == 0) {
+    mom[M_N * M + c] = (double)N;
+    mom[M_UX * M + c] = Ux;
+    mom[M_UY * M + c] = Uy;
+    mom[M_UZ * M + c] = Uz;
+  }
+  if (threadIdx.x < 17) {
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < 17; ++k)
+      if (k == (int)threadIdx.x) v = s[k];
+    mom[(M_PXX + threadIdx.x) * M + c] = v * invN;
+  }
+}
+
+// Per-cell state (Secs. II.A, III.A.1, III.A.2, IV.A, IV.B).
+__global__ void k_reconstruct(GridP g, GasP gas, const double* mom, double dt,
+                              const double* dt_cell, double* cs, int64_t* counters) {
+  const int64_t M = g.M;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= M) return;
+  const double R = gas.R, Th = gas.theta;
+  double v[NCS];
+#pragma unroll
+  for (int k = 0; k < NCS; ++k) v[k] = 0.0;
+  const double N = mom[M_N * M + c];
+  const double vol = g.volume[c];
+  v[CS_NP] = N;
+  v[CS_NDENS] = vol > 0.0 ? N * g.fnum / vol : 0.0;
+  v[CS_UX] = mom[M_UX * M + c];
+  v[CS_UY] = mom[M_UY * M + c];
+  v[CS_UZ] = mom[M_UZ * M + c];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v[CS_PXX + k] = mom[(M_PXX + k) * M + c];
+  const double trP = v[CS_PXX] + v[CS_PYY] + v[CS_PZZ];
+  const double ibar = mom[M_IBAR * M + c];
+  const double erot = mom[M_EROT * M + c];
+  const double Ttr = trP / (3.0 * R), Trot = erot / R;
+  const double Tvib = ibar > 0.0 ? Th / log1p(1.0 / ibar) : 0.0;
+  v[CS_TTR] = Ttr; v[CS_TROT] = Trot; v[CS_TVIB] = Tvib;
+  v[CS_ETR] = 0.5 * trP; v[CS_EROT] = erot; v[CS_EVIB] = ibar * R * Th;
+  const double dtc = dt_cell ? dt_cell[c] : dt;
+  v[CS_DT] = dtc;
+  const bool collide = N >= 2.0 && Ttr > 0.0 && isfinite(Ttr) && vol > 0.0;
+  if (collide) {
+    const double mu = gas.mu_ref * pow(Ttr / gas.T_ref, gas.omega);
+    const double mup = mu / (v[CS_NDENS] * KB * Ttr);
+    const double tauc = gas.K * mup;
+    const double zr = zrot(gas, Ttr), zv = zvib(gas, Ttr);
+    const double Pr = prandtl(gas, Ttr);
+    const double A = 2.0 * mup;
+    const double r3 = (A - Pr * dtc) / (A + Pr * dtc);
+    const double r2 = (A - dtc) / (A + dtc);
+    const double al = cbrt(r3);
+    // 1 - alpha^2 = (1 - r3)(1 + alpha)/(1 + alpha + alpha^2), no cancellation
+    const double oma2 = (2.0 * Pr * dtc / (A + Pr * dtc)) * (1.0 + al) / (1.0 + al + al * al);
+    const double nu = (r2 - al * al) / oma2;
+    const double a = dtc / (dtc + 2.0 * zr * tauc);
+    const double b = dtc / (dtc + 2.0 * zv * tauc);
+    const double Tc = tcheck<double>(Th, Ttr, Trot, Tvib, a, b);
+    const double cb = cbar_R<double>(Th, Tc, Tvib);
+    const double D = 1.5 + a + b * cb;
+    const double g1 = 3.0 * a / D, g2 = 3.0 * b * cb / D, g3 = 2.0 * a * b * cb / D;
+    v[CS_MU] = mu; v[CS_MUP] = mup; v[CS_TAUC] = tauc;
+    v[CS_ZROT] = zr; v[CS_ZVIB] = zv; v[CS_PR] = Pr;
+    v[CS_A] = a; v[CS_B] = b; v[CS_R2] = r2; v[CS_R3] = r3;
+    v[CS_ALPHA] = al; v[CS_OMA2] = oma2; v[CS_NU] = nu;
+    v[CS_EROT_NEW] = erot + R * (g1 * (Ttr - Trot) - g3 * (Trot - Tvib));
+    v[CS_EVIB_NEW] = v[CS_EVIB] + R * (g2 * (Ttr - Tvib) + g3 * (Trot - Tvib));
+    v[CS_COLLIDE] = 1.0;
+    const int cut = g.flags ? (g.flags[c] & (USP_FLAG_SOLID | USP_FLAG_CUT)) : 0;
+    v[CS_NBR_OK] = cut ? 0.0 : 1.0;
+  } else if (N >= 1.0) {
+    count_event(counters, USP_CNT_CELL_SKIP);
+  }
+#pragma unroll
+  for (int k = 0; k < NCS; ++k) cs[k * M + c] = v[k];
+}
+
+template <typename S>
+hipError_t launch_moments(const GridP& g, const PartP<S>& p, const int64_t* offsets, double* mom,
+                          hipStream_t st) {
+  k_moments<S><<<g.M, CELL_BLOCK, 0, st>>>(g, p, offsets, mom);
+  return hipGetLastError();
+}
+
+hipError_t launch_reconstruct(const GridP& g, const GasP& gas, const double* mom, double dt,
+                              const double* dt_cell, double* cs, int64_t* counters, hipStream_t st) {
+  k_reconstruct<<<cdiv(g.M, 128), 128, 0, st>>>(g, gas, mom, dt, dt_cell, cs, counters);
+  return hipGetLastError();
+}
+
+template hipError_t launch_moments<float>(const GridP&, const PartP<float>&, const int64_t*,
+                                          double*, hipStream_t);
+template hipError_t launch_moments<double>(const GridP&, const PartP<double>&, const int64_t*,
+                                           double*, hipStream_t);
+
+}  // namespace usp

@@ -1,0 +1,308 @@
+"""Python binding of libusp (the C ABI declared in include/usp.h).
+
+Argument marshalling only: every step of the particle update runs in the
+HIP kernels of libusp.so.  Tensors are PyTorch device tensors (PyTorch is
+used for device memory and streams).  The functions keep the C names:
+usp_bin, usp_moments, usp_reconstruct, usp_collide, usp_conserve,
+usp_advect, usp_step.  If libusp.so is missing the import of this module
+fails: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libusp.so")
+
+USP_F32, USP_F64 = 0, 1
+NMOM, NCS, NCOUNTERS = 21, 35, 16
+
+
+class UspGas(C.Structure):
+    _fields_ = [("m", C.c_double), ("theta_vib", C.c_double), ("T_ref", C.c_double),
+                ("mu_ref", C.c_double), ("omega", C.c_double), ("alpha_vss", C.c_double),
+                ("zrot_model", C.c_int32), ("Z_rot", C.c_double), ("Z_rot_inf", C.c_double),
+                ("T_star", C.c_double), ("zvib_model", C.c_int32), ("Z_vib", C.c_double),
+                ("C1", C.c_double), ("C2", C.c_double), ("sigma_vib", C.c_double),
+                ("d_ref", C.c_double), ("pr_model", C.c_int32), ("Pr_const", C.c_double)]
+
+
+class UspGrid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("x0", C.c_double), ("y0", C.c_double), ("dx", C.c_double), ("dy", C.c_double),
+                ("fnum", C.c_double), ("volume", C.c_void_p), ("flags", C.c_void_p)]
+
+
+class UspBC(C.Structure):
+    _fields_ = [("kind", C.c_int32 * 4), ("Tw", C.c_double * 4), ("fs_n", C.c_double),
+                ("fs_T", C.c_double), ("fs_U", C.c_double * 3), ("depth", C.c_double),
+                ("cyl", C.c_int32), ("cyl_xc", C.c_double), ("cyl_yc", C.c_double),
+                ("cyl_r", C.c_double), ("cyl_Tw", C.c_double), ("g", C.c_double * 3)]
+
+
+class UspParticles(C.Structure):
+    _fields_ = [("prec", C.c_int32), ("capacity", C.c_int64), ("x", C.c_void_p),
+                ("y", C.c_void_p), ("cx", C.c_void_p), ("cy", C.c_void_p), ("cz", C.c_void_p),
+                ("erot", C.c_void_p), ("vib", C.c_void_p), ("cell", C.c_void_p),
+                ("pid", C.c_void_p), ("count", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libusp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2508_05642_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u64, d, sz = (C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double,
+                                    C.c_size_t)
+        L.usp_status_str.argtypes = [i32]
+        L.usp_status_str.restype = C.c_char_p
+        for nm in ("usp_mom_name", "usp_cs_name", "usp_counter_name"):
+            getattr(L, nm).argtypes = [i32]
+            getattr(L, nm).restype = C.c_char_p
+        L.usp_version.restype = C.c_char_p
+        L.usp_workspace_bytes.argtypes = [vp, i64]
+        L.usp_workspace_bytes.restype = sz
+        L.usp_bin.argtypes = [vp, vp, vp, vp, vp, sz, vp, vp]
+        L.usp_moments.argtypes = [vp, vp, vp, vp, vp]
+        L.usp_reconstruct.argtypes = [vp, vp, vp, d, vp, vp, vp, vp]
+        L.usp_collide.argtypes = [vp, vp, vp, vp, vp, u64, u64, vp, vp]
+        L.usp_conserve.argtypes = [vp, vp, vp, vp, vp, u64, u64, vp, vp]
+        L.usp_advect.argtypes = [vp, vp, vp, d, vp, u64, u64, vp, sz, vp, vp]
+        L.usp_step.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, vp, vp, vp, sz, u64, u64, i32, vp, vp]
+        for nm in ("usp_bin", "usp_moments", "usp_reconstruct", "usp_collide", "usp_conserve",
+                   "usp_advect", "usp_step"):
+            getattr(L, nm).restype = i32
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["usp_status_str", "usp_mom_name", "usp_cs_name", "usp_counter_name", "usp_version",
+            "usp_workspace_bytes", "usp_bin", "usp_moments", "usp_reconstruct", "usp_collide",
+            "usp_conserve", "usp_advect", "usp_step"]
+
+
+def names(kind):
+    fn = {"mom": lib().usp_mom_name, "cs": lib().usp_cs_name, "cnt": lib().usp_counter_name}[kind]
+    n = {"mom": NMOM, "cs": NCS, "cnt": NCOUNTERS}[kind]
+    return [fn(k).decode() for k in range(n)]
+
+
+class UspError(RuntimeError):
+    pass
+
+
+def _check(st, what):
+    if st != 0:
+        raise UspError(f"{what}: {lib().usp_status_str(st).decode()} ({st})")
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+# ---- struct builders (duck-typed descriptions with the C field names) ----
+def make_gas(g):
+    return UspGas(g.m, g.theta_vib, g.T_ref, g.mu_ref, g.omega, g.alpha_vss, g.zrot_model,
+                  g.Z_rot, g.Z_rot_inf, g.T_star, g.zvib_model, g.Z_vib, g.C1, g.C2,
+                  g.sigma_vib, g.d_ref, g.pr_model, g.Pr_const)
+
+
+def make_bc(b):
+    return UspBC((C.c_int32 * 4)(*b.kind), (C.c_double * 4)(*b.Tw), b.fs_n, b.fs_T,
+                 (C.c_double * 3)(*b.fs_U), b.depth, b.cyl, b.cyl_xc, b.cyl_yc, b.cyl_r,
+                 b.cyl_Tw, (C.c_double * 3)(*b.g))
+
+
+# ---- the seven entry points -------------------------------------------------
+def usp_bin(grid, pin, pout, offsets, ws, counters, stream=None):
+    _check(lib().usp_bin(C.byref(grid), C.byref(pin), C.byref(pout), _ptr(offsets), _ptr(ws),
+                         ws.numel(), _ptr(counters), _stream(stream)), "usp_bin")
+
+
+def usp_moments(grid, p, offsets, mom, stream=None):
+    _check(lib().usp_moments(C.byref(grid), C.byref(p), _ptr(offsets), _ptr(mom),
+                             _stream(stream)), "usp_moments")
+
+
+def usp_reconstruct(grid, gas, mom, dt, dt_cell, cs, counters, stream=None):
+    _check(lib().usp_reconstruct(C.byref(grid), C.byref(gas), _ptr(mom), dt, _ptr(dt_cell),
+                                 _ptr(cs), _ptr(counters), _stream(stream)), "usp_reconstruct")
+
+
+def usp_collide(grid, gas, cs, offsets, p, seed, step, counters, stream=None):
+    _check(lib().usp_collide(C.byref(grid), C.byref(gas), _ptr(cs), _ptr(offsets), C.byref(p),
+                             seed, step, _ptr(counters), _stream(stream)), "usp_collide")
+
+
+def usp_conserve(grid, gas, cs, offsets, p, seed, step, counters, stream=None):
+    _check(lib().usp_conserve(C.byref(grid), C.byref(gas), _ptr(cs), _ptr(offsets), C.byref(p),
+                              seed, step, _ptr(counters), _stream(stream)), "usp_conserve")
+
+
+def usp_advect(grid, gas, bc, dt, p, seed, step, ws, counters, stream=None):
+    _check(lib().usp_advect(C.byref(grid), C.byref(gas), C.byref(bc), dt, C.byref(p), seed, step,
+                            _ptr(ws), ws.numel(), _ptr(counters), _stream(stream)), "usp_advect")
+
+
+def usp_step(grid, gas, bc, dt, dt_cell, p, p_alt, offsets, mom, cs, ws, seed, step, nsteps,
+             counters, stream=None):
+    """nsteps full steps; p and p_alt (UspParticles) are swapped in place as
+    the library swaps them, so p describes the current state afterwards."""
+    _check(lib().usp_step(C.byref(grid), C.byref(gas), C.byref(bc) if bc is not None else None,
+                          dt, _ptr(dt_cell), C.byref(p), C.byref(p_alt), _ptr(offsets),
+                          _ptr(mom), _ptr(cs), _ptr(ws), ws.numel(), seed, step, nsteps,
+                          _ptr(counters), _stream(stream)), "usp_step")
+
+
+# ---- device-resident state for one problem ---------------------------------
+class DeviceState:
+    """Device buffers for one problem: two particle buffers, offsets,
+    moments, cell state, workspace and counters.  `prob` carries gas, grid,
+    bc, dt, dt_cell, seed and f32 (field names as in the C structs)."""
+
+    FIELDS = ("x", "y", "cx", "cy", "cz", "erot")
+
+    def __init__(self, prob, parts, device="cuda", capacity=None):
+        self.prob = prob
+        self.dev = torch.device(device)
+        g = prob.grid
+        self.M = g.nx * g.ny
+        self.dim = g.dim
+        self.prec = USP_F32 if prob.f32 else USP_F64
+        self.fdt = torch.float32 if prob.f32 else torch.float64
+        cap = int(capacity or parts["cap"])
+        self.cap = cap
+        self.volume = torch.as_tensor(np.ascontiguousarray(g.volume, np.float64), device=self.dev)
+        flags = g.flags if g.flags is not None else np.zeros(self.M, np.uint8)
+        self.flags = torch.as_tensor(np.ascontiguousarray(flags, np.uint8), device=self.dev)
+        self.grid = UspGrid(g.dim, g.nx, g.ny, g.x0, g.y0, g.dx, g.dy, g.fnum,
+                            self.volume.data_ptr(), self.flags.data_ptr())
+        self.gas = make_gas(prob.gas)
+        self.bc = make_bc(prob.bc)
+        self.dt_cell = (None if prob.dt_cell is None else
+                        torch.as_tensor(np.asarray(prob.dt_cell, np.float64), device=self.dev))
+        self.bufs = [self._alloc(), self._alloc()]
+        self.load(parts)
+        self.offsets = torch.zeros(self.M + 1, dtype=torch.int64, device=self.dev)
+        self.mom = torch.zeros(NMOM * self.M, dtype=torch.float64, device=self.dev)
+        self.cs = torch.zeros(NCS * self.M, dtype=torch.float64, device=self.dev)
+        wsb = lib().usp_workspace_bytes(C.byref(self.grid), cap)
+        if wsb == 0:
+            raise UspError("usp_workspace_bytes rejected the grid/capacity")
+        self.ws = torch.zeros(wsb, dtype=torch.uint8, device=self.dev)
+        self.counters = torch.zeros(NCOUNTERS, dtype=torch.int64, device=self.dev)
+
+    def _alloc(self):
+        cap, dev, f = self.cap, self.dev, self.fdt
+        b = {k: torch.zeros(cap, dtype=f, device=dev) for k in ("cx", "cy", "cz", "erot")}
+        b["x"] = torch.zeros(cap, dtype=f, device=dev) if self.dim == 2 else None
+        b["y"] = torch.zeros(cap, dtype=f, device=dev) if self.dim >= 1 else None
+        b["vib"] = torch.zeros(cap, dtype=torch.uint8, device=dev)
+        b["cell"] = torch.full((cap,), -1, dtype=torch.int32, device=dev)
+        b["pid"] = torch.zeros(cap, dtype=torch.int32, device=dev)  # uint32 bits
+        b["count"] = torch.zeros(2, dtype=torch.int64, device=dev)
+        b["struct"] = UspParticles(self.prec, cap, _ptr(b["x"]), _ptr(b["y"]), _ptr(b["cx"]),
+                                   _ptr(b["cy"]), _ptr(b["cz"]), _ptr(b["erot"]), _ptr(b["vib"]),
+                                   _ptr(b["cell"]), _ptr(b["pid"]), _ptr(b["count"]))
+        return b
+
+    def load(self, parts):
+        """Copy a host particle dict into buffer 0 (the current one)."""
+        n = int(parts["n"])
+        if n > self.cap:
+            raise ValueError("more particles than capacity")
+        B = self.bufs[0]
+        for k in self.FIELDS:
+            if B[k] is not None:
+                src = parts.get(k)
+                if src is None:
+                    raise ValueError(f"particle array {k} required for dim {self.dim}")
+                B[k][:n] = torch.as_tensor(np.asarray(src[:n]), dtype=self.fdt)
+        vib = np.asarray(parts["vib"][:n])
+        if vib.size and (vib.min() < 0 or vib.max() > 255):
+            raise ValueError("vibrational levels must be in [0, 255]")
+        B["vib"][:n] = torch.as_tensor(vib.astype(np.uint8))
+        B["cell"][:n] = torch.as_tensor(np.asarray(parts["cell"][:n], np.int32))
+        B["pid"][:n] = torch.as_tensor(np.asarray(parts["pid"][:n]).astype(np.uint32).view(np.int32))
+        B["count"][:] = torch.tensor([n, int(parts["next_pid"])], dtype=torch.int64)
+        self.cur = 0
+
+    @property
+    def p(self):
+        return self.bufs[self.cur]["struct"]
+
+    @property
+    def p_alt(self):
+        return self.bufs[1 - self.cur]["struct"]
+
+    def state(self):
+        """Host copy of the current particle state (numpy, first n entries)."""
+        torch.cuda.synchronize()
+        B = self.bufs[self.cur]
+        n, nxt = (int(v) for v in B["count"].cpu())
+        out = {"n": n, "next_pid": nxt}
+        for k in self.FIELDS:
+            out[k] = None if B[k] is None else B[k][:n].cpu().numpy().astype(np.float64)
+        out["vib"] = B["vib"][:n].cpu().numpy().astype(np.int32)
+        out["cell"] = B["cell"][:n].cpu().numpy()
+        out["pid"] = B["pid"][:n].cpu().numpy().view(np.uint32)
+        return out
+
+    def moments(self):
+        return self.mom.view(NMOM, self.M).cpu().numpy()
+
+    def cellstate(self):
+        return self.cs.view(NCS, self.M).cpu().numpy()
+
+    def cnt(self):
+        return dict(zip(names("cnt"), self.counters.cpu().tolist()))
+
+    # -- phases (the C entry points on this state) ------------------------
+    def bin(self, stream=None):
+        usp_bin(self.grid, self.p, self.p_alt, self.offsets, self.ws, self.counters, stream)
+        self.cur = 1 - self.cur
+
+    def do_moments(self, stream=None):
+        usp_moments(self.grid, self.p, self.offsets, self.mom, stream)
+
+    def do_reconstruct(self, stream=None):
+        usp_reconstruct(self.grid, self.gas, self.mom, self.prob.dt, self.dt_cell, self.cs,
+                        self.counters, stream)
+
+    def collide(self, step, stream=None):
+        usp_collide(self.grid, self.gas, self.cs, self.offsets, self.p, self.prob.seed, step,
+                    self.counters, stream)
+
+    def conserve(self, step, stream=None):
+        usp_conserve(self.grid, self.gas, self.cs, self.offsets, self.p, self.prob.seed, step,
+                     self.counters, stream)
+
+    def advect(self, step, stream=None):
+        usp_advect(self.grid, self.gas, self.bc, self.prob.dt, self.p, self.prob.seed, step,
+                   self.ws, self.counters, stream)
+
+    def step(self, step, nsteps=1, stream=None):
+        a, b = self.bufs[self.cur]["struct"], self.bufs[1 - self.cur]["struct"]
+        usp_step(self.grid, self.gas, self.bc if self.dim >= 1 else None, self.prob.dt,
+                 self.dt_cell, a, b, self.offsets, self.mom, self.cs, self.ws, self.prob.seed,
+                 step, nsteps, self.counters, stream)
+        # the library swapped the struct contents once per step
+        if nsteps % 2 == 1:
+            B0, B1 = self.bufs[self.cur], self.bufs[1 - self.cur]
+            B0["struct"], B1["struct"] = B1["struct"], B0["struct"]
+            self.cur = 1 - self.cur

@@ -1,0 +1,344 @@
+"""GPU (libusp, through the C ABI) against the CPU oracle, phase by phase,
+on identical seeded inputs.
+
+Bars (integer work bit-exact; floating point as stated):
+  * bin: cell indices, offsets and permutation identical;
+  * moments, cell state (FP64): within 1e-10 of each moment's natural scale;
+  * collide/conserve/advect: FP64 state within 1e-9 of the velocity /
+    energy / length scale; FP32 state within 2e-5 of that scale (the update
+    runs in single precision); vibrational levels equal on >= 99.99% of
+    particles (the discrete decisions are FP64 on both sides but their
+    inputs differ by rounding in the FP32 path).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import usp_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _usp():
+    from paper_2508_05642_amd import usp
+    return usp
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# --------------------------------------------------------------------------
+# problems
+# --------------------------------------------------------------------------
+def prob_0d(f32, seed=31):
+    counts = [0, 1, 2, 3, 17, 250, 3000, 64]
+    rng = np.random.default_rng(seed)
+    M = len(counts)
+    prob, parts = W.batch0d(counts, T_tr=rng.uniform(2000, 20000, M), T_rot=rng.uniform(200, 1000, M),
+                            T_vib=rng.uniform(200, 3000, M), dens=10 ** rng.uniform(21, 24, M),
+                            dt=2e-8, f32=f32, seed=seed,
+                            U=[(rng.normal() * 500, rng.normal() * 500, 0.0) for _ in range(M)],
+                            anis=[(1.0, 1.0 + 0.5 * k, 1.0) for k in range(M)])
+    return prob, parts
+
+
+def prob_1d(f32):
+    prob = W.poiseuille(kn=0.05, cells=16, ppc=60, f32=f32)
+    parts = W.particles_for(prob)
+    # shear the initial state so the reconstruction has gradients to use
+    y = parts["y"][: parts["n"]].astype(np.float64)
+    parts["cx"][: parts["n"]] += (200.0 * np.sin(np.pi * y / 1e-3)).astype(parts["cx"].dtype)
+    return prob, parts
+
+
+def prob_2d(f32, scale=0.05):
+    prob = W.cylinder(scale=scale, f32=f32)
+    parts = W.particles_for(prob)
+    return prob, parts
+
+
+CASES = [("0d", False), ("0d", True), ("1d", False), ("1d", True), ("2d", True), ("2d", False)]
+
+
+def make(kind, f32):
+    return {"0d": prob_0d, "1d": prob_1d, "2d": prob_2d}[kind](f32)
+
+
+def pair(kind, f32):
+    usp = _usp()
+    prob, parts = make(kind, f32)
+    _say(f"[parity] case={kind} f32={f32} n={parts['n']} cells={prob.grid.ncells}")
+    return prob, usp.DeviceState(prob, parts), oracle.Sim(prob, parts)
+
+
+def load_into_oracle(sim, st):
+    """Overwrite the oracle's current particle arrays with a GPU state
+    (same length and order)."""
+    A = sim.bufs[sim.cur]
+    n = st["n"]
+    assert n == sim.n
+    for k in ("x", "y", "cx", "cy", "cz", "erot"):
+        if A[k] is not None:
+            A[k][:n] = st[k]
+    A["vib"][:n] = st["vib"]
+    A["cell"][:n] = st["cell"]
+    A["pid"][:n] = st["pid"]
+
+
+def vel_scale(prob, sim):
+    cs = sim.cellstate()
+    T = cs[oracle.CS_NAMES.index("TTR")]
+    U = np.abs(cs[oracle.CS_NAMES.index("UX"):oracle.CS_NAMES.index("UZ") + 1]).max(axis=0)
+    return float(np.max(np.sqrt(prob.gas.R * np.maximum(T, 1.0)) + U))
+
+
+def compare_states(a, b, prob, vscale, tol, what, vib_min=0.9999):
+    assert a["n"] == b["n"], (what, a["n"], b["n"])
+    assert np.array_equal(a["pid"], b["pid"]), what
+    R = prob.gas.R
+    escale = vscale ** 2
+    worst = {}
+    for k, sc in (("cx", vscale), ("cy", vscale), ("cz", vscale), ("erot", escale)):
+        d = np.abs(a[k] - b[k]) / sc
+        worst[k] = float(d.max()) if d.size else 0.0
+    g = prob.grid
+    if a.get("y") is not None and b.get("y") is not None and g.dim >= 1:
+        worst["y"] = float((np.abs(a["y"] - b["y"]) / (g.ny * g.dy)).max()) if a["n"] else 0.0
+    if a.get("x") is not None and b.get("x") is not None and g.dim == 2:
+        worst["x"] = float((np.abs(a["x"] - b["x"]) / (g.nx * g.dx)).max()) if a["n"] else 0.0
+    agree = float(np.mean(a["vib"] == b["vib"])) if a["n"] else 1.0
+    _say(f"  {what}: worst scaled diff {worst}, vib agreement {agree:.6f}")
+    for k, v in worst.items():
+        assert v <= tol, (what, k, v)
+    assert agree >= vib_min, (what, agree)
+    return worst, agree
+
+
+# --------------------------------------------------------------------------
+# bin
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,f32", CASES)
+def test_bin_bit_exact(kind, f32):
+    prob, gpu, orc = pair(kind, f32)
+    gpu.bin()
+    orc.bin()
+    a, b = gpu.state(), orc.state()
+    assert a["n"] == b["n"]
+    assert np.array_equal(gpu.offsets.cpu().numpy(), orc.offsets)
+    for k in ("pid", "cell", "vib"):
+        assert np.array_equal(a[k], b[k]), k
+    for k in ("x", "y", "cx", "cy", "cz", "erot"):
+        if b[k] is not None:
+            assert np.array_equal(a[k], b[k]), k
+
+
+def test_bin_drops_marked_and_solid_and_keeps_order():
+    usp = _usp()
+    prob, parts = prob_2d(True)
+    n = parts["n"]
+    rng = np.random.default_rng(3)
+    kill = rng.choice(n, n // 10, replace=False)
+    parts["cell"][kill] = -1
+    # a few particles deliberately inside the body (solid cells)
+    g = prob.grid
+    solid = np.nonzero(g.flags & W.FLAG_SOLID)[0]
+    put = rng.choice(n, 20, replace=False)
+    cells = solid[rng.integers(0, len(solid), 20)]
+    parts["x"][put] = (g.x0 + (cells % g.nx + 0.5) * g.dx).astype(np.float32)
+    parts["y"][put] = (g.y0 + (cells // g.nx + 0.5) * g.dy).astype(np.float32)
+    parts["cell"][put] = 0
+    gpu = usp.DeviceState(prob, parts)
+    orc = oracle.Sim(prob, parts)
+    gpu.bin()
+    orc.bin()
+    a, b = gpu.state(), orc.state()
+    assert gpu.cnt()["SOLID_DROP"] == orc.cnt()["SOLID_DROP"] > 0
+    assert a["n"] == b["n"] and np.array_equal(a["pid"], b["pid"]) and np.array_equal(a["cell"], b["cell"])
+
+
+def test_bin_empty_and_large_cells():
+    """No particles at all; and one cell holding more particles than the
+    on-chip sort buffer (the global-memory sort path)."""
+    usp = _usp()
+    prob, parts = W.batch0d([0, 0, 0], [1000.0] * 3, [300.0] * 3, [300.0] * 3, [1e22] * 3,
+                            dt=1e-8, f32=True)
+    gpu = usp.DeviceState(prob, parts)
+    gpu.bin()
+    assert gpu.state()["n"] == 0
+    assert np.all(gpu.offsets.cpu().numpy() == 0)
+    # 2D: 9000 particles piled into one cell, shuffled input order
+    grid = W.Grid(dim=2, nx=4, ny=3, x0=0.0, y0=0.0, dx=1.0, dy=1.0, fnum=1.0,
+                  volume=np.ones(12), flags=np.zeros(12, np.uint8))
+    prob = W.Problem("big", W.Gas(), grid, W.BC(), dt=1e-8, seed=1, f32=True)
+    rng = np.random.default_rng(9)
+    n = 12000
+    x = rng.random(n) * 4
+    y = rng.random(n) * 3
+    x[:9000] = 1.0 + 0.999 * rng.random(9000)
+    y[:9000] = 1.0 + 0.999 * rng.random(9000)
+    perm = rng.permutation(n)
+    x, y = x[perm], y[perm]
+    parts = dict(n=n, cap=n, x=x.astype(np.float32), y=y.astype(np.float32),
+                 cx=rng.standard_normal(n).astype(np.float32), cy=np.zeros(n, np.float32),
+                 cz=np.zeros(n, np.float32), erot=np.zeros(n, np.float32),
+                 vib=np.zeros(n, np.int32), cell=np.zeros(n, np.int32),
+                 pid=np.arange(n, dtype=np.uint32), next_pid=n)
+    gpu = usp.DeviceState(prob, parts)
+    orc = oracle.Sim(prob, parts)
+    gpu.bin()
+    orc.bin()
+    a, b = gpu.state(), orc.state()
+    assert np.array_equal(gpu.offsets.cpu().numpy(), orc.offsets)
+    assert np.array_equal(a["pid"], b["pid"])
+
+
+# --------------------------------------------------------------------------
+# moments and cell state
+# --------------------------------------------------------------------------
+def _mom_scales(prob, om):
+    R = prob.gas.R
+    names = oracle.MOM_NAMES
+    T = np.maximum((om[names.index("PXX")] + om[names.index("PYY")] + om[names.index("PZZ")]) / 3, 1.0)
+    c = np.sqrt(T)   # sqrt(R T)
+    Ib = np.maximum(1.0, om[names.index("IBAR")])
+    U = np.abs(om[1:4]).max(axis=0)
+    sc = {"N": np.ones_like(T), "IBAR": Ib}
+    for k in ("UX", "UY", "UZ"):
+        sc[k] = c + U
+    for k in ("PXX", "PYY", "PZZ", "PXY", "PXZ", "PYZ", "EROT"):
+        sc[k] = T + np.abs(om[names.index("EROT")])
+    for k in ("QTRX", "QTRY", "QTRZ", "QROTX", "QROTY", "QROTZ"):
+        sc[k] = (T + np.abs(om[names.index("EROT")])) * c
+    for k in ("QIX", "QIY", "QIZ"):
+        sc[k] = c * Ib
+    return sc
+
+
+@pytest.mark.parametrize("kind,f32", CASES)
+def test_moments_and_cellstate(kind, f32):
+    prob, gpu, orc = pair(kind, f32)
+    gpu.bin(); orc.bin()
+    gpu.do_moments(); orc.do_moments()
+    gm, om = gpu.moments(), orc.moments()
+    sc = _mom_scales(prob, om)
+    worst = 0.0
+    for k, name in enumerate(oracle.MOM_NAMES):
+        assert usp_name(k, "mom") == name
+        d = np.abs(gm[k] - om[k]) / sc[name]
+        worst = max(worst, float(d.max()))
+    _say(f"  moments worst scaled diff {worst:.3e}")
+    assert worst < 1e-10
+    gpu.do_reconstruct(); orc.do_cellstate()
+    gc, oc = gpu.cellstate(), orc.cellstate()
+    worst = {}
+    for k, name in enumerate(oracle.CS_NAMES):
+        assert usp_name(k, "cs") == name
+        fs = np.max(np.abs(oc[k])) + 1e-300
+        d = np.abs(gc[k] - oc[k]) / (np.abs(oc[k]) + 1e-6 * fs)
+        worst[name] = float(d.max())
+    _say(f"  cellstate worst {max(worst.values()):.3e} at {max(worst, key=worst.get)}")
+    assert max(worst.values()) < 1e-9, worst
+    assert gpu.cnt()["CELL_SKIP"] == sum(1 for c in range(orc.M)
+                                         if 0 < oc[0, c] and oc[oracle.CS_NAMES.index("COLLIDE"), c] == 0)
+
+
+def usp_name(k, kind):
+    return _usp().names(kind)[k]
+
+
+# --------------------------------------------------------------------------
+# collide, conserve, advect -- each on identical inputs
+# --------------------------------------------------------------------------
+def _tol(f32):
+    return 2e-5 if f32 else 1e-9
+
+
+@pytest.mark.parametrize("kind,f32", CASES)
+def test_collide_conserve_advect(kind, f32):
+    prob, gpu, orc = pair(kind, f32)
+    step = 4
+    gpu.bin(); orc.bin()
+    gpu.do_moments(); orc.do_moments()
+    gpu.do_reconstruct(); orc.do_cellstate()
+    vs = vel_scale(prob, orc)
+    gpu.collide(step); orc.collide(step)
+    compare_states(gpu.state(), orc.state(), prob, vs, _tol(f32), "collide")
+    load_into_oracle(orc, gpu.state())
+    gpu.conserve(step); orc.conserve(step)
+    compare_states(gpu.state(), orc.state(), prob, vs, _tol(f32), "conserve")
+    if prob.grid.dim >= 1:
+        load_into_oracle(orc, gpu.state())
+        gpu.advect(step); orc.advect(step)
+        a, b = gpu.state(), orc.state()
+        compare_states(a, b, prob, vs, _tol(f32), "advect")
+        assert np.array_equal(a["cell"] >= 0, b["cell"] >= 0)
+        same = np.mean(a["cell"] == b["cell"])
+        assert same >= 0.9999, same
+        ca, cb = gpu.cnt(), orc.cnt()
+        for k in ("INJECTED", "DELETED", "WALL_HITS", "CAPACITY"):
+            assert ca[k] == cb[k], (k, ca[k], cb[k])
+
+
+@pytest.mark.parametrize("kind,f32", CASES)
+def test_full_steps(kind, f32):
+    """usp_step (one call, several steps) against the oracle's steps."""
+    prob, gpu, orc = pair(kind, f32)
+    nsteps = 3
+    gpu.step(10, nsteps)
+    orc.step_native(10, nsteps)
+    a, b = gpu.state(), orc.state()
+    assert a["n"] == b["n"], (a["n"], b["n"])
+    ia, ib = np.argsort(a["pid"], kind="stable"), np.argsort(b["pid"], kind="stable")
+    assert np.array_equal(a["pid"][ia], b["pid"][ib])
+    for k in list(a):
+        if isinstance(a[k], np.ndarray):
+            a[k] = a[k][ia]
+            b[k] = b[k][ib]
+    vs = vel_scale(prob, orc)
+    # a few steps compound the single-step differences
+    compare_states(a, b, prob, vs, 20 * _tol(f32), f"{nsteps} steps", vib_min=0.999)
+    ca, cb = gpu.cnt(), orc.cnt()
+    for k in ("INJECTED", "SOLID_DROP"):
+        assert ca[k] == cb[k], (k, ca[k], cb[k])
+
+
+def test_determinism_repeat():
+    """The same step twice from the same input is bit-identical."""
+    usp = _usp()
+    prob, parts = prob_2d(True)
+    outs = []
+    for _ in range(2):
+        g = usp.DeviceState(prob, parts)
+        g.step(0, 2)
+        outs.append(g.state())
+    for k in ("x", "y", "cx", "cy", "cz", "erot", "vib", "cell", "pid"):
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+def test_capacity_limit_counts_dropped_injections():
+    usp = _usp()
+    prob, parts = prob_2d(True)
+    n = parts["n"]
+    gpu = usp.DeviceState(prob, parts, capacity=n + 5)
+    gpu.bin(); gpu.do_moments(); gpu.do_reconstruct(); gpu.collide(0); gpu.conserve(0)
+    gpu.advect(0)
+    st, cnt = gpu.state(), gpu.cnt()
+    assert st["n"] == n + 5
+    assert cnt["INJECTED"] == 5 and cnt["CAPACITY"] > 0
+
+
+def test_invalid_arguments_rejected_on_host():
+    usp = _usp()
+    prob, parts = prob_0d(True)
+    gpu = usp.DeviceState(prob, parts)
+    with pytest.raises(usp.UspError):
+        usp.usp_reconstruct(gpu.grid, gpu.gas, gpu.mom, -1.0, None, gpu.cs, gpu.counters)
+    with pytest.raises(usp.UspError):
+        usp.usp_bin(gpu.grid, gpu.p, gpu.p, gpu.offsets, gpu.ws, gpu.counters)

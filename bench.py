@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Throughput of the full USP-FPM step on one MI355X.
+
+Workload: Mach-10 N2 over a cylinder (half body), 600 x 300 cells of 1 mm,
+~36.1M particles at start (FP32 particle state, FP64 cell accumulators),
+VHS gas with Parker / Millikan-White collision numbers, dt = 1.25e-7 s.
+A step is bin -> moments -> cell state -> collide -> conserve -> advect
+(with injection), each a call of the C ABI on torch's current stream so
+HIP events bracket every phase.  `value` is particle-steps/s over exactly
+--steps timed steps (inputs resident in HBM), after --warmup steps.
+
+Also reported: the HBM roofline of the dominant kernel (algorithmic bytes
+per launch / its average event-timed duration) and the CPU oracle timed on
+the host on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "particle-steps/s (full USP-FPM step) + HBM GB/s; adjoint/forward time ratio"
+PHASES = ("bin", "moments", "reconstruct", "collide", "conserve", "advect")
+# kernel launched by each single-kernel phase
+PHASE_KERNEL = {"collide": "k_collide", "conserve": "k_conserve", "moments": "k_moments",
+                "reconstruct": "k_reconstruct"}
+
+
+def algorithmic_bytes(phase, n, M):
+    """Bytes a phase must move at minimum for n particles and M cells (FP32
+    state: x, y, cx, cy, cz, erot 4 B each, vib 1 B, cell 4 B, pid 4 B;
+    cell-state plane 8 B per field)."""
+    per_particle = {
+        # read x, y, cell (12), write the sorted copy of every array (33) after
+        # reading it (33): the stable rebin moves the whole state once
+        "bin": 12 + 33 + 33,
+        # read cx, cy, cz, erot, vib
+        "moments": 17,
+        "reconstruct": 0,
+        # read x, y, cx, cy, cz, erot, vib, cell, pid; write cx, cy, cz, erot, vib
+        "collide": 33 + 17,
+        # read cx, cy, cz, erot, vib; write cx, cy, cz, erot
+        "conserve": 17 + 16,
+        # read x, y, cx, cy, cz, erot, vib, cell, pid; write x, y, c, erot, vib, cell
+        "advect": 33 + 29,
+    }[phase]
+    per_cell = {"bin": 4 + 8, "moments": 21 * 8, "reconstruct": (21 + 35) * 8,
+                "collide": 35 * 8, "conserve": 8 * 8, "advect": 0}[phase]
+    return per_particle * n + per_cell * M
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_gpu(args):
+    import numpy as np
+    import torch
+
+    import usp_workloads as W
+    from paper_2508_05642_amd import usp
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prob = W.cylinder(scale=args.scale, f32=True)
+    parts = W.particles_for(prob)
+    n0 = parts["n"]
+    log(f"workload ready: {n0} particles, {prob.grid.ncells} cells")
+    st = usp.DeviceState(prob, parts, device="cuda:0")
+    M = prob.grid.ncells
+    step = 0
+
+    def one_step(s, ev=None, nlog=None, k=None):
+        if ev: ev[0].record()
+        st.bin()
+        if nlog is not None:
+            nlog[k].copy_(st.bufs[st.cur]["count"][0])
+        if ev: ev[1].record()
+        st.do_moments()
+        if ev: ev[2].record()
+        st.do_reconstruct()
+        if ev: ev[3].record()
+        st.collide(s)
+        if ev: ev[4].record()
+        st.conserve(s)
+        if ev: ev[5].record()
+        st.advect(s)
+        if ev: ev[6].record()
+
+    for _ in range(args.warmup):
+        one_step(step)
+        step += 1
+    torch.cuda.synchronize()
+    log(f"{args.warmup} warmup steps done")
+    K = args.steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(K)]
+    nlog = torch.zeros(K, dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        one_step(step, evs[k], nlog, k)
+        step += 1
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    ns = nlog.cpu().numpy()
+    phase_ms = {ph: 0.0 for ph in PHASES}
+    for k in range(K):
+        for j, ph in enumerate(PHASES):
+            phase_ms[ph] += evs[k][j].elapsed_time(evs[k][j + 1])
+    phase_ms = {ph: v / K for ph, v in phase_ms.items()}
+    total_ps = float(ns.sum())
+    n_mean = float(ns.mean())
+    dom = max(PHASES, key=lambda p: phase_ms[p])
+    ach = algorithmic_bytes(dom, n_mean, M) / (phase_ms[dom] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": PHASE_KERNEL.get(dom, dom), "phase": dom,
+            "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_ms": round(phase_ms[dom], 4),
+            "algorithmic_bytes_per_launch": int(algorithmic_bytes(dom, n_mean, M))}
+    step_bytes = sum(algorithmic_bytes(p, n_mean, M) for p in PHASES)
+    cnt = st.cnt()
+    res = dict(
+        metric=METRIC, value=round(total_ps / wall, 1), unit="particle-steps/s", n_gpus=1,
+        steps=K, warmup=args.warmup, ms_per_step=round(wall / K * 1e3, 4),
+        higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+        data="synthetic",
+        config={"workload": f"cylinder_mach10_{prob.grid.nx}x{prob.grid.ny}",
+                "particles_start": int(n0), "particles_mean": int(n_mean), "cells": M,
+                "state": "f32", "accumulation": "f64", "dt_s": prob.dt,
+                "first_timed_step": args.warmup, "parallelism": "single-gpu"},
+        phase_ms=phase_ms,
+        step_algorithmic_gbs=round(step_bytes / (wall / K) / 1e9, 1),
+        roofline=roof,
+        counters={k: v for k, v in cnt.items() if v},
+    )
+    return res, prob, parts
+
+
+def run_cpu_baseline(prob, parts, nsteps):
+    import oracle
+    sim = oracle.Sim(prob, parts)
+    total = 0
+    t0 = time.perf_counter()
+    for s in range(nsteps):
+        sim.bin()
+        total += sim.n
+        sim.do_moments()
+        sim.do_cellstate()
+        sim.collide(s)
+        sim.conserve(s)
+        sim.advect(s)
+    dt = time.perf_counter() - t0
+    return {"value": round(total / dt, 1), "unit": "particle-steps/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{nsteps} full steps of the same cylinder workload from its initial "
+                      f"state ({parts['n']} particles), FP64 oracle, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--scale", type=float, default=1.0,
+                    help="grid scale of the cylinder workload (1.0 = full size)")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+    res, prob, parts = run_gpu(args)
+    log(f"GPU: {res['value']:.4g} particle-steps/s, {res['ms_per_step']} ms/step")
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = run_cpu_baseline(prob, parts, args.cpu_steps)
+        log(f"CPU oracle: {res['cpu_baseline']['value']:.4g} particle-steps/s")
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

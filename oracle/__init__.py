@@ -106,6 +106,7 @@ def lib():
         L.orc_inflow_speed.argtypes = [u64, u64, C.c_uint32, d]
         L.orc_inflow_speed.restype = d
         L.orc_set_threads.argtypes = [i32]
+        L.orc_get_threads.restype = i32
         _lib = L
     return _lib
 
@@ -306,6 +307,10 @@ class Sim:
             self.structs = [self.structs[1], self.structs[0]]
             self.cur = 1 - self.cur
         self.sorted = False
+
+
+def threads():
+    return lib().orc_get_threads()
 
 
 def sample_nb(u, r, p):

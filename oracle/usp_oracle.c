@@ -29,6 +29,14 @@ void orc_set_threads(int32_t n) {
 #endif
 }
 
+int32_t orc_get_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 static double store(double v, int32_t f32) { return f32 ? (double)(float)v : v; }
 
 /* ======================================================================== */

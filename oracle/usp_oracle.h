@@ -200,6 +200,7 @@ int32_t orc_sample_b(double u, int32_t n, double p);
 double orc_inflow_speed(uint64_t seed, uint64_t step, uint32_t pid, double s);
 
 void orc_set_threads(int32_t n);
+int32_t orc_get_threads(void);
 
 #ifdef __cplusplus
 }

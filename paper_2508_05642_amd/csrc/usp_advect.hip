@@ -58,6 +58,7 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_advect(GridP g, GasP gas, BcP bc,
   double t = dt;
   int bounces = 0, events = 0;
   bool deleted = false;
+  uint32_t ev = 0;
   const uint32_t id = p.pid[i];
   for (;;) {
     double th = INFINITY;
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_advect(GridP g, GasP gas, BcP bc,
     x += cx * th;
     y += cy * th;
     t -= th;
-    if (++events > 4 * MAX_BOUNCE) { count_event(counters, USP_CNT_BOUNCE_LIMIT); break; }
+    if (++events > 4 * MAX_BOUNCE) { ev |= 1u << USP_CNT_BOUNCE_LIMIT; break; }
     const int kind = side == 4 ? USP_BC_DIFFUSE : bc.kind[side];
     if (side == USP_SIDE_XLO) x = xlo;
     if (side == USP_SIDE_XHI) x = xhi;
@@ -106,13 +107,12 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_advect(GridP g, GasP gas, BcP bc,
       if (side == USP_SIDE_XLO || side == USP_SIDE_XHI) cx = -cx; else cy = -cy;
       continue;
     }
-    if (bounces >= MAX_BOUNCE) { count_event(counters, USP_CNT_BOUNCE_LIMIT); break; }
+    if (bounces >= MAX_BOUNCE) { ev |= 1u << USP_CNT_BOUNCE_LIMIT; break; }
     double cn, ta, tb, ner;
     int nlv;
     const double Tw = side == 4 ? bc.cyl_Tw : bc.Tw[side];
     wall_draw(gas, Tw, seed, id, step, bounces, &cn, &ta, &tb, &ner, &nlv);
     ++bounces;
-    count_event(counters, USP_CNT_WALL_HITS);
     er = ner;
     lv = nlv;
     if (side == USP_SIDE_YLO || side == USP_SIDE_YHI) {
@@ -135,19 +135,20 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_advect(GridP g, GasP gas, BcP bc,
   }
   if (deleted) {
     p.cell[i] = -1;
-    count_event(counters, USP_CNT_DELETED);
-    return;
+    ev |= 1u << USP_CNT_DELETED;
+  } else {
+    S xs = S(0);
+    if (g.dim == 2) { xs = settle<S>(x, xlo, xhi); p.x[i] = xs; }
+    const S ys = settle<S>(y, ylo, yhi);
+    p.y[i] = ys;
+    p.cx[i] = (S)cx;
+    p.cy[i] = (S)cy;
+    p.cz[i] = (S)cz;
+    p.erot[i] = (S)er;
+    p.vib[i] = (uint8_t)lv;
+    p.cell[i] = cell_of<S>(g, xs, ys);
   }
-  S xs = S(0);
-  if (g.dim == 2) { xs = settle<S>(x, xlo, xhi); p.x[i] = xs; }
-  const S ys = settle<S>(y, ylo, yhi);
-  p.y[i] = ys;
-  p.cx[i] = (S)cx;
-  p.cy[i] = (S)cy;
-  p.cz[i] = (S)cz;
-  p.erot[i] = (S)er;
-  p.vib[i] = (uint8_t)lv;
-  p.cell[i] = cell_of<S>(g, xs, ys);
+  flush_events(counters, ev, USP_CNT_WALL_HITS, bounces);
 }
 
 // ---- free-stream injection ------------------------------------------------

@@ -1,11 +1,13 @@
 // usp_bin.hip -- binning: stable counting sort of particles by cell.
 //
-// 1. key + histogram: cell of every live particle (integer atomics only);
+// 1. key + histogram: cell of every live particle (integer atomics only,
+//    one per run of equal keys in a wave);
 // 2. exclusive scan of the histogram -> cell offsets (reduce, top, down);
 // 3. slot claim: each particle takes a slot in its cell's range with an
 //    atomic cursor (order inside a cell is arbitrary at this point);
-// 4. per-cell sort of the claimed input indices, ascending: this restores
-//    input order inside every cell, so the result is the stable sort;
+// 4. per-cell sort of the claimed input indices, ascending (one wave per
+//    cell by rank counting; a block per cell above 1024 particles): this
+//    restores input order inside every cell, so the result is the stable sort;
 // 5. gather of every state array through the permutation.
 // All results are deterministic: the only atomics are integer ones and the
 // per-cell sort removes their ordering.
@@ -23,25 +25,46 @@ __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
   if (i < n) p[i] = v;
 }
 
+// Runs of equal keys in consecutive lanes of a wave (particles arrive
+// mostly sorted by cell, so a wave holds a few long runs).  Returns the
+// lane of this lane's run head and, for heads, the run length.
+__device__ __forceinline__ void wave_runs(int32_t key, int* head_lane, int* run_len) {
+  const int lane = threadIdx.x & 63;
+  const int32_t prev = __shfl_up(key, 1, 64);
+  const bool head = lane == 0 || key != prev;
+  const uint64_t heads = __ballot(head);
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  *head_lane = 63 - __clzll(heads & upto);
+  const uint64_t above = heads & ~upto;
+  const int next = above ? (__ffsll((long long)above) - 1) : 64;
+  *run_len = head ? next - lane : 0;
+}
+
 template <typename S>
 __global__ __launch_bounds__(BIN_BLOCK) void k_bin_key(GridP g, PartP<S> in, int32_t* key,
                                                        int32_t* counts, int64_t* counters) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= in.count[0]) return;
-  int32_t c = in.cell[i];
-  if (c >= 0) {
-    if (g.dim == 0) {
-      if (c >= g.M) c = -1;
-    } else {
-      c = cell_of<S>(g, g.dim == 2 ? in.x[i] : S(0), in.y[i]);
+  const bool live = i < in.count[0];
+  int32_t c = -1;
+  if (live) {
+    c = in.cell[i];
+    if (c >= 0) {
+      if (g.dim == 0) {
+        if (c >= g.M) c = -1;
+      } else {
+        c = cell_of<S>(g, g.dim == 2 ? in.x[i] : S(0), in.y[i]);
+      }
     }
+    if (c >= 0 && g.flags && (g.flags[c] & USP_FLAG_SOLID)) {
+      c = -1;
+      count_event(counters, USP_CNT_SOLID_DROP);
+    }
+    key[i] = c;
   }
-  if (c >= 0 && g.flags && (g.flags[c] & USP_FLAG_SOLID)) {
-    c = -1;
-    count_event(counters, USP_CNT_SOLID_DROP);
-  }
-  key[i] = c;
-  if (c >= 0) atomicAdd(&counts[c], 1);
+  // one atomic per run of equal keys
+  int hl, len;
+  wave_runs(c, &hl, &len);
+  if (len > 0 && c >= 0) atomicAdd(&counts[c], len);
 }
 
 // ---- exclusive scan of int32 counts into int64 offsets -------------------
@@ -125,11 +148,14 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_claim(const int32_t* key, const i
                                                      const int64_t* offsets, int32_t* cursor,
                                                      uint32_t* perm) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count[0]) return;
-  const int32_t c = key[i];
-  if (c < 0) return;
-  const int64_t slot = offsets[c] + atomicAdd(&cursor[c], 1);
-  perm[slot] = (uint32_t)i;
+  const int32_t c = i < count[0] ? key[i] : -1;
+  // the run head claims slots for its whole run; members follow in order
+  int hl, len;
+  wave_runs(c, &hl, &len);
+  int32_t base = 0;
+  if (len > 0 && c >= 0) base = atomicAdd(&cursor[c], len);
+  base = __shfl(base, hl, 64);
+  if (c >= 0) perm[offsets[c] + base + ((threadIdx.x & 63) - hl)] = (uint32_t)i;
 }
 
 // Ascending sort network in which every compare-exchange puts the smaller
@@ -155,12 +181,62 @@ __device__ __forceinline__ void sort_net(uint32_t* a, int n) {
   }
 }
 
-__global__ __launch_bounds__(BIN_BLOCK) void k_segsort(const int64_t* offsets, uint32_t* perm) {
+// One wave sorts one cell's slot list (distinct input indices) by rank
+// counting: each lane holds K entries in registers; every entry's rank is
+// the number of entries below it, counted against all entries broadcast one
+// at a time with readlane.  Entries beyond n hold UINT32_MAX and never count.
+template <int K>
+__device__ __forceinline__ void wave_rank_sort(uint32_t* seg, int n) {
+  const int lane = threadIdx.x & 63;
+  uint32_t v[K];
+  int r[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int j = k * 64 + lane;
+    v[k] = j < n ? seg[j] : 0xFFFFFFFFu;
+    r[k] = 0;
+  }
+#pragma unroll
+  for (int s = 0; s < K; ++s) {
+    const int lim = n - s * 64 < 64 ? n - s * 64 : 64;
+    for (int l = 0; l < lim; ++l) {
+      const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)v[s], l);
+#pragma unroll
+      for (int k = 0; k < K; ++k) r[k] += (w < v[k]) ? 1 : 0;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int j = k * 64 + lane;
+    if (j < n) seg[r[k]] = v[k];
+  }
+}
+
+constexpr int WAVE_SORT_MAX = 1024;
+
+__global__ __launch_bounds__(BIN_BLOCK) void k_segsort_wave(const int64_t* offsets, int64_t M,
+                                                            uint32_t* perm) {
+  const int64_t c = (int64_t)blockIdx.x * (BIN_BLOCK / 64) + (threadIdx.x >> 6);
+  if (c >= M) return;
+  const int64_t o0 = offsets[c];
+  const int n = (int)(offsets[c + 1] - o0);
+  if (n <= 1 || n > WAVE_SORT_MAX) return;
+  uint32_t* seg = perm + o0;
+  if (n <= 64) wave_rank_sort<1>(seg, n);
+  else if (n <= 128) wave_rank_sort<2>(seg, n);
+  else if (n <= 256) wave_rank_sort<4>(seg, n);
+  else if (n <= 512) wave_rank_sort<8>(seg, n);
+  else wave_rank_sort<16>(seg, n);
+}
+
+// cells above WAVE_SORT_MAX: one block per cell, sort network in LDS (or in
+// global memory beyond SORT_LDS entries)
+__global__ __launch_bounds__(BIN_BLOCK) void k_segsort_big(const int64_t* offsets, uint32_t* perm) {
   __shared__ uint32_t s[SORT_LDS];
   const int64_t c = blockIdx.x;
   const int64_t o0 = offsets[c];
   const int n = (int)(offsets[c + 1] - o0);
-  if (n <= 1) return;
+  if (n <= WAVE_SORT_MAX) return;
   uint32_t* seg = perm + o0;
   if (n <= SORT_LDS) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) s[i] = seg[i];
@@ -207,7 +283,8 @@ hipError_t launch_bin(const GridP& g, const PartP<S>& in, const PartP<S>& out, i
   k_scan_down<<<nb, BIN_BLOCK, 0, st>>>(cursor, M, blocksums, offsets);
   k_fill_i32<<<cdiv(M, 256), 256, 0, st>>>(cursor, 0, M);
   k_claim<<<cdiv(cap, BIN_BLOCK), BIN_BLOCK, 0, st>>>(key, in.count, offsets, cursor, perm);
-  k_segsort<<<M, BIN_BLOCK, 0, st>>>(offsets, perm);
+  k_segsort_wave<<<cdiv(M, BIN_BLOCK / 64), BIN_BLOCK, 0, st>>>(offsets, M, perm);
+  k_segsort_big<<<M, BIN_BLOCK, 0, st>>>(offsets, perm);
   k_gather<S><<<cdiv(cap, BIN_BLOCK), BIN_BLOCK, 0, st>>>(in, out, perm, key, g.dim == 2,
                                                           g.dim >= 1);
   return hipGetLastError();

@@ -265,7 +265,7 @@ __global__ __launch_bounds__(PART_BLOCK) void k_collide(GridP g, GasP gas, const
     const double fl = 0.05 * cs[(CS_TTR + k) * M + c];
     if (Tk[k] < fl) { Tk[k] = fl; clamped = true; }
   }
-  if (clamped) count_event(counters, USP_CNT_INTERP_CLAMP);
+  uint32_t ev = clamped ? (1u << USP_CNT_INTERP_CLAMP) : 0u;
 
   // ---- per-particle coefficients -----------------------------------------
   CellCoef cc;
@@ -285,14 +285,11 @@ __global__ __launch_bounds__(PART_BLOCK) void k_collide(GridP g, GasP gas, const
       pc.clamp_rot = pd.clamp_rot; pc.clamp_m = pd.clamp_m;
     }
   }
-  if (pc.fallback) count_event(counters, USP_CNT_CHOL_FALLBACK);
-  if (pc.nu_zero) count_event(counters, USP_CNT_NU_ZERO);
-  if (pc.skip) {
-    count_event(counters, USP_CNT_TREL_SKIP);
-    return;
-  }
-  if (pc.clamp_rot) count_event(counters, USP_CNT_TREL_CLAMP);
-  if (pc.clamp_m) count_event(counters, USP_CNT_TREL_CLAMP);
+  if (pc.fallback) ev |= 1u << USP_CNT_CHOL_FALLBACK;
+  if (pc.nu_zero) ev |= 1u << USP_CNT_NU_ZERO;
+  if (pc.skip) ev |= 1u << USP_CNT_TREL_SKIP;
+  if (pc.clamp_rot || pc.clamp_m) ev |= 1u << USP_CNT_TREL_CLAMP;
+  if (!pc.skip) {
   const T R = (T)gas.R;
   const T al = pc.al;
   const T oma2 = (T)pc.oma2;
@@ -323,33 +320,104 @@ __global__ __launch_bounds__(PART_BLOCK) void k_collide(GridP g, GasP gas, const
   const double ms = (double)mstar;
   const double pNB = 1.0 / (1.0 + ms * oma2d);
   double pB = (1.0 + ms) * oma2d;
-  if (pB > 1.0) { pB = 1.0; count_event(counters, USP_CNT_PB_CLAMP); }
+  if (pB > 1.0) { pB = 1.0; ev |= 1u << USP_CNT_PB_CLAMP; }
   int nI = I + sample_nb(u01d(w1.w[0]), I + 1, pNB) - sample_b(u01d(w1.w[1]), I, pB);
-  if (nI > VIB_MAX) { nI = VIB_MAX; count_event(counters, USP_CNT_VIB_SAT); }
+  if (nI > VIB_MAX) { nI = VIB_MAX; ev |= 1u << USP_CNT_VIB_SAT; }
   p.vib[i] = (uint8_t)nI;
+  }
+  flush_events(counters, ev);
 }
 
 // ---------------------------------------------------------------------------
-// Conservation (Sec. IV.C): one block per cell.
+// Conservation (Sec. IV.C): one wave per cell.  The serial vibrational
+// picks run on an LDS copy of the cell's levels (cells up to CONS_LDS
+// particles; larger cells pick in global memory).
 // ---------------------------------------------------------------------------
-template <int NV>
-__device__ __forceinline__ void cons_block_sum(double (&v)[NV], double* lds) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) lds[wid * NV + k] = v[k];
+constexpr int CONS_WAVES = CONS_BLOCK / 64;
+constexpr int CONS_LDS = 2048;
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// The vibrational correction of Sec. IV.C, |I_delta| single-level moves on
+// particles picked uniformly at random (draw j: counter (cell, step, 2, j/4),
+// word j%4; a decrement that hits level 0, or an increment that hits the top
+// level, is redrawn).  The draws are sequential by definition; here a wave
+// evaluates 64 consecutive draws at once and reproduces the sequential
+// outcome exactly: draw j on particle k is accepted iff the level of k,
+// after the accepted earlier draws on k, still allows the move, i.e. iff
+// dup < L (decrement) or L + dup < VIB_MAX (increment), dup being the number
+// of earlier draws of the chunk on k; only the first |I_delta| accepted draws
+// are applied.  Gives up after 64 N draws or when a decrement is impossible.
+// Returns 1 if any level changed; *SI is updated.  Called by a whole wave.
+__device__ int wave_picks(uint8_t* lv, int64_t N, int64_t Id, int64_t* SI_io, uint32_t c,
+                          uint32_t step, uint64_t seed, int64_t* counters) {
+  const int lane = threadIdx.x & 63;
+  const int64_t maxatt = 64 * N;
+  int64_t att = 0, SI = *SI_io;
+  uint32_t jbase = 1;
+  int moved = 0;
+  const double Nd = (double)N;
+  while (Id != 0) {
+    if (att >= maxatt || (Id < 0 && SI == 0)) {
+      if (lane == 0) count_event(counters, USP_CNT_PICK_FAIL);
+      break;
+    }
+    const bool valid = att + lane < maxatt;
+    const uint32_t j = jbase + (uint32_t)lane;
+    const U4 w = philox(c, step, TAG_CONSERVE, j >> 2, seed);
+    const uint32_t wj = (j & 3) == 0 ? w.w[0] : (j & 3) == 1 ? w.w[1] : (j & 3) == 2 ? w.w[2] : w.w[3];
+    int64_t k = (int64_t)floor(u01d(wj) * Nd);
+    if (k >= N) k = N - 1;
+    const int kk = (int)k;
+    int dup = 0;
+    for (int l = 0; l < 64; ++l) {
+      const int kl = __builtin_amdgcn_readlane(kk, l);
+      dup += (l < lane && kl == kk) ? 1 : 0;
+    }
+    const int L = valid ? (int)lv[k] : 0;
+    const bool acc = valid && (Id > 0 ? (L + dup < VIB_MAX) : (dup < L));
+    const uint64_t accm = __ballot(acc);
+    const int64_t need = Id > 0 ? Id : -Id;
+    const int nacc = __popcll(accm);
+    uint64_t applied;
+    int consumed;
+    if (nacc >= need) {
+      // lane of the need-th accepted draw: the last draw made
+      uint64_t m = accm;
+      for (int64_t t = 1; t < need; ++t) m &= m - 1;
+      const int cut = __ffsll((long long)m) - 1;
+      applied = accm & (cut == 63 ? ~0ull : ((2ull << cut) - 1ull));
+      consumed = cut + 1;
+    } else {
+      applied = accm;
+      consumed = (int)__popcll(__ballot(valid));
+    }
+    const bool app = (applied >> lane) & 1ull;
+    // the first applied lane of each particle writes the combined move
+    int cnt = 0;
+    bool first = app;
+    for (int l = 0; l < 64; ++l) {
+      const int kl = __builtin_amdgcn_readlane(kk, l);
+      if (((applied >> l) & 1ull) && kl == kk) {
+        ++cnt;
+        if (l < lane) first = false;
+      }
+    }
+    const int napp = (int)__popcll(applied);
+    wave_sync_lds();
+    if (first) lv[k] = (uint8_t)(Id > 0 ? L + cnt : L - cnt);
+    wave_sync_lds();
+    if (napp) moved = 1;
+    SI += Id > 0 ? napp : -napp;
+    Id += Id > 0 ? -napp : napp;
+    att += consumed;
+    jbase += (uint32_t)consumed;
   }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double s = lds[k];
-#pragma unroll
-    for (int w = 1; w < CONS_BLOCK / 64; ++w) s += lds[w * NV + k];
-    v[k] = s;
-  }
-  __syncthreads();
+  *SI_io = SI;
+  return moved;
 }
 
 template <typename S>
@@ -357,62 +425,49 @@ __global__ __launch_bounds__(CONS_BLOCK) void k_conserve(GridP g, GasP gas, cons
                                                          const int64_t* offsets, PartP<S> p,
                                                          uint64_t seed, uint32_t step,
                                                          int64_t* counters) {
-  __shared__ double lds[(CONS_BLOCK / 64) * 6];
-  __shared__ double fac[6];  // rot factor, vel scale, U* (3), flags
-  const int64_t M = g.M, c = blockIdx.x;
+  __shared__ uint8_t lv_s[CONS_WAVES][CONS_LDS];
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t M = g.M;
+  const int64_t c = (int64_t)blockIdx.x * CONS_WAVES + wid;
+  if (c >= M) return;
   const int64_t o0 = offsets[c], o1 = offsets[c + 1], N = o1 - o0;
   if (N == 0 || cs[CS_COLLIDE * M + c] == 0.0) return;
+  const bool staged = N <= CONS_LDS;
+  uint8_t* lds = lv_s[wid];
   const double Un[3] = {cs[CS_UX * M + c], cs[CS_UY * M + c], cs[CS_UZ * M + c]};
   double s[6] = {0, 0, 0, 0, 0, 0};
-  for (int64_t i = o0 + threadIdx.x; i < o1; i += CONS_BLOCK) {
+  for (int64_t i = o0 + lane; i < o1; i += 64) {
     const double d0 = (double)p.cx[i] - Un[0], d1 = (double)p.cy[i] - Un[1],
                  d2 = (double)p.cz[i] - Un[2];
     s[0] += d0; s[1] += d1; s[2] += d2;
     s[3] += d0 * d0 + d1 * d1 + d2 * d2;
     s[4] += (double)p.erot[i];
-    s[5] += (double)p.vib[i];
+    const uint8_t v = p.vib[i];
+    s[5] += (double)v;
+    if (staged) lds[i - o0] = v;
   }
-  cons_block_sum<6>(s, lds);
-  if (threadIdx.x == 0) {
-    const double Nd = (double)N;
-    const double RTh = gas.R * gas.theta;
-    const double m1[3] = {s[0] / Nd, s[1] / Nd, s[2] / Nd};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s[k] = wave_sum(s[k]);
+  wave_sync_lds();
+  const double Nd = (double)N;
+  const double m1[3] = {s[0] / Nd, s[1] / Nd, s[2] / Nd};
+  const double RTh = gas.R * gas.theta;
+  // (i) vibrational levels: I_delta = floor(N (e_target - e*)/(R theta) + U),
+  // then |I_delta| single-level moves on randomly picked particles
+  int64_t SI = (int64_t)s[5];
+  const double X = Nd * cs[CS_EVIB_NEW * M + c] / RTh - (double)SI;
+  const int64_t Id0 = (int64_t)floor(X + u01d(philox((uint32_t)c, step, TAG_CONSERVE, 0u, seed).w[0]));
+  uint8_t* lv = staged ? lds : p.vib + o0;
+  const int moved = wave_picks(lv, N, Id0, &SI, (uint32_t)c, step, seed, counters);
+  double frot = 0.0, sc = 0.0;
+  if (lane == 0) {
     const double etr_s = 0.5 * (s[3] / Nd - (m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2]));
-    int64_t SI = (int64_t)s[5];
-    // (i) vibrational levels: I_delta = floor(N (e_target - e*)/(R theta) + U)
-    const double X = Nd * cs[CS_EVIB_NEW * M + c] / RTh - (double)SI;
-    U4 w = philox((uint32_t)c, step, TAG_CONSERVE, 0u, seed);
-    int64_t Id = (int64_t)floor(X + u01d(w.w[0]));
-    int64_t att = 0;
-    const int64_t maxatt = 64 * N;
-    uint32_t j = 1;
-    uint32_t blk = 0;
-    while (Id != 0) {
-      if (att >= maxatt || (Id < 0 && SI == 0)) {
-        count_event(counters, USP_CNT_PICK_FAIL);
-        break;
-      }
-      if ((j >> 2) != blk) { blk = j >> 2; w = philox((uint32_t)c, step, TAG_CONSERVE, blk, seed); }
-      const double uu = u01d(w.w[j & 3]);
-      ++j;
-      ++att;
-      int64_t k = (int64_t)floor(uu * Nd);
-      if (k >= N) k = N - 1;
-      uint8_t* lv = &p.vib[o0 + k];
-      const int cur = *lv;
-      if (Id > 0) {
-        if (cur < VIB_MAX) { *lv = (uint8_t)(cur + 1); ++SI; --Id; }
-      } else {
-        if (cur > 0) { *lv = (uint8_t)(cur - 1); --SI; ++Id; }
-      }
-    }
     // (ii) rotational scaling to the cell target
     const double erot_s = s[4] / Nd, erot_t = cs[CS_EROT_NEW * M + c];
-    double erot_a = erot_s, frot = 1.0, do_rot = 0.0;
+    double erot_a = erot_s;
     if (erot_s > 0.0 && erot_t > 0.0) {
       frot = erot_t / erot_s;
       erot_a = erot_t;
-      do_rot = 1.0;
     } else {
       count_event(counters, USP_CNT_CONS_SKIP);
     }
@@ -420,19 +475,15 @@ __global__ __launch_bounds__(CONS_BLOCK) void k_conserve(GridP g, GasP gas, cons
     const double evib_a = (double)SI * RTh / Nd;
     const double E0 = cs[CS_ETR * M + c] + cs[CS_EROT * M + c] + cs[CS_EVIB * M + c];
     const double s2 = (E0 - erot_a - evib_a) / etr_s;
-    double sc = 0.0;
     if (etr_s > 0.0 && s2 > 0.0) sc = sqrt(s2);
     else count_event(counters, USP_CNT_CONS_SKIP);
-    fac[0] = do_rot > 0.0 ? frot : 0.0;
-    fac[1] = sc;
-    fac[2] = Un[0] + m1[0];
-    fac[3] = Un[1] + m1[1];
-    fac[4] = Un[2] + m1[2];
   }
-  __syncthreads();
-  const double frot = fac[0], sc = fac[1];
-  const double Us0 = fac[2], Us1 = fac[3], Us2 = fac[4];
-  for (int64_t i = o0 + threadIdx.x; i < o1; i += CONS_BLOCK) {
+  frot = __shfl(frot, 0, 64);
+  sc = __shfl(sc, 0, 64);
+  wave_sync_lds();
+  const double Us0 = Un[0] + m1[0], Us1 = Un[1] + m1[1], Us2 = Un[2] + m1[2];
+  for (int64_t i = o0 + lane; i < o1; i += 64) {
+    if (staged && moved) p.vib[i] = lds[i - o0];
     if (frot > 0.0) p.erot[i] = (S)((double)p.erot[i] * frot);
     if (sc > 0.0) {
       p.cx[i] = (S)(Un[0] + sc * ((double)p.cx[i] - Us0));
@@ -456,7 +507,7 @@ template <typename S>
 hipError_t launch_conserve(const GridP& g, const GasP& gas, const double* cs,
                            const int64_t* offsets, const PartP<S>& p, uint64_t seed, uint64_t step,
                            int64_t* counters, hipStream_t st) {
-  k_conserve<S><<<g.M, CONS_BLOCK, 0, st>>>(g, gas, cs, offsets, p, seed, (uint32_t)step, counters);
+  k_conserve<S><<<cdiv(g.M, CONS_WAVES), CONS_BLOCK, 0, st>>>(g, gas, cs, offsets, p, seed, (uint32_t)step, counters);
   return hipGetLastError();
 }
 

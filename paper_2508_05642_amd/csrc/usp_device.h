@@ -188,6 +188,27 @@ __device__ __forceinline__ void count_event(int64_t* counters, int k, int64_t v 
   if (counters) atomicAdd((unsigned long long*)&counters[k], (unsigned long long)v);
 }
 
+// Events of the active lanes of a wave, one atomic per event kind: bit k of
+// `ev` marks event k for this lane; `extra` adds a small per-lane count
+// (< 16) to event `extra_k`.
+__device__ __forceinline__ void flush_events(int64_t* counters, uint32_t ev, int extra_k = -1,
+                                             int extra = 0) {
+  if (!counters) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t active = __ballot(1);
+  const int leader = __ffsll((long long)active) - 1;
+  if (!__ballot(ev != 0u || extra != 0)) return;
+  for (int k = 0; k < USP_NCOUNTERS; ++k) {
+    const uint64_t m = __ballot((ev >> k) & 1u);
+    if (m && lane == leader) atomicAdd((unsigned long long*)&counters[k], (unsigned long long)__popcll(m));
+  }
+  if (extra_k >= 0) {
+    unsigned long long tot = 0;
+    for (int b = 0; b < 4; ++b) tot += (unsigned long long)__popcll(__ballot((extra >> b) & 1)) << b;
+    if (tot && lane == leader) atomicAdd((unsigned long long*)&counters[extra_k], tot);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // wave64 / block reductions in a fixed order (deterministic)
 // ---------------------------------------------------------------------------

@@ -6,53 +6,35 @@ namespace usp {
 constexpr int CELL_BLOCK = 256;
 constexpr int CELL_WAVES = CELL_BLOCK / 64;
 
-// Sum NV values over the block in a fixed order: wave butterflies, then the
-// four wave partials in wave order.  Every thread receives the totals.
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) lds[wid * NV + k] = v[k];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double s = lds[k];
-#pragma unroll
-    for (int w = 1; w < CELL_WAVES; ++w) s += lds[w * NV + k];
-    v[k] = s;
-  }
-  __syncthreads();
-}
-
 // Moments of one cell (Sec. II.A): U = <c>, then central second and third
-// moments about U, per unit mass.
+// moments about U, per unit mass.  One wave per cell, two passes over its
+// particles, FP64 sums reduced by a fixed butterfly (deterministic).
 template <typename S>
 __global__ __launch_bounds__(CELL_BLOCK) void k_moments(GridP g, PartP<S> p, const int64_t* offsets,
                                                         double* mom) {
-  __shared__ double lds[CELL_WAVES * 17];
-  const int64_t M = g.M, c = blockIdx.x;
+  const int64_t M = g.M;
+  const int64_t c = (int64_t)blockIdx.x * CELL_WAVES + (threadIdx.x >> 6);
+  if (c >= M) return;
+  const int lane = threadIdx.x & 63;
   const int64_t o0 = offsets[c], o1 = offsets[c + 1], N = o1 - o0;
   if (N == 0) {
-    if (threadIdx.x < NMOM) mom[threadIdx.x * M + c] = 0.0;
+    if (lane < NMOM) mom[lane * M + c] = 0.0;
     return;
   }
   double s1[3] = {0.0, 0.0, 0.0};
-  for (int64_t i = o0 + threadIdx.x; i < o1; i += CELL_BLOCK) {
+  for (int64_t i = o0 + lane; i < o1; i += 64) {
     s1[0] += (double)p.cx[i];
     s1[1] += (double)p.cy[i];
     s1[2] += (double)p.cz[i];
   }
-  block_sum<3>(s1, lds);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) s1[k] = wave_sum(s1[k]);
   const double invN = 1.0 / (double)N;
   const double Ux = s1[0] * invN, Uy = s1[1] * invN, Uz = s1[2] * invN;
   double s[17];
 #pragma unroll
   for (int k = 0; k < 17; ++k) s[k] = 0.0;
-  for (int64_t i = o0 + threadIdx.x; i < o1; i += CELL_BLOCK) {
+  for (int64_t i = o0 + lane; i < o1; i += 64) {
     const double Cx = (double)p.cx[i] - Ux, Cy = (double)p.cy[i] - Uy, Cz = (double)p.cz[i] - Uz;
     const double e = (double)p.erot[i], I = (double)p.vib[i];
     const double hC2 = 0.5 * (Cx * Cx + Cy * Cy + Cz * Cz);
@@ -63,19 +45,20 @@ __global__ __launch_bounds__(CELL_BLOCK) void k_moments(GridP g, PartP<S> p, con
     s[11] += Cx * e; s[12] += Cy * e; s[13] += Cz * e;
     s[14] += Cx * I; s[15] += Cy * I; s[16] += Cz * I;
   }
-  block_sum<17>(s, lds);
-  if (threadIdx.x == 0) {
+#pragma unroll
+  for (int k = 0; k < 17; ++k) s[k] = wave_sum(s[k]);
+  if (lane == 0) {
     mom[M_N * M + c] = (double)N;
     mom[M_UX * M + c] = Ux;
     mom[M_UY * M + c] = Uy;
     mom[M_UZ * M + c] = Uz;
   }
-  if (threadIdx.x < 17) {
+  if (lane < 17) {
     double v = 0.0;
 #pragma unroll
     for (int k = 0; k < 17; ++k)
-      if (k == (int)threadIdx.x) v = s[k];
-    mom[(M_PXX + threadIdx.x) * M + c] = v * invN;
+      if (k == lane) v = s[k];
+    mom[(M_PXX + lane) * M + c] = v * invN;
   }
 }
 
@@ -146,7 +129,7 @@ __global__ void k_reconstruct(GridP g, GasP gas, const double* mom, double dt,
 template <typename S>
 hipError_t launch_moments(const GridP& g, const PartP<S>& p, const int64_t* offsets, double* mom,
                           hipStream_t st) {
-  k_moments<S><<<g.M, CELL_BLOCK, 0, st>>>(g, p, offsets, mom);
+  k_moments<S><<<cdiv(g.M, CELL_WAVES), CELL_BLOCK, 0, st>>>(g, p, offsets, mom);
   return hipGetLastError();
 }
 

@@ -342,3 +342,41 @@ def test_invalid_arguments_rejected_on_host():
         usp.usp_reconstruct(gpu.grid, gpu.gas, gpu.mom, -1.0, None, gpu.cs, gpu.counters)
     with pytest.raises(usp.UspError):
         usp.usp_bin(gpu.grid, gpu.p, gpu.p, gpu.offsets, gpu.ws, gpu.counters)
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_conserve_vibrational_picks_exact(f32):
+    """Large forced corrections: the GPU's wave-parallel pick evaluation
+    reproduces the sequential picks of the oracle exactly (increments,
+    decrements with level-0 redraws, an impossible decrement that stops at
+    zero, and a cell beyond the on-chip staging size)."""
+    usp = _usp()
+    counts = [40, 700, 1500, 3000, 500]
+    M = len(counts)
+    prob, parts = W.batch0d(counts, T_tr=[3000.0] * M, T_rot=[3000.0] * M,
+                            T_vib=[2500.0, 2000.0, 900.0, 2500.0, 1500.0],
+                            dens=[1e22] * M, dt=1e-8, f32=f32, seed=77)
+    gpu = usp.DeviceState(prob, parts)
+    orc = oracle.Sim(prob, parts)
+    gpu.bin(); orc.bin()
+    gpu.do_moments(); orc.do_moments()
+    gpu.do_reconstruct(); orc.do_cellstate()
+    st = orc.state()
+    R, th = prob.gas.R, prob.gas.theta_vib
+    SI = np.array([st["vib"][orc.offsets[c]:orc.offsets[c + 1]].sum() for c in range(M)])
+    delta = np.array([+130.0, -(SI[1] - 3) + 0.0, +900.0, -(SI[3] // 2), -(SI[4] + 50)])
+    k = oracle.CS_NAMES.index("EVIB_NEW")
+    target = (SI + delta + 0.25) * R * th / np.array(counts)
+    cs_o = orc.cs.reshape(oracle.NCS, M)
+    cs_o[k] = target
+    gcs = gpu.cs.view(usp.NCS, M)
+    gcs[k] = torch.as_tensor(target, dtype=torch.float64, device=gcs.device)
+    gpu.conserve(9); orc.conserve(9)
+    a, b = gpu.state(), orc.state()
+    assert np.array_equal(a["vib"], b["vib"])
+    assert gpu.cnt()["PICK_FAIL"] == orc.cnt()["PICK_FAIL"] == 1
+    assert a["vib"][orc.offsets[4]:orc.offsets[5]].sum() == 0
+    for c in range(M):
+        got = a["vib"][orc.offsets[c]:orc.offsets[c + 1]].sum() - SI[c]
+        if c != 4:
+            assert got in (delta[c], delta[c] + 1), (c, got, delta[c])

@@ -361,15 +361,17 @@ def cylinder_particles(prob: Problem, init_seed=None):
     iy = cell // g.nx
     x = g.x0 + (ix + rng.random(N)) * g.dx
     y = g.y0 + (iy + rng.random(N)) * g.dy
-    # cut cells: redraw points that fell inside the body
-    for _ in range(200):
-        bad = (x - bc.cyl_xc) ** 2 + (y - bc.cyl_yc) ** 2 < bc.cyl_r ** 2
-        nb = int(bad.sum())
-        if nb == 0:
+    # cut cells: redraw points that fell inside the body (only particles of
+    # cut cells can be inside)
+    cut = np.nonzero((g.flags[cell] & FLAG_CUT) != 0)[0]
+    for _ in range(1000):
+        bad = cut[(x[cut] - bc.cyl_xc) ** 2 + (y[cut] - bc.cyl_yc) ** 2 < bc.cyl_r ** 2]
+        if len(bad) == 0:
             break
-        x[bad] = g.x0 + (ix[bad] + rng.random(nb)) * g.dx
-        y[bad] = g.y0 + (iy[bad] + rng.random(nb)) * g.dy
-    keep = ~((x - bc.cyl_xc) ** 2 + (y - bc.cyl_yc) ** 2 < bc.cyl_r ** 2)
+        x[bad] = g.x0 + (ix[bad] + rng.random(len(bad))) * g.dx
+        y[bad] = g.y0 + (iy[bad] + rng.random(len(bad))) * g.dy
+    keep = np.ones(N, bool)
+    keep[cut] = ~((x[cut] - bc.cyl_xc) ** 2 + (y[cut] - bc.cyl_yc) ** 2 < bc.cyl_r ** 2)
     x, y, cell = x[keep], y[keep], cell[keep]
     N = len(x)
     # keep positions strictly inside the domain after rounding to storage

@@ -15,7 +15,7 @@ constexpr int CONS_BLOCK = 256;
 // binomial B(n, p) draws by sequential CDF inversion: the smallest k with
 // u < F(k).  The pmf recurrences and the order of every FP64 operation are
 // fixed (no contraction) so that decisions are reproducible.
-__device__ __noinline__ int sample_nb(double u, int r, double p) {
+__device__ __forceinline__ int sample_nb(double u, int r, double p) {
 #pragma clang fp contract(off)
   const double q = 1.0 - p;
   double pk = 1.0;
@@ -32,7 +32,7 @@ __device__ __noinline__ int sample_nb(double u, int r, double p) {
   return k;
 }
 
-__device__ __noinline__ int sample_b(double u, int n, double p) {
+__device__ __forceinline__ int sample_b(double u, int n, double p) {
 #pragma clang fp contract(off)
   if (n <= 0 || p <= 0.0) return 0;
   if (p >= 1.0) return n;

@@ -180,9 +180,15 @@ size_t usp_workspace_bytes(const usp_grid* grid, int64_t capacity);
    cell are dropped; the rest are written to `out` sorted by cell, stable in
    input order.  offsets: device int64[M+1], cell c owns [offsets[c],
    offsets[c+1]).  out->count[0] becomes the kept count, out->count[1] =
-   in->count[1].  in and out must not alias. */
+   in->count[1].  in and out must not alias.
+   in_offsets (device int64[M+1], may be NULL, may alias offsets): when the
+   input's first in_offsets[M] particles are the output of an earlier bin
+   with these offsets (updated in place since, as usp_step does, with any
+   later particles appended), the fast route that exploits it is taken.  The
+   result is the same either way; NULL means nothing is known. */
 usp_status usp_bin(const usp_grid* grid, const usp_particles* in, usp_particles* out,
-                   int64_t* offsets, void* ws, size_t ws_bytes, int64_t* counters, void* stream);
+                   int64_t* offsets, const int64_t* in_offsets, void* ws, size_t ws_bytes,
+                   int64_t* counters, void* stream);
 
 /* Moments (Sec. II.A) of every cell from a binned state: mom = device
    double[USP_NMOM*M].  Two passes per cell (U, then central moments),

@@ -63,9 +63,13 @@ WsLayout ws_layout(int64_t M, int64_t capacity, int nfaces) {
   WsLayout L;
   size_t o = 0;
   L.key = o; o = align256(o + sizeof(int32_t) * (size_t)capacity);
-  L.cursor = o; o = align256(o + sizeof(int32_t) * (size_t)M);
   L.perm = o; o = align256(o + sizeof(uint32_t) * (size_t)capacity);
   L.blocksums = o; o = align256(o + sizeof(int64_t) * (size_t)(cdiv(M, 1024) + 1));
+  L.t9 = o; o = align256(o + sizeof(int32_t) * 9 * (size_t)M);
+  L.cell_i32 = o; o = align256(o + sizeof(int32_t) * 6 * (size_t)M);
+  L.old_off = o; o = align256(o + sizeof(int64_t) * (size_t)(M + 1));
+  L.far_off = o; o = align256(o + sizeof(int64_t) * (size_t)(M + 1));
+  L.far = o; o = align256(o + sizeof(int32_t) * 4 * (size_t)capacity);
   L.face_cnt = o; o = align256(o + sizeof(int32_t) * (size_t)(nfaces + 1));
   L.face_off = o; o = align256(o + sizeof(int64_t) * (size_t)(nfaces + 1));
   L.misc = o; o = align256(o + sizeof(int64_t) * 8);
@@ -110,11 +114,12 @@ usp_status hip_status(hipError_t e) { return e == hipSuccess ? USP_OK : USP_EDEV
 
 template <typename S>
 usp_status do_bin(const usp_grid* grid, const usp_particles* in, usp_particles* out,
-                  int64_t* offsets, void* ws, int64_t* counters, hipStream_t st) {
+                  int64_t* offsets, const int64_t* in_offsets, void* ws, int64_t* counters,
+                  hipStream_t st) {
   const GridP g = make_grid(grid);
   const WsLayout L = ws_layout(g.M, in->capacity, n_faces(g));
-  return hip_status(launch_bin<S>(g, make_parts<S>(in), make_parts<S>(out), offsets, (char*)ws, L,
-                                  counters, st));
+  return hip_status(launch_bin<S>(g, make_parts<S>(in), make_parts<S>(out), offsets, in_offsets,
+                                  (char*)ws, L, counters, st));
 }
 
 template <typename S>
@@ -129,7 +134,10 @@ usp_status do_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, d
   char* w = (char*)ws;
   for (int32_t s = 0; s < nsteps; ++s) {
     const uint64_t sn = step + (uint64_t)s;
-    hipError_t e = launch_bin<S>(g, make_parts<S>(p), make_parts<S>(p_alt), offsets, w, L, counters, st);
+    // from the second step on, the input is the previous step's binned
+    // state (segments in `offsets`) followed by the injected particles
+    hipError_t e = launch_bin<S>(g, make_parts<S>(p), make_parts<S>(p_alt), offsets,
+                                 s > 0 ? offsets : nullptr, w, L, counters, st);
     if (e != hipSuccess) return USP_EDEVICE;
     const usp_particles tmp = *p;
     *p = *p_alt;
@@ -185,14 +193,15 @@ size_t usp_workspace_bytes(const usp_grid* grid, int64_t capacity) {
 }
 
 usp_status usp_bin(const usp_grid* grid, const usp_particles* in, usp_particles* out,
-                   int64_t* offsets, void* ws, size_t ws_bytes, int64_t* counters, void* stream) {
+                   int64_t* offsets, const int64_t* in_offsets, void* ws, size_t ws_bytes,
+                   int64_t* counters, void* stream) {
   if (!grid_ok(grid) || !parts_ok(in, grid) || !parts_ok(out, grid) || !offsets || !ws) return USP_EINVAL;
   if (in->prec != out->prec || out->capacity < in->capacity) return USP_EINVAL;
   if (in->cx == out->cx || in->count == out->count) return USP_EINVAL;
   if (ws_bytes < usp_workspace_bytes(grid, in->capacity)) return USP_EINVAL;
   hipStream_t st = (hipStream_t)stream;
-  return in->prec == USP_F32 ? do_bin<float>(grid, in, out, offsets, ws, counters, st)
-                             : do_bin<double>(grid, in, out, offsets, ws, counters, st);
+  return in->prec == USP_F32 ? do_bin<float>(grid, in, out, offsets, in_offsets, ws, counters, st)
+                             : do_bin<double>(grid, in, out, offsets, in_offsets, ws, counters, st);
 }
 
 usp_status usp_moments(const usp_grid* grid, const usp_particles* p, const int64_t* offsets,

@@ -1,16 +1,23 @@
 // usp_bin.hip -- binning: stable counting sort of particles by cell.
 //
-// 1. key + histogram: cell of every live particle (integer atomics only,
-//    one per run of equal keys in a wave);
-// 2. exclusive scan of the histogram -> cell offsets (reduce, top, down);
-// 3. slot claim: each particle takes a slot in its cell's range with an
-//    atomic cursor (order inside a cell is arbitrary at this point);
-// 4. per-cell sort of the claimed input indices, ascending (one wave per
-//    cell by rank counting; a block per cell above 1024 particles): this
-//    restores input order inside every cell, so the result is the stable sort;
-// 5. gather of every state array through the permutation.
-// All results are deterministic: the only atomics are integer ones and the
-// per-cell sort removes their ordering.
+// The output order is fixed by definition: particles sorted by cell, in
+// input order inside a cell, removed particles dropped.  Two routes give it:
+//
+// * Binned input (the usual case: the previous step's sorted state, whose
+//   segment offsets are passed in, followed by a tail of injected
+//   particles).  A particle of old cell k lands in k + d with d in a small
+//   neighbour set, so a new cell's particles come from at most 9 source
+//   segments, which appear in ascending order in the input.  One wave per
+//   source segment ranks its particles inside each group with ballots
+//   (k_bin_group); one thread per new cell turns the group counts into
+//   positions, interleaving the rare far moves by input index
+//   (k_cell_bases); one wave per source segment then writes every particle
+//   straight to its final slot (k_bin_scatter).  No atomics, no sorting.
+// * The tail, and every particle when no input offsets are given: slots are
+//   claimed after the cell's prefix particles with one integer atomic per
+//   run of equal keys, and each cell's claimed indices are sorted ascending
+//   (restoring input order) before the copy.
+// All results are deterministic.
 #include "usp_device.h"
 
 namespace usp {
@@ -38,33 +45,6 @@ __device__ __forceinline__ void wave_runs(int32_t key, int* head_lane, int* run_
   const uint64_t above = heads & ~upto;
   const int next = above ? (__ffsll((long long)above) - 1) : 64;
   *run_len = head ? next - lane : 0;
-}
-
-template <typename S>
-__global__ __launch_bounds__(BIN_BLOCK) void k_bin_key(GridP g, PartP<S> in, int32_t* key,
-                                                       int32_t* counts, int64_t* counters) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = i < in.count[0];
-  int32_t c = -1;
-  if (live) {
-    c = in.cell[i];
-    if (c >= 0) {
-      if (g.dim == 0) {
-        if (c >= g.M) c = -1;
-      } else {
-        c = cell_of<S>(g, g.dim == 2 ? in.x[i] : S(0), in.y[i]);
-      }
-    }
-    if (c >= 0 && g.flags && (g.flags[c] & USP_FLAG_SOLID)) {
-      c = -1;
-      count_event(counters, USP_CNT_SOLID_DROP);
-    }
-    key[i] = c;
-  }
-  // one atomic per run of equal keys
-  int hl, len;
-  wave_runs(c, &hl, &len);
-  if (len > 0 && c >= 0) atomicAdd(&counts[c], len);
 }
 
 // ---- exclusive scan of int32 counts into int64 offsets -------------------
@@ -118,8 +98,10 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_scan_top(int64_t* blocksums, int6
   }
   if (threadIdx.x == 0) {
     offsets[M] = carry;
-    out_count[0] = carry;
-    out_count[1] = in_count[1];
+    if (out_count) {
+      out_count[0] = carry;
+      out_count[1] = in_count[1];
+    }
   }
 }
 
@@ -142,20 +124,6 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_scan_down(const int32_t* counts, 
     if (j < M) offsets[j] = run;
     run += v[k];
   }
-}
-
-__global__ __launch_bounds__(BIN_BLOCK) void k_claim(const int32_t* key, const int64_t* count,
-                                                     const int64_t* offsets, int32_t* cursor,
-                                                     uint32_t* perm) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t c = i < count[0] ? key[i] : -1;
-  // the run head claims slots for its whole run; members follow in order
-  int hl, len;
-  wave_runs(c, &hl, &len);
-  int32_t base = 0;
-  if (len > 0 && c >= 0) base = atomicAdd(&cursor[c], len);
-  base = __shfl(base, hl, 64);
-  if (c >= 0) perm[offsets[c] + base + ((threadIdx.x & 63) - hl)] = (uint32_t)i;
 }
 
 // Ascending sort network in which every compare-exchange puts the smaller
@@ -181,12 +149,300 @@ __device__ __forceinline__ void sort_net(uint32_t* a, int n) {
   }
 }
 
-// One wave sorts one cell's slot list (distinct input indices) by rank
-// counting: each lane holds K entries in registers; every entry's rank is
-// the number of entries below it, counted against all entries broadcast one
-// at a time with readlane.  Entries beyond n hold UINT32_MAX and never count.
-template <int K>
-__device__ __forceinline__ void wave_rank_sort(uint32_t* seg, int n) {
+// ---------------------------------------------------------------------------
+// Neighbour groups.  A particle of old cell k whose new cell is c = k + d
+// with d in D (the cell itself and its 8 neighbours in 2D, +-1 in 1D) belongs
+// to group d; any other destination is a far move.  D is listed in
+// descending order, so the source cells k = c - d of a new cell c come in
+// ascending order, which is input order for a binned input.
+// ---------------------------------------------------------------------------
+struct Nbr {
+  int n;
+  int d[9];
+};
+
+__host__ __device__ inline Nbr nbr_set(const GridP& g) {
+  Nbr r;
+  if (g.dim == 2 && g.nx >= 3) {
+    const int nx = g.nx;
+    const int v[9] = {nx + 1, nx, nx - 1, 1, 0, -1, -nx + 1, -nx, -nx - 1};
+    r.n = 9;
+    for (int k = 0; k < 9; ++k) r.d[k] = v[k];
+  } else {
+    r.n = 3;
+    r.d[0] = 1; r.d[1] = 0; r.d[2] = -1;
+    for (int k = 3; k < 9; ++k) r.d[k] = 0;
+  }
+  return r;
+}
+
+constexpr int GRP_FAR = 9;
+constexpr int GRP_GONE = 15;
+
+template <typename S>
+__device__ __forceinline__ int32_t new_key(const GridP& g, const PartP<S>& in, int64_t i,
+                                           bool* solid) {
+  int32_t c = in.cell[i];
+  *solid = false;
+  if (c >= 0) {
+    if (g.dim == 0) {
+      if (c >= g.M) c = -1;
+    } else {
+      c = cell_of<S>(g, g.dim == 2 ? in.x[i] : S(0), in.y[i]);
+    }
+  }
+  if (c >= 0 && g.flags && (g.flags[c] & USP_FLAG_SOLID)) {
+    c = -1;
+    *solid = true;
+  }
+  return c;
+}
+
+__device__ __forceinline__ int64_t sorted_len(const int64_t* old_off, int64_t M, const int64_t* count) {
+  const int64_t a = old_off[M], b = count[0];
+  return a < b ? (a > 0 ? a : 0) : b;
+}
+
+// A: one wave per old cell k.  New cell of every particle of the segment,
+// its group, and its rank among the earlier particles of the segment in the
+// same group (64 at a time with ballots).  Writes grp[i] = rank << 4 | group,
+// the group counts T9[k][.], and appends far moves to an unordered list.
+template <typename S>
+__global__ __launch_bounds__(BIN_BLOCK) void k_bin_group(GridP g, Nbr nb, PartP<S> in,
+                                                         const int64_t* old_off, int32_t* grp,
+                                                         int32_t* T9, int32_t* far_cnt,
+                                                         int32_t* far_c, int32_t* far_i,
+                                                         int32_t* far_total, int64_t* counters) {
+  const int64_t M = g.M;
+  const int64_t k = (int64_t)blockIdx.x * (BIN_BLOCK / 64) + (threadIdx.x >> 6);
+  if (k >= M) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t ns = sorted_len(old_off, M, in.count);
+  int64_t lo = old_off[k], hi = old_off[k + 1];
+  lo = lo < 0 ? 0 : (lo > ns ? ns : lo);
+  hi = hi < lo ? lo : (hi > ns ? ns : hi);
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  int running[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) running[q] = 0;
+  for (int64_t base = lo; base < hi; base += 64) {
+    const int64_t i = base + lane;
+    const bool active = i < hi;
+    int grpid = 14;  // inactive lane
+    int32_t c = -1;
+    if (active) {
+      bool solid;
+      c = new_key<S>(g, in, i, &solid);
+      if (solid) count_event(counters, USP_CNT_SOLID_DROP);
+      if (c < 0) {
+        grpid = GRP_GONE;
+      } else {
+        const int64_t d = (int64_t)c - k;
+        grpid = GRP_FAR;
+        for (int q = 0; q < nb.n; ++q)
+          if (d == nb.d[q]) grpid = q;
+      }
+    }
+    int rank = 0;
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+      const uint64_t m = __ballot(grpid == q);
+      if (grpid == q) rank = running[q] + __popcll(m & lt);
+      running[q] += __popcll(m);
+    }
+    if (active) grp[i] = (rank << 4) | grpid;
+    if (grpid == GRP_FAR) {
+      const int j = atomicAdd(far_total, 1);
+      far_c[j] = c;
+      far_i[j] = (int32_t)i;
+      atomicAdd(&far_cnt[c], 1);
+    }
+  }
+  if (lane < nb.n) {
+    int v = 0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+      if (q == lane) v = running[q];
+    T9[k * 9 + lane] = v;
+  }
+}
+
+// Keys of the unsorted tail [ns, n) (injected particles, or every particle
+// when the input is not binned): one atomic per run of equal keys.
+template <typename S>
+__global__ __launch_bounds__(BIN_BLOCK) void k_tail_key(GridP g, PartP<S> in, const int64_t* old_off,
+                                                        int32_t* key, int32_t* tail_cnt,
+                                                        int64_t* counters) {
+  const int64_t M = g.M;
+  const int64_t ns = sorted_len(old_off, M, in.count), n = in.count[0];
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * BIN_BLOCK;
+  for (int64_t b = ns + (int64_t)blockIdx.x * BIN_BLOCK + (threadIdx.x & ~63); b < n; b += stride) {
+    const int64_t i = b + lane;
+    int32_t c = -1;
+    if (i < n) {
+      bool solid;
+      c = new_key<S>(g, in, i, &solid);
+      if (solid) count_event(counters, USP_CNT_SOLID_DROP);
+      key[i] = c;
+    }
+    int hl, len;
+    wave_runs(c, &hl, &len);
+    if (len > 0 && c >= 0) atomicAdd(&tail_cnt[c], len);
+  }
+}
+
+// Far moves into per-cell lists (the order inside a list is fixed later).
+__global__ __launch_bounds__(BIN_BLOCK) void k_far_place(const int32_t* far_total,
+                                                         const int32_t* far_c, const int32_t* far_i,
+                                                         const int64_t* far_off, int32_t* far_cur,
+                                                         int32_t* far_list) {
+  const int nt = *far_total;
+  for (int j = blockIdx.x * BIN_BLOCK + threadIdx.x; j < nt; j += gridDim.x * BIN_BLOCK) {
+    const int32_t c = far_c[j];
+    far_list[far_off[c] + atomicAdd(&far_cur[c], 1)] = far_i[j];
+  }
+}
+
+// C: one thread per new cell c.  The source groups (k = c - d, ascending k)
+// and the far moves into c (ascending index) interleave in input order;
+// T9[k][q] becomes the group's first position inside c, far_base the far
+// moves' positions.  cnt_total[c] = prefix particles + tail particles.
+__global__ __launch_bounds__(BIN_BLOCK) void k_cell_bases(GridP g, Nbr nb, const int64_t* old_off,
+                                                          const int64_t* count, int32_t* T9,
+                                                          const int64_t* far_off, int32_t* far_list,
+                                                          int32_t* far_base, const int32_t* tail_cnt,
+                                                          int32_t* nontail, int32_t* cnt_total) {
+  const int64_t M = g.M;
+  const int64_t c = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x;
+  if (c >= M) return;
+  const int64_t ns = sorted_len(old_off, M, count);
+  const int64_t f0 = far_off[c], f1 = far_off[c + 1];
+  for (int64_t a = f0 + 1; a < f1; ++a) {  // insertion sort (lists are tiny)
+    const int32_t v = far_list[a];
+    int64_t b = a - 1;
+    while (b >= f0 && far_list[b] > v) { far_list[b + 1] = far_list[b]; --b; }
+    far_list[b + 1] = v;
+  }
+  int32_t run = 0;
+  int64_t fp = f0;
+  for (int q = 0; q < nb.n; ++q) {
+    const int64_t k = c - nb.d[q];
+    if (k < 0 || k >= M) continue;
+    int64_t kstart = old_off[k];
+    kstart = kstart < 0 ? 0 : (kstart > ns ? ns : kstart);
+    while (fp < f1 && far_list[fp] < kstart) far_base[fp++] = run++;
+    const int32_t cnt = T9[k * 9 + q];
+    T9[k * 9 + q] = run;
+    run += cnt;
+  }
+  while (fp < f1) far_base[fp++] = run++;
+  nontail[c] = run;
+  cnt_total[c] = run + tail_cnt[c];
+}
+
+template <typename S>
+__device__ __forceinline__ void copy_particle(const PartP<S>& in, const PartP<S>& out, int64_t i,
+                                              int64_t p, int32_t c, bool has_x, bool has_y) {
+  if (has_x) out.x[p] = in.x[i];
+  if (has_y) out.y[p] = in.y[i];
+  out.cx[p] = in.cx[i];
+  out.cy[p] = in.cy[i];
+  out.cz[p] = in.cz[i];
+  out.erot[p] = in.erot[i];
+  out.vib[p] = in.vib[i];
+  out.pid[p] = in.pid[i];
+  out.cell[p] = c;
+}
+
+// E: one wave per old cell; every grouped particle goes straight to
+// offsets[c] + (group base in c) + (rank in group).
+template <typename S>
+__global__ __launch_bounds__(BIN_BLOCK) void k_bin_scatter(GridP g, Nbr nb, PartP<S> in, PartP<S> out,
+                                                           const int64_t* old_off, const int32_t* grp,
+                                                           const int32_t* T9, const int64_t* offsets) {
+  const int64_t M = g.M;
+  const int64_t k = (int64_t)blockIdx.x * (BIN_BLOCK / 64) + (threadIdx.x >> 6);
+  if (k >= M) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t ns = sorted_len(old_off, M, in.count);
+  int64_t lo = old_off[k], hi = old_off[k + 1];
+  lo = lo < 0 ? 0 : (lo > ns ? ns : lo);
+  hi = hi < lo ? lo : (hi > ns ? ns : hi);
+  if (lo >= hi) return;
+  // lane q < nb.n holds the first slot of group q and its cell
+  int64_t gbase = 0;
+  int32_t gcell = 0;
+  if (lane < nb.n) {
+    int dq = 0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+      if (q == lane) dq = nb.d[q];
+    const int64_t c = k + dq;
+    if (c >= 0 && c < M) {
+      gcell = (int32_t)c;
+      gbase = offsets[c] + T9[k * 9 + lane];
+    }
+  }
+  const bool hx = g.dim == 2, hy = g.dim >= 1;
+  for (int64_t base = lo; base < hi; base += 64) {
+    const int64_t i = base + lane;
+    const int32_t gv = i < hi ? grp[i] : (GRP_GONE);
+    const int q = gv & 15;
+    const int64_t b = __shfl(gbase, q < 9 ? q : 0, 64);
+    const int32_t c = __shfl(gcell, q < 9 ? q : 0, 64);
+    if (i < hi && q < nb.n) copy_particle<S>(in, out, i, b + (gv >> 4), c, hx, hy);
+  }
+}
+
+// far moves: each list entry finds its position inside its cell
+template <typename S>
+__global__ __launch_bounds__(BIN_BLOCK) void k_far_scatter(GridP g, PartP<S> in, PartP<S> out,
+                                                           const int32_t* far_total,
+                                                           const int32_t* far_c, const int32_t* far_i,
+                                                           const int64_t* far_off,
+                                                           const int32_t* far_list,
+                                                           const int32_t* far_base,
+                                                           const int64_t* offsets) {
+  const int nt = *far_total;
+  for (int j = blockIdx.x * BIN_BLOCK + threadIdx.x; j < nt; j += gridDim.x * BIN_BLOCK) {
+    const int32_t c = far_c[j], i = far_i[j];
+    int64_t fp = far_off[c];
+    const int64_t f1 = far_off[c + 1];
+    while (fp < f1 && far_list[fp] != i) ++fp;
+    if (fp < f1) copy_particle<S>(in, out, i, offsets[c] + far_base[fp], c, g.dim == 2, g.dim >= 1);
+  }
+}
+
+// tail: slots after the prefix particles of each cell, claimed per run
+__global__ __launch_bounds__(BIN_BLOCK) void k_tail_claim(int64_t M, const int64_t* old_off,
+                                                          const int64_t* count, const int32_t* key,
+                                                          const int64_t* offsets,
+                                                          const int32_t* nontail, int32_t* cursor,
+                                                          uint32_t* perm) {
+  const int64_t ns = sorted_len(old_off, M, count), n = count[0];
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * BIN_BLOCK;
+  for (int64_t b = ns + (int64_t)blockIdx.x * BIN_BLOCK + (threadIdx.x & ~63); b < n; b += stride) {
+    const int64_t i = b + lane;
+    const int32_t c = i < n ? key[i] : -1;
+    int hl, len;
+    wave_runs(c, &hl, &len);
+    int32_t base = 0;
+    if (len > 0 && c >= 0) base = atomicAdd(&cursor[c], len);
+    base = __shfl(base, hl, 64);
+    if (c >= 0) perm[offsets[c] + nontail[c] + base + (lane - hl)] = (uint32_t)i;
+  }
+}
+
+// One wave sorts one cell's tail slot list (distinct input indices) by rank
+// counting and copies each particle to its rank's slot: each lane holds K
+// entries; an entry's rank is the number of entries below it, counted
+// against all entries broadcast with readlane.
+template <int K, typename S>
+__device__ __forceinline__ void wave_rank_copy(const uint32_t* seg, int n, int64_t dst0,
+                                               const PartP<S>& in, const PartP<S>& out, int32_t c,
+                                               bool hx, bool hy) {
   const int lane = threadIdx.x & 63;
   uint32_t v[K];
   int r[K];
@@ -208,91 +464,128 @@ __device__ __forceinline__ void wave_rank_sort(uint32_t* seg, int n) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int j = k * 64 + lane;
-    if (j < n) seg[r[k]] = v[k];
+    if (j < n) copy_particle<S>(in, out, v[k], dst0 + r[k], c, hx, hy);
   }
 }
 
 constexpr int WAVE_SORT_MAX = 1024;
 
-__global__ __launch_bounds__(BIN_BLOCK) void k_segsort_wave(const int64_t* offsets, int64_t M,
-                                                            uint32_t* perm) {
+template <typename S>
+__global__ __launch_bounds__(BIN_BLOCK) void k_tail_sort_copy(GridP g, PartP<S> in, PartP<S> out,
+                                                              const int64_t* offsets,
+                                                              const int32_t* nontail,
+                                                              const uint32_t* perm) {
+  const int64_t M = g.M;
   const int64_t c = (int64_t)blockIdx.x * (BIN_BLOCK / 64) + (threadIdx.x >> 6);
   if (c >= M) return;
-  const int64_t o0 = offsets[c];
-  const int n = (int)(offsets[c + 1] - o0);
-  if (n <= 1 || n > WAVE_SORT_MAX) return;
-  uint32_t* seg = perm + o0;
-  if (n <= 64) wave_rank_sort<1>(seg, n);
-  else if (n <= 128) wave_rank_sort<2>(seg, n);
-  else if (n <= 256) wave_rank_sort<4>(seg, n);
-  else if (n <= 512) wave_rank_sort<8>(seg, n);
-  else wave_rank_sort<16>(seg, n);
+  const int64_t t0 = offsets[c] + nontail[c];
+  const int n = (int)(offsets[c + 1] - t0);
+  if (n <= 0 || n > WAVE_SORT_MAX) return;
+  const bool hx = g.dim == 2, hy = g.dim >= 1;
+  const uint32_t* seg = perm + t0;
+  if (n <= 64) wave_rank_copy<1, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
+  else if (n <= 128) wave_rank_copy<2, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
+  else if (n <= 256) wave_rank_copy<4, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
+  else if (n <= 512) wave_rank_copy<8, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
+  else wave_rank_copy<16, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
 }
 
-// cells above WAVE_SORT_MAX: one block per cell, sort network in LDS (or in
-// global memory beyond SORT_LDS entries)
-__global__ __launch_bounds__(BIN_BLOCK) void k_segsort_big(const int64_t* offsets, uint32_t* perm) {
+// tails above WAVE_SORT_MAX: one block per cell, sort network in LDS (or in
+// global memory beyond SORT_LDS entries), then the copy
+template <typename S>
+__global__ __launch_bounds__(BIN_BLOCK) void k_tail_sort_copy_big(GridP g, PartP<S> in, PartP<S> out,
+                                                                  const int64_t* offsets,
+                                                                  const int32_t* nontail,
+                                                                  uint32_t* perm) {
   __shared__ uint32_t s[SORT_LDS];
   const int64_t c = blockIdx.x;
-  const int64_t o0 = offsets[c];
-  const int n = (int)(offsets[c + 1] - o0);
+  const int64_t t0 = offsets[c] + nontail[c];
+  const int n = (int)(offsets[c + 1] - t0);
   if (n <= WAVE_SORT_MAX) return;
-  uint32_t* seg = perm + o0;
+  uint32_t* seg = perm + t0;
+  const bool hx = g.dim == 2, hy = g.dim >= 1;
   if (n <= SORT_LDS) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) s[i] = seg[i];
     __syncthreads();
     sort_net<true>(s, n);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) seg[i] = s[i];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) copy_particle<S>(in, out, s[i], t0 + i, (int32_t)c, hx, hy);
   } else {
     sort_net<false>(seg, n);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) copy_particle<S>(in, out, seg[i], t0 + i, (int32_t)c, hx, hy);
   }
 }
 
-template <typename S>
-__global__ __launch_bounds__(BIN_BLOCK) void k_gather(PartP<S> in, PartP<S> out,
-                                                      const uint32_t* perm, const int32_t* key,
-                                                      int has_x, int has_y) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= out.count[0]) return;
-  const uint32_t i = perm[p];
-  if (has_x) out.x[p] = in.x[i];
-  if (has_y) out.y[p] = in.y[i];
-  out.cx[p] = in.cx[i];
-  out.cy[p] = in.cy[i];
-  out.cz[p] = in.cz[i];
-  out.erot[p] = in.erot[i];
-  out.vib[p] = in.vib[i];
-  out.pid[p] = in.pid[i];
-  out.cell[p] = key[i];
+__global__ void k_copy_i64(const int64_t* src, int64_t* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src ? src[i] : 0;
+}
+
+__global__ void k_zero_i32x(int32_t* a, int32_t* b, int32_t* c, int32_t* d, int64_t n,
+                            int32_t* scalar) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) { a[i] = 0; b[i] = 0; c[i] = 0; d[i] = 0; }
+  if (i == 0) *scalar = 0;
+}
+
+static void launch_scan(const int32_t* cnt, int64_t M, int64_t* out_off, int64_t* blocksums,
+                        int64_t* out_count, const int64_t* in_count, hipStream_t st) {
+  const int64_t nb = cdiv(M, SCAN_TILE);
+  k_scan_reduce<<<nb, BIN_BLOCK, 0, st>>>(cnt, M, blocksums);
+  k_scan_top<<<1, BIN_BLOCK, 0, st>>>(blocksums, nb, out_off, M, out_count, in_count);
+  k_scan_down<<<nb, BIN_BLOCK, 0, st>>>(cnt, M, blocksums, out_off);
 }
 
 template <typename S>
 hipError_t launch_bin(const GridP& g, const PartP<S>& in, const PartP<S>& out, int64_t* offsets,
-                      char* ws, const WsLayout& L, int64_t* counters, hipStream_t st) {
+                      const int64_t* in_offsets, char* ws, const WsLayout& L, int64_t* counters,
+                      hipStream_t st) {
   int32_t* key = (int32_t*)(ws + L.key);
-  int32_t* cursor = (int32_t*)(ws + L.cursor);
   uint32_t* perm = (uint32_t*)(ws + L.perm);
   int64_t* blocksums = (int64_t*)(ws + L.blocksums);
+  int32_t* T9 = (int32_t*)(ws + L.t9);
+  int32_t* tail_cnt = (int32_t*)(ws + L.cell_i32);
+  int32_t* cursor = tail_cnt + g.M;
+  int32_t* far_cnt = cursor + g.M;
+  int32_t* far_cur = far_cnt + g.M;
+  int32_t* nontail = far_cur + g.M;
+  int32_t* cnt_total = nontail + g.M;
+  int64_t* old_off = (int64_t*)(ws + L.old_off);
+  int64_t* far_off = (int64_t*)(ws + L.far_off);
+  int32_t* far_c = (int32_t*)(ws + L.far);
+  int32_t* far_i = far_c + in.capacity;
+  int32_t* far_list = far_i + in.capacity;
+  int32_t* far_base = far_list + in.capacity;
+  int32_t* far_total = (int32_t*)(ws + L.misc) + 8;
   const int64_t M = g.M;
-  const int64_t cap = in.capacity;
-  const int64_t nb = cdiv(M, SCAN_TILE);
-  k_fill_i32<<<cdiv(M, 256), 256, 0, st>>>(cursor, 0, M);
-  k_bin_key<S><<<cdiv(cap, BIN_BLOCK), BIN_BLOCK, 0, st>>>(g, in, key, cursor, counters);
-  k_scan_reduce<<<nb, BIN_BLOCK, 0, st>>>(cursor, M, blocksums);
-  k_scan_top<<<1, BIN_BLOCK, 0, st>>>(blocksums, nb, offsets, M, out.count, in.count);
-  k_scan_down<<<nb, BIN_BLOCK, 0, st>>>(cursor, M, blocksums, offsets);
-  k_fill_i32<<<cdiv(M, 256), 256, 0, st>>>(cursor, 0, M);
-  k_claim<<<cdiv(cap, BIN_BLOCK), BIN_BLOCK, 0, st>>>(key, in.count, offsets, cursor, perm);
-  k_segsort_wave<<<cdiv(M, BIN_BLOCK / 64), BIN_BLOCK, 0, st>>>(offsets, M, perm);
-  k_segsort_big<<<M, BIN_BLOCK, 0, st>>>(offsets, perm);
-  k_gather<S><<<cdiv(cap, BIN_BLOCK), BIN_BLOCK, 0, st>>>(in, out, perm, key, g.dim == 2,
-                                                          g.dim >= 1);
+  const Nbr nb = nbr_set(g);
+  const int TAIL_GRID = 512;
+  k_copy_i64<<<cdiv(M + 1, 256), 256, 0, st>>>(in_offsets, old_off, M + 1);
+  k_zero_i32x<<<cdiv(M, 256), 256, 0, st>>>(tail_cnt, cursor, far_cnt, far_cur, M, far_total);
+  k_bin_group<S><<<cdiv(M, BIN_BLOCK / 64), BIN_BLOCK, 0, st>>>(g, nb, in, old_off, key, T9, far_cnt,
+                                                                 far_c, far_i, far_total, counters);
+  k_tail_key<S><<<TAIL_GRID, BIN_BLOCK, 0, st>>>(g, in, old_off, key, tail_cnt, counters);
+  launch_scan(far_cnt, M, far_off, blocksums, nullptr, nullptr, st);
+  k_far_place<<<64, BIN_BLOCK, 0, st>>>(far_total, far_c, far_i, far_off, far_cur, far_list);
+  k_cell_bases<<<cdiv(M, BIN_BLOCK), BIN_BLOCK, 0, st>>>(g, nb, old_off, in.count, T9, far_off,
+                                                          far_list, far_base, tail_cnt, nontail,
+                                                          cnt_total);
+  launch_scan(cnt_total, M, offsets, blocksums, out.count, in.count, st);
+  k_bin_scatter<S><<<cdiv(M, BIN_BLOCK / 64), BIN_BLOCK, 0, st>>>(g, nb, in, out, old_off, key, T9,
+                                                                   offsets);
+  k_far_scatter<S><<<64, BIN_BLOCK, 0, st>>>(g, in, out, far_total, far_c, far_i, far_off, far_list,
+                                             far_base, offsets);
+  k_tail_claim<<<TAIL_GRID, BIN_BLOCK, 0, st>>>(M, old_off, in.count, key, offsets, nontail, cursor,
+                                                perm);
+  k_tail_sort_copy<S><<<cdiv(M, BIN_BLOCK / 64), BIN_BLOCK, 0, st>>>(g, in, out, offsets, nontail, perm);
+  k_tail_sort_copy_big<S><<<M, BIN_BLOCK, 0, st>>>(g, in, out, offsets, nontail, perm);
   return hipGetLastError();
 }
 
 template hipError_t launch_bin<float>(const GridP&, const PartP<float>&, const PartP<float>&,
-                                      int64_t*, char*, const WsLayout&, int64_t*, hipStream_t);
+                                      int64_t*, const int64_t*, char*, const WsLayout&, int64_t*,
+                                      hipStream_t);
 template hipError_t launch_bin<double>(const GridP&, const PartP<double>&, const PartP<double>&,
-                                       int64_t*, char*, const WsLayout&, int64_t*, hipStream_t);
+                                       int64_t*, const int64_t*, char*, const WsLayout&, int64_t*,
+                                       hipStream_t);
 
 }  // namespace usp

@@ -75,7 +75,8 @@ template <typename S> PartP<S> make_parts(const usp_particles* p);
 
 // workspace layout (byte offsets into the caller's scratch buffer)
 struct WsLayout {
-  size_t key, cursor, perm, blocksums, face_cnt, face_off, misc, total;
+  size_t key, perm, blocksums, t9, cell_i32, old_off, far_off, far, face_cnt, face_off, misc,
+      total;
 };
 WsLayout ws_layout(int64_t M, int64_t capacity, int nfaces);
 int n_faces(const GridP& g);
@@ -83,7 +84,8 @@ int n_faces(const GridP& g);
 // launchers (return hipError_t of the last launch)
 template <typename S>
 hipError_t launch_bin(const GridP& g, const PartP<S>& in, const PartP<S>& out, int64_t* offsets,
-                      char* ws, const WsLayout& L, int64_t* counters, hipStream_t st);
+                      const int64_t* in_offsets, char* ws, const WsLayout& L, int64_t* counters,
+                      hipStream_t st);
 template <typename S>
 hipError_t launch_moments(const GridP& g, const PartP<S>& p, const int64_t* offsets, double* mom,
                           hipStream_t st);

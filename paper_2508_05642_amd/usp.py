@@ -72,7 +72,7 @@ def lib():
         L.usp_version.restype = C.c_char_p
         L.usp_workspace_bytes.argtypes = [vp, i64]
         L.usp_workspace_bytes.restype = sz
-        L.usp_bin.argtypes = [vp, vp, vp, vp, vp, sz, vp, vp]
+        L.usp_bin.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp, vp]
         L.usp_moments.argtypes = [vp, vp, vp, vp, vp]
         L.usp_reconstruct.argtypes = [vp, vp, vp, d, vp, vp, vp, vp]
         L.usp_collide.argtypes = [vp, vp, vp, vp, vp, u64, u64, vp, vp]
@@ -129,9 +129,10 @@ def make_bc(b):
 
 
 # ---- the seven entry points -------------------------------------------------
-def usp_bin(grid, pin, pout, offsets, ws, counters, stream=None):
-    _check(lib().usp_bin(C.byref(grid), C.byref(pin), C.byref(pout), _ptr(offsets), _ptr(ws),
-                         ws.numel(), _ptr(counters), _stream(stream)), "usp_bin")
+def usp_bin(grid, pin, pout, offsets, ws, counters, stream=None, in_offsets=None):
+    _check(lib().usp_bin(C.byref(grid), C.byref(pin), C.byref(pout), _ptr(offsets),
+                         _ptr(in_offsets), _ptr(ws), ws.numel(), _ptr(counters),
+                         _stream(stream)), "usp_bin")
 
 
 def usp_moments(grid, p, offsets, mom, stream=None):
@@ -241,6 +242,7 @@ class DeviceState:
         B["pid"][:n] = torch.as_tensor(np.asarray(parts["pid"][:n]).astype(np.uint32).view(np.int32))
         B["count"][:] = torch.tensor([n, int(parts["next_pid"])], dtype=torch.int64)
         self.cur = 0
+        self.binned = False
 
     @property
     def p(self):
@@ -273,9 +275,15 @@ class DeviceState:
         return dict(zip(names("cnt"), self.counters.cpu().tolist()))
 
     # -- phases (the C entry points on this state) ------------------------
-    def bin(self, stream=None):
-        usp_bin(self.grid, self.p, self.p_alt, self.offsets, self.ws, self.counters, stream)
+    def bin(self, stream=None, use_offsets=True):
+        """Rebin the current state.  Once this state has been binned, the
+        previous offsets describe its prefix (the phases keep the order) and
+        are passed on, unless use_offsets is False."""
+        prev = self.offsets if (use_offsets and self.binned) else None
+        usp_bin(self.grid, self.p, self.p_alt, self.offsets, self.ws, self.counters, stream,
+                in_offsets=prev)
         self.cur = 1 - self.cur
+        self.binned = True
 
     def do_moments(self, stream=None):
         usp_moments(self.grid, self.p, self.offsets, self.mom, stream)
@@ -301,6 +309,8 @@ class DeviceState:
         usp_step(self.grid, self.gas, self.bc if self.dim >= 1 else None, self.prob.dt,
                  self.dt_cell, a, b, self.offsets, self.mom, self.cs, self.ws, self.prob.seed,
                  step, nsteps, self.counters, stream)
+        if nsteps > 0:
+            self.binned = True
         # the library swapped the struct contents once per step
         if nsteps % 2 == 1:
             B0, B1 = self.bufs[self.cur], self.bufs[1 - self.cur]

@@ -380,3 +380,53 @@ def test_conserve_vibrational_picks_exact(f32):
         got = a["vib"][orc.offsets[c]:orc.offsets[c + 1]].sum() - SI[c]
         if c != 4:
             assert got in (delta[c], delta[c] + 1), (c, got, delta[c])
+
+
+@pytest.mark.parametrize("kind", ["2d", "1d", "0d"])
+def test_bin_fast_route_far_moves_deletions_tail(kind):
+    """Rebin of a binned state (the route that uses the previous offsets)
+    after far moves, removals and an appended tail: identical to the
+    oracle's plain stable sort of the same input."""
+    usp = _usp()
+    prob, parts = make(kind, True)
+    gpu = usp.DeviceState(prob, parts)
+    gpu.bin()
+    B = gpu.bufs[gpu.cur]
+    st = gpu.state()
+    n = st["n"]
+    g = prob.grid
+    rng = np.random.default_rng(11)
+    if g.dim >= 1:
+        sel = rng.choice(n, max(1, n // 30), replace=False)
+        y = st["y"].copy()
+        y[sel] += rng.choice([-3, -2, 2, 3], len(sel)) * g.dy
+        y = np.clip(y, g.y0, g.y0 + g.ny * g.dy * (1 - 1e-6))
+        B["y"][:n] = torch.as_tensor(y.astype(np.float32))
+        if g.dim == 2:
+            x = st["x"].copy()
+            x[sel] += rng.choice([-5, -2, 2, 4], len(sel)) * g.dx
+            x = np.clip(x, g.x0, g.x0 + g.nx * g.dx * (1 - 1e-6))
+            B["x"][:n] = torch.as_tensor(x.astype(np.float32))
+    dead = rng.choice(n, max(1, n // 100), replace=False)
+    cell = st["cell"].copy()
+    cell[dead] = -1
+    B["cell"][:n] = torch.as_tensor(cell)
+    # append a tail of new particles (copies of random ones, fresh ids)
+    k = min(500, gpu.cap - n)
+    src = rng.choice(n, k)
+    for f in ("x", "y", "cx", "cy", "cz", "erot", "vib", "cell"):
+        if B[f] is not None:
+            B[f][n:n + k] = B[f][torch.as_tensor(src, device=B[f].device)]
+    B["pid"][n:n + k] = torch.arange(n + 10_000_000, n + 10_000_000 + k, dtype=torch.int32,
+                                     device=B["pid"].device)
+    B["count"][0] += k
+    full = gpu.state()
+    orc = oracle.Sim(prob, dict(full, cap=gpu.cap))
+    gpu.bin()            # previous offsets known: the fast route
+    orc.bin()
+    a, b = gpu.state(), orc.state()
+    assert a["n"] == b["n"]
+    assert np.array_equal(gpu.offsets.cpu().numpy(), orc.offsets)
+    for f in ("pid", "cell", "vib", "x", "y", "cx", "cy", "cz", "erot"):
+        if b[f] is not None:
+            assert np.array_equal(a[f], b[f]), f

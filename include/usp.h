@@ -160,7 +160,9 @@ typedef struct {
    N, U(3), Pi(6: xx yy zz xy xz yz), e_rot, mean level, q_tr(3) =
    (1/2)<C^2 C>, q_rot(3) = <C eps_rot>, <C I>(3) (times R theta = q_vib). */
 #define USP_NMOM 21
-/* Cell-state planes: see usp_cs_name(k). */
+/* Cell-state buffer: USP_NCS FP64 planes (names: usp_cs_name(k)) followed
+   by one packed 128-byte record per cell that the particle update reads;
+   usp_cellstate_bytes() gives its size. */
 #define USP_NCS 35
 
 const char* usp_status_str(usp_status s);
@@ -168,6 +170,10 @@ const char* usp_mom_name(int32_t k);
 const char* usp_cs_name(int32_t k);
 const char* usp_counter_name(int32_t k);
 const char* usp_version(void);
+
+/* Bytes of the cell-state buffer `cs` for this grid (0 if the grid is
+   invalid). */
+size_t usp_cellstate_bytes(const usp_grid* grid);
 
 /* Bytes of scratch the caller passes as `ws` to usp_bin, usp_advect and
    usp_step for this grid and particle capacity. */
@@ -200,8 +206,8 @@ usp_status usp_moments(const usp_grid* grid, const usp_particles* p, const int64
    viscosity, tau_c, Z's, Pr, the USP-FPM coefficients alpha (eq.
    USP-FPM_alpha_tr), nu (eq. USP-FPM_nu), a = dt/(dt + 2 tau_rot), b =
    dt/(dt + 2 tau_vib), the cell energy targets of eqs. e_rot/e_vib_relax and
-   the stencil usability flag used by the reconstruction (Sec. III.B).
-   cs = device double[USP_NCS*M].  dt_cell (device, M) overrides dt per cell
+   the stencil usability flag and quadrant stencils used by the
+   reconstruction (Sec. III.B).  cs = device buffer of usp_cellstate_bytes().  dt_cell (device, M) overrides dt per cell
    when not NULL (independent 0D boxes). */
 usp_status usp_reconstruct(const usp_grid* grid, const usp_gas* gas, const double* mom,
                            double dt, const double* dt_cell, double* cs, int64_t* counters,

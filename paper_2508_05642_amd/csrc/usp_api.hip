@@ -186,6 +186,11 @@ const char* usp_counter_name(int32_t k) {
 }
 const char* usp_version(void) { return "libusp 0.1 (gfx950)"; }
 
+size_t usp_cellstate_bytes(const usp_grid* grid) {
+  if (!grid_ok(grid)) return 0;
+  return cellstate_bytes((int64_t)grid->nx * grid->ny);
+}
+
 size_t usp_workspace_bytes(const usp_grid* grid, int64_t capacity) {
   if (!grid_ok(grid) || capacity <= 0) return 0;
   const GridP g = make_grid(grid);

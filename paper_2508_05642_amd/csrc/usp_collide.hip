@@ -199,132 +199,219 @@ __device__ PartCoef<T> particle_coef(T R, T Th, T Ttr, T Trot, T Tvib, const T P
   return r;
 }
 
+// Stencil of a particle: the quadrant of its position in its cell selects
+// one of the four precomputed stencils (see k_stencil); weights are the
+// offsets from the cell centre over the signed spacing.
+struct Stencil {
+  int64_t c10, c01, c11;
+  double wx, wy;
+  bool hx, hy, hxy;
+};
+
 template <typename S>
-__global__ __launch_bounds__(PART_BLOCK) void k_collide(GridP g, GasP gas, const double* __restrict__ cs,
-                                                        PartP<S> p, uint64_t seed, uint32_t step,
-                                                        int64_t* counters) {
-  using T = S;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= p.count[0]) return;
-  const int32_t c = p.cell[i];
-  if (c < 0) return;
-  const int64_t M = g.M;
-  if (cs[CS_COLLIDE * M + c] == 0.0) return;
-
-  // ---- first-order polynomial reconstruction (Sec. III.B), FP64 --------
-  int64_t c10 = c, c01 = c, c11 = c;
-  double wx = 0.0, wy = 0.0;
-  bool hx = false, hy = false, hxy = false;
-  if (g.dim >= 1) {
-    const int nx = g.nx;
-    const int ci = g.dim == 2 ? c % nx : 0;
-    const int cj = g.dim == 2 ? c / nx : c;
-    auto ok = [&](int ii, int jj) -> bool {
-      if (ii < 0 || jj < 0 || ii >= g.nx || jj >= g.ny) return false;
-      return cs[CS_NBR_OK * M + (int64_t)jj * nx + ii] != 0.0;
-    };
-    // cell centre with explicitly rounded operations (no contraction)
-    const double yc = __dadd_rn(g.y0, __dmul_rn(cj + 0.5, g.dy));
-    const double dyv = (double)p.y[i] - yc;
-    const int sy = dyv >= 0.0 ? 1 : -1;
-    int ty = 0;
-    if (ok(ci, cj + sy)) ty = sy;
-    else if (ok(ci, cj - sy)) ty = -sy;
-    if (ty) { hy = true; wy = dyv / (ty * g.dy); c01 = (int64_t)(cj + ty) * nx + ci; }
-    if (g.dim == 2) {
-      const double xc = __dadd_rn(g.x0, __dmul_rn(ci + 0.5, g.dx));
-      const double dxv = (double)p.x[i] - xc;
-      const int sx = dxv >= 0.0 ? 1 : -1;
-      int tx = 0;
-      if (ok(ci + sx, cj)) tx = sx;
-      else if (ok(ci - sx, cj)) tx = -sx;
-      if (tx) { hx = true; wx = dxv / (tx * g.dx); c10 = (int64_t)cj * nx + ci + tx; }
-      if (tx && ty && ok(ci + tx, cj + ty)) { hxy = true; c11 = (int64_t)(cj + ty) * nx + ci + tx; }
-    }
+__device__ __forceinline__ Stencil particle_stencil(const GridP& g, int32_t bits, int32_t c,
+                                                    const PartP<S>& p, int64_t i) {
+  Stencil st;
+  st.c10 = st.c01 = st.c11 = c;
+  st.wx = st.wy = 0.0;
+  st.hx = st.hy = st.hxy = false;
+  if (g.dim == 0) return st;
+  const int nx = g.nx;
+  const int ci = g.dim == 2 ? c % nx : 0;
+  const int cj = g.dim == 2 ? c / nx : c;
+  // cell centre with explicitly rounded operations (no contraction)
+  const double dyv = (double)p.y[i] - __dadd_rn(g.y0, __dmul_rn(cj + 0.5, g.dy));
+  double dxv = 0.0;
+  int q = dyv >= 0.0 ? 2 : 0;
+  if (g.dim == 2) {
+    dxv = (double)p.x[i] - __dadd_rn(g.x0, __dmul_rn(ci + 0.5, g.dx));
+    q |= dxv >= 0.0 ? 1 : 0;
   }
-  auto interp = [&](int f) -> double {
-    const double* F = cs + (int64_t)f * M;
-    const double f00 = F[c];
-    double phi = f00;
-    const double f10 = F[c10], f01 = F[c01];
-    if (hx) phi += (f10 - f00) * wx;
-    if (hy) phi += (f01 - f00) * wy;
-    if (hxy) phi += (f00 - f10 - f01 + F[c11]) * wx * wy;
-    return phi;
-  };
-  T U[3], P[6];
-  double Pd[6], Tk[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) U[k] = (T)interp(CS_UX + k);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) { Pd[k] = interp(CS_PXX + k); P[k] = (T)Pd[k]; }
-  bool clamped = false;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    Tk[k] = interp(CS_TTR + k);
-    const double fl = 0.05 * cs[(CS_TTR + k) * M + c];
-    if (Tk[k] < fl) { Tk[k] = fl; clamped = true; }
-  }
-  uint32_t ev = clamped ? (1u << USP_CNT_INTERP_CLAMP) : 0u;
+  const int f = (bits >> (5 * q)) & 31;
+  const int tx = (f & 3) == 1 ? 1 : ((f & 3) == 2 ? -1 : 0);
+  const int ty = ((f >> 2) & 3) == 1 ? 1 : (((f >> 2) & 3) == 2 ? -1 : 0);
+  if (ty) { st.hy = true; st.wy = dyv / (ty * g.dy); st.c01 = (int64_t)(cj + ty) * nx + ci; }
+  if (tx) { st.hx = true; st.wx = dxv / (tx * g.dx); st.c10 = (int64_t)cj * nx + ci + tx; }
+  if ((f >> 4) & 1) { st.hxy = true; st.c11 = (int64_t)(cj + ty) * nx + ci + tx; }
+  return st;
+}
 
-  // ---- per-particle coefficients -----------------------------------------
+// first-order polynomial reconstruction from the FP64 planes
+__device__ __forceinline__ double interp_planes(const double* __restrict__ cs, int64_t M, int f,
+                                                int64_t c, const Stencil& st) {
+  const double* F = cs + (int64_t)f * M;
+  const double f00 = F[c];
+  double phi = f00;
+  const double f10 = F[st.c10], f01 = F[st.c01];
+  if (st.hx) phi += (f10 - f00) * st.wx;
+  if (st.hy) phi += (f01 - f00) * st.wy;
+  if (st.hxy) phi += (f00 - f10 - f01 + F[st.c11]) * st.wx * st.wy;
+  return phi;
+}
+
+__device__ __forceinline__ CellCoef coef_planes(const double* __restrict__ cs, int64_t M, int64_t c) {
   CellCoef cc;
   cc.a = cs[CS_A * M + c]; cc.b = cs[CS_B * M + c]; cc.al = cs[CS_ALPHA * M + c];
   cc.oma2 = cs[CS_OMA2 * M + c]; cc.nu = cs[CS_NU * M + c]; cc.r2 = cs[CS_R2 * M + c];
   cc.A2 = 2.0 * cs[CS_MUP * M + c]; cc.Pr = cs[CS_PR * M + c]; cc.dt = cs[CS_DT * M + c];
-  PartCoef<T> pc = particle_coef<T>((T)gas.R, (T)gas.theta, (T)Tk[0], (T)Tk[1], (T)Tk[2], P, cc);
-  if constexpr (sizeof(T) == 4) {
-    // The Cholesky test is a branch: near the positive-definiteness
-    // boundary it is taken in FP64, from the FP64 interpolated values.
-    if (pc.fallback || pc.margin < T(1e-4)) {
-      const PartCoef<double> pd = particle_coef<double>(gas.R, gas.theta, Tk[0], Tk[1], Tk[2], Pd, cc);
-#pragma unroll
-      for (int k = 0; k < 6; ++k) pc.L[k] = (T)pd.L[k];
-      pc.al = (T)pd.al; pc.oma2 = pd.oma2; pc.Trot_rel = (T)pd.Trot_rel; pc.mstar = (T)pd.mstar;
-      pc.skip = pd.skip; pc.fallback = pd.fallback; pc.nu_zero = pd.nu_zero;
-      pc.clamp_rot = pd.clamp_rot; pc.clamp_m = pd.clamp_m;
-    }
-  }
-  if (pc.fallback) ev |= 1u << USP_CNT_CHOL_FALLBACK;
-  if (pc.nu_zero) ev |= 1u << USP_CNT_NU_ZERO;
-  if (pc.skip) ev |= 1u << USP_CNT_TREL_SKIP;
-  if (pc.clamp_rot || pc.clamp_m) ev |= 1u << USP_CNT_TREL_CLAMP;
-  if (!pc.skip) {
-  const T R = (T)gas.R;
-  const T al = pc.al;
-  const T oma2 = (T)pc.oma2;
-  const double oma2d = pc.oma2;
-  const T* L = pc.L;
-  const T Trot_rel = pc.Trot_rel, mstar = pc.mstar;
+  return cc;
+}
 
-  // ---- draws: Philox blocks (pid, step, 0, 0) and (pid, step, 0, 1) ----
+// FP64 values at the particle: U, Pi, and the floored temperatures
+__device__ __forceinline__ bool fields_planes(const double* __restrict__ cs, int64_t M, int64_t c,
+                                              const Stencil& st, double U[3], double P[6],
+                                              double Tk[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) U[k] = interp_planes(cs, M, CS_UX + k, c, st);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) P[k] = interp_planes(cs, M, CS_PXX + k, c, st);
+  bool clamped = false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    Tk[k] = interp_planes(cs, M, CS_TTR + k, c, st);
+    const double fl = 0.05 * cs[(CS_TTR + k) * M + c];
+    if (Tk[k] < fl) { Tk[k] = fl; clamped = true; }
+  }
+  return clamped;
+}
+
+// Draws and the velocity (eq. update_ci), rotational (eq. update_erot) and
+// vibrational (eq. update_evib) updates of particle i.
+template <typename S, typename T>
+__device__ __forceinline__ void update_particle(const PartP<S>& p, int64_t i, const T U[3],
+                                                const PartCoef<T>& pc, T R, uint64_t seed,
+                                                uint32_t step, uint32_t* ev) {
   const uint32_t id = p.pid[i];
   const U4 w0 = philox(id, step, TAG_COLLIDE, 0u, seed);
   const U4 w1 = philox(id, step, TAG_COLLIDE, 1u, seed);
   T G1, G2, G3, G4;
   box_muller<T>(w0.w[0], w0.w[1], &G1, &G2);
   box_muller<T>(w0.w[2], w0.w[3], &G3, &G4);
-
-  // ---- velocity (eq. update_ci), rotation (eq. update_erot) -------------
+  const T al = pc.al, oma2 = (T)pc.oma2;
+  const T* L = pc.L;
   const T sq = sqrt(oma2);
   const T Cx = (T)p.cx[i] - U[0], Cy = (T)p.cy[i] - U[1], Cz = (T)p.cz[i] - U[2];
   p.cx[i] = (S)(U[0] + al * Cx + sq * (L[0] * G1));
   p.cy[i] = (S)(U[1] + al * Cy + sq * (L[1] * G1 + L[2] * G2));
   p.cz[i] = (S)(U[2] + al * Cz + sq * (L[3] * G1 + L[4] * G2 + L[5] * G3));
-  const T half = T(0.5) * R * Trot_rel * oma2;
+  const T half = T(0.5) * R * pc.Trot_rel * oma2;
   const T root = sqrt((T)p.erot[i]) * al + sqrt(half) * G4;
   p.erot[i] = (S)(half + root * root);
-
-  // ---- vibrational level (eq. update_evib), decisions in FP64 ----------
+  // discrete decisions in FP64
   const int I = p.vib[i];
-  const double ms = (double)mstar;
-  const double pNB = 1.0 / (1.0 + ms * oma2d);
-  double pB = (1.0 + ms) * oma2d;
-  if (pB > 1.0) { pB = 1.0; ev |= 1u << USP_CNT_PB_CLAMP; }
+  const double ms = (double)pc.mstar;
+  const double pNB = 1.0 / (1.0 + ms * pc.oma2);
+  double pB = (1.0 + ms) * pc.oma2;
+  if (pB > 1.0) { pB = 1.0; *ev |= 1u << USP_CNT_PB_CLAMP; }
   int nI = I + sample_nb(u01d(w1.w[0]), I + 1, pNB) - sample_b(u01d(w1.w[1]), I, pB);
-  if (nI > VIB_MAX) { nI = VIB_MAX; ev |= 1u << USP_CNT_VIB_SAT; }
+  if (nI > VIB_MAX) { nI = VIB_MAX; *ev |= 1u << USP_CNT_VIB_SAT; }
   p.vib[i] = (uint8_t)nI;
+}
+
+__device__ __forceinline__ void note_coef_events(const PartCoef<float>& a, uint32_t* ev) {
+  if (a.fallback) *ev |= 1u << USP_CNT_CHOL_FALLBACK;
+  if (a.nu_zero) *ev |= 1u << USP_CNT_NU_ZERO;
+  if (a.skip) *ev |= 1u << USP_CNT_TREL_SKIP;
+  if (a.clamp_rot || a.clamp_m) *ev |= 1u << USP_CNT_TREL_CLAMP;
+}
+__device__ __forceinline__ void note_coef_events(const PartCoef<double>& a, uint32_t* ev) {
+  if (a.fallback) *ev |= 1u << USP_CNT_CHOL_FALLBACK;
+  if (a.nu_zero) *ev |= 1u << USP_CNT_NU_ZERO;
+  if (a.skip) *ev |= 1u << USP_CNT_TREL_SKIP;
+  if (a.clamp_rot || a.clamp_m) *ev |= 1u << USP_CNT_TREL_CLAMP;
+}
+
+// FP32 state: fields from the packed cell records (16-byte loads), FP32
+// reconstruction and coefficient chain; near the positive-definiteness
+// boundary of the diffusion tensor the chain is redone in FP64 from the
+// FP64 planes, so that branch is taken in FP64.
+__global__ __launch_bounds__(PART_BLOCK) void k_collide_f32(GridP g, GasP gas,
+                                                            const double* __restrict__ cs,
+                                                            PartP<float> p, uint64_t seed,
+                                                            uint32_t step, int64_t* counters) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.count[0]) return;
+  const int32_t c = p.cell[i];
+  if (c < 0) return;
+  const int64_t M = g.M;
+  const CellRec* __restrict__ rec = cell_records(cs, M);
+  const float4* r4 = (const float4*)(rec + c);
+  const float4 q4 = r4[3];  // fl[3], stencil
+  const float4 q5 = r4[4];  // a, b, al, nu
+  const CellRec& own = rec[c];
+  if (own.collide == 0) return;
+  const Stencil st = particle_stencil<float>(g, __float_as_int(q4.w), c, p, i);
+  // fields of the stencil cells
+  float f00[12], f10[12], f01[12], f11[12];
+  auto load12 = [&](int64_t cc, float* o) {
+    const float4* v = (const float4*)(rec + cc);
+    const float4 a0 = v[0], a1 = v[1], a2 = v[2];
+    o[0] = a0.x; o[1] = a0.y; o[2] = a0.z; o[3] = a0.w; o[4] = a1.x; o[5] = a1.y;
+    o[6] = a1.z; o[7] = a1.w; o[8] = a2.x; o[9] = a2.y; o[10] = a2.z; o[11] = a2.w;
+  };
+  load12(c, f00);
+  load12(st.c10, f10);
+  load12(st.c01, f01);
+  load12(st.c11, f11);
+  const float wx = (float)st.wx, wy = (float)st.wy, wxy = (float)(st.wx * st.wy);
+  float v12[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    float phi = f00[k];
+    if (st.hx) phi += (f10[k] - f00[k]) * wx;
+    if (st.hy) phi += (f01[k] - f00[k]) * wy;
+    if (st.hxy) phi += (f00[k] - f10[k] - f01[k] + f11[k]) * wxy;
+    v12[k] = phi;
   }
+  float U[3] = {v12[0], v12[1], v12[2]};
+  float Tk[3] = {v12[3], v12[4], v12[5]};
+  float P[6] = {v12[6], v12[7], v12[8], v12[9], v12[10], v12[11]};
+  const float fl[3] = {q4.x, q4.y, q4.z};
+  uint32_t ev = 0;
+  bool clamped = false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (Tk[k] < fl[k]) { Tk[k] = fl[k]; clamped = true; }
+  if (clamped) ev |= 1u << USP_CNT_INTERP_CLAMP;
+  CellCoef cc;
+  cc.a = q5.x; cc.b = q5.y; cc.al = q5.z; cc.nu = q5.w;
+  cc.oma2 = own.oma2; cc.r2 = own.r2; cc.A2 = own.A2; cc.Pr = own.Pr; cc.dt = own.dt;
+  PartCoef<float> pc = particle_coef<float>((float)gas.R, (float)gas.theta, Tk[0], Tk[1], Tk[2], P, cc);
+  if (pc.fallback || pc.margin < 1e-4f) {
+    double Ud[3], Pd[6], Td[3];
+    fields_planes(cs, M, c, st, Ud, Pd, Td);
+    const CellCoef cd = coef_planes(cs, M, c);
+    const PartCoef<double> pd = particle_coef<double>(gas.R, gas.theta, Td[0], Td[1], Td[2], Pd, cd);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) pc.L[k] = (float)pd.L[k];
+    pc.al = (float)pd.al; pc.oma2 = pd.oma2; pc.Trot_rel = (float)pd.Trot_rel;
+    pc.mstar = (float)pd.mstar;
+    pc.skip = pd.skip; pc.fallback = pd.fallback; pc.nu_zero = pd.nu_zero;
+    pc.clamp_rot = pd.clamp_rot; pc.clamp_m = pd.clamp_m;
+  }
+  note_coef_events(pc, &ev);
+  if (!pc.skip) update_particle<float, float>(p, i, U, pc, (float)gas.R, seed, step, &ev);
+  flush_events(counters, ev);
+}
+
+// FP64 state: fields and coefficients from the FP64 planes.
+__global__ __launch_bounds__(PART_BLOCK) void k_collide_f64(GridP g, GasP gas,
+                                                            const double* __restrict__ cs,
+                                                            PartP<double> p, uint64_t seed,
+                                                            uint32_t step, int64_t* counters) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.count[0]) return;
+  const int32_t c = p.cell[i];
+  if (c < 0) return;
+  const int64_t M = g.M;
+  if (cs[CS_COLLIDE * M + c] == 0.0) return;
+  const Stencil st = particle_stencil<double>(g, cell_records(cs, M)[c].stencil, c, p, i);
+  double U[3], P[6], Tk[3];
+  uint32_t ev = fields_planes(cs, M, c, st, U, P, Tk) ? (1u << USP_CNT_INTERP_CLAMP) : 0u;
+  const CellCoef cc = coef_planes(cs, M, c);
+  const PartCoef<double> pc = particle_coef<double>(gas.R, gas.theta, Tk[0], Tk[1], Tk[2], P, cc);
+  note_coef_events(pc, &ev);
+  if (!pc.skip) update_particle<double, double>(p, i, U, pc, gas.R, seed, step, &ev);
   flush_events(counters, ev);
 }
 
@@ -498,8 +585,12 @@ hipError_t launch_collide(const GridP& g, const GasP& gas, const double* cs, con
                           const PartP<S>& p, uint64_t seed, uint64_t step, int64_t* counters,
                           hipStream_t st) {
   (void)offsets;
-  k_collide<S><<<cdiv(p.capacity, PART_BLOCK), PART_BLOCK, 0, st>>>(g, gas, cs, p, seed,
-                                                                    (uint32_t)step, counters);
+  if constexpr (sizeof(S) == 4)
+    k_collide_f32<<<cdiv(p.capacity, PART_BLOCK), PART_BLOCK, 0, st>>>(g, gas, cs, p, seed,
+                                                                      (uint32_t)step, counters);
+  else
+    k_collide_f64<<<cdiv(p.capacity, PART_BLOCK), PART_BLOCK, 0, st>>>(g, gas, cs, p, seed,
+                                                                      (uint32_t)step, counters);
   return hipGetLastError();
 }
 

@@ -24,6 +24,26 @@ enum Cs {
 };
 static_assert(NCS == USP_NCS, "cell-state plane count");
 
+// Packed per-cell record for the particle update, stored after the FP64
+// cell-state planes: the reconstructed fields and temperature floors in
+// FP32, the quadrant stencils, and the cell coefficients.
+struct alignas(16) CellRec {
+  float U[3], T[3], P[6];  // interpolated fields (16-byte loads: 0..2)
+  float fl[3];             // temperature floors, 5% of the cell values
+  int32_t stencil;         // 4 quadrants x 5 bits: tx (2), ty (2), cross (1)
+  float a, b, al, nu;
+  double oma2, r2, A2, Pr, dt;
+  int32_t collide, pad;
+};
+static_assert(sizeof(CellRec) == 128, "cell record size");
+
+// bytes of the cell-state buffer: FP64 planes, then one CellRec per cell
+__host__ __device__ inline size_t cellstate_bytes(int64_t M) { return (size_t)M * (NCS * sizeof(double) + sizeof(CellRec)); }
+__host__ __device__ inline CellRec* cell_records(double* cs, int64_t M) { return (CellRec*)(cs + (size_t)NCS * M); }
+__host__ __device__ inline const CellRec* cell_records(const double* cs, int64_t M) {
+  return (const CellRec*)(cs + (size_t)NCS * M);
+}
+
 constexpr int VIB_MAX = 255;
 constexpr int MAX_BOUNCE = 8;
 constexpr int NB_KMAX = 512;

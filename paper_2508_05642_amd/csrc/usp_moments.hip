@@ -124,6 +124,55 @@ __global__ void k_reconstruct(GridP g, GasP gas, const double* mom, double dt,
   }
 #pragma unroll
   for (int k = 0; k < NCS; ++k) cs[k * M + c] = v[k];
+  CellRec r;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    r.U[k] = (float)v[CS_UX + k];
+    r.T[k] = (float)v[CS_TTR + k];
+    r.fl[k] = (float)(0.05 * v[CS_TTR + k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) r.P[k] = (float)v[CS_PXX + k];
+  r.stencil = 0;
+  r.a = (float)v[CS_A]; r.b = (float)v[CS_B]; r.al = (float)v[CS_ALPHA]; r.nu = (float)v[CS_NU];
+  r.oma2 = v[CS_OMA2]; r.r2 = v[CS_R2]; r.A2 = 2.0 * v[CS_MUP]; r.Pr = v[CS_PR]; r.dt = v[CS_DT];
+  r.collide = v[CS_COLLIDE] != 0.0 ? 1 : 0;
+  r.pad = 0;
+  cell_records(cs, M)[c] = r;
+}
+
+// Quadrant stencils of the reconstruction (Sec. III.B), one thread per
+// cell, after the cell state: quadrant q = (x >= x_i) + 2 (y >= y_j) keeps
+// the x neighbour direction tx and y direction ty (toward the quadrant,
+// else the opposite side, else none) and whether the diagonal cell
+// completes the cross term.  Field: 2 bits tx (1: +1, 2: -1), 2 bits ty,
+// 1 bit cross, 5 bits per quadrant.
+__global__ void k_stencil(GridP g, double* cs) {
+  const int64_t M = g.M;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= M || g.dim == 0) return;
+  const int nx = g.nx;
+  const int ci = g.dim == 2 ? (int)(c % nx) : 0;
+  const int cj = g.dim == 2 ? (int)(c / nx) : (int)c;
+  auto ok = [&](int ii, int jj) -> bool {
+    if (ii < 0 || jj < 0 || ii >= g.nx || jj >= g.ny) return false;
+    return cs[CS_NBR_OK * M + (int64_t)jj * nx + ii] != 0.0;
+  };
+  int32_t bits = 0;
+  for (int q = 0; q < 4; ++q) {
+    const int sx = (q & 1) ? 1 : -1, sy = (q & 2) ? 1 : -1;
+    int ty = 0, tx = 0;
+    if (ok(ci, cj + sy)) ty = sy;
+    else if (ok(ci, cj - sy)) ty = -sy;
+    if (g.dim == 2) {
+      if (ok(ci + sx, cj)) tx = sx;
+      else if (ok(ci - sx, cj)) tx = -sx;
+    }
+    const int cross = (tx && ty && ok(ci + tx, cj + ty)) ? 1 : 0;
+    const int f = (tx == 1 ? 1 : tx == -1 ? 2 : 0) | ((ty == 1 ? 1 : ty == -1 ? 2 : 0) << 2) | (cross << 4);
+    bits |= f << (5 * q);
+  }
+  cell_records(cs, M)[c].stencil = bits;
 }
 
 template <typename S>
@@ -136,6 +185,7 @@ hipError_t launch_moments(const GridP& g, const PartP<S>& p, const int64_t* offs
 hipError_t launch_reconstruct(const GridP& g, const GasP& gas, const double* mom, double dt,
                               const double* dt_cell, double* cs, int64_t* counters, hipStream_t st) {
   k_reconstruct<<<cdiv(g.M, 128), 128, 0, st>>>(g, gas, mom, dt, dt_cell, cs, counters);
+  k_stencil<<<cdiv(g.M, 256), 256, 0, st>>>(g, cs);
   return hipGetLastError();
 }
 

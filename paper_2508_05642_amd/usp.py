@@ -72,6 +72,8 @@ def lib():
         L.usp_version.restype = C.c_char_p
         L.usp_workspace_bytes.argtypes = [vp, i64]
         L.usp_workspace_bytes.restype = sz
+        L.usp_cellstate_bytes.argtypes = [vp]
+        L.usp_cellstate_bytes.restype = sz
         L.usp_bin.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp, vp]
         L.usp_moments.argtypes = [vp, vp, vp, vp, vp]
         L.usp_reconstruct.argtypes = [vp, vp, vp, d, vp, vp, vp, vp]
@@ -87,7 +89,7 @@ def lib():
 
 
 EXPORTED = ["usp_status_str", "usp_mom_name", "usp_cs_name", "usp_counter_name", "usp_version",
-            "usp_workspace_bytes", "usp_bin", "usp_moments", "usp_reconstruct", "usp_collide",
+            "usp_workspace_bytes", "usp_cellstate_bytes", "usp_bin", "usp_moments", "usp_reconstruct", "usp_collide",
             "usp_conserve", "usp_advect", "usp_step"]
 
 
@@ -201,7 +203,8 @@ class DeviceState:
         self.load(parts)
         self.offsets = torch.zeros(self.M + 1, dtype=torch.int64, device=self.dev)
         self.mom = torch.zeros(NMOM * self.M, dtype=torch.float64, device=self.dev)
-        self.cs = torch.zeros(NCS * self.M, dtype=torch.float64, device=self.dev)
+        csb = lib().usp_cellstate_bytes(C.byref(self.grid))
+        self.cs = torch.zeros(csb // 8, dtype=torch.float64, device=self.dev)
         wsb = lib().usp_workspace_bytes(C.byref(self.grid), cap)
         if wsb == 0:
             raise UspError("usp_workspace_bytes rejected the grid/capacity")
@@ -269,7 +272,7 @@ class DeviceState:
         return self.mom.view(NMOM, self.M).cpu().numpy()
 
     def cellstate(self):
-        return self.cs.view(NCS, self.M).cpu().numpy()
+        return self.cs[: NCS * self.M].view(NCS, self.M).cpu().numpy()
 
     def cnt(self):
         return dict(zip(names("cnt"), self.counters.cpu().tolist()))

@@ -369,7 +369,7 @@ def test_conserve_vibrational_picks_exact(f32):
     target = (SI + delta + 0.25) * R * th / np.array(counts)
     cs_o = orc.cs.reshape(oracle.NCS, M)
     cs_o[k] = target
-    gcs = gpu.cs.view(usp.NCS, M)
+    gcs = gpu.cs[: usp.NCS * M].view(usp.NCS, M)
     gcs[k] = torch.as_tensor(target, dtype=torch.float64, device=gcs.device)
     gpu.conserve(9); orc.conserve(9)
     a, b = gpu.state(), orc.state()

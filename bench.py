@@ -4,9 +4,9 @@
 Workload: Mach-10 N2 over a cylinder (half body), 600 x 300 cells of 1 mm,
 ~36.1M particles at start (FP32 particle state, FP64 cell accumulators),
 VHS gas with Parker / Millikan-White collision numbers, dt = 1.25e-7 s.
-A step is bin -> moments -> cell state -> collide -> conserve -> advect
-(with injection), each a call of the C ABI on torch's current stream so
-HIP events bracket every phase.  `value` is particle-steps/s over exactly
+A step is bin -> moments -> cell state -> the fused particle phase
+(collide + conserve + advect with injection, one pass), each a call of the
+C ABI on torch's current stream so HIP events bracket every phase.  `value` is particle-steps/s over exactly
 --steps timed steps (inputs resident in HBM), after --warmup steps.
 
 Also reported: the HBM roofline of the dominant kernel (algorithmic bytes
@@ -25,12 +25,11 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "particle-steps/s (full USP-FPM step) + HBM GB/s; adjoint/forward time ratio"
-PHASES = ("bin", "moments", "reconstruct", "collide", "conserve", "advect")
-# phases that are one kernel launch (bin is a pipeline of nine kernels, the
-# largest of which is far below k_collide; advect adds small injection
-# kernels)
-PHASE_KERNEL = {"collide": "k_collide", "conserve": "k_conserve", "moments": "k_moments",
-                "reconstruct": "k_reconstruct"}
+PHASES = ("bin", "moments", "reconstruct", "update")
+# the kernel that dominates each phase (bin is a pipeline of small kernels
+# around two passes; update adds two tiny tile-index kernels before and the
+# injection kernels after k_update)
+PHASE_KERNEL = {"update": "k_update", "moments": "k_moments", "reconstruct": "k_reconstruct"}
 
 
 def algorithmic_bytes(phase, n, M):
@@ -44,15 +43,15 @@ def algorithmic_bytes(phase, n, M):
         # read cx, cy, cz, erot, vib
         "moments": 17,
         "reconstruct": 0,
-        # read x, y, cx, cy, cz, erot, vib, cell, pid; write cx, cy, cz, erot, vib
-        "collide": 33 + 17,
-        # read cx, cy, cz, erot, vib; write cx, cy, cz, erot
-        "conserve": 17 + 16,
-        # read x, y, cx, cy, cz, erot, vib, cell, pid; write x, y, c, erot, vib, cell
-        "advect": 33 + 29,
+        # read x, y, cx, cy, cz, erot, vib, cell, pid; write x, y, cx, cy, cz,
+        # erot, vib, cell
+        "update": 33 + 29,
     }[phase]
-    per_cell = {"bin": 4 + 8, "moments": 21 * 8, "reconstruct": (21 + 35) * 8,
-                "collide": 35 * 8, "conserve": 8 * 8, "advect": 0}[phase]
+    # per cell: offsets 8; moments 21 planes; cell state reads 21 planes and
+    # writes 35 planes + a 128-byte record; update reads the record and 9
+    # conservation planes
+    per_cell = {"bin": 4 + 8, "moments": 21 * 8 + 8, "reconstruct": (21 + 35) * 8 + 128,
+                "update": 128 + 9 * 8 + 8}[phase]
     return per_particle * n + per_cell * M
 
 
@@ -87,12 +86,8 @@ def run_gpu(args):
         if ev: ev[2].record()
         st.do_reconstruct()
         if ev: ev[3].record()
-        st.collide(s)
+        st.update(s)
         if ev: ev[4].record()
-        st.conserve(s)
-        if ev: ev[5].record()
-        st.advect(s)
-        if ev: ev[6].record()
 
     for _ in range(args.warmup):
         one_step(step)
@@ -100,7 +95,7 @@ def run_gpu(args):
     torch.cuda.synchronize()
     log(f"{args.warmup} warmup steps done")
     K = args.steps
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(K)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(PHASES) + 1)] for _ in range(K)]
     nlog = torch.zeros(K, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -175,8 +175,8 @@ const char* usp_version(void);
    invalid). */
 size_t usp_cellstate_bytes(const usp_grid* grid);
 
-/* Bytes of scratch the caller passes as `ws` to usp_bin, usp_advect and
-   usp_step for this grid and particle capacity. */
+/* Bytes of scratch the caller passes as `ws` to usp_bin, usp_advect,
+   usp_update and usp_step for this grid and particle capacity. */
 size_t usp_workspace_bytes(const usp_grid* grid, int64_t capacity);
 
 /* Bin (the per-cell organisation the collision step of Sec. IV.D loops
@@ -243,10 +243,26 @@ usp_status usp_advect(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc
                       usp_particles* p, uint64_t seed, uint64_t step, void* ws, size_t ws_bytes,
                       int64_t* counters, void* stream);
 
-/* nsteps full steps (bin, moments, reconstruct, collide, conserve, advect)
-   starting at step index `step`.  p and p_alt are the two particle buffers;
+/* The particle phase of a step in one pass: usp_collide, usp_conserve and
+   usp_advect (with injection) fused, bit-identical to calling the three in
+   that order (Secs. III.A-III.B, IV.C and the flow chart of Sec. IV.D).
+   p must be binned with `offsets` (count[0] == offsets[M], as usp_bin
+   leaves it); particles past offsets[M] are not updated.  cs from
+   usp_reconstruct of the same state.  bc and dt > 0 are required for
+   dim >= 1; for dim 0 bc may be NULL and dt is unused (no flight).  A
+   workgroup owns the cells whose first particle lies in one window of 1024
+   (FP32) or 512 (FP64) particle slots; tile boundaries go to `ws`.
+   Errors: USP_EINVAL for a null or inconsistent argument or a short ws. */
+usp_status usp_update(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
+                      const double* cs, const int64_t* offsets, usp_particles* p,
+                      void* ws, size_t ws_bytes, uint64_t seed, uint64_t step,
+                      int64_t* counters, void* stream);
+
+/* nsteps full steps (bin, moments, reconstruct, then the fused particle
+   phase of usp_update) starting at step index `step`.  p and p_alt are the two particle buffers;
    on return *p describes the buffer that holds the state (the two structs
-   are swapped as needed).  offsets, mom, cs as above (they describe the last
+   are swapped as needed); p_alt->capacity >= p->capacity and ws is sized
+   for p_alt->capacity.  offsets, mom, cs as above (they describe the last
    step's pre-collision state on return). */
 usp_status usp_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
                     const double* dt_cell, usp_particles* p, usp_particles* p_alt,

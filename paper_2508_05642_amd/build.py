@@ -13,6 +13,10 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 instructions (v_pk_*_f32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no hoisting of constant materialisation out of loops: the particle
+    # loops inline long math routines whose constants would otherwise stay
+    # live in VGPRs for the whole loop
+    "-mllvm", "-disable-machine-licm",
 ]
 
 

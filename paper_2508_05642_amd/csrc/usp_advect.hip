@@ -3,41 +3,11 @@
 // Flight arithmetic is FP64 for both state precisions (a few dozen FP64
 // operations per particle); the result is rounded to the stored precision
 // and kept inside the domain.
-#include "usp_device.h"
+#include "usp_particle.h"
 
 namespace usp {
 
 constexpr int ADV_BLOCK = 256;
-
-// Wall re-emission draws for bounce `b`: blocks (2b, 2b+1) of the wall
-// stream.  Normal speed from the flux-weighted half-range Maxwellian,
-// tangential components Gaussian, exponential rotational energy and a
-// Boltzmann level, all at the wall temperature.
-__device__ __forceinline__ void wall_draw(const GasP& gas, double Tw, uint64_t seed, uint32_t pid,
-                                          uint32_t step, int b, double* cn, double* ta, double* tb,
-                                          double* er, int* lv) {
-  const U4 w0 = philox(pid, step, TAG_WALL, (uint32_t)(2 * b), seed);
-  const U4 w1 = philox(pid, step, TAG_WALL, (uint32_t)(2 * b + 1), seed);
-  const double R = gas.R, sig = sqrt(R * Tw);
-  *cn = sqrt(-2.0 * R * Tw * log(u01d(w0.w[0])));
-  const double r = sqrt(-2.0 * log(u01d(w0.w[1])));
-  double sn, cs;
-  sincospi(2.0 * u01d(w0.w[2]), &sn, &cs);
-  *ta = sig * r * cs;
-  *tb = sig * r * sn;
-  *er = -R * Tw * log(u01d(w0.w[3]));
-  const double l = floor(log(u01d(w1.w[0])) / (-gas.theta / Tw));
-  *lv = l > (double)VIB_MAX ? VIB_MAX : (int)l;
-}
-
-template <typename S>
-__device__ __forceinline__ S settle(double v, double lo, double hi) {
-  S vs = (S)v;
-  const S los = (S)lo, his = (S)hi;
-  if (vs >= his) vs = nextafter(his, (S)(-INFINITY));
-  if (vs < los) vs = los;
-  return vs;
-}
 
 template <typename S>
 __global__ __launch_bounds__(ADV_BLOCK) void k_advect(GridP g, GasP gas, BcP bc, double dt,
@@ -46,109 +16,8 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_advect(GridP g, GasP gas, BcP bc,
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.count[0]) return;
   if (p.cell[i] < 0) return;
-  // body-force kick, rounded to storage as the state is, then the flight
-  double cx = (double)(S)((double)p.cx[i] + bc.g[0] * dt);
-  double cy = (double)(S)((double)p.cy[i] + bc.g[1] * dt);
-  double cz = (double)(S)((double)p.cz[i] + bc.g[2] * dt);
-  double x = g.dim == 2 ? (double)p.x[i] : 0.0, y = (double)p.y[i];
-  double er = (double)p.erot[i];
-  int lv = p.vib[i];
-  const double xlo = (double)(S)g.x0, xhi = (double)edge<S>(g.x0, g.dx, g.nx);
-  const double ylo = (double)(S)g.y0, yhi = (double)edge<S>(g.y0, g.dy, g.ny);
-  double t = dt;
-  int bounces = 0, events = 0;
-  bool deleted = false;
-  uint32_t ev = 0;
-  const uint32_t id = p.pid[i];
-  for (;;) {
-    double th = INFINITY;
-    int side = -1;
-    if (g.dim == 2) {
-      if (cx < 0.0 && x + cx * t < xlo) { const double tt = (xlo - x) / cx; if (tt < th) { th = tt; side = USP_SIDE_XLO; } }
-      if (cx > 0.0 && x + cx * t >= xhi) { const double tt = (xhi - x) / cx; if (tt < th) { th = tt; side = USP_SIDE_XHI; } }
-    }
-    if (cy < 0.0 && y + cy * t < ylo) { const double tt = (ylo - y) / cy; if (tt < th) { th = tt; side = USP_SIDE_YLO; } }
-    if (cy > 0.0 && y + cy * t >= yhi) { const double tt = (yhi - y) / cy; if (tt < th) { th = tt; side = USP_SIDE_YHI; } }
-    if (g.dim == 2 && bc.cyl) {
-      const double px = x - bc.cyl_xc, py = y - bc.cyl_yc;
-      const double A = cx * cx + cy * cy, B = px * cx + py * cy;
-      const double C = px * px + py * py - bc.cyl_r * bc.cyl_r;
-      if (B < 0.0 && A > 0.0) {
-        double tt = -1.0;
-        if (C <= 0.0) tt = 0.0;
-        else {
-          const double disc = B * B - A * C;
-          if (disc > 0.0) tt = (-B - sqrt(disc)) / A;
-        }
-        if (tt >= 0.0 && tt <= t && tt < th) { th = tt; side = 4; }
-      }
-    }
-    if (side < 0) { x += cx * t; y += cy * t; break; }
-    if (th < 0.0) th = 0.0;
-    if (th > t) th = t;
-    x += cx * th;
-    y += cy * th;
-    t -= th;
-    if (++events > 4 * MAX_BOUNCE) { ev |= 1u << USP_CNT_BOUNCE_LIMIT; break; }
-    const int kind = side == 4 ? USP_BC_DIFFUSE : bc.kind[side];
-    if (side == USP_SIDE_XLO) x = xlo;
-    if (side == USP_SIDE_XHI) x = xhi;
-    if (side == USP_SIDE_YLO) y = ylo;
-    if (side == USP_SIDE_YHI) y = yhi;
-    if (kind == USP_BC_FREESTREAM || kind == USP_BC_OUTFLOW) { deleted = true; break; }
-    if (kind == USP_BC_PERIODIC) {
-      if (side == USP_SIDE_XLO) x = xhi;
-      else if (side == USP_SIDE_XHI) x = xlo;
-      else if (side == USP_SIDE_YLO) y = yhi;
-      else y = ylo;
-      continue;
-    }
-    if (kind == USP_BC_SPECULAR) {
-      if (side == USP_SIDE_XLO || side == USP_SIDE_XHI) cx = -cx; else cy = -cy;
-      continue;
-    }
-    if (bounces >= MAX_BOUNCE) { ev |= 1u << USP_CNT_BOUNCE_LIMIT; break; }
-    double cn, ta, tb, ner;
-    int nlv;
-    const double Tw = side == 4 ? bc.cyl_Tw : bc.Tw[side];
-    wall_draw(gas, Tw, seed, id, step, bounces, &cn, &ta, &tb, &ner, &nlv);
-    ++bounces;
-    er = ner;
-    lv = nlv;
-    if (side == USP_SIDE_YLO || side == USP_SIDE_YHI) {
-      cy = side == USP_SIDE_YLO ? cn : -cn;
-      cx = ta; cz = tb;
-    } else if (side == USP_SIDE_XLO || side == USP_SIDE_XHI) {
-      cx = side == USP_SIDE_XLO ? cn : -cn;
-      cy = ta; cz = tb;
-    } else {
-      double nxv = x - bc.cyl_xc, nyv = y - bc.cyl_yc;
-      const double nn = sqrt(nxv * nxv + nyv * nyv);
-      nxv /= nn;
-      nyv /= nn;
-      x = bc.cyl_xc + bc.cyl_r * nxv;
-      y = bc.cyl_yc + bc.cyl_r * nyv;
-      cx = cn * nxv - ta * nyv;
-      cy = cn * nyv + ta * nxv;
-      cz = tb;
-    }
-  }
-  if (deleted) {
-    p.cell[i] = -1;
-    ev |= 1u << USP_CNT_DELETED;
-  } else {
-    S xs = S(0);
-    if (g.dim == 2) { xs = settle<S>(x, xlo, xhi); p.x[i] = xs; }
-    const S ys = settle<S>(y, ylo, yhi);
-    p.y[i] = ys;
-    p.cx[i] = (S)cx;
-    p.cy[i] = (S)cy;
-    p.cz[i] = (S)cz;
-    p.erot[i] = (S)er;
-    p.vib[i] = (uint8_t)lv;
-    p.cell[i] = cell_of<S>(g, xs, ys);
-  }
-  flush_events(counters, ev, USP_CNT_WALL_HITS, bounces);
+  advect_one<S>(g, gas, bc, dt, p, i, p.cx[i], p.cy[i], p.cz[i], p.erot[i], p.vib[i], seed, step,
+                counters);
 }
 
 // ---- free-stream injection ------------------------------------------------
@@ -346,13 +215,12 @@ __global__ void k_inject_finish(int64_t* count, const int64_t* misc) {
 
 int n_faces(const GridP& g) { return g.dim == 2 ? 2 * (g.nx + g.ny) : 0; }
 
+// Free-stream injection of one step: per-face counts, their scan (with the
+// capacity check) and the new particles appended after the current ones.
 template <typename S>
-hipError_t launch_advect(const GridP& g, const GasP& gas, const BcP& bc, double dt,
+hipError_t launch_inject(const GridP& g, const GasP& gas, const BcP& bc, double dt,
                          const PartP<S>& p, uint64_t seed, uint64_t step, char* ws,
                          const WsLayout& L, int64_t* counters, hipStream_t st) {
-  if (g.dim == 0) return hipSuccess;
-  k_advect<S><<<cdiv(p.capacity, ADV_BLOCK), ADV_BLOCK, 0, st>>>(g, gas, bc, dt, p, seed,
-                                                                (uint32_t)step, counters);
   const int64_t nf = n_faces(g);
   bool any = false;
   int64_t bound = 0;
@@ -375,6 +243,24 @@ hipError_t launch_advect(const GridP& g, const GasP& gas, const BcP& bc, double 
   return hipGetLastError();
 }
 
+template <typename S>
+hipError_t launch_advect(const GridP& g, const GasP& gas, const BcP& bc, double dt,
+                         const PartP<S>& p, uint64_t seed, uint64_t step, char* ws,
+                         const WsLayout& L, int64_t* counters, hipStream_t st) {
+  if (g.dim == 0) return hipSuccess;
+  k_advect<S><<<cdiv(p.capacity, ADV_BLOCK), ADV_BLOCK, 0, st>>>(g, gas, bc, dt, p, seed,
+                                                                (uint32_t)step, counters);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_inject<S>(g, gas, bc, dt, p, seed, step, ws, L, counters, st);
+}
+
+template hipError_t launch_inject<float>(const GridP&, const GasP&, const BcP&, double,
+                                         const PartP<float>&, uint64_t, uint64_t, char*,
+                                         const WsLayout&, int64_t*, hipStream_t);
+template hipError_t launch_inject<double>(const GridP&, const GasP&, const BcP&, double,
+                                          const PartP<double>&, uint64_t, uint64_t, char*,
+                                          const WsLayout&, int64_t*, hipStream_t);
 template hipError_t launch_advect<float>(const GridP&, const GasP&, const BcP&, double,
                                          const PartP<float>&, uint64_t, uint64_t, char*,
                                          const WsLayout&, int64_t*, hipStream_t);

@@ -73,6 +73,7 @@ WsLayout ws_layout(int64_t M, int64_t capacity, int nfaces) {
   L.face_cnt = o; o = align256(o + sizeof(int32_t) * (size_t)(nfaces + 1));
   L.face_off = o; o = align256(o + sizeof(int64_t) * (size_t)(nfaces + 1));
   L.misc = o; o = align256(o + sizeof(int64_t) * 8);
+  L.tiles = o; o = align256(o + sizeof(int32_t) * (size_t)(cdiv(capacity, UPDATE_TILE_F64) + 2));
   L.total = o;
   return L;
 }
@@ -130,7 +131,9 @@ usp_status do_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, d
   const GridP g = make_grid(grid);
   const GasP gp = make_gas(gas);
   const BcP bp = make_bc(bc);
-  const WsLayout L = ws_layout(g.M, p->capacity, n_faces(g));
+  // the two buffers swap every step: lay the scratch out for the larger
+  const int64_t cap = p->capacity > p_alt->capacity ? p->capacity : p_alt->capacity;
+  const WsLayout L = ws_layout(g.M, cap, n_faces(g));
   char* w = (char*)ws;
   for (int32_t s = 0; s < nsteps; ++s) {
     const uint64_t sn = step + (uint64_t)s;
@@ -145,9 +148,8 @@ usp_status do_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, d
     const PartP<S> q = make_parts<S>(p);
     if ((e = launch_moments<S>(g, q, offsets, mom, st)) != hipSuccess) return USP_EDEVICE;
     if ((e = launch_reconstruct(g, gp, mom, dt, dt_cell, cs, counters, st)) != hipSuccess) return USP_EDEVICE;
-    if ((e = launch_collide<S>(g, gp, cs, offsets, q, seed, sn, counters, st)) != hipSuccess) return USP_EDEVICE;
-    if ((e = launch_conserve<S>(g, gp, cs, offsets, q, seed, sn, counters, st)) != hipSuccess) return USP_EDEVICE;
-    if ((e = launch_advect<S>(g, gp, bp, dt, q, seed, sn, w, L, counters, st)) != hipSuccess) return USP_EDEVICE;
+    if ((e = launch_update<S>(g, gp, bp, dt, cs, offsets, q, seed, sn, w, L, counters, st)) != hipSuccess)
+      return USP_EDEVICE;
   }
   return USP_OK;
 }
@@ -271,6 +273,28 @@ usp_status usp_advect(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc
                         : launch_advect<double>(g, gp, bp, dt, make_parts<double>(p), seed, step, (char*)ws, L, counters, st));
 }
 
+usp_status usp_update(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
+                      const double* cs, const int64_t* offsets, usp_particles* p, void* ws,
+                      size_t ws_bytes, uint64_t seed, uint64_t step, int64_t* counters,
+                      void* stream) {
+  if (!grid_ok(grid) || !gas_ok(gas) || !parts_ok(p, grid) || !cs || !offsets || !ws)
+    return USP_EINVAL;
+  if (grid->dim >= 1 && (!bc || !(dt > 0.0))) return USP_EINVAL;
+  if (ws_bytes < usp_workspace_bytes(grid, p->capacity)) return USP_EINVAL;
+  const GridP g = make_grid(grid);
+  const GasP gp = make_gas(gas);
+  const BcP bp = make_bc(bc);
+  if (g.dim == 2) {
+    for (int k = 0; k < 4; ++k)
+      if (bp.kind[k] == USP_BC_FREESTREAM && !(bp.fs_T > 0.0 && bp.depth > 0.0)) return USP_EINVAL;
+  }
+  const WsLayout L = ws_layout(g.M, p->capacity, n_faces(g));
+  hipStream_t st = (hipStream_t)stream;
+  return hip_status(p->prec == USP_F32
+                        ? launch_update<float>(g, gp, bp, dt, cs, offsets, make_parts<float>(p), seed, step, (char*)ws, L, counters, st)
+                        : launch_update<double>(g, gp, bp, dt, cs, offsets, make_parts<double>(p), seed, step, (char*)ws, L, counters, st));
+}
+
 usp_status usp_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
                     const double* dt_cell, usp_particles* p, usp_particles* p_alt,
                     int64_t* offsets, double* mom, double* cs, void* ws, size_t ws_bytes,
@@ -281,7 +305,7 @@ usp_status usp_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, 
   if (p->prec != p_alt->prec || p_alt->capacity < p->capacity || p->cx == p_alt->cx) return USP_EINVAL;
   if (grid->dim >= 1 && (!bc || !(dt > 0.0))) return USP_EINVAL;
   if (!dt_cell && !(dt > 0.0)) return USP_EINVAL;
-  if (ws_bytes < usp_workspace_bytes(grid, p->capacity)) return USP_EINVAL;
+  if (ws_bytes < usp_workspace_bytes(grid, p_alt->capacity)) return USP_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   return p->prec == USP_F32
              ? do_step<float>(grid, gas, bc, dt, dt_cell, p, p_alt, offsets, mom, cs, ws, seed, step, nsteps, counters, st)

@@ -96,8 +96,11 @@ template <typename S> PartP<S> make_parts(const usp_particles* p);
 // workspace layout (byte offsets into the caller's scratch buffer)
 struct WsLayout {
   size_t key, perm, blocksums, t9, cell_i32, old_off, far_off, far, face_cnt, face_off, misc,
-      total;
+      tiles, total;
 };
+// particle slots per tile of the fused particle phase (FP32 / FP64 state)
+constexpr int UPDATE_TILE_F32 = 1024;
+constexpr int UPDATE_TILE_F64 = 512;
 WsLayout ws_layout(int64_t M, int64_t capacity, int nfaces);
 int n_faces(const GridP& g);
 
@@ -123,6 +126,16 @@ template <typename S>
 hipError_t launch_advect(const GridP& g, const GasP& gas, const BcP& bc, double dt,
                          const PartP<S>& p, uint64_t seed, uint64_t step, char* ws,
                          const WsLayout& L, int64_t* counters, hipStream_t st);
+
+template <typename S>
+hipError_t launch_inject(const GridP& g, const GasP& gas, const BcP& bc, double dt,
+                         const PartP<S>& p, uint64_t seed, uint64_t step, char* ws,
+                         const WsLayout& L, int64_t* counters, hipStream_t st);
+template <typename S>
+hipError_t launch_update(const GridP& g, const GasP& gas, const BcP& bc, double dt,
+                         const double* cs, const int64_t* offsets, const PartP<S>& p,
+                         uint64_t seed, uint64_t step, char* ws, const WsLayout& L,
+                         int64_t* counters, hipStream_t st);
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

@@ -1,0 +1,739 @@
+// usp_particle.h -- per-particle and per-cell device functions of the
+// USP-FPM update: the particle update (Secs. III.A-III.B), the
+// conservation scheme (Sec. IV.C) and the free flight with boundaries.
+// Shared by the separate phase kernels and the fused update kernel, so
+// both produce the same bits.
+//
+// Precision: the particle update runs in the state precision S (float for
+// FP32 states, double for FP64 states); reconstruction weights, all cell
+// quantities and the discrete vibrational decisions are FP64.
+#pragma once
+#include "usp_device.h"
+
+namespace usp {
+
+// Negative-binomial NB(r, p) (failures before the r-th success) and
+// binomial B(n, p) draws by sequential CDF inversion: the smallest k with
+// u < F(k).  The pmf recurrences and the order of every FP64 operation are
+// fixed (no contraction) so that decisions are reproducible.
+__device__ __forceinline__ int sample_nb(double u, int r, double p) {
+#pragma clang fp contract(off)
+  const double q = 1.0 - p;
+  double pk = 1.0;
+  for (int i = 0; i < r; ++i) pk = pk * p;
+  double F = pk;
+  int k = 0;
+  while (u >= F && k < NB_KMAX) {
+    double t = q * (double)(r + k);
+    t = t / (double)(k + 1);
+    pk = pk * t;
+    F = F + pk;
+    k = k + 1;
+  }
+  return k;
+}
+
+__device__ __forceinline__ int sample_b(double u, int n, double p) {
+#pragma clang fp contract(off)
+  if (n <= 0 || p <= 0.0) return 0;
+  if (p >= 1.0) return n;
+  const double q = 1.0 - p;
+  double pk = 1.0;
+  for (int i = 0; i < n; ++i) pk = pk * q;
+  const double ratio = p / q;
+  double F = pk;
+  int k = 0;
+  while (u >= F && k < n) {
+    double t = ratio * (double)(n - k);
+    t = t / (double)(k + 1);
+    pk = pk * t;
+    F = F + pk;
+    k = k + 1;
+  }
+  return k;
+}
+
+// smallest and largest eigenvalue of a symmetric 3x3 (trigonometric form)
+template <typename T>
+__device__ __forceinline__ void eig_minmax(const T P[6], T* lmin, T* lmax) {
+  const T p1 = P[3] * P[3] + P[4] * P[4] + P[5] * P[5];
+  if (p1 == T(0)) {
+    *lmin = fmin(P[0], fmin(P[1], P[2]));
+    *lmax = fmax(P[0], fmax(P[1], P[2]));
+    return;
+  }
+  const T q = (P[0] + P[1] + P[2]) / T(3);
+  const T a = P[0] - q, b = P[1] - q, c = P[2] - q;
+  const T p2 = a * a + b * b + c * c + T(2) * p1;
+  const T p = sqrt(p2 / T(6));
+  const T ip = T(1) / p;
+  const T b11 = a * ip, b22 = b * ip, b33 = c * ip, b12 = P[3] * ip, b13 = P[4] * ip,
+          b23 = P[5] * ip;
+  const T det = b11 * (b22 * b33 - b23 * b23) - b12 * (b12 * b33 - b23 * b13) +
+                b13 * (b12 * b23 - b22 * b13);
+  T r = det / T(2);
+  r = fmin(T(1), fmax(T(-1), r));
+  const T phi = acos(r) / T(3);
+  *lmax = q + T(2) * p * cos(phi);
+  *lmin = q + T(2) * p * cos(phi + T(2.0943951023931954923));
+}
+
+// Cell-level coefficients (FP64, from the cell state).
+struct CellCoef {
+  double a, b, al, oma2, nu, r2, A2, Pr, dt;
+};
+
+// Per-particle coefficients of the update.
+template <typename T>
+struct PartCoef {
+  T L[6];          // Cholesky factor of Lambda = tau D_tr
+  T al;            // alpha_tr = alpha_rot = alpha_vib
+  double oma2;     // 1 - alpha^2 (FP64: it feeds the discrete decisions)
+  T Trot_rel, mstar;
+  T margin;        // smallest relative pivot of the accepted factor
+  bool skip, fallback, nu_zero, clamp_rot, clamp_m;
+};
+
+// Cholesky with the smallest relative pivot min(d2/S_yy, d3/S_zz) returned.
+template <typename T>
+__device__ __forceinline__ bool chol3m(const T S[6], T L[6], T* margin) {
+  if (!(S[0] > T(0))) return false;
+  const T l11 = sqrt(S[0]);
+  const T l21 = S[3] / l11, l31 = S[4] / l11;
+  const T d2 = S[1] - l21 * l21;
+  if (!(d2 > T(0))) return false;
+  const T l22 = sqrt(d2);
+  const T l32 = (S[5] - l31 * l21) / l22;
+  const T d3 = S[2] - l31 * l31 - l32 * l32;
+  if (!(d3 > T(0))) return false;
+  L[0] = l11; L[1] = l21; L[2] = l22; L[3] = l31; L[4] = l32; L[5] = sqrt(d3);
+  *margin = fmin(d2 / S[1], d3 / S[2]);
+  return true;
+}
+
+// The chain of Secs. III.A.1-III.A.3 for one particle: rescaled
+// temperature and gamma coefficients from the interpolated temperatures,
+// relaxation temperatures (eqs. T_tr_USP, T_rot_USP, T_vib_USP), the
+// diffusion tensor (eq. D_tr) and its Cholesky test, and on failure the nu
+// clamp and alpha refit (eqs. nu_USP_positivity, alpha_USP_positivity_1..4).
+template <typename T>
+__device__ PartCoef<T> particle_coef(T R, T Th, T Ttr, T Trot, T Tvib, const T P[6],
+                                     const CellCoef& cc) {
+  PartCoef<T> r;
+  r.skip = r.fallback = r.nu_zero = r.clamp_rot = r.clamp_m = false;
+  r.margin = T(1);
+  const T a = (T)cc.a, b = (T)cc.b;
+  T al = (T)cc.al;
+  double oma2d = cc.oma2;
+  T nu = (T)cc.nu;
+  const T Tc = tcheck<T>(Th, Ttr, Trot, Tvib, a, b);
+  const T cb = cbar_R<T>(Th, Tc, Tvib);
+  const T D = T(1.5) + a + b * cb;
+  const T g1 = T(3) * a / D, g2 = T(3) * b * cb / D, g3 = T(2) * a * b * cb / D;
+  const T Xtr = g1 * (Ttr - Trot) + g2 * (Ttr - Tvib);
+  const T Xrot = g1 * (Ttr - Trot) - g3 * (Trot - Tvib);
+  const T Xvib = g2 * (Ttr - Tvib) + g3 * (Trot - Tvib);
+  const T mvib = mlevel<T>(Th, Tvib);
+  T oma2 = (T)oma2d;
+  T Ttr_rel = Ttr - Xtr / (T(1.5) * oma2);
+  T Trot_rel = Trot + Xrot / oma2;
+  T mstar = mvib + Xvib / (oma2 * Th);
+  const T RT = R * Ttr;
+  T Lam[6];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) Lam[k] = R * Ttr_rel + nu * (P[k] - RT);
+#pragma unroll
+  for (int k = 3; k < 6; ++k) Lam[k] = nu * P[k];
+  bool ok = chol3m<T>(Lam, r.L, &r.margin);
+  if (!ok) {
+    r.fallback = true;
+    if (!(Ttr_rel > T(0))) {
+      r.skip = true;
+      return r;
+    }
+    T lmin, lmax;
+    eig_minmax<T>(P, &lmin, &lmax);
+    const T RTr = R * Ttr_rel;
+    const T shrink = T(1) - T(1.0 / 1048576.0);
+    if (nu <= T(0)) {
+      if (lmax > RT) nu = fmax(nu, -RTr / (lmax - RT) * shrink);
+    } else {
+      if (lmin < RT) nu = fmin(nu, RTr / (RT - lmin) * shrink);
+    }
+    double a2 = ((double)nu - cc.r2) / ((double)nu - 1.0);
+    a2 = fmin(1.0, fmax(0.0, a2));
+    const double ap = sqrt(a2), am = -ap;
+    const double Prp = cc.A2 * (1.0 - ap * ap * ap) / (cc.dt * (1.0 + ap * ap * ap));
+    const double Prm = cc.A2 * (1.0 - am * am * am) / (cc.dt * (1.0 + am * am * am));
+    al = (T)((fabs(Prm - cc.Pr) < fabs(Prp - cc.Pr)) ? am : ap);
+    oma2d = 1.0 - a2;
+    if (!(oma2d > 0.0)) {
+      r.skip = true;
+      return r;
+    }
+    oma2 = (T)oma2d;
+    Ttr_rel = Ttr - Xtr / (T(1.5) * oma2);
+    Trot_rel = Trot + Xrot / oma2;
+    mstar = mvib + Xvib / (oma2 * Th);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Lam[k] = R * Ttr_rel + nu * (P[k] - RT);
+#pragma unroll
+    for (int k = 3; k < 6; ++k) Lam[k] = nu * P[k];
+    ok = chol3m<T>(Lam, r.L, &r.margin);
+    if (!ok) {
+      r.nu_zero = true;
+      if (Ttr_rel > T(0)) {
+        const T s0 = sqrt(R * Ttr_rel);
+        r.L[0] = s0; r.L[1] = T(0); r.L[2] = s0; r.L[3] = T(0); r.L[4] = T(0); r.L[5] = s0;
+      } else {
+        r.skip = true;
+        return r;
+      }
+    }
+  }
+  if (Trot_rel < T(0)) { Trot_rel = T(0); r.clamp_rot = true; }
+  if (mstar < T(0)) { mstar = T(0); r.clamp_m = true; }
+  r.al = al;
+  r.oma2 = oma2d;
+  r.Trot_rel = Trot_rel;
+  r.mstar = mstar;
+  return r;
+}
+
+// Stencil of a particle: the quadrant of its position in its cell selects
+// one of the four precomputed stencils (see k_stencil); weights are the
+// offsets from the cell centre over the signed spacing.
+struct Stencil {
+  int64_t c10, c01, c11;
+  double wx, wy;
+  bool hx, hy, hxy;
+};
+
+template <typename S>
+__device__ __forceinline__ Stencil particle_stencil(const GridP& g, int32_t bits, int32_t c,
+                                                    const PartP<S>& p, int64_t i) {
+  Stencil st;
+  st.c10 = st.c01 = st.c11 = c;
+  st.wx = st.wy = 0.0;
+  st.hx = st.hy = st.hxy = false;
+  if (g.dim == 0) return st;
+  const int nx = g.nx;
+  const int ci = g.dim == 2 ? c % nx : 0;
+  const int cj = g.dim == 2 ? c / nx : c;
+  // cell centre with explicitly rounded operations (no contraction)
+  const double dyv = (double)p.y[i] - __dadd_rn(g.y0, __dmul_rn(cj + 0.5, g.dy));
+  double dxv = 0.0;
+  int q = dyv >= 0.0 ? 2 : 0;
+  if (g.dim == 2) {
+    dxv = (double)p.x[i] - __dadd_rn(g.x0, __dmul_rn(ci + 0.5, g.dx));
+    q |= dxv >= 0.0 ? 1 : 0;
+  }
+  const int f = (bits >> (5 * q)) & 31;
+  const int tx = (f & 3) == 1 ? 1 : ((f & 3) == 2 ? -1 : 0);
+  const int ty = ((f >> 2) & 3) == 1 ? 1 : (((f >> 2) & 3) == 2 ? -1 : 0);
+  if (ty) { st.hy = true; st.wy = dyv / (ty * g.dy); st.c01 = (int64_t)(cj + ty) * nx + ci; }
+  if (tx) { st.hx = true; st.wx = dxv / (tx * g.dx); st.c10 = (int64_t)cj * nx + ci + tx; }
+  if ((f >> 4) & 1) { st.hxy = true; st.c11 = (int64_t)(cj + ty) * nx + ci + tx; }
+  return st;
+}
+
+// first-order polynomial reconstruction from the FP64 planes
+__device__ __forceinline__ double interp_planes(const double* __restrict__ cs, int64_t M, int f,
+                                                int64_t c, const Stencil& st) {
+  const double* F = cs + (int64_t)f * M;
+  const double f00 = F[c];
+  double phi = f00;
+  const double f10 = F[st.c10], f01 = F[st.c01];
+  if (st.hx) phi += (f10 - f00) * st.wx;
+  if (st.hy) phi += (f01 - f00) * st.wy;
+  if (st.hxy) phi += (f00 - f10 - f01 + F[st.c11]) * st.wx * st.wy;
+  return phi;
+}
+
+__device__ __forceinline__ CellCoef coef_planes(const double* __restrict__ cs, int64_t M, int64_t c) {
+  CellCoef cc;
+  cc.a = cs[CS_A * M + c]; cc.b = cs[CS_B * M + c]; cc.al = cs[CS_ALPHA * M + c];
+  cc.oma2 = cs[CS_OMA2 * M + c]; cc.nu = cs[CS_NU * M + c]; cc.r2 = cs[CS_R2 * M + c];
+  cc.A2 = 2.0 * cs[CS_MUP * M + c]; cc.Pr = cs[CS_PR * M + c]; cc.dt = cs[CS_DT * M + c];
+  return cc;
+}
+
+// FP64 values at the particle: U, Pi, and the floored temperatures
+__device__ __forceinline__ bool fields_planes(const double* __restrict__ cs, int64_t M, int64_t c,
+                                              const Stencil& st, double U[3], double P[6],
+                                              double Tk[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) U[k] = interp_planes(cs, M, CS_UX + k, c, st);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) P[k] = interp_planes(cs, M, CS_PXX + k, c, st);
+  bool clamped = false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    Tk[k] = interp_planes(cs, M, CS_TTR + k, c, st);
+    const double fl = 0.05 * cs[(CS_TTR + k) * M + c];
+    if (Tk[k] < fl) { Tk[k] = fl; clamped = true; }
+  }
+  return clamped;
+}
+
+// New values of one particle (changed == false: the particle keeps its
+// state because its cell or the particle itself is skipped).
+template <typename S>
+struct PartNew {
+  S cx, cy, cz, erot;
+  int vib;
+  bool changed;
+};
+
+// Draws and the velocity (eq. update_ci), rotational (eq. update_erot) and
+// vibrational (eq. update_evib) updates of particle i.
+template <typename S, typename T>
+__device__ __forceinline__ void update_particle(const PartP<S>& p, int64_t i, const T U[3],
+                                                const PartCoef<T>& pc, T R, uint64_t seed,
+                                                uint32_t step, uint32_t* ev, PartNew<S>* o) {
+  const uint32_t id = p.pid[i];
+  const U4 w0 = philox(id, step, TAG_COLLIDE, 0u, seed);
+  const U4 w1 = philox(id, step, TAG_COLLIDE, 1u, seed);
+  T G1, G2, G3, G4;
+  box_muller<T>(w0.w[0], w0.w[1], &G1, &G2);
+  box_muller<T>(w0.w[2], w0.w[3], &G3, &G4);
+  const T al = pc.al, oma2 = (T)pc.oma2;
+  const T* L = pc.L;
+  const T sq = sqrt(oma2);
+  const T Cx = (T)p.cx[i] - U[0], Cy = (T)p.cy[i] - U[1], Cz = (T)p.cz[i] - U[2];
+  o->cx = (S)(U[0] + al * Cx + sq * (L[0] * G1));
+  o->cy = (S)(U[1] + al * Cy + sq * (L[1] * G1 + L[2] * G2));
+  o->cz = (S)(U[2] + al * Cz + sq * (L[3] * G1 + L[4] * G2 + L[5] * G3));
+  const T half = T(0.5) * R * pc.Trot_rel * oma2;
+  const T root = sqrt((T)p.erot[i]) * al + sqrt(half) * G4;
+  o->erot = (S)(half + root * root);
+  // discrete decisions in FP64
+  const int I = p.vib[i];
+  const double ms = (double)pc.mstar;
+  const double pNB = 1.0 / (1.0 + ms * pc.oma2);
+  double pB = (1.0 + ms) * pc.oma2;
+  if (pB > 1.0) { pB = 1.0; *ev |= 1u << USP_CNT_PB_CLAMP; }
+  int nI = I + sample_nb(u01d(w1.w[0]), I + 1, pNB) - sample_b(u01d(w1.w[1]), I, pB);
+  if (nI > VIB_MAX) { nI = VIB_MAX; *ev |= 1u << USP_CNT_VIB_SAT; }
+  o->vib = nI;
+  o->changed = true;
+}
+
+__device__ __forceinline__ void note_coef_events(const PartCoef<float>& a, uint32_t* ev) {
+  if (a.fallback) *ev |= 1u << USP_CNT_CHOL_FALLBACK;
+  if (a.nu_zero) *ev |= 1u << USP_CNT_NU_ZERO;
+  if (a.skip) *ev |= 1u << USP_CNT_TREL_SKIP;
+  if (a.clamp_rot || a.clamp_m) *ev |= 1u << USP_CNT_TREL_CLAMP;
+}
+__device__ __forceinline__ void note_coef_events(const PartCoef<double>& a, uint32_t* ev) {
+  if (a.fallback) *ev |= 1u << USP_CNT_CHOL_FALLBACK;
+  if (a.nu_zero) *ev |= 1u << USP_CNT_NU_ZERO;
+  if (a.skip) *ev |= 1u << USP_CNT_TREL_SKIP;
+  if (a.clamp_rot || a.clamp_m) *ev |= 1u << USP_CNT_TREL_CLAMP;
+}
+
+// Particle update of particle i in cell c (Secs. III.A-III.B).
+// FP32 state: fields from the packed cell records (16-byte loads), FP32
+// reconstruction and coefficient chain; near the positive-definiteness
+// boundary of the diffusion tensor the chain is redone in FP64 from the
+// FP64 planes, so that branch is taken in FP64.
+__device__ __forceinline__ PartNew<float> collide_one(const GridP& g, const GasP& gas,
+                                                     const double* __restrict__ cs,
+                                                     const PartP<float>& p, int64_t i, int32_t c,
+                                                     uint64_t seed, uint32_t step, uint32_t* evp) {
+  PartNew<float> o;
+  o.changed = false;
+  const int64_t M = g.M;
+  const CellRec* __restrict__ rec = cell_records(cs, M);
+  const float4* r4 = (const float4*)(rec + c);
+  const float4 q4 = r4[3];  // fl[3], stencil
+  const float4 q5 = r4[4];  // a, b, al, nu
+  const CellRec& own = rec[c];
+  if (own.collide == 0) return o;
+  const Stencil st = particle_stencil<float>(g, __float_as_int(q4.w), c, p, i);
+  // fields of the stencil cells
+  float f00[12], f10[12], f01[12], f11[12];
+  auto load12 = [&](int64_t cc, float* o) {
+    const float4* v = (const float4*)(rec + cc);
+    const float4 a0 = v[0], a1 = v[1], a2 = v[2];
+    o[0] = a0.x; o[1] = a0.y; o[2] = a0.z; o[3] = a0.w; o[4] = a1.x; o[5] = a1.y;
+    o[6] = a1.z; o[7] = a1.w; o[8] = a2.x; o[9] = a2.y; o[10] = a2.z; o[11] = a2.w;
+  };
+  load12(c, f00);
+  load12(st.c10, f10);
+  load12(st.c01, f01);
+  load12(st.c11, f11);
+  const float wx = (float)st.wx, wy = (float)st.wy, wxy = (float)(st.wx * st.wy);
+  float v12[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    float phi = f00[k];
+    if (st.hx) phi += (f10[k] - f00[k]) * wx;
+    if (st.hy) phi += (f01[k] - f00[k]) * wy;
+    if (st.hxy) phi += (f00[k] - f10[k] - f01[k] + f11[k]) * wxy;
+    v12[k] = phi;
+  }
+  float U[3] = {v12[0], v12[1], v12[2]};
+  float Tk[3] = {v12[3], v12[4], v12[5]};
+  float P[6] = {v12[6], v12[7], v12[8], v12[9], v12[10], v12[11]};
+  const float fl[3] = {q4.x, q4.y, q4.z};
+  uint32_t ev = 0;
+  bool clamped = false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (Tk[k] < fl[k]) { Tk[k] = fl[k]; clamped = true; }
+  if (clamped) ev |= 1u << USP_CNT_INTERP_CLAMP;
+  CellCoef cc;
+  cc.a = q5.x; cc.b = q5.y; cc.al = q5.z; cc.nu = q5.w;
+  cc.oma2 = own.oma2; cc.r2 = own.r2; cc.A2 = own.A2; cc.Pr = own.Pr; cc.dt = own.dt;
+  PartCoef<float> pc = particle_coef<float>((float)gas.R, (float)gas.theta, Tk[0], Tk[1], Tk[2], P, cc);
+  if (pc.fallback || pc.margin < 1e-4f) {
+    double Ud[3], Pd[6], Td[3];
+    fields_planes(cs, M, c, st, Ud, Pd, Td);
+    const CellCoef cd = coef_planes(cs, M, c);
+    const PartCoef<double> pd = particle_coef<double>(gas.R, gas.theta, Td[0], Td[1], Td[2], Pd, cd);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) pc.L[k] = (float)pd.L[k];
+    pc.al = (float)pd.al; pc.oma2 = pd.oma2; pc.Trot_rel = (float)pd.Trot_rel;
+    pc.mstar = (float)pd.mstar;
+    pc.skip = pd.skip; pc.fallback = pd.fallback; pc.nu_zero = pd.nu_zero;
+    pc.clamp_rot = pd.clamp_rot; pc.clamp_m = pd.clamp_m;
+  }
+  note_coef_events(pc, &ev);
+  if (!pc.skip) update_particle<float, float>(p, i, U, pc, (float)gas.R, seed, step, &ev, &o);
+  *evp |= ev;
+  return o;
+}
+
+// FP64 state: fields and coefficients from the FP64 planes.
+__device__ __forceinline__ PartNew<double> collide_one(const GridP& g, const GasP& gas,
+                                                      const double* __restrict__ cs,
+                                                      const PartP<double>& p, int64_t i,
+                                                      int32_t c, uint64_t seed, uint32_t step,
+                                                      uint32_t* evp) {
+  PartNew<double> o;
+  o.changed = false;
+  const int64_t M = g.M;
+  if (cs[CS_COLLIDE * M + c] == 0.0) return o;
+  const Stencil st = particle_stencil<double>(g, cell_records(cs, M)[c].stencil, c, p, i);
+  double U[3], P[6], Tk[3];
+  uint32_t ev = fields_planes(cs, M, c, st, U, P, Tk) ? (1u << USP_CNT_INTERP_CLAMP) : 0u;
+  const CellCoef cc = coef_planes(cs, M, c);
+  const PartCoef<double> pc = particle_coef<double>(gas.R, gas.theta, Tk[0], Tk[1], Tk[2], P, cc);
+  note_coef_events(pc, &ev);
+  if (!pc.skip) update_particle<double, double>(p, i, U, pc, gas.R, seed, step, &ev, &o);
+  *evp |= ev;
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// Conservation (Sec. IV.C): one wave per cell.  The serial vibrational
+// picks run on an LDS copy of the cell's levels (cells up to CONS_LDS
+// particles; larger cells pick in global memory).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// The vibrational correction of Sec. IV.C, |I_delta| single-level moves on
+// particles picked uniformly at random (draw j: counter (cell, step, 2, j/4),
+// word j%4; a decrement that hits level 0, or an increment that hits the top
+// level, is redrawn).  The draws are sequential by definition; here a wave
+// evaluates 64 consecutive draws at once and reproduces the sequential
+// outcome exactly: draw j on particle k is accepted iff the level of k,
+// after the accepted earlier draws on k, still allows the move, i.e. iff
+// dup < L (decrement) or L + dup < VIB_MAX (increment), dup being the number
+// of earlier draws of the chunk on k; only the first |I_delta| accepted draws
+// are applied.  Gives up after 64 N draws or when a decrement is impossible.
+// Returns 1 if any level changed; *SI is updated.  Called by a whole wave.
+__device__ int wave_picks(uint8_t* lv, int64_t N, int64_t Id, int64_t* SI_io, uint32_t c,
+                          uint32_t step, uint64_t seed, int64_t* counters) {
+  const int lane = threadIdx.x & 63;
+  const int64_t maxatt = 64 * N;
+  int64_t att = 0, SI = *SI_io;
+  uint32_t jbase = 1;
+  int moved = 0;
+  const double Nd = (double)N;
+  while (Id != 0) {
+    if (att >= maxatt || (Id < 0 && SI == 0)) {
+      if (lane == 0) count_event(counters, USP_CNT_PICK_FAIL);
+      break;
+    }
+    const bool valid = att + lane < maxatt;
+    const uint32_t j = jbase + (uint32_t)lane;
+    const U4 w = philox(c, step, TAG_CONSERVE, j >> 2, seed);
+    const uint32_t wj = (j & 3) == 0 ? w.w[0] : (j & 3) == 1 ? w.w[1] : (j & 3) == 2 ? w.w[2] : w.w[3];
+    int64_t k = (int64_t)floor(u01d(wj) * Nd);
+    if (k >= N) k = N - 1;
+    const int kk = (int)k;
+    int dup = 0;
+    for (int l = 0; l < 64; ++l) {
+      const int kl = __builtin_amdgcn_readlane(kk, l);
+      dup += (l < lane && kl == kk) ? 1 : 0;
+    }
+    const int L = valid ? (int)lv[k] : 0;
+    const bool acc = valid && (Id > 0 ? (L + dup < VIB_MAX) : (dup < L));
+    const uint64_t accm = __ballot(acc);
+    const int64_t need = Id > 0 ? Id : -Id;
+    const int nacc = __popcll(accm);
+    uint64_t applied;
+    int consumed;
+    if (nacc >= need) {
+      // lane of the need-th accepted draw: the last draw made
+      uint64_t m = accm;
+      for (int64_t t = 1; t < need; ++t) m &= m - 1;
+      const int cut = __ffsll((long long)m) - 1;
+      applied = accm & (cut == 63 ? ~0ull : ((2ull << cut) - 1ull));
+      consumed = cut + 1;
+    } else {
+      applied = accm;
+      consumed = (int)__popcll(__ballot(valid));
+    }
+    const bool app = (applied >> lane) & 1ull;
+    // the first applied lane of each particle writes the combined move
+    int cnt = 0;
+    bool first = app;
+    for (int l = 0; l < 64; ++l) {
+      const int kl = __builtin_amdgcn_readlane(kk, l);
+      if (((applied >> l) & 1ull) && kl == kk) {
+        ++cnt;
+        if (l < lane) first = false;
+      }
+    }
+    const int napp = (int)__popcll(applied);
+    wave_sync_lds();
+    if (first) lv[k] = (uint8_t)(Id > 0 ? L + cnt : L - cnt);
+    wave_sync_lds();
+    if (napp) moved = 1;
+    SI += Id > 0 ? napp : -napp;
+    Id += Id > 0 ? -napp : napp;
+    att += consumed;
+    jbase += (uint32_t)consumed;
+  }
+  *SI_io = SI;
+  return moved;
+}
+
+// Conservation of one cell by one wave (Sec. IV.C).  The cell's particles
+// are [o0, o1); their post-collision values sit at vx[i - base] etc.
+// (LDS or global).  The vibrational picks run on `lv`, the cell's levels
+// (LDS or global); if `copy` is set, vx's levels are first copied to lv and
+// copied back after the picks.
+template <typename S, typename PS>
+__device__ __forceinline__ void conserve_cell(const GasP& gas, const double* __restrict__ cs,
+                                              int64_t M, int64_t c, int64_t o0, int64_t o1,
+                                              PS* vcx, PS* vcy, PS* vcz, PS* verot, uint8_t* vvib,
+                                              int64_t base, uint8_t* lv, bool copy,
+                                              uint64_t seed, uint32_t step, int64_t* counters) {
+  const int lane = threadIdx.x & 63;
+  const int64_t N = o1 - o0;
+  const double Un[3] = {cs[CS_UX * M + c], cs[CS_UY * M + c], cs[CS_UZ * M + c]};
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t i = o0 + lane; i < o1; i += 64) {
+    const int64_t j = i - base;
+    const double d0 = (double)vcx[j] - Un[0], d1 = (double)vcy[j] - Un[1],
+                 d2 = (double)vcz[j] - Un[2];
+    s[0] += d0; s[1] += d1; s[2] += d2;
+    s[3] += d0 * d0 + d1 * d1 + d2 * d2;
+    s[4] += (double)verot[j];
+    const uint8_t v = vvib[j];
+    s[5] += (double)v;
+    if (copy) lv[i - o0] = v;
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s[k] = wave_sum(s[k]);
+  wave_sync_lds();
+  const double Nd = (double)N;
+  const double m1[3] = {s[0] / Nd, s[1] / Nd, s[2] / Nd};
+  const double RTh = gas.R * gas.theta;
+  // (i) vibrational levels: I_delta = floor(N (e_target - e*)/(R theta) + U),
+  // then |I_delta| single-level moves on randomly picked particles
+  int64_t SI = (int64_t)s[5];
+  const double X = Nd * cs[CS_EVIB_NEW * M + c] / RTh - (double)SI;
+  const int64_t Id0 = (int64_t)floor(X + u01d(philox((uint32_t)c, step, TAG_CONSERVE, 0u, seed).w[0]));
+  const int moved = wave_picks(lv, N, Id0, &SI, (uint32_t)c, step, seed, counters);
+  double frot = 0.0, sc = 0.0;
+  if (lane == 0) {
+    const double etr_s = 0.5 * (s[3] / Nd - (m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2]));
+    // (ii) rotational scaling to the cell target
+    const double erot_s = s[4] / Nd, erot_t = cs[CS_EROT_NEW * M + c];
+    double erot_a = erot_s;
+    if (erot_s > 0.0 && erot_t > 0.0) {
+      frot = erot_t / erot_s;
+      erot_a = erot_t;
+    } else {
+      count_event(counters, USP_CNT_CONS_SKIP);
+    }
+    // (iii) velocity scaling about U*, toward U^n (momentum and energy)
+    const double evib_a = (double)SI * RTh / Nd;
+    const double E0 = cs[CS_ETR * M + c] + cs[CS_EROT * M + c] + cs[CS_EVIB * M + c];
+    const double s2 = (E0 - erot_a - evib_a) / etr_s;
+    if (etr_s > 0.0 && s2 > 0.0) sc = sqrt(s2);
+    else count_event(counters, USP_CNT_CONS_SKIP);
+  }
+  frot = __shfl(frot, 0, 64);
+  sc = __shfl(sc, 0, 64);
+  wave_sync_lds();
+  const double Us0 = Un[0] + m1[0], Us1 = Un[1] + m1[1], Us2 = Un[2] + m1[2];
+  for (int64_t i = o0 + lane; i < o1; i += 64) {
+    const int64_t j = i - base;
+    if (copy && moved) vvib[j] = lv[i - o0];
+    if (frot > 0.0) verot[j] = (S)((double)verot[j] * frot);
+    if (sc > 0.0) {
+      vcx[j] = (S)(Un[0] + sc * ((double)vcx[j] - Us0));
+      vcy[j] = (S)(Un[1] + sc * ((double)vcy[j] - Us1));
+      vcz[j] = (S)(Un[2] + sc * ((double)vcz[j] - Us2));
+    }
+  }
+}
+
+// Wall re-emission draws for bounce `b`: blocks (2b, 2b+1) of the wall
+// stream.  Normal speed from the flux-weighted half-range Maxwellian,
+// tangential components Gaussian, exponential rotational energy and a
+// Boltzmann level, all at the wall temperature.
+__device__ __forceinline__ void wall_draw(const GasP& gas, double Tw, uint64_t seed, uint32_t pid,
+                                          uint32_t step, int b, double* cn, double* ta, double* tb,
+                                          double* er, int* lv) {
+  const U4 w0 = philox(pid, step, TAG_WALL, (uint32_t)(2 * b), seed);
+  const U4 w1 = philox(pid, step, TAG_WALL, (uint32_t)(2 * b + 1), seed);
+  const double R = gas.R, sig = sqrt(R * Tw);
+  *cn = sqrt(-2.0 * R * Tw * log(u01d(w0.w[0])));
+  const double r = sqrt(-2.0 * log(u01d(w0.w[1])));
+  double sn, cs;
+  sincospi(2.0 * u01d(w0.w[2]), &sn, &cs);
+  *ta = sig * r * cs;
+  *tb = sig * r * sn;
+  *er = -R * Tw * log(u01d(w0.w[3]));
+  const double l = floor(log(u01d(w1.w[0])) / (-gas.theta / Tw));
+  *lv = l > (double)VIB_MAX ? VIB_MAX : (int)l;
+}
+
+template <typename S>
+__device__ __forceinline__ S settle(double v, double lo, double hi) {
+  S vs = (S)v;
+  const S los = (S)lo, his = (S)hi;
+  if (vs >= his) vs = nextafter(his, (S)(-INFINITY));
+  if (vs < los) vs = los;
+  return vs;
+}
+
+// Free flight of particle i over dt with its post-collision values (cx0,
+// cy0, cz0, er0, lv0): body-force kick, then straight flight with
+// periodic, specular, outflow/free-stream and diffuse-wall boundaries (wall
+// re-emission continues the remaining flight time).  Writes position,
+// velocity, rot/vib state and the new cell (or -1 on deletion) to p.
+template <typename S>
+__device__ __forceinline__ void advect_one(const GridP& g, const GasP& gas, const BcP& bc,
+                                           double dt, const PartP<S>& p, int64_t i, S cx0, S cy0,
+                                           S cz0, S er0, int lv0, uint64_t seed, uint32_t step,
+                                           int64_t* counters) {
+  // body-force kick, rounded to storage as the state is, then the flight
+  double cx = (double)(S)((double)cx0 + bc.g[0] * dt);
+  double cy = (double)(S)((double)cy0 + bc.g[1] * dt);
+  double cz = (double)(S)((double)cz0 + bc.g[2] * dt);
+  double x = g.dim == 2 ? (double)p.x[i] : 0.0, y = (double)p.y[i];
+  double er = (double)er0;
+  int lv = lv0;
+  const double xlo = (double)(S)g.x0, xhi = (double)edge<S>(g.x0, g.dx, g.nx);
+  const double ylo = (double)(S)g.y0, yhi = (double)edge<S>(g.y0, g.dy, g.ny);
+  double t = dt;
+  int bounces = 0, events = 0;
+  bool deleted = false;
+  uint32_t ev = 0;
+  const uint32_t id = p.pid[i];
+  for (;;) {
+    double th = INFINITY;
+    int side = -1;
+    if (g.dim == 2) {
+      if (cx < 0.0 && x + cx * t < xlo) { const double tt = (xlo - x) / cx; if (tt < th) { th = tt; side = USP_SIDE_XLO; } }
+      if (cx > 0.0 && x + cx * t >= xhi) { const double tt = (xhi - x) / cx; if (tt < th) { th = tt; side = USP_SIDE_XHI; } }
+    }
+    if (cy < 0.0 && y + cy * t < ylo) { const double tt = (ylo - y) / cy; if (tt < th) { th = tt; side = USP_SIDE_YLO; } }
+    if (cy > 0.0 && y + cy * t >= yhi) { const double tt = (yhi - y) / cy; if (tt < th) { th = tt; side = USP_SIDE_YHI; } }
+    if (g.dim == 2 && bc.cyl) {
+      const double px = x - bc.cyl_xc, py = y - bc.cyl_yc;
+      const double A = cx * cx + cy * cy, B = px * cx + py * cy;
+      const double C = px * px + py * py - bc.cyl_r * bc.cyl_r;
+      if (B < 0.0 && A > 0.0) {
+        double tt = -1.0;
+        if (C <= 0.0) tt = 0.0;
+        else {
+          const double disc = B * B - A * C;
+          if (disc > 0.0) tt = (-B - sqrt(disc)) / A;
+        }
+        if (tt >= 0.0 && tt <= t && tt < th) { th = tt; side = 4; }
+      }
+    }
+    if (side < 0) { x += cx * t; y += cy * t; break; }
+    if (th < 0.0) th = 0.0;
+    if (th > t) th = t;
+    x += cx * th;
+    y += cy * th;
+    t -= th;
+    if (++events > 4 * MAX_BOUNCE) { ev |= 1u << USP_CNT_BOUNCE_LIMIT; break; }
+    const int kind = side == 4 ? USP_BC_DIFFUSE : bc.kind[side];
+    if (side == USP_SIDE_XLO) x = xlo;
+    if (side == USP_SIDE_XHI) x = xhi;
+    if (side == USP_SIDE_YLO) y = ylo;
+    if (side == USP_SIDE_YHI) y = yhi;
+    if (kind == USP_BC_FREESTREAM || kind == USP_BC_OUTFLOW) { deleted = true; break; }
+    if (kind == USP_BC_PERIODIC) {
+      if (side == USP_SIDE_XLO) x = xhi;
+      else if (side == USP_SIDE_XHI) x = xlo;
+      else if (side == USP_SIDE_YLO) y = yhi;
+      else y = ylo;
+      continue;
+    }
+    if (kind == USP_BC_SPECULAR) {
+      if (side == USP_SIDE_XLO || side == USP_SIDE_XHI) cx = -cx; else cy = -cy;
+      continue;
+    }
+    if (bounces >= MAX_BOUNCE) { ev |= 1u << USP_CNT_BOUNCE_LIMIT; break; }
+    double cn, ta, tb, ner;
+    int nlv;
+    const double Tw = side == 4 ? bc.cyl_Tw : bc.Tw[side];
+    wall_draw(gas, Tw, seed, id, step, bounces, &cn, &ta, &tb, &ner, &nlv);
+    ++bounces;
+    er = ner;
+    lv = nlv;
+    if (side == USP_SIDE_YLO || side == USP_SIDE_YHI) {
+      cy = side == USP_SIDE_YLO ? cn : -cn;
+      cx = ta; cz = tb;
+    } else if (side == USP_SIDE_XLO || side == USP_SIDE_XHI) {
+      cx = side == USP_SIDE_XLO ? cn : -cn;
+      cy = ta; cz = tb;
+    } else {
+      double nxv = x - bc.cyl_xc, nyv = y - bc.cyl_yc;
+      const double nn = sqrt(nxv * nxv + nyv * nyv);
+      nxv /= nn;
+      nyv /= nn;
+      x = bc.cyl_xc + bc.cyl_r * nxv;
+      y = bc.cyl_yc + bc.cyl_r * nyv;
+      cx = cn * nxv - ta * nyv;
+      cy = cn * nyv + ta * nxv;
+      cz = tb;
+    }
+  }
+  if (deleted) {
+    // a deleted particle keeps its position and its values before the flight
+    p.cell[i] = -1;
+    p.cx[i] = cx0; p.cy[i] = cy0; p.cz[i] = cz0; p.erot[i] = er0; p.vib[i] = (uint8_t)lv0;
+    ev |= 1u << USP_CNT_DELETED;
+  } else {
+    S xs = S(0);
+    if (g.dim == 2) { xs = settle<S>(x, xlo, xhi); p.x[i] = xs; }
+    const S ys = settle<S>(y, ylo, yhi);
+    p.y[i] = ys;
+    p.cx[i] = (S)cx;
+    p.cy[i] = (S)cy;
+    p.cz[i] = (S)cz;
+    p.erot[i] = (S)er;
+    p.vib[i] = (uint8_t)lv;
+    p.cell[i] = cell_of<S>(g, xs, ys);
+  }
+  flush_events(counters, ev, USP_CNT_WALL_HITS, bounces);
+}
+
+}  // namespace usp

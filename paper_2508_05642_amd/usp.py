@@ -80,9 +80,10 @@ def lib():
         L.usp_collide.argtypes = [vp, vp, vp, vp, vp, u64, u64, vp, vp]
         L.usp_conserve.argtypes = [vp, vp, vp, vp, vp, u64, u64, vp, vp]
         L.usp_advect.argtypes = [vp, vp, vp, d, vp, u64, u64, vp, sz, vp, vp]
+        L.usp_update.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, sz, u64, u64, vp, vp]
         L.usp_step.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, vp, vp, vp, sz, u64, u64, i32, vp, vp]
         for nm in ("usp_bin", "usp_moments", "usp_reconstruct", "usp_collide", "usp_conserve",
-                   "usp_advect", "usp_step"):
+                   "usp_advect", "usp_update", "usp_step"):
             getattr(L, nm).restype = i32
         _lib = L
     return _lib
@@ -90,7 +91,7 @@ def lib():
 
 EXPORTED = ["usp_status_str", "usp_mom_name", "usp_cs_name", "usp_counter_name", "usp_version",
             "usp_workspace_bytes", "usp_cellstate_bytes", "usp_bin", "usp_moments", "usp_reconstruct", "usp_collide",
-            "usp_conserve", "usp_advect", "usp_step"]
+            "usp_conserve", "usp_advect", "usp_update", "usp_step"]
 
 
 def names(kind):
@@ -155,6 +156,12 @@ def usp_collide(grid, gas, cs, offsets, p, seed, step, counters, stream=None):
 def usp_conserve(grid, gas, cs, offsets, p, seed, step, counters, stream=None):
     _check(lib().usp_conserve(C.byref(grid), C.byref(gas), _ptr(cs), _ptr(offsets), C.byref(p),
                               seed, step, _ptr(counters), _stream(stream)), "usp_conserve")
+
+
+def usp_update(grid, gas, bc, dt, cs, offsets, p, seed, step, ws, counters, stream=None):
+    _check(lib().usp_update(C.byref(grid), C.byref(gas), None if bc is None else C.byref(bc), dt,
+                            _ptr(cs), _ptr(offsets), C.byref(p), _ptr(ws), ws.numel(), seed, step,
+                            _ptr(counters), _stream(stream)), "usp_update")
 
 
 def usp_advect(grid, gas, bc, dt, p, seed, step, ws, counters, stream=None):
@@ -306,6 +313,11 @@ class DeviceState:
     def advect(self, step, stream=None):
         usp_advect(self.grid, self.gas, self.bc, self.prob.dt, self.p, self.prob.seed, step,
                    self.ws, self.counters, stream)
+
+    def update(self, step, stream=None):
+        """collide + conserve + advect in one fused pass (binned state)."""
+        usp_update(self.grid, self.gas, self.bc if self.dim >= 1 else None, self.prob.dt, self.cs,
+                   self.offsets, self.p, self.prob.seed, step, self.ws, self.counters, stream)
 
     def step(self, step, nsteps=1, stream=None):
         a, b = self.bufs[self.cur]["struct"], self.bufs[1 - self.cur]["struct"]

@@ -430,3 +430,37 @@ def test_bin_fast_route_far_moves_deletions_tail(kind):
     for f in ("pid", "cell", "vib", "x", "y", "cx", "cy", "cz", "erot"):
         if b[f] is not None:
             assert np.array_equal(a[f], b[f]), f
+
+
+@pytest.mark.parametrize("kind,f32", CASES + [("2d_big", True)])
+def test_update_fused_equals_phases(kind, f32):
+    """usp_update (collide + conserve + advect in one pass) gives the same
+    bits and event counts as usp_collide, usp_conserve, usp_advect in turn;
+    the 0D case has a cell larger than the LDS stage (in-place tile) next to
+    staged tiles."""
+    usp = _usp()
+    if kind == "2d_big":
+        prob, parts = prob_2d(f32, scale=0.2)
+    else:
+        prob, parts = make(kind, f32)
+    _say(f"[fused] case={kind} f32={f32} n={parts['n']} cells={prob.grid.ncells}")
+    a = usp.DeviceState(prob, parts)
+    b = usp.DeviceState(prob, parts)
+    for s in (3, 4):
+        for st in (a, b):
+            st.bin(); st.do_moments(); st.do_reconstruct()
+        a.collide(s); a.conserve(s); a.advect(s)
+        b.update(s)
+        torch.cuda.synchronize()
+        sa, sb = a.state(), b.state()
+        assert sa["n"] == sb["n"]
+        for k in sa:
+            if isinstance(sa[k], np.ndarray):
+                bad = np.nonzero(sa[k] != sb[k])[0]
+                if bad.size:
+                    _say(f"  step {s} field {k}: {bad.size} of {sa['n']} differ; first {bad[:8]}")
+                    for j in bad[:4]:
+                        _say("   ", j, {f: (sa[f][j], sb[f][j]) for f in sa
+                                       if isinstance(sa[f], np.ndarray)})
+                assert bad.size == 0, (s, k)
+        assert a.cnt() == b.cnt(), (a.cnt(), b.cnt())

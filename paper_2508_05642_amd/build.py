@@ -17,6 +17,11 @@ HIPCC_FLAGS = [
     # loops inline long math routines whose constants would otherwise stay
     # live in VGPRs for the whole loop
     "-mllvm", "-disable-machine-licm",
+    # FP32 divide and sqrt to ~2 ulp (hardware reciprocal/sqrt) instead of
+    # the correctly rounded sequences: single precision appears only in the
+    # FP32 particle arithmetic, which is held to a tolerance; every discrete
+    # decision and all cell quantities are FP64
+    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
 ]
 
 

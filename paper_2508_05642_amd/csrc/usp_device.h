@@ -36,11 +36,14 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 // uniform (w + 1/2) 2^-32 in (0,1), exact in double
 __device__ __forceinline__ double u01d(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
 
-// ln u for the same u, with full relative accuracy in single precision
-// (near u = 1 through log1p of the exactly formed 1 - u)
+// ln u for the same u in single precision.  Below 1 - 2^-7 the float u
+// (relative rounding 2^-24) gives ln u to ~2^-17 relative; above it
+// ln(1 - v) = -v (1 + v/2 + v^2/3 + v^3/4 + v^4/5) with v = 1 - u formed
+// exactly from ~w (truncation below 1e-10 relative).
 __device__ __forceinline__ float logu(uint32_t w, float) {
-  if (w < 0x80000000u) return logf(((float)w + 0.5f) * 0x1p-32f);
-  return log1pf(-(((float)(~w) + 0.5f) * 0x1p-32f));
+  if (w < 0xFE000000u) return logf(((float)w + 0.5f) * 0x1p-32f);
+  const float v = ((float)(~w) + 0.5f) * 0x1p-32f;
+  return -v * (1.0f + v * (0.5f + v * (1.0f / 3.0f + v * (0.25f + v * 0.2f))));
 }
 __device__ __forceinline__ double logu(uint32_t w, double) { return log(u01d(w)); }
 
@@ -74,18 +77,12 @@ __device__ __forceinline__ T mlevel(T theta, T Temp) {
   return T(1) / expm1(x);
 }
 
-// c_v,vib / R = x^2 e^{-x} / (1 - e^{-x})^2, x = theta/T
-template <typename T>
-__device__ __forceinline__ T cv_vib_R(T x) {
-  if (x > T(700)) return T(0);
-  const T e = exp(-x), d = -expm1(-x);
-  return x * x * e / (d * d);
-}
-
 // Rescaled translational temperature: root of
 //   (3/2 + a) T + b theta m(T) = 3/2 T_tr + a T_rot + b theta m(T_vib)
 // (the energy balance behind the gamma coefficients of Sec. III.A.1),
-// safeguarded Newton on [0, rhs/(3/2 + a)].
+// safeguarded Newton on [0, rhs/(3/2 + a)].  With x = theta/T and
+// m = 1/(e^x - 1), dm/dT = x^2 m (1 + m)/T, so one expm1 per iteration
+// gives both f and f'.
 template <typename T>
 __device__ __forceinline__ T tcheck(T theta, T Ttr, T Trot, T Tvib, T a, T b) {
   const T ca = T(1.5) + a;
@@ -96,9 +93,13 @@ __device__ __forceinline__ T tcheck(T theta, T Ttr, T Trot, T Tvib, T a, T b) {
   if (!(t > T(0) && t <= hi)) t = hi;
   const T tol = sizeof(T) == 4 ? T(3e-7) : T(1e-14);
   for (int it = 0; it < 40; ++it) {
-    const T f = ca * t + b * theta * mlevel(theta, t) - rhs;
+    const T x = theta / t;
+    // m(T) and c_v,vib/R; e^x overflows to inf for large x, giving m = 0
+    const T m = x > T(700) ? T(0) : T(1) / expm1(x);
+    const T cv = x * x * m * (T(1) + m);
+    const T f = ca * t + b * theta * m - rhs;
     if (f > T(0)) hi = t; else lo = t;
-    const T fp = ca + b * cv_vib_R(theta / t);
+    const T fp = ca + b * cv;
     T tn = t - f / fp;
     if (!(tn > lo && tn < hi)) tn = T(0.5) * (lo + hi);
     const T dt = fabs(tn - t);

@@ -27,6 +27,8 @@ GridP make_grid(const usp_grid* g) {
   p.dim = g->dim; p.nx = g->nx; p.ny = g->ny;
   p.M = (int64_t)g->nx * g->ny;
   p.x0 = g->x0; p.y0 = g->y0; p.dx = g->dx; p.dy = g->dy; p.fnum = g->fnum;
+  p.idx = g->dx > 0.0 ? 1.0 / g->dx : 0.0;
+  p.idy = g->dy > 0.0 ? 1.0 / g->dy : 0.0;
   p.volume = g->volume; p.flags = g->flags;
   return p;
 }

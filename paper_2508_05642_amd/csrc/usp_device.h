@@ -48,8 +48,35 @@ __device__ __forceinline__ float logu(uint32_t w, float) {
 __device__ __forceinline__ double logu(uint32_t w, double) { return log(u01d(w)); }
 
 // (sin, cos)(2 pi u) for the same u
+// sin and cos of |x| <= pi/3 by their Taylor series in nested form,
+// cos x = 1 - x^2/(1*2) (1 - x^2/(3*4) (1 - ...)) and likewise sin x / x
+// with (2*3), (4*5), ...; NT terms leave a truncation below 4e-9 (NT = 5,
+// float) or 1e-18 (NT = 9, double) on that interval.
+template <typename T, int NT>
+__device__ __forceinline__ void sincos_series(T x, T* s, T* c) {
+  const T x2 = x * x;
+  T cc = T(1), ss = T(1);
+#pragma unroll
+  for (int k = NT; k >= 1; --k) {
+    cc = T(1) - x2 * T(1.0 / double((2 * k - 1) * (2 * k))) * cc;
+    ss = T(1) - x2 * T(1.0 / double((2 * k) * (2 * k + 1))) * ss;
+  }
+  *c = cc;
+  *s = x * ss;
+}
+// In single precision: the quarter turn q nearest to u and the remainder
+// u - q/4 in [-1/8, 1/8] are formed exactly from w (wrapping 32-bit
+// arithmetic), the series runs on |theta| <= pi/4, then a rotation by q
+// quarter turns.
 __device__ __forceinline__ void sincos2pi(uint32_t w, float* s, float* c) {
-  sincospif(((float)w + 0.5f) * 0x1p-31f, s, c);
+  const uint32_t q = ((w + 0x20000000u) >> 30) & 3u;
+  const int32_t r = (int32_t)(w - (q << 30));
+  const float th = (((float)r + 0.5f) * 0x1p-32f) * 6.2831853071795865f;
+  float st, ct;
+  sincos_series<float, 5>(th, &st, &ct);
+  const float a = (q & 1u) ? ct : st, b = (q & 1u) ? st : ct;
+  *s = (q == 1u || q == 0u) ? a : -a;
+  *c = (q == 0u || q == 3u) ? b : -b;
 }
 __device__ __forceinline__ void sincos2pi(uint32_t w, double* s, double* c) {
   sincospi(u01d(w) * 2.0, s, c);
@@ -167,10 +194,12 @@ __device__ __forceinline__ S edge(double o, double d, int k) {
   return (S)__dadd_rn(o, __dmul_rn((double)k, d));
 }
 
+// (id = 1/d gives the first guess; the two correction loops make the
+// index exact against the edge table whatever the guess)
 template <typename S>
-__device__ __forceinline__ int axis_index(S v, double o, double d, int n) {
+__device__ __forceinline__ int axis_index(S v, double o, double d, double id, int n) {
   if (!(v >= edge<S>(o, d, 0)) || v >= edge<S>(o, d, n)) return -1;
-  int k = (int)floor(((double)v - o) / d);
+  int k = (int)floor(((double)v - o) * id);
   k = k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
   while (k > 0 && edge<S>(o, d, k) > v) --k;
   while (k < n - 1 && edge<S>(o, d, k + 1) <= v) ++k;
@@ -179,9 +208,9 @@ __device__ __forceinline__ int axis_index(S v, double o, double d, int n) {
 
 template <typename S>
 __device__ __forceinline__ int32_t cell_of(const GridP& g, S x, S y) {
-  if (g.dim == 1) return axis_index<S>(y, g.y0, g.dy, g.ny);
-  const int ix = axis_index<S>(x, g.x0, g.dx, g.nx);
-  const int iy = axis_index<S>(y, g.y0, g.dy, g.ny);
+  if (g.dim == 1) return axis_index<S>(y, g.y0, g.dy, g.idy, g.ny);
+  const int ix = axis_index<S>(x, g.x0, g.dx, g.idx, g.nx);
+  const int iy = axis_index<S>(y, g.y0, g.dy, g.idy, g.ny);
   if (ix < 0 || iy < 0) return -1;
   return iy * g.nx + ix;
 }

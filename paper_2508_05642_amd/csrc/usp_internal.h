@@ -65,6 +65,7 @@ struct GridP {
   int dim, nx, ny;
   int64_t M;
   double x0, y0, dx, dy, fnum;
+  double idx, idy;  // 1/dx, 1/dy (first guess of a cell index only)
   const double* volume;
   const uint8_t* flags;
 };

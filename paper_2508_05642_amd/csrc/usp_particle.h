@@ -53,7 +53,17 @@ __device__ __forceinline__ int sample_b(double u, int n, double p) {
   return k;
 }
 
-// smallest and largest eigenvalue of a symmetric 3x3 (trigonometric form)
+// sin and cos of 0 <= x <= pi/3 (series of usp_device.h)
+__device__ __forceinline__ void sincos_third(float x, float* s, float* c) {
+  sincos_series<float, 5>(x, s, c);
+}
+__device__ __forceinline__ void sincos_third(double x, double* s, double* c) {
+  sincos_series<double, 9>(x, s, c);
+}
+
+// smallest and largest eigenvalue of a symmetric 3x3 (trigonometric form:
+// lambda = q + 2 p cos(phi + 2 pi k/3), phi = acos(det B / 2)/3 in
+// [0, pi/3]; cos(phi + 2 pi/3) = -(cos phi + sqrt(3) sin phi)/2)
 template <typename T>
 __device__ __forceinline__ void eig_minmax(const T P[6], T* lmin, T* lmax) {
   const T p1 = P[3] * P[3] + P[4] * P[4] + P[5] * P[5];
@@ -74,8 +84,10 @@ __device__ __forceinline__ void eig_minmax(const T P[6], T* lmin, T* lmax) {
   T r = det / T(2);
   r = fmin(T(1), fmax(T(-1), r));
   const T phi = acos(r) / T(3);
-  *lmax = q + T(2) * p * cos(phi);
-  *lmin = q + T(2) * p * cos(phi + T(2.0943951023931954923));
+  T sn, cs;
+  sincos_third(phi, &sn, &cs);
+  *lmax = q + T(2) * p * cs;
+  *lmin = q - p * (cs + T(1.7320508075688772935) * sn);
 }
 
 // Cell-level coefficients (FP64, from the cell state).
@@ -333,16 +345,19 @@ __device__ __forceinline__ void note_coef_events(const PartCoef<double>& a, uint
 }
 
 // Particle update of particle i in cell c (Secs. III.A-III.B).
-// FP32 state: fields from the packed cell records (16-byte loads), FP32
-// reconstruction and coefficient chain; near the positive-definiteness
-// boundary of the diffusion tensor the chain is redone in FP64 from the
-// FP64 planes, so that branch is taken in FP64.
-__device__ __forceinline__ PartNew<float> collide_one(const GridP& g, const GasP& gas,
+// FP32 state, first pass: fields from the packed cell records (16-byte
+// loads), FP32 reconstruction and coefficient chain.  When the Cholesky
+// test of the diffusion tensor fails, or passes with a relative pivot below
+// 1e-4, the particle is left unchanged with *esc set and no coefficient
+// events: collide_esc then redoes it with every branch taken in FP64.
+__device__ __forceinline__ PartNew<float> collide_f32(const GridP& g, const GasP& gas,
                                                      const double* __restrict__ cs,
                                                      const PartP<float>& p, int64_t i, int32_t c,
-                                                     uint64_t seed, uint32_t step, uint32_t* evp) {
+                                                     uint64_t seed, uint32_t step, uint32_t* evp,
+                                                     bool* esc) {
   PartNew<float> o;
   o.changed = false;
+  *esc = false;
   const int64_t M = g.M;
   const CellRec* __restrict__ rec = cell_records(cs, M);
   const float4* r4 = (const float4*)(rec + c);
@@ -386,22 +401,58 @@ __device__ __forceinline__ PartNew<float> collide_one(const GridP& g, const GasP
   CellCoef cc;
   cc.a = q5.x; cc.b = q5.y; cc.al = q5.z; cc.nu = q5.w;
   cc.oma2 = own.oma2; cc.r2 = own.r2; cc.A2 = own.A2; cc.Pr = own.Pr; cc.dt = own.dt;
-  PartCoef<float> pc = particle_coef<float>((float)gas.R, (float)gas.theta, Tk[0], Tk[1], Tk[2], P, cc);
+  const PartCoef<float> pc = particle_coef<float>((float)gas.R, (float)gas.theta, Tk[0], Tk[1], Tk[2], P, cc);
   if (pc.fallback || pc.margin < 1e-4f) {
-    double Ud[3], Pd[6], Td[3];
-    fields_planes(cs, M, c, st, Ud, Pd, Td);
-    const CellCoef cd = coef_planes(cs, M, c);
-    const PartCoef<double> pd = particle_coef<double>(gas.R, gas.theta, Td[0], Td[1], Td[2], Pd, cd);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) pc.L[k] = (float)pd.L[k];
-    pc.al = (float)pd.al; pc.oma2 = pd.oma2; pc.Trot_rel = (float)pd.Trot_rel;
-    pc.mstar = (float)pd.mstar;
-    pc.skip = pd.skip; pc.fallback = pd.fallback; pc.nu_zero = pd.nu_zero;
-    pc.clamp_rot = pd.clamp_rot; pc.clamp_m = pd.clamp_m;
+    *esc = true;
+    *evp |= ev;
+    return o;
   }
   note_coef_events(pc, &ev);
   if (!pc.skip) update_particle<float, float>(p, i, U, pc, (float)gas.R, seed, step, &ev, &o);
   *evp |= ev;
+  return o;
+}
+
+// FP32 state, second pass for the particles collide_f32 escalated: U, Pi
+// and the temperatures interpolated from the FP64 planes with the same
+// stencil, the coefficient chain with its Cholesky test and fallback in
+// FP64, then the update in FP32 (the interpolation clamp was reported by
+// the first pass).
+__device__ __forceinline__ PartNew<float> collide_esc(const GridP& g, const GasP& gas,
+                                                     const double* __restrict__ cs,
+                                                     const PartP<float>& p, int64_t i, int32_t c,
+                                                     uint64_t seed, uint32_t step, uint32_t* evp) {
+  PartNew<float> o;
+  o.changed = false;
+  const int64_t M = g.M;
+  const Stencil st = particle_stencil<float>(g, cell_records(cs, M)[c].stencil, c, p, i);
+  double Ud[3], Pd[6], Td[3];
+  fields_planes(cs, M, c, st, Ud, Pd, Td);
+  const CellCoef cd = coef_planes(cs, M, c);
+  const PartCoef<double> pd = particle_coef<double>(gas.R, gas.theta, Td[0], Td[1], Td[2], Pd, cd);
+  PartCoef<float> pc;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) pc.L[k] = (float)pd.L[k];
+  pc.al = (float)pd.al; pc.oma2 = pd.oma2; pc.Trot_rel = (float)pd.Trot_rel;
+  pc.mstar = (float)pd.mstar; pc.margin = (float)pd.margin;
+  pc.skip = pd.skip; pc.fallback = pd.fallback; pc.nu_zero = pd.nu_zero;
+  pc.clamp_rot = pd.clamp_rot; pc.clamp_m = pd.clamp_m;
+  uint32_t ev = 0;
+  note_coef_events(pc, &ev);
+  const float U[3] = {(float)Ud[0], (float)Ud[1], (float)Ud[2]};
+  if (!pc.skip) update_particle<float, float>(p, i, U, pc, (float)gas.R, seed, step, &ev, &o);
+  *evp |= ev;
+  return o;
+}
+
+// Both passes in one call.
+__device__ __forceinline__ PartNew<float> collide_one(const GridP& g, const GasP& gas,
+                                                     const double* __restrict__ cs,
+                                                     const PartP<float>& p, int64_t i, int32_t c,
+                                                     uint64_t seed, uint32_t step, uint32_t* evp) {
+  bool esc;
+  PartNew<float> o = collide_f32(g, gas, cs, p, i, c, seed, step, evp, &esc);
+  if (esc) o = collide_esc(g, gas, cs, p, i, c, seed, step, evp);
   return o;
 }
 
@@ -652,8 +703,12 @@ __device__ __forceinline__ void advect_one(const GridP& g, const GasP& gas, cons
     }
     if (cy < 0.0 && y + cy * t < ylo) { const double tt = (ylo - y) / cy; if (tt < th) { th = tt; side = USP_SIDE_YLO; } }
     if (cy > 0.0 && y + cy * t >= yhi) { const double tt = (yhi - y) / cy; if (tt < th) { th = tt; side = USP_SIDE_YHI; } }
-    if (g.dim == 2 && bc.cyl) {
-      const double px = x - bc.cyl_xc, py = y - bc.cyl_yc;
+    // the body can only be reached within t if |p| <= r + |c| t, and
+    // |c| <= |cx| + |cy|: a cheap, slightly widened pre-test (the exact
+    // test below decides)
+    const double px = x - bc.cyl_xc, py = y - bc.cyl_yc;
+    const double reach = bc.cyl_r + (fabs(cx) + fabs(cy)) * t;
+    if (g.dim == 2 && bc.cyl && px * px + py * py <= reach * reach * (1.0 + 1e-9)) {
       const double A = cx * cx + cy * cy, B = px * cx + py * cy;
       const double C = px * px + py * py - bc.cyl_r * bc.cyl_r;
       if (B < 0.0 && A > 0.0) {

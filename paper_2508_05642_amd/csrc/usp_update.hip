@@ -42,30 +42,50 @@ __global__ void k_tile_first(const int64_t* __restrict__ offsets, int64_t M, int
   for (int64_t t = lo; t <= hi; ++t) first[t] = (int32_t)c;
 }
 
+// First and second pass of the particle update: in FP32 the first pass
+// flags the particles that need the FP64 chain (see collide_f32); the FP64
+// state has a single pass.
+__device__ __forceinline__ PartNew<float> update_first(const GridP& g, const GasP& gas,
+                                                      const double* cs, const PartP<float>& p,
+                                                      int64_t i, int32_t c, uint64_t seed,
+                                                      uint32_t step, uint32_t* ev, bool* esc) {
+  return collide_f32(g, gas, cs, p, i, c, seed, step, ev, esc);
+}
+__device__ __forceinline__ PartNew<double> update_first(const GridP& g, const GasP& gas,
+                                                       const double* cs, const PartP<double>& p,
+                                                       int64_t i, int32_t c, uint64_t seed,
+                                                       uint32_t step, uint32_t* ev, bool* esc) {
+  *esc = false;
+  return collide_one(g, gas, cs, p, i, c, seed, step, ev);
+}
+__device__ __forceinline__ PartNew<float> update_second(const GridP& g, const GasP& gas,
+                                                       const double* cs, const PartP<float>& p,
+                                                       int64_t i, int32_t c, uint64_t seed,
+                                                       uint32_t step, uint32_t* ev) {
+  return collide_esc(g, gas, cs, p, i, c, seed, step, ev);
+}
+__device__ __forceinline__ PartNew<double> update_second(const GridP&, const GasP&, const double*,
+                                                        const PartP<double>&, int64_t, int32_t,
+                                                        uint64_t, uint32_t, uint32_t*) {
+  PartNew<double> o;
+  o.changed = false;
+  return o;
+}
+
 // The three phases of one tile; vx* = stage (LDS, indexed i - base) or the
-// particle arrays themselves (base 0).
-template <typename S, bool STAGED>
+// particle arrays themselves (base 0).  esc/nesc: LDS list of the
+// particles of the current chunk (CAP slots) left for the second pass.
+template <typename S, bool STAGED, int CAP>
 __device__ __forceinline__ void tile_pass(const GridP& g, const GasP& gas, const BcP& bc,
                                           double dt, const double* __restrict__ cs,
                                           const int64_t* __restrict__ offsets, const PartP<S>& p,
                                           int64_t c0, int64_t c1, int64_t i0, int64_t i1,
                                           S* vcx, S* vcy, S* vcz, S* ver, uint8_t* vvb,
-                                          int64_t base, uint64_t seed, uint32_t step, bool advect,
+                                          int64_t base, uint16_t* esc_list, int* nesc,
+                                          uint64_t seed, uint32_t step, bool advect,
                                           int64_t* counters) {
   const int64_t M = g.M;
-  // A: particle update
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += UPD_BLOCK) {
-    const int32_t c = p.cell[i];
-    uint32_t ev = 0;
-    PartNew<S> o;
-    o.changed = false;
-    // The cell-state planes are read only on the rare FP64 path; opaque
-    // copies of their base and stride keep the compiler from holding every
-    // plane's address live across the loop.
-    GridP gl = g;
-    const double* csl = cs;
-    asm volatile("" : "+s"(csl), "+s"(gl.M));
-    if (c >= 0) o = collide_one(gl, gas, csl, p, i, c, seed, step, &ev);
+  auto put = [&](int64_t i, PartNew<S> o) {
     if (STAGED) {
       if (!o.changed) {
         o.cx = p.cx[i]; o.cy = p.cy[i]; o.cz = p.cz[i]; o.erot = p.erot[i]; o.vib = p.vib[i];
@@ -76,9 +96,40 @@ __device__ __forceinline__ void tile_pass(const GridP& g, const GasP& gas, const
       p.cx[i] = o.cx; p.cy[i] = o.cy; p.cz[i] = o.cz; p.erot[i] = o.erot;
       p.vib[i] = (uint8_t)o.vib;
     }
-    flush_events(counters, ev);
+  };
+  // A: particle update, in chunks of CAP particles (one chunk when staged):
+  // first pass thread per particle, then the listed particles' second pass
+  for (int64_t cb = i0; cb < i1; cb += CAP) {
+    const int64_t ce = cb + CAP < i1 ? cb + CAP : i1;
+    if (threadIdx.x == 0) *nesc = 0;
+    __syncthreads();
+    for (int64_t i = cb + threadIdx.x; i < ce; i += UPD_BLOCK) {
+      const int32_t c = p.cell[i];
+      uint32_t ev = 0;
+      bool esc = false;
+      PartNew<S> o;
+      o.changed = false;
+      // The cell-state planes are read only on the second pass; opaque
+      // copies of their base and stride keep the compiler from holding
+      // every plane's address live across the loop.
+      GridP gl = g;
+      const double* csl = cs;
+      asm volatile("" : "+s"(csl), "+s"(gl.M));
+      if (c >= 0) o = update_first(gl, gas, csl, p, i, c, seed, step, &ev, &esc);
+      if (esc) esc_list[atomicAdd(nesc, 1)] = (uint16_t)(i - cb);
+      else put(i, o);
+      flush_events(counters, ev);
+    }
+    __syncthreads();
+    const int ne = *nesc;
+    for (int k = threadIdx.x; k < ne; k += UPD_BLOCK) {
+      const int64_t i = cb + esc_list[k];
+      uint32_t ev = 0;
+      put(i, update_second(g, gas, cs, p, i, p.cell[i], seed, step, &ev));
+      flush_events(counters, ev);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   // B: conservation, wave per cell
   const int wid = threadIdx.x >> 6;
   for (int64_t c = c0 + wid; c < c1; c += UPD_WAVES) {
@@ -102,7 +153,7 @@ __device__ __forceinline__ void tile_pass(const GridP& g, const GasP& gas, const
 }
 
 template <typename S>
-__global__ __launch_bounds__(UPD_BLOCK) void k_update(GridP g, GasP gas, BcP bc, double dt,
+__global__ __launch_bounds__(UPD_BLOCK, 4) void k_update(GridP g, GasP gas, BcP bc, double dt,
                                                       const double* __restrict__ cs,
                                                       const int64_t* __restrict__ offsets,
                                                       const int32_t* __restrict__ first,
@@ -111,16 +162,19 @@ __global__ __launch_bounds__(UPD_BLOCK) void k_update(GridP g, GasP gas, BcP bc,
   constexpr int CAP = UpdCfg<S>::STAGE;
   __shared__ S scx[CAP], scy[CAP], scz[CAP], ser[CAP];
   __shared__ uint8_t svb[CAP];
+  __shared__ uint16_t esc_list[CAP];
+  __shared__ int nesc;
   const int64_t t = blockIdx.x;
   const int64_t c0 = first[t], c1 = first[t + 1];
   if (c0 >= c1) return;
   const int64_t i0 = offsets[c0], i1 = offsets[c1];
   if (i1 - i0 <= CAP)
-    tile_pass<S, true>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1, scx, scy, scz, ser, svb,
-                       i0, seed, step, advect != 0, counters);
+    tile_pass<S, true, CAP>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1, scx, scy, scz, ser,
+                            svb, i0, esc_list, &nesc, seed, step, advect != 0, counters);
   else
-    tile_pass<S, false>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1, p.cx, p.cy, p.cz,
-                        p.erot, p.vib, 0, seed, step, advect != 0, counters);
+    tile_pass<S, false, CAP>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1, p.cx, p.cy, p.cz,
+                             p.erot, p.vib, 0, esc_list, &nesc, seed, step, advect != 0,
+                             counters);
 }
 
 template <typename S>

@@ -190,8 +190,12 @@ size_t usp_workspace_bytes(const usp_grid* grid, int64_t capacity);
    in_offsets (device int64[M+1], may be NULL, may alias offsets): when the
    input's first in_offsets[M] particles are the output of an earlier bin
    with these offsets (updated in place since, as usp_step does, with any
-   later particles appended), the fast route that exploits it is taken.  The
-   result is the same either way; NULL means nothing is known. */
+   later particles appended), the fast route that exploits it is taken.
+   On that route the prefix particles' in->cell must be current (the cell of
+   the position, or -1 if removed, as usp_advect and usp_update leave it):
+   their cells are taken from in->cell, not recomputed from positions.
+   Appended particles, and every particle when in_offsets is NULL, are
+   binned from their positions.  NULL means nothing is known. */
 usp_status usp_bin(const usp_grid* grid, const usp_particles* in, usp_particles* out,
                    int64_t* offsets, const int64_t* in_offsets, void* ws, size_t ws_bytes,
                    int64_t* counters, void* stream);

@@ -68,7 +68,7 @@ WsLayout ws_layout(int64_t M, int64_t capacity, int nfaces) {
   L.perm = o; o = align256(o + sizeof(uint32_t) * (size_t)capacity);
   L.blocksums = o; o = align256(o + sizeof(int64_t) * (size_t)(cdiv(M, 1024) + 1));
   L.t9 = o; o = align256(o + sizeof(int32_t) * 9 * (size_t)M);
-  L.cell_i32 = o; o = align256(o + sizeof(int32_t) * 6 * (size_t)M);
+  L.cell_i32 = o; o = align256(o + sizeof(int32_t) * 7 * (size_t)M);
   L.old_off = o; o = align256(o + sizeof(int64_t) * (size_t)(M + 1));
   L.far_off = o; o = align256(o + sizeof(int64_t) * (size_t)(M + 1));
   L.far = o; o = align256(o + sizeof(int32_t) * 4 * (size_t)capacity);

@@ -231,8 +231,12 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin_group(GridP g, Nbr nb, PartP<
     int grpid = 14;  // inactive lane
     int32_t c = -1;
     if (active) {
-      bool solid;
-      c = new_key<S>(g, in, i, &solid);
+      // a binned prefix carries its current cells (the flight rewrote them
+      // from the new positions); only the solid-cell test remains
+      c = in.cell[i];
+      if (g.dim == 0 && c >= M) c = -1;
+      bool solid = false;
+      if (c >= 0 && g.flags && (g.flags[c] & USP_FLAG_SOLID)) { c = -1; solid = true; }
       if (solid) count_event(counters, USP_CNT_SOLID_DROP);
       if (c < 0) {
         grpid = GRP_GONE;
@@ -272,6 +276,7 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin_group(GridP g, Nbr nb, PartP<
 template <typename S>
 __global__ __launch_bounds__(BIN_BLOCK) void k_tail_key(GridP g, PartP<S> in, const int64_t* old_off,
                                                         int32_t* key, int32_t* tail_cnt,
+                                                        int32_t* tail_cells, int32_t* n_tail_cells,
                                                         int64_t* counters) {
   const int64_t M = g.M;
   const int64_t ns = sorted_len(old_off, M, in.count), n = in.count[0];
@@ -288,7 +293,9 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_tail_key(GridP g, PartP<S> in, co
     }
     int hl, len;
     wave_runs(c, &hl, &len);
-    if (len > 0 && c >= 0) atomicAdd(&tail_cnt[c], len);
+    // the run that opens a cell's tail also lists the cell
+    if (len > 0 && c >= 0 && atomicAdd(&tail_cnt[c], len) == 0)
+      tail_cells[atomicAdd(n_tail_cells, 1)] = c;
   }
 }
 
@@ -470,24 +477,29 @@ __device__ __forceinline__ void wave_rank_copy(const uint32_t* seg, int n, int64
 
 constexpr int WAVE_SORT_MAX = 1024;
 
+// one wave per listed cell (grid-stride over the list of cells with a tail)
 template <typename S>
 __global__ __launch_bounds__(BIN_BLOCK) void k_tail_sort_copy(GridP g, PartP<S> in, PartP<S> out,
                                                               const int64_t* offsets,
                                                               const int32_t* nontail,
-                                                              const uint32_t* perm) {
-  const int64_t M = g.M;
-  const int64_t c = (int64_t)blockIdx.x * (BIN_BLOCK / 64) + (threadIdx.x >> 6);
-  if (c >= M) return;
-  const int64_t t0 = offsets[c] + nontail[c];
-  const int n = (int)(offsets[c + 1] - t0);
-  if (n <= 0 || n > WAVE_SORT_MAX) return;
-  const bool hx = g.dim == 2, hy = g.dim >= 1;
-  const uint32_t* seg = perm + t0;
-  if (n <= 64) wave_rank_copy<1, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
-  else if (n <= 128) wave_rank_copy<2, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
-  else if (n <= 256) wave_rank_copy<4, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
-  else if (n <= 512) wave_rank_copy<8, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
-  else wave_rank_copy<16, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
+                                                              const uint32_t* perm,
+                                                              const int32_t* tail_cells,
+                                                              const int32_t* n_tail_cells) {
+  const int nl = *n_tail_cells;
+  const int w0 = blockIdx.x * (BIN_BLOCK / 64) + (threadIdx.x >> 6);
+  for (int w = w0; w < nl; w += gridDim.x * (BIN_BLOCK / 64)) {
+    const int64_t c = tail_cells[w];
+    const int64_t t0 = offsets[c] + nontail[c];
+    const int n = (int)(offsets[c + 1] - t0);
+    if (n <= 0 || n > WAVE_SORT_MAX) continue;
+    const bool hx = g.dim == 2, hy = g.dim >= 1;
+    const uint32_t* seg = perm + t0;
+    if (n <= 64) wave_rank_copy<1, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
+    else if (n <= 128) wave_rank_copy<2, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
+    else if (n <= 256) wave_rank_copy<4, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
+    else if (n <= 512) wave_rank_copy<8, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
+    else wave_rank_copy<16, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
+  }
 }
 
 // tails above WAVE_SORT_MAX: one block per cell, sort network in LDS (or in
@@ -496,22 +508,28 @@ template <typename S>
 __global__ __launch_bounds__(BIN_BLOCK) void k_tail_sort_copy_big(GridP g, PartP<S> in, PartP<S> out,
                                                                   const int64_t* offsets,
                                                                   const int32_t* nontail,
-                                                                  uint32_t* perm) {
+                                                                  uint32_t* perm,
+                                                                  const int32_t* tail_cells,
+                                                                  const int32_t* n_tail_cells) {
   __shared__ uint32_t s[SORT_LDS];
-  const int64_t c = blockIdx.x;
-  const int64_t t0 = offsets[c] + nontail[c];
-  const int n = (int)(offsets[c + 1] - t0);
-  if (n <= WAVE_SORT_MAX) return;
-  uint32_t* seg = perm + t0;
-  const bool hx = g.dim == 2, hy = g.dim >= 1;
-  if (n <= SORT_LDS) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s[i] = seg[i];
-    __syncthreads();
-    sort_net<true>(s, n);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) copy_particle<S>(in, out, s[i], t0 + i, (int32_t)c, hx, hy);
-  } else {
-    sort_net<false>(seg, n);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) copy_particle<S>(in, out, seg[i], t0 + i, (int32_t)c, hx, hy);
+  const int nl = *n_tail_cells;
+  for (int w = blockIdx.x; w < nl; w += gridDim.x) {
+    const int64_t c = tail_cells[w];
+    const int64_t t0 = offsets[c] + nontail[c];
+    const int n = (int)(offsets[c + 1] - t0);
+    if (n <= WAVE_SORT_MAX) continue;
+    uint32_t* seg = perm + t0;
+    const bool hx = g.dim == 2, hy = g.dim >= 1;
+    if (n <= SORT_LDS) {
+      for (int i = threadIdx.x; i < n; i += blockDim.x) s[i] = seg[i];
+      __syncthreads();
+      sort_net<true>(s, n);
+      for (int i = threadIdx.x; i < n; i += blockDim.x) copy_particle<S>(in, out, s[i], t0 + i, (int32_t)c, hx, hy);
+      __syncthreads();
+    } else {
+      sort_net<false>(seg, n);
+      for (int i = threadIdx.x; i < n; i += blockDim.x) copy_particle<S>(in, out, seg[i], t0 + i, (int32_t)c, hx, hy);
+    }
   }
 }
 
@@ -521,10 +539,10 @@ __global__ void k_copy_i64(const int64_t* src, int64_t* dst, int64_t n) {
 }
 
 __global__ void k_zero_i32x(int32_t* a, int32_t* b, int32_t* c, int32_t* d, int64_t n,
-                            int32_t* scalar) {
+                            int32_t* scalar, int32_t* scalar2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) { a[i] = 0; b[i] = 0; c[i] = 0; d[i] = 0; }
-  if (i == 0) *scalar = 0;
+  if (i == 0) { *scalar = 0; *scalar2 = 0; }
 }
 
 static void launch_scan(const int32_t* cnt, int64_t M, int64_t* out_off, int64_t* blocksums,
@@ -556,14 +574,18 @@ hipError_t launch_bin(const GridP& g, const PartP<S>& in, const PartP<S>& out, i
   int32_t* far_list = far_i + in.capacity;
   int32_t* far_base = far_list + in.capacity;
   int32_t* far_total = (int32_t*)(ws + L.misc) + 8;
+  int32_t* n_tail_cells = (int32_t*)(ws + L.misc) + 9;
+  int32_t* tail_cells = cnt_total + g.M;
   const int64_t M = g.M;
   const Nbr nb = nbr_set(g);
   const int TAIL_GRID = 512;
   k_copy_i64<<<cdiv(M + 1, 256), 256, 0, st>>>(in_offsets, old_off, M + 1);
-  k_zero_i32x<<<cdiv(M, 256), 256, 0, st>>>(tail_cnt, cursor, far_cnt, far_cur, M, far_total);
+  k_zero_i32x<<<cdiv(M, 256), 256, 0, st>>>(tail_cnt, cursor, far_cnt, far_cur, M, far_total,
+                                             n_tail_cells);
   k_bin_group<S><<<cdiv(M, BIN_BLOCK / 64), BIN_BLOCK, 0, st>>>(g, nb, in, old_off, key, T9, far_cnt,
                                                                  far_c, far_i, far_total, counters);
-  k_tail_key<S><<<TAIL_GRID, BIN_BLOCK, 0, st>>>(g, in, old_off, key, tail_cnt, counters);
+  k_tail_key<S><<<TAIL_GRID, BIN_BLOCK, 0, st>>>(g, in, old_off, key, tail_cnt, tail_cells,
+                                                 n_tail_cells, counters);
   launch_scan(far_cnt, M, far_off, blocksums, nullptr, nullptr, st);
   k_far_place<<<64, BIN_BLOCK, 0, st>>>(far_total, far_c, far_i, far_off, far_cur, far_list);
   k_cell_bases<<<cdiv(M, BIN_BLOCK), BIN_BLOCK, 0, st>>>(g, nb, old_off, in.count, T9, far_off,
@@ -576,8 +598,10 @@ hipError_t launch_bin(const GridP& g, const PartP<S>& in, const PartP<S>& out, i
                                              far_base, offsets);
   k_tail_claim<<<TAIL_GRID, BIN_BLOCK, 0, st>>>(M, old_off, in.count, key, offsets, nontail, cursor,
                                                 perm);
-  k_tail_sort_copy<S><<<cdiv(M, BIN_BLOCK / 64), BIN_BLOCK, 0, st>>>(g, in, out, offsets, nontail, perm);
-  k_tail_sort_copy_big<S><<<M, BIN_BLOCK, 0, st>>>(g, in, out, offsets, nontail, perm);
+  k_tail_sort_copy<S><<<TAIL_GRID, BIN_BLOCK, 0, st>>>(g, in, out, offsets, nontail, perm,
+                                                       tail_cells, n_tail_cells);
+  k_tail_sort_copy_big<S><<<TAIL_GRID, BIN_BLOCK, 0, st>>>(g, in, out, offsets, nontail, perm,
+                                                           tail_cells, n_tail_cells);
   return hipGetLastError();
 }
 

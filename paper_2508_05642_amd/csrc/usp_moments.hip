@@ -4,62 +4,110 @@
 namespace usp {
 
 constexpr int CELL_BLOCK = 256;
-constexpr int CELL_WAVES = CELL_BLOCK / 64;
 
 // Moments of one cell (Sec. II.A): U = <c>, then central second and third
-// moments about U, per unit mass.  One wave per cell, two passes over its
-// particles, FP64 sums reduced by a fixed butterfly (deterministic).
+// moments about U, per unit mass.  One wave per cell and one pass: sums of
+// d = c - c_0 (c_0 = the cell's first particle, so every d is exact in
+// FP64 and of the order of the thermal speed) and of its products, turned
+// into central moments with m = <d>:
+//   sum C_i C_j = S_ij - N m_i m_j,
+//   sum |C|^2 C_i = S3_i - m_i tr S - 2 (S m)_i + 2 N |m|^2 m_i,
+//   sum C_i e = S_ie - m_i sum e.
+// FP64 sums reduced by a fixed butterfly (deterministic).
+template <typename S>
+__device__ __forceinline__ void mom_add(const PartP<S>& p, int64_t i, double r0, double r1,
+                                        double r2, double* s) {
+  const double d0 = (double)p.cx[i] - r0, d1 = (double)p.cy[i] - r1, d2 = (double)p.cz[i] - r2;
+  const double e = (double)p.erot[i], I = (double)p.vib[i];
+  const double q = d0 * d0 + d1 * d1 + d2 * d2;
+  s[0] += d0; s[1] += d1; s[2] += d2;
+  s[3] += d0 * d0; s[4] += d1 * d1; s[5] += d2 * d2;
+  s[6] += d0 * d1; s[7] += d0 * d2; s[8] += d1 * d2;
+  s[9] += q * d0; s[10] += q * d1; s[11] += q * d2;
+  s[12] += e; s[13] += d0 * e; s[14] += d1 * e; s[15] += d2 * e;
+  s[16] += I; s[17] += d0 * I; s[18] += d1 * I; s[19] += d2 * I;
+}
+
+// Sum over a row of 16 lanes by DPP row permutes (swap of neighbours, of
+// pairs, mirror within 8, mirror within 16): every lane of the row ends
+// with the same bits (each step adds two equal-pattern operands).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return v;
+}
+
+// 16 lanes per cell, four cells per wave (every lane stays active for the
+// row permutes; lanes of cells past M carry zeros).
+constexpr int MOM_LANES = 16;
+
 template <typename S>
 __global__ __launch_bounds__(CELL_BLOCK) void k_moments(GridP g, PartP<S> p, const int64_t* offsets,
                                                         double* mom) {
   const int64_t M = g.M;
-  const int64_t c = (int64_t)blockIdx.x * CELL_WAVES + (threadIdx.x >> 6);
-  if (c >= M) return;
-  const int lane = threadIdx.x & 63;
-  const int64_t o0 = offsets[c], o1 = offsets[c + 1], N = o1 - o0;
+  const int64_t c = ((int64_t)blockIdx.x * CELL_BLOCK + threadIdx.x) / MOM_LANES;
+  const int sub = threadIdx.x & (MOM_LANES - 1);
+  const bool valid = c < M;
+  const int64_t o0 = valid ? offsets[c] : 0, o1 = valid ? offsets[c + 1] : 0, N = o1 - o0;
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+  if (N > 0) { r0 = (double)p.cx[o0]; r1 = (double)p.cy[o0]; r2 = (double)p.cz[o0]; }
+  double s[20];
+#pragma unroll
+  for (int k = 0; k < 20; ++k) s[k] = 0.0;
+  int64_t i = o0 + sub;
+  for (; i + MOM_LANES < o1; i += 2 * MOM_LANES) {
+    mom_add<S>(p, i, r0, r1, r2, s);
+    mom_add<S>(p, i + MOM_LANES, r0, r1, r2, s);
+  }
+  if (i < o1) mom_add<S>(p, i, r0, r1, r2, s);
+#pragma unroll
+  for (int k = 0; k < 20; ++k) s[k] = row16_sum(s[k]);
+  if (!valid) return;
+  double v[NMOM];
   if (N == 0) {
-    if (lane < NMOM) mom[lane * M + c] = 0.0;
-    return;
-  }
-  double s1[3] = {0.0, 0.0, 0.0};
-  for (int64_t i = o0 + lane; i < o1; i += 64) {
-    s1[0] += (double)p.cx[i];
-    s1[1] += (double)p.cy[i];
-    s1[2] += (double)p.cz[i];
-  }
 #pragma unroll
-  for (int k = 0; k < 3; ++k) s1[k] = wave_sum(s1[k]);
-  const double invN = 1.0 / (double)N;
-  const double Ux = s1[0] * invN, Uy = s1[1] * invN, Uz = s1[2] * invN;
-  double s[17];
+    for (int k = 0; k < NMOM; ++k) v[k] = 0.0;
+  } else {
+    const double Nd = (double)N, invN = 1.0 / Nd;
+    const double m[3] = {s[0] * invN, s[1] * invN, s[2] * invN};
+    const double Sm[3] = {s[3] * m[0] + s[6] * m[1] + s[7] * m[2],
+                          s[6] * m[0] + s[4] * m[1] + s[8] * m[2],
+                          s[7] * m[0] + s[8] * m[1] + s[5] * m[2]};
+    const double tr = s[3] + s[4] + s[5], mm = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
+    v[M_N] = Nd;
+    v[M_UX] = r0 + m[0]; v[M_UY] = r1 + m[1]; v[M_UZ] = r2 + m[2];
+    v[M_PXX] = s[3] * invN - m[0] * m[0];
+    v[M_PYY] = s[4] * invN - m[1] * m[1];
+    v[M_PZZ] = s[5] * invN - m[2] * m[2];
+    v[M_PXY] = s[6] * invN - m[0] * m[1];
+    v[M_PXZ] = s[7] * invN - m[0] * m[2];
+    v[M_PYZ] = s[8] * invN - m[1] * m[2];
+    v[M_EROT] = s[12] * invN;
+    v[M_IBAR] = s[16] * invN;
 #pragma unroll
-  for (int k = 0; k < 17; ++k) s[k] = 0.0;
-  for (int64_t i = o0 + lane; i < o1; i += 64) {
-    const double Cx = (double)p.cx[i] - Ux, Cy = (double)p.cy[i] - Uy, Cz = (double)p.cz[i] - Uz;
-    const double e = (double)p.erot[i], I = (double)p.vib[i];
-    const double hC2 = 0.5 * (Cx * Cx + Cy * Cy + Cz * Cz);
-    s[0] += Cx * Cx; s[1] += Cy * Cy; s[2] += Cz * Cz;
-    s[3] += Cx * Cy; s[4] += Cx * Cz; s[5] += Cy * Cz;
-    s[6] += e; s[7] += I;
-    s[8] += hC2 * Cx; s[9] += hC2 * Cy; s[10] += hC2 * Cz;
-    s[11] += Cx * e; s[12] += Cy * e; s[13] += Cz * e;
-    s[14] += Cx * I; s[15] += Cy * I; s[16] += Cz * I;
+    for (int k = 0; k < 3; ++k) {
+      v[M_QTRX + k] = 0.5 * (s[9 + k] - m[k] * tr - 2.0 * Sm[k] + 2.0 * Nd * mm * m[k]) * invN;
+      v[M_QROTX + k] = (s[13 + k] - m[k] * s[12]) * invN;
+      v[M_QIX + k] = (s[17 + k] - m[k] * s[16]) * invN;
+    }
   }
+  // lane k of the row stores moments k and k + 16
+  double w0 = 0.0, w1 = 0.0;
 #pragma unroll
-  for (int k = 0; k < 17; ++k) s[k] = wave_sum(s[k]);
-  if (lane == 0) {
-    mom[M_N * M + c] = (double)N;
-    mom[M_UX * M + c] = Ux;
-    mom[M_UY * M + c] = Uy;
-    mom[M_UZ * M + c] = Uz;
+  for (int k = 0; k < NMOM; ++k) {
+    if (k == sub) w0 = v[k];
+    if (k == sub + MOM_LANES) w1 = v[k];
   }
-  if (lane < 17) {
-    double v = 0.0;
-#pragma unroll
-    for (int k = 0; k < 17; ++k)
-      if (k == lane) v = s[k];
-    mom[(M_PXX + lane) * M + c] = v * invN;
-  }
+  mom[sub * M + c] = w0;
+  if (sub + MOM_LANES < NMOM) mom[(sub + MOM_LANES) * M + c] = w1;
 }
 
 // Per-cell state (Secs. II.A, III.A.1, III.A.2, IV.A, IV.B).
@@ -178,7 +226,7 @@ __global__ void k_stencil(GridP g, double* cs) {
 template <typename S>
 hipError_t launch_moments(const GridP& g, const PartP<S>& p, const int64_t* offsets, double* mom,
                           hipStream_t st) {
-  k_moments<S><<<cdiv(g.M, CELL_WAVES), CELL_BLOCK, 0, st>>>(g, p, offsets, mom);
+  k_moments<S><<<cdiv(g.M * MOM_LANES, CELL_BLOCK), CELL_BLOCK, 0, st>>>(g, p, offsets, mom);
   return hipGetLastError();
 }
 

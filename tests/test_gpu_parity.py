@@ -382,6 +382,23 @@ def test_conserve_vibrational_picks_exact(f32):
             assert got in (delta[c], delta[c] + 1), (c, got, delta[c])
 
 
+def _axis(v, o, d, n):
+    """Cell index along one axis by definition: the number of interior edges
+    e_k = fl32(o + k d) (k = 1..n-1) at or below v; -1 outside [e_0, e_n)."""
+    e = (o + np.arange(n + 1, dtype=np.float64) * d).astype(np.float32).astype(np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    k = np.searchsorted(e[1:n], v, side="right")
+    return np.where((v >= e[0]) & (v < e[n]), k, -1)
+
+
+def cell_index(g, x, y):
+    iy = _axis(y, g.y0, g.dy, g.ny)
+    if g.dim == 1:
+        return iy.astype(np.int32)
+    ix = _axis(x, g.x0, g.dx, g.nx)
+    return np.where((ix >= 0) & (iy >= 0), iy * g.nx + ix, -1).astype(np.int32)
+
+
 @pytest.mark.parametrize("kind", ["2d", "1d", "0d"])
 def test_bin_fast_route_far_moves_deletions_tail(kind):
     """Rebin of a binned state (the route that uses the previous offsets)
@@ -407,8 +424,12 @@ def test_bin_fast_route_far_moves_deletions_tail(kind):
             x[sel] += rng.choice([-5, -2, 2, 4], len(sel)) * g.dx
             x = np.clip(x, g.x0, g.x0 + g.nx * g.dx * (1 - 1e-6))
             B["x"][:n] = torch.as_tensor(x.astype(np.float32))
-    dead = rng.choice(n, max(1, n // 100), replace=False)
     cell = st["cell"].copy()
+    if g.dim >= 1:
+        # moved particles carry their new cell, as the flight leaves it
+        f32 = lambda a: a.astype(np.float32).astype(np.float64)
+        cell = cell_index(g, f32(x) if g.dim == 2 else None, f32(y))
+    dead = rng.choice(n, max(1, n // 100), replace=False)
     cell[dead] = -1
     B["cell"][:n] = torch.as_tensor(cell)
     # append a tail of new particles (copies of random ones, fresh ids)

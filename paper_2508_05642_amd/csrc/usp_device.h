@@ -194,13 +194,19 @@ __device__ __forceinline__ S edge(double o, double d, int k) {
   return (S)__dadd_rn(o, __dmul_rn((double)k, d));
 }
 
-// (id = 1/d gives the first guess; the two correction loops make the
-// index exact against the edge table whatever the guess)
+// (id = 1/d gives the first guess.  The stored edges lie within a small
+// fraction of a cell of o + k d, so the guess is normally right or off by
+// one and the common path checks it against its two edges; otherwise the
+// correction loops make the index exact against the edge table.)
 template <typename S>
 __device__ __forceinline__ int axis_index(S v, double o, double d, double id, int n) {
   if (!(v >= edge<S>(o, d, 0)) || v >= edge<S>(o, d, n)) return -1;
   int k = (int)floor(((double)v - o) * id);
   k = k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
+  const S e0 = edge<S>(o, d, k), e1 = edge<S>(o, d, k + 1);
+  if (e0 <= v && v < e1) return k;
+  if (v < e0 && k > 0 && edge<S>(o, d, k - 1) <= v) return k - 1;
+  if (v >= e1 && k < n - 1 && v < edge<S>(o, d, k + 2)) return k + 1;
   while (k > 0 && edge<S>(o, d, k) > v) --k;
   while (k < n - 1 && edge<S>(o, d, k + 1) <= v) ++k;
   return k;
@@ -244,11 +250,33 @@ __device__ __forceinline__ void flush_events(int64_t* counters, uint32_t ev, int
 // ---------------------------------------------------------------------------
 // wave64 / block reductions in a fixed order (deterministic)
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// FP64 sum over the 16 lanes of each row by DPP row permutes (swap of
+// neighbours, of pairs, mirror within 8, mirror within 16); every lane of
+// the row ends with the same bits (each step adds two operands whose
+// roles are mirrored in the partner lane).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
   return v;
+}
+
+// FP64 sum over a whole wave (all 64 lanes active): the four row sums,
+// then (r0 + r1) + (r2 + r3); the result is uniform.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = row16_sum(v);
+  auto lane_val = [&](int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+  };
+  return (lane_val(0) + lane_val(16)) + (lane_val(32) + lane_val(48));
 }
 
 }  // namespace usp

@@ -28,23 +28,6 @@ __device__ __forceinline__ void mom_add(const PartP<S>& p, int64_t i, double r0,
   s[16] += I; s[17] += d0 * I; s[18] += d1 * I; s[19] += d2 * I;
 }
 
-// Sum over a row of 16 lanes by DPP row permutes (swap of neighbours, of
-// pairs, mirror within 8, mirror within 16): every lane of the row ends
-// with the same bits (each step adds two equal-pattern operands).
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double row16_sum(double v) {
-  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141>(v);  // row_half_mirror
-  v += dpp_f64<0x140>(v);  // row_mirror
-  return v;
-}
-
 // 16 lanes per cell, four cells per wave (every lane stays active for the
 // row permutes; lanes of cells past M carry zeros).
 constexpr int MOM_LANES = 16;

@@ -488,6 +488,18 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// One level up (+1) or down (-1) for level byte b, by an integer atomic on
+// the aligned 32-bit word that holds it (LDS or global).  The caller's
+// acceptance keeps every level within [0, VIB_MAX], so no carry or borrow
+// reaches a neighbouring byte, and the atomics commute.
+__device__ __forceinline__ void level_step(uint8_t* b, int dir) {
+  const uintptr_t a = (uintptr_t)b;
+  uint32_t* w = (uint32_t*)(a & ~(uintptr_t)3);
+  const uint32_t one = 1u << (8 * (unsigned)(a & 3));
+  if (dir > 0) atomicAdd(w, one);
+  else atomicSub(w, one);
+}
+
 // The vibrational correction of Sec. IV.C, |I_delta| single-level moves on
 // particles picked uniformly at random (draw j: counter (cell, step, 2, j/4),
 // word j%4; a decrement that hits level 0, or an increment that hits the top
@@ -497,10 +509,12 @@ __device__ __forceinline__ void wave_sync_lds() {
 // after the accepted earlier draws on k, still allows the move, i.e. iff
 // dup < L (decrement) or L + dup < VIB_MAX (increment), dup being the number
 // of earlier draws of the chunk on k; only the first |I_delta| accepted draws
-// are applied.  Gives up after 64 N draws or when a decrement is impossible.
-// Returns 1 if any level changed; *SI is updated.  Called by a whole wave.
+// are applied, each as one level step.  When no level can reach VIB_MAX
+// (`low`), every increment is accepted and dup is not needed.  Gives up
+// after 64 N draws or when a decrement is impossible.  Returns 1 if any
+// level changed; *SI is updated.  Called by a whole wave.
 __device__ int wave_picks(uint8_t* lv, int64_t N, int64_t Id, int64_t* SI_io, uint32_t c,
-                          uint32_t step, uint64_t seed, int64_t* counters) {
+                          uint32_t step, uint64_t seed, bool low, int64_t* counters) {
   const int lane = threadIdx.x & 63;
   const int64_t maxatt = 64 * N;
   int64_t att = 0, SI = *SI_io;
@@ -512,6 +526,7 @@ __device__ int wave_picks(uint8_t* lv, int64_t N, int64_t Id, int64_t* SI_io, ui
       if (lane == 0) count_event(counters, USP_CNT_PICK_FAIL);
       break;
     }
+    const int64_t need = Id > 0 ? Id : -Id;
     const bool valid = att + lane < maxatt;
     const uint32_t j = jbase + (uint32_t)lane;
     const U4 w = philox(c, step, TAG_CONSERVE, j >> 2, seed);
@@ -519,15 +534,20 @@ __device__ int wave_picks(uint8_t* lv, int64_t N, int64_t Id, int64_t* SI_io, ui
     int64_t k = (int64_t)floor(u01d(wj) * Nd);
     if (k >= N) k = N - 1;
     const int kk = (int)k;
-    int dup = 0;
-    for (int l = 0; l < 64; ++l) {
-      const int kl = __builtin_amdgcn_readlane(kk, l);
-      dup += (l < lane && kl == kk) ? 1 : 0;
+    bool acc;
+    if (Id > 0 && low) {
+      acc = valid;
+    } else {
+      int dup = 0;
+#pragma unroll
+      for (int l = 0; l < 64; ++l) {
+        const int kl = __builtin_amdgcn_readlane(kk, l);
+        dup += (l < lane && kl == kk) ? 1 : 0;
+      }
+      const int L = valid ? (int)lv[k] : 0;
+      acc = valid && (Id > 0 ? (L + dup < VIB_MAX) : (dup < L));
     }
-    const int L = valid ? (int)lv[k] : 0;
-    const bool acc = valid && (Id > 0 ? (L + dup < VIB_MAX) : (dup < L));
     const uint64_t accm = __ballot(acc);
-    const int64_t need = Id > 0 ? Id : -Id;
     const int nacc = __popcll(accm);
     uint64_t applied;
     int consumed;
@@ -542,20 +562,9 @@ __device__ int wave_picks(uint8_t* lv, int64_t N, int64_t Id, int64_t* SI_io, ui
       applied = accm;
       consumed = (int)__popcll(__ballot(valid));
     }
-    const bool app = (applied >> lane) & 1ull;
-    // the first applied lane of each particle writes the combined move
-    int cnt = 0;
-    bool first = app;
-    for (int l = 0; l < 64; ++l) {
-      const int kl = __builtin_amdgcn_readlane(kk, l);
-      if (((applied >> l) & 1ull) && kl == kk) {
-        ++cnt;
-        if (l < lane) first = false;
-      }
-    }
     const int napp = (int)__popcll(applied);
     wave_sync_lds();
-    if (first) lv[k] = (uint8_t)(Id > 0 ? L + cnt : L - cnt);
+    if ((applied >> lane) & 1ull) level_step(lv + k, Id > 0 ? 1 : -1);
     wave_sync_lds();
     if (napp) moved = 1;
     SI += Id > 0 ? napp : -napp;
@@ -582,6 +591,7 @@ __device__ __forceinline__ void conserve_cell(const GasP& gas, const double* __r
   const int64_t N = o1 - o0;
   const double Un[3] = {cs[CS_UX * M + c], cs[CS_UY * M + c], cs[CS_UZ * M + c]};
   double s[6] = {0, 0, 0, 0, 0, 0};
+  int lmax = 0;
   for (int64_t i = o0 + lane; i < o1; i += 64) {
     const int64_t j = i - base;
     const double d0 = (double)vcx[j] - Un[0], d1 = (double)vcy[j] - Un[1],
@@ -591,6 +601,7 @@ __device__ __forceinline__ void conserve_cell(const GasP& gas, const double* __r
     s[4] += (double)verot[j];
     const uint8_t v = vvib[j];
     s[5] += (double)v;
+    lmax = v > lmax ? v : lmax;
     if (copy) lv[i - o0] = v;
   }
 #pragma unroll
@@ -604,7 +615,10 @@ __device__ __forceinline__ void conserve_cell(const GasP& gas, const double* __r
   int64_t SI = (int64_t)s[5];
   const double X = Nd * cs[CS_EVIB_NEW * M + c] / RTh - (double)SI;
   const int64_t Id0 = (int64_t)floor(X + u01d(philox((uint32_t)c, step, TAG_CONSERVE, 0u, seed).w[0]));
-  const int moved = wave_picks(lv, N, Id0, &SI, (uint32_t)c, step, seed, counters);
+  // no level can reach VIB_MAX through these increments
+  const int64_t need0 = Id0 > 0 ? Id0 : 0;
+  const bool low = !__ballot((int64_t)lmax + need0 >= VIB_MAX);
+  const int moved = wave_picks(lv, N, Id0, &SI, (uint32_t)c, step, seed, low, counters);
   double frot = 0.0, sc = 0.0;
   if (lane == 0) {
     const double etr_s = 0.5 * (s[3] / Nd - (m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2]));

@@ -485,3 +485,41 @@ def test_update_fused_equals_phases(kind, f32):
                                        if isinstance(sa[f], np.ndarray)})
                 assert bad.size == 0, (s, k)
         assert a.cnt() == b.cnt(), (a.cnt(), b.cnt())
+
+
+@pytest.mark.parametrize("kind", ["2d", "1d"])
+def test_bin_positions_on_edges(kind):
+    """Cell index of positions exactly on the stored cell edges and one ulp
+    either side (domain ends included): identical to the oracle's bin."""
+    usp = _usp()
+    prob, parts = make(kind, True)
+    g = prob.grid
+    n = parts["n"]
+    rng = np.random.default_rng(5)
+
+    def edge_values(o, d, m, size):
+        e = (o + np.arange(m + 1, dtype=np.float64) * d).astype(np.float32)
+        k = rng.integers(0, m + 1, size)
+        v = e[k]
+        side = rng.integers(0, 3, size)
+        v = np.where(side == 1, np.nextafter(v, np.float32(np.inf)), v)
+        v = np.where(side == 2, np.nextafter(v, np.float32(-np.inf)), v)
+        hi = np.nextafter(e[m], np.float32(-np.inf))
+        return np.clip(v, e[0], hi).astype(np.float32)
+
+    sel = rng.choice(n, n // 4, replace=False)
+    parts = dict(parts)
+    parts["y"] = parts["y"].copy()
+    parts["y"][sel] = edge_values(g.y0, g.dy, g.ny, len(sel))
+    if g.dim == 2:
+        parts["x"] = parts["x"].copy()
+        parts["x"][sel] = edge_values(g.x0, g.dx, g.nx, len(sel))
+    gpu = usp.DeviceState(prob, parts)
+    orc = oracle.Sim(prob, parts)
+    gpu.bin()
+    orc.bin()
+    a, b = gpu.state(), orc.state()
+    assert a["n"] == b["n"]
+    assert np.array_equal(gpu.offsets.cpu().numpy(), orc.offsets)
+    assert np.array_equal(a["pid"], b["pid"])
+    assert np.array_equal(a["cell"], b["cell"])

@@ -24,6 +24,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64
+# instruction per SIMD every 4 cycles (16 lanes per cycle)
+VALU_PEAK = 256 * 4 * 2.4e9 / 4
+COUNTERS_MD = os.path.join(ROOT, "profiles", "counters_cylinder_600x300.md")
 METRIC = "particle-steps/s (full USP-FPM step) + HBM GB/s; adjoint/forward time ratio"
 PHASES = ("bin", "moments", "reconstruct", "update")
 # the kernel that dominates each phase (bin is a pipeline of small kernels
@@ -53,6 +57,25 @@ def algorithmic_bytes(phase, n, M):
     per_cell = {"bin": 4 + 8, "moments": 21 * 8 + 8, "reconstruct": (21 + 35) * 8 + 128,
                 "update": 128 + 9 * 8 + 8}[phase]
     return per_particle * n + per_cell * M
+
+
+def stored_counters(kernel):
+    """Per-launch PMC figures of `kernel` from the committed profile summary,
+    or None when they were taken on other sources or flags than the library
+    being run (fingerprint mismatch)."""
+    from paper_2508_05642_amd import build
+    try:
+        lines = open(COUNTERS_MD).read().splitlines()
+    except OSError:
+        return None
+    fp = build.fingerprint()
+    for ln in lines:
+        if not ln.startswith("counters:"):
+            continue
+        kv = dict(t.split("=", 1) for t in ln.split()[1:])
+        if kv.get("kernel") == kernel and kv.get("fingerprint") == fp:
+            return {k: (float(v) if k not in ("kernel", "fingerprint") else v) for k, v in kv.items()}
+    return None
 
 
 def log(msg):
@@ -114,12 +137,25 @@ def run_gpu(args):
     total_ps = float(ns.sum())
     n_mean = float(ns.mean())
     dom = max(PHASE_KERNEL, key=lambda p: phase_ms[p])
-    ach = algorithmic_bytes(dom, n_mean, M) / (phase_ms[dom] * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": PHASE_KERNEL[dom], "phase": dom,
-            "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-            "avg_ms": round(phase_ms[dom], 4),
-            "algorithmic_bytes_per_launch": int(algorithmic_bytes(dom, n_mean, M))}
+    t_dom = phase_ms[dom] * 1e-3
+    hbm = {"achieved": round(algorithmic_bytes(dom, n_mean, M) / t_dom / 1e9, 1),
+           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(algorithmic_bytes(dom, n_mean, M) / t_dom / 1e9 / HBM_PEAK_GBS, 4),
+           "algorithmic_bytes_per_launch": int(algorithmic_bytes(dom, n_mean, M))}
+    ctr = stored_counters(PHASE_KERNEL[dom])
+    if ctr:
+        # VALU wave-instructions per particle (PMC, same sources and flags,
+        # same steps) x particles per launch / event-timed launch
+        ach = ctr["valu_per_particle"] * n_mean / t_dom
+        roof = {"bound": "alu", "kernel": PHASE_KERNEL[dom], "phase": dom,
+                "achieved": round(ach / 1e9, 2), "peak": round(VALU_PEAK / 1e9, 1),
+                "unit": "G VALU wave-instr/s", "frac": round(ach / VALU_PEAK, 4),
+                "traffic": int(ctr["fetch_bytes"] + ctr["write_bytes"]),
+                "valu_per_particle": ctr["valu_per_particle"], "avg_ms": round(phase_ms[dom], 4),
+                "hbm": hbm}
+    else:
+        roof = dict(bound="hbm", kernel=PHASE_KERNEL[dom], phase=dom, traffic=None,
+                    avg_ms=round(phase_ms[dom], 4), **hbm)
     step_bytes = sum(algorithmic_bytes(p, n_mean, M) for p in PHASES)
     cnt = st.cnt()
     res = dict(

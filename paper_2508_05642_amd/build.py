@@ -25,6 +25,20 @@ HIPCC_FLAGS = [
 ]
 
 
+def fingerprint():
+    """SHA-256 of every kernel source, the public header and the compiler
+    flags: identifies the code that a stored counter measurement belongs
+    to."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in SRC + HDR:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    h.update(" ".join(HIPCC_FLAGS).encode())
+    return h.hexdigest()[:16]
+
+
 def stale():
     if not os.path.exists(LIB):
         return True

@@ -262,8 +262,28 @@ usp_status usp_update(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc
                       void* ws, size_t ws_bytes, uint64_t seed, uint64_t step,
                       int64_t* counters, void* stream);
 
+/* nsteps full steps of independent 0D cells (dim 0) in few launches: per
+   step the moments and cell state of each cell (Secs. II.A, III.A, IV.A,
+   IV.B), the particle update and the conservation (Secs. III.A-III.B, IV.C),
+   with no rebin (0D particles never change cell).  A workgroup owns a tile
+   of whole cells and keeps their particles in LDS for all the steps of a
+   launch.  Bit-identical to usp_step on the same state.
+   p must be binned with `offsets` (count[0] == offsets[M]; a first
+   usp_bin or usp_step leaves it so).  dt_cell (device double[M], may be
+   NULL) overrides dt per cell.  mom and cs as for usp_moments /
+   usp_reconstruct; they describe the last step's pre-collision state on
+   return.  tile: particle slots per tile window (512, 1024 or 2048; 0 =
+   1024; FP64 states: 0 or 512).  steps_per_launch: steps each launch runs
+   (0 = all nsteps in one launch).  Errors: USP_EINVAL for dim != 0, a
+   null or inconsistent argument, a tile value not listed, or a short ws. */
+usp_status usp_batch(const usp_grid* grid, const usp_gas* gas, double dt, const double* dt_cell,
+                     usp_particles* p, const int64_t* offsets, double* mom, double* cs, void* ws,
+                     size_t ws_bytes, int32_t tile, int32_t steps_per_launch, uint64_t seed,
+                     uint64_t step, int32_t nsteps, int64_t* counters, void* stream);
+
 /* nsteps full steps (bin, moments, reconstruct, then the fused particle
-   phase of usp_update) starting at step index `step`.  p and p_alt are the two particle buffers;
+   phase of usp_update) starting at step index `step`; in 0D only the first
+   step bins.  p and p_alt are the two particle buffers;
    on return *p describes the buffer that holds the state (the two structs
    are swapped as needed); p_alt->capacity >= p->capacity and ws is sized
    for p_alt->capacity.  offsets, mom, cs as above (they describe the last

@@ -140,13 +140,17 @@ usp_status do_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, d
   for (int32_t s = 0; s < nsteps; ++s) {
     const uint64_t sn = step + (uint64_t)s;
     // from the second step on, the input is the previous step's binned
-    // state (segments in `offsets`) followed by the injected particles
-    hipError_t e = launch_bin<S>(g, make_parts<S>(p), make_parts<S>(p_alt), offsets,
-                                 s > 0 ? offsets : nullptr, w, L, counters, st);
-    if (e != hipSuccess) return USP_EDEVICE;
-    const usp_particles tmp = *p;
-    *p = *p_alt;
-    *p_alt = tmp;
+    // state (segments in `offsets`) followed by the injected particles; in
+    // 0D nothing moves between cells, so only the first step bins
+    hipError_t e = hipSuccess;
+    if (s == 0 || g.dim != 0) {
+      e = launch_bin<S>(g, make_parts<S>(p), make_parts<S>(p_alt), offsets,
+                        s > 0 ? offsets : nullptr, w, L, counters, st);
+      if (e != hipSuccess) return USP_EDEVICE;
+      const usp_particles tmp = *p;
+      *p = *p_alt;
+      *p_alt = tmp;
+    }
     const PartP<S> q = make_parts<S>(p);
     if ((e = launch_moments<S>(g, q, offsets, mom, st)) != hipSuccess) return USP_EDEVICE;
     if ((e = launch_reconstruct(g, gp, mom, dt, dt_cell, cs, counters, st)) != hipSuccess) return USP_EDEVICE;
@@ -295,6 +299,25 @@ usp_status usp_update(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc
   return hip_status(p->prec == USP_F32
                         ? launch_update<float>(g, gp, bp, dt, cs, offsets, make_parts<float>(p), seed, step, (char*)ws, L, counters, st)
                         : launch_update<double>(g, gp, bp, dt, cs, offsets, make_parts<double>(p), seed, step, (char*)ws, L, counters, st));
+}
+
+usp_status usp_batch(const usp_grid* grid, const usp_gas* gas, double dt, const double* dt_cell,
+                     usp_particles* p, const int64_t* offsets, double* mom, double* cs, void* ws,
+                     size_t ws_bytes, int32_t tile, int32_t steps_per_launch, uint64_t seed,
+                     uint64_t step, int32_t nsteps, int64_t* counters, void* stream) {
+  if (!grid_ok(grid) || grid->dim != 0 || !gas_ok(gas) || !parts_ok(p, grid)) return USP_EINVAL;
+  if (!offsets || !mom || !cs || !ws || nsteps < 0 || steps_per_launch < 0) return USP_EINVAL;
+  if (!dt_cell && !(dt > 0.0)) return USP_EINVAL;
+  if (tile != 0 && tile != 512 && tile != 1024 && tile != 2048) return USP_EINVAL;
+  if (p->prec == USP_F64 && tile != 0 && tile != 512) return USP_EINVAL;
+  if (ws_bytes < usp_workspace_bytes(grid, p->capacity)) return USP_EINVAL;
+  const GridP g = make_grid(grid);
+  const GasP gp = make_gas(gas);
+  const WsLayout L = ws_layout(g.M, p->capacity, n_faces(g));
+  hipStream_t st = (hipStream_t)stream;
+  return hip_status(p->prec == USP_F32
+                        ? launch_batch<float>(g, gp, dt, dt_cell, mom, cs, offsets, make_parts<float>(p), tile, steps_per_launch, seed, step, nsteps, (char*)ws, L, counters, st)
+                        : launch_batch<double>(g, gp, dt, dt_cell, mom, cs, offsets, make_parts<double>(p), tile, steps_per_launch, seed, step, nsteps, (char*)ws, L, counters, st));
 }
 
 usp_status usp_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,

@@ -1,0 +1,127 @@
+// usp_batch.hip -- many independent 0D cells advanced several steps per
+// launch (the persistent form of the step for dim 0).
+//
+// In 0D no particle changes cell and no cell reads a neighbour, so a
+// workgroup that owns a tile of whole cells can run step after step without
+// any grid-wide synchronisation: per step the moments and cell state of its
+// cells (16 lanes per cell), the particle update (thread per particle) and
+// the conservation (wave per cell), all on an LDS stage that holds the
+// tile's velocities, rotational energies and levels from the first step to
+// the last.  Tiles larger than the stage run in place in global memory.
+// Every phase calls the device functions of the step kernels in the same
+// order, so the result is bit-identical to usp_step on the same state.
+#include "usp_tile.h"
+
+namespace usp {
+
+template <typename S, bool STAGED, int CAP>
+__device__ __forceinline__ void batch_tile(const GridP& g, const GasP& gas, double dt,
+                                           const double* dt_cell, double* mom, double* cs,
+                                           const int64_t* __restrict__ offsets,
+                                           const PartP<S>& p, int64_t c0, int64_t c1,
+                                           int64_t i0, int64_t i1, const Stage<S>& st,
+                                           uint16_t* esc_list, int* nesc, uint64_t seed,
+                                           uint64_t step0, int nsteps, int64_t* counters) {
+  if (STAGED) {
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += UPD_BLOCK) st.store(i, load_state(p, i));
+    __syncthreads();
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    const uint32_t step = (uint32_t)(step0 + (uint64_t)s);
+    tile_cells<S>(g, gas, dt, dt_cell, mom, cs, offsets, c0, c1, st, counters);
+    __syncthreads();
+    tile_update<S, CAP, true>(g, gas, cs, p, i0, i1, st, st, esc_list, nesc, seed, step,
+                              counters);
+    tile_conserve<S>(gas, cs, g.M, offsets, c0, c1, st, seed, step, counters);
+    __syncthreads();
+  }
+  if (STAGED) {
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += UPD_BLOCK) {
+      const PartNew<S> v = st.load(i);
+      p.cx[i] = v.cx; p.cy[i] = v.cy; p.cz[i] = v.cz; p.erot[i] = v.erot; p.vib[i] = (uint8_t)v.vib;
+    }
+  }
+}
+
+// CAP = stage size (twice the tile window); WPE = waves per SIMD the
+// register budget is held to (what the stage's LDS allows).
+template <typename S, int CAP, int WPE>
+__global__ __launch_bounds__(UPD_BLOCK, WPE) void k_batch(GridP g, GasP gas, double dt,
+                                                          const double* dt_cell, double* mom,
+                                                          double* cs,
+                                                          const int64_t* __restrict__ offsets,
+                                                          const int32_t* __restrict__ first,
+                                                          PartP<S> p, uint64_t seed,
+                                                          uint64_t step0, int nsteps,
+                                                          int64_t* counters) {
+  __shared__ S scx[CAP], scy[CAP], scz[CAP], ser[CAP];
+  __shared__ uint8_t svb[CAP];
+  __shared__ uint16_t esc_list[CAP];
+  __shared__ int nesc;
+  const int64_t t = blockIdx.x;
+  const int64_t c0 = first[t], c1 = first[t + 1];
+  if (c0 >= c1) return;
+  const int64_t i0 = offsets[c0], i1 = offsets[c1];
+  if (i1 - i0 <= CAP) {
+    Stage<S> st;
+    st.cx = scx; st.cy = scy; st.cz = scz; st.erot = ser; st.vib = svb; st.base = i0;
+    batch_tile<S, true, CAP>(g, gas, dt, dt_cell, mom, cs, offsets, p, c0, c1, i0, i1, st,
+                             esc_list, &nesc, seed, step0, nsteps, counters);
+  } else {
+    batch_tile<S, false, CAP>(g, gas, dt, dt_cell, mom, cs, offsets, p, c0, c1, i0, i1,
+                              global_stage(p), esc_list, &nesc, seed, step0, nsteps, counters);
+  }
+}
+
+template <typename S, int TILE, int WPE>
+static hipError_t batch_launches(const GridP& g, const GasP& gas, double dt,
+                                 const double* dt_cell, double* mom, double* cs,
+                                 const int64_t* offsets, const PartP<S>& p, int spl,
+                                 uint64_t seed, uint64_t step, int nsteps, int32_t* first,
+                                 int64_t* counters, hipStream_t st) {
+  const int64_t ntiles = cdiv(p.capacity, TILE);
+  hipError_t e = launch_tiles(offsets, g.M, TILE, ntiles, first, st);
+  for (int s = 0; s < nsteps && e == hipSuccess; s += spl) {
+    const int k = nsteps - s < spl ? nsteps - s : spl;
+    k_batch<S, 2 * TILE, WPE><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, dt, dt_cell, mom, cs, offsets,
+                                                           first, p, seed, step + (uint64_t)s, k,
+                                                           counters);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+template <typename S>
+hipError_t launch_batch(const GridP& g, const GasP& gas, double dt, const double* dt_cell,
+                        double* mom, double* cs, const int64_t* offsets, const PartP<S>& p,
+                        int tile, int steps_per_launch, uint64_t seed, uint64_t step,
+                        int nsteps, char* ws, const WsLayout& L, int64_t* counters,
+                        hipStream_t st) {
+  int32_t* first = (int32_t*)(ws + L.tiles);
+  const int spl = steps_per_launch > 0 ? steps_per_launch : (nsteps > 0 ? nsteps : 1);
+  if (nsteps <= 0) return hipSuccess;
+  if constexpr (sizeof(S) == 4) {
+    if (tile == 512)
+      return batch_launches<S, 512, 4>(g, gas, dt, dt_cell, mom, cs, offsets, p, spl, seed, step,
+                                       nsteps, first, counters, st);
+    if (tile == 2048)
+      return batch_launches<S, 2048, 2>(g, gas, dt, dt_cell, mom, cs, offsets, p, spl, seed, step,
+                                        nsteps, first, counters, st);
+    return batch_launches<S, 1024, 4>(g, gas, dt, dt_cell, mom, cs, offsets, p, spl, seed, step,
+                                      nsteps, first, counters, st);
+  } else {
+    return batch_launches<S, 512, 4>(g, gas, dt, dt_cell, mom, cs, offsets, p, spl, seed, step,
+                                     nsteps, first, counters, st);
+  }
+}
+
+template hipError_t launch_batch<float>(const GridP&, const GasP&, double, const double*, double*,
+                                        double*, const int64_t*, const PartP<float>&, int, int,
+                                        uint64_t, uint64_t, int, char*, const WsLayout&, int64_t*,
+                                        hipStream_t);
+template hipError_t launch_batch<double>(const GridP&, const GasP&, double, const double*, double*,
+                                         double*, const int64_t*, const PartP<double>&, int, int,
+                                         uint64_t, uint64_t, int, char*, const WsLayout&,
+                                         int64_t*, hipStream_t);
+
+}  // namespace usp

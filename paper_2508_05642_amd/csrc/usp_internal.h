@@ -138,6 +138,17 @@ hipError_t launch_update(const GridP& g, const GasP& gas, const BcP& bc, double 
                          uint64_t seed, uint64_t step, char* ws, const WsLayout& L,
                          int64_t* counters, hipStream_t st);
 
+// first[t] (t = 0..ntiles) = first cell of tile t: the cells whose first
+// particle slot lies in [t T, (t+1) T)
+hipError_t launch_tiles(const int64_t* offsets, int64_t M, int64_t T, int64_t ntiles,
+                        int32_t* first, hipStream_t st);
+template <typename S>
+hipError_t launch_batch(const GridP& g, const GasP& gas, double dt, const double* dt_cell,
+                        double* mom, double* cs, const int64_t* offsets, const PartP<S>& p,
+                        int tile, int steps_per_launch, uint64_t seed, uint64_t step,
+                        int nsteps, char* ws, const WsLayout& L, int64_t* counters,
+                        hipStream_t st);
+
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace usp

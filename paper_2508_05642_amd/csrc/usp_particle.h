@@ -288,7 +288,8 @@ __device__ __forceinline__ bool fields_planes(const double* __restrict__ cs, int
   return clamped;
 }
 
-// New values of one particle (changed == false: the particle keeps its
+// Velocity, rotational energy and level of one particle: the values an
+// update reads (`in`) or produces (changed == false: the particle keeps its
 // state because its cell or the particle itself is skipped).
 template <typename S>
 struct PartNew {
@@ -297,10 +298,19 @@ struct PartNew {
   bool changed;
 };
 
+template <typename S>
+__device__ __forceinline__ PartNew<S> load_state(const PartP<S>& p, int64_t i) {
+  PartNew<S> v;
+  v.cx = p.cx[i]; v.cy = p.cy[i]; v.cz = p.cz[i]; v.erot = p.erot[i]; v.vib = p.vib[i];
+  v.changed = false;
+  return v;
+}
+
 // Draws and the velocity (eq. update_ci), rotational (eq. update_erot) and
 // vibrational (eq. update_evib) updates of particle i.
 template <typename S, typename T>
-__device__ __forceinline__ void update_particle(const PartP<S>& p, int64_t i, const T U[3],
+__device__ __forceinline__ void update_particle(const PartP<S>& p, int64_t i, const PartNew<S>& in,
+                                                const T U[3],
                                                 const PartCoef<T>& pc, T R, uint64_t seed,
                                                 uint32_t step, uint32_t* ev, PartNew<S>* o) {
   const uint32_t id = p.pid[i];
@@ -312,15 +322,15 @@ __device__ __forceinline__ void update_particle(const PartP<S>& p, int64_t i, co
   const T al = pc.al, oma2 = (T)pc.oma2;
   const T* L = pc.L;
   const T sq = sqrt(oma2);
-  const T Cx = (T)p.cx[i] - U[0], Cy = (T)p.cy[i] - U[1], Cz = (T)p.cz[i] - U[2];
+  const T Cx = (T)in.cx - U[0], Cy = (T)in.cy - U[1], Cz = (T)in.cz - U[2];
   o->cx = (S)(U[0] + al * Cx + sq * (L[0] * G1));
   o->cy = (S)(U[1] + al * Cy + sq * (L[1] * G1 + L[2] * G2));
   o->cz = (S)(U[2] + al * Cz + sq * (L[3] * G1 + L[4] * G2 + L[5] * G3));
   const T half = T(0.5) * R * pc.Trot_rel * oma2;
-  const T root = sqrt((T)p.erot[i]) * al + sqrt(half) * G4;
+  const T root = sqrt((T)in.erot) * al + sqrt(half) * G4;
   o->erot = (S)(half + root * root);
   // discrete decisions in FP64
-  const int I = p.vib[i];
+  const int I = in.vib;
   const double ms = (double)pc.mstar;
   const double pNB = 1.0 / (1.0 + ms * pc.oma2);
   double pB = (1.0 + ms) * pc.oma2;
@@ -353,8 +363,8 @@ __device__ __forceinline__ void note_coef_events(const PartCoef<double>& a, uint
 __device__ __forceinline__ PartNew<float> collide_f32(const GridP& g, const GasP& gas,
                                                      const double* __restrict__ cs,
                                                      const PartP<float>& p, int64_t i, int32_t c,
-                                                     uint64_t seed, uint32_t step, uint32_t* evp,
-                                                     bool* esc) {
+                                                     const PartNew<float>& in, uint64_t seed,
+                                                     uint32_t step, uint32_t* evp, bool* esc) {
   PartNew<float> o;
   o.changed = false;
   *esc = false;
@@ -408,7 +418,7 @@ __device__ __forceinline__ PartNew<float> collide_f32(const GridP& g, const GasP
     return o;
   }
   note_coef_events(pc, &ev);
-  if (!pc.skip) update_particle<float, float>(p, i, U, pc, (float)gas.R, seed, step, &ev, &o);
+  if (!pc.skip) update_particle<float, float>(p, i, in, U, pc, (float)gas.R, seed, step, &ev, &o);
   *evp |= ev;
   return o;
 }
@@ -421,7 +431,8 @@ __device__ __forceinline__ PartNew<float> collide_f32(const GridP& g, const GasP
 __device__ __forceinline__ PartNew<float> collide_esc(const GridP& g, const GasP& gas,
                                                      const double* __restrict__ cs,
                                                      const PartP<float>& p, int64_t i, int32_t c,
-                                                     uint64_t seed, uint32_t step, uint32_t* evp) {
+                                                     const PartNew<float>& in, uint64_t seed,
+                                                     uint32_t step, uint32_t* evp) {
   PartNew<float> o;
   o.changed = false;
   const int64_t M = g.M;
@@ -440,7 +451,7 @@ __device__ __forceinline__ PartNew<float> collide_esc(const GridP& g, const GasP
   uint32_t ev = 0;
   note_coef_events(pc, &ev);
   const float U[3] = {(float)Ud[0], (float)Ud[1], (float)Ud[2]};
-  if (!pc.skip) update_particle<float, float>(p, i, U, pc, (float)gas.R, seed, step, &ev, &o);
+  if (!pc.skip) update_particle<float, float>(p, i, in, U, pc, (float)gas.R, seed, step, &ev, &o);
   *evp |= ev;
   return o;
 }
@@ -449,10 +460,11 @@ __device__ __forceinline__ PartNew<float> collide_esc(const GridP& g, const GasP
 __device__ __forceinline__ PartNew<float> collide_one(const GridP& g, const GasP& gas,
                                                      const double* __restrict__ cs,
                                                      const PartP<float>& p, int64_t i, int32_t c,
-                                                     uint64_t seed, uint32_t step, uint32_t* evp) {
+                                                     const PartNew<float>& in, uint64_t seed,
+                                                     uint32_t step, uint32_t* evp) {
   bool esc;
-  PartNew<float> o = collide_f32(g, gas, cs, p, i, c, seed, step, evp, &esc);
-  if (esc) o = collide_esc(g, gas, cs, p, i, c, seed, step, evp);
+  PartNew<float> o = collide_f32(g, gas, cs, p, i, c, in, seed, step, evp, &esc);
+  if (esc) o = collide_esc(g, gas, cs, p, i, c, in, seed, step, evp);
   return o;
 }
 
@@ -460,7 +472,8 @@ __device__ __forceinline__ PartNew<float> collide_one(const GridP& g, const GasP
 __device__ __forceinline__ PartNew<double> collide_one(const GridP& g, const GasP& gas,
                                                       const double* __restrict__ cs,
                                                       const PartP<double>& p, int64_t i,
-                                                      int32_t c, uint64_t seed, uint32_t step,
+                                                      int32_t c, const PartNew<double>& in,
+                                                      uint64_t seed, uint32_t step,
                                                       uint32_t* evp) {
   PartNew<double> o;
   o.changed = false;
@@ -472,7 +485,7 @@ __device__ __forceinline__ PartNew<double> collide_one(const GridP& g, const Gas
   const CellCoef cc = coef_planes(cs, M, c);
   const PartCoef<double> pc = particle_coef<double>(gas.R, gas.theta, Tk[0], Tk[1], Tk[2], P, cc);
   note_coef_events(pc, &ev);
-  if (!pc.skip) update_particle<double, double>(p, i, U, pc, gas.R, seed, step, &ev, &o);
+  if (!pc.skip) update_particle<double, double>(p, i, in, U, pc, gas.R, seed, step, &ev, &o);
   *evp |= ev;
   return o;
 }

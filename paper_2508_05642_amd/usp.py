@@ -81,9 +81,11 @@ def lib():
         L.usp_conserve.argtypes = [vp, vp, vp, vp, vp, u64, u64, vp, vp]
         L.usp_advect.argtypes = [vp, vp, vp, d, vp, u64, u64, vp, sz, vp, vp]
         L.usp_update.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, sz, u64, u64, vp, vp]
+        L.usp_batch.argtypes = [vp, vp, d, vp, vp, vp, vp, vp, vp, sz, i32, i32, u64, u64, i32, vp,
+                                vp]
         L.usp_step.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, vp, vp, vp, sz, u64, u64, i32, vp, vp]
         for nm in ("usp_bin", "usp_moments", "usp_reconstruct", "usp_collide", "usp_conserve",
-                   "usp_advect", "usp_update", "usp_step"):
+                   "usp_advect", "usp_update", "usp_batch", "usp_step"):
             getattr(L, nm).restype = i32
         _lib = L
     return _lib
@@ -91,7 +93,7 @@ def lib():
 
 EXPORTED = ["usp_status_str", "usp_mom_name", "usp_cs_name", "usp_counter_name", "usp_version",
             "usp_workspace_bytes", "usp_cellstate_bytes", "usp_bin", "usp_moments", "usp_reconstruct", "usp_collide",
-            "usp_conserve", "usp_advect", "usp_update", "usp_step"]
+            "usp_conserve", "usp_advect", "usp_update", "usp_batch", "usp_step"]
 
 
 def names(kind):
@@ -156,6 +158,13 @@ def usp_collide(grid, gas, cs, offsets, p, seed, step, counters, stream=None):
 def usp_conserve(grid, gas, cs, offsets, p, seed, step, counters, stream=None):
     _check(lib().usp_conserve(C.byref(grid), C.byref(gas), _ptr(cs), _ptr(offsets), C.byref(p),
                               seed, step, _ptr(counters), _stream(stream)), "usp_conserve")
+
+
+def usp_batch(grid, gas, dt, dt_cell, p, offsets, mom, cs, ws, tile, steps_per_launch, seed, step,
+              nsteps, counters, stream=None):
+    _check(lib().usp_batch(C.byref(grid), C.byref(gas), dt, _ptr(dt_cell), C.byref(p), _ptr(offsets),
+                           _ptr(mom), _ptr(cs), _ptr(ws), ws.numel(), tile, steps_per_launch, seed,
+                           step, nsteps, _ptr(counters), _stream(stream)), "usp_batch")
 
 
 def usp_update(grid, gas, bc, dt, cs, offsets, p, seed, step, ws, counters, stream=None):
@@ -326,8 +335,16 @@ class DeviceState:
                  step, nsteps, self.counters, stream)
         if nsteps > 0:
             self.binned = True
-        # the library swapped the struct contents once per step
-        if nsteps % 2 == 1:
+        # the library swapped the struct contents once per rebin: a now
+        # describes the buffer that holds the state
+        if a.cx != self.bufs[self.cur]["cx"].data_ptr():
             B0, B1 = self.bufs[self.cur], self.bufs[1 - self.cur]
             B0["struct"], B1["struct"] = B1["struct"], B0["struct"]
             self.cur = 1 - self.cur
+
+    def batch(self, step, nsteps, tile=0, steps_per_launch=0, stream=None):
+        """nsteps steps of a binned 0D state with usp_batch (same bits as
+        step())."""
+        usp_batch(self.grid, self.gas, self.prob.dt, self.dt_cell, self.p, self.offsets, self.mom,
+                  self.cs, self.ws, tile, steps_per_launch, self.prob.seed, step, nsteps,
+                  self.counters, stream)

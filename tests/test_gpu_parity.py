@@ -523,3 +523,104 @@ def test_bin_positions_on_edges(kind):
     assert np.array_equal(gpu.offsets.cpu().numpy(), orc.offsets)
     assert np.array_equal(a["pid"], b["pid"])
     assert np.array_equal(a["cell"], b["cell"])
+
+
+def _snapshot(st):
+    keep = {"bufs": [{k: (v.clone() if torch.is_tensor(v) else None) for k, v in B.items()
+                      if k != "struct"} for B in st.bufs]}
+    for k in ("offsets", "mom", "cs", "counters"):
+        keep[k] = getattr(st, k).clone()
+    keep["cur"] = st.cur
+    keep["binned"] = st.binned
+    return keep
+
+
+def _restore(st, keep):
+    for B, S in zip(st.bufs, keep["bufs"]):
+        for k, v in S.items():
+            if v is not None:
+                B[k].copy_(v)
+    for k in ("offsets", "mom", "cs", "counters"):
+        getattr(st, k).copy_(keep[k])
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("f32,tile,spl", [(True, 0, 0), (True, 512, 1), (True, 2048, 2),
+                                          (False, 0, 0), (False, 512, 2)])
+def test_batch_equals_step(f32, tile, spl):
+    """usp_batch (several steps per launch, state held in LDS) gives the same
+    bits and counts as usp_step; the 0D problem has a cell of 3000 particles
+    (larger than the stage at tile 512/1024: in-place tiles) next to staged
+    ones, empty cells and single-particle cells."""
+    usp = _usp()
+    prob, parts = prob_0d(f32)
+    _say(f"[batch] f32={f32} tile={tile} spl={spl} n={parts['n']}")
+    a = usp.DeviceState(prob, parts)
+    b = usp.DeviceState(prob, parts)
+    a.step(10, 4)
+    b.step(10, 1)
+    b.batch(11, 3, tile, spl)
+    torch.cuda.synchronize()
+    sa, sb = a.state(), b.state()
+    assert sa["n"] == sb["n"]
+    for k in sa:
+        if isinstance(sa[k], np.ndarray):
+            assert np.array_equal(sa[k], sb[k]), k
+    assert a.cnt() == b.cnt(), (a.cnt(), b.cnt())
+    assert np.array_equal(a.moments(), b.moments())
+    assert np.array_equal(a.cellstate(), b.cellstate())
+
+
+def test_batch_c2_full_size():
+    """The batched 0D workload at full size (4096 cells, ~3.0M particles,
+    FP32) in one persistent launch: three steps against the oracle's, all
+    particles (the oracle runs them in about a second)."""
+    usp = _usp()
+    prob, parts = W.batch_c2()
+    _say(f"[batch c2] n={parts['n']} cells={prob.grid.ncells}")
+    gpu = usp.DeviceState(prob, parts)
+    orc = oracle.Sim(prob, parts)
+    gpu.step(0, 1)
+    gpu.batch(1, 2, 0, 0)
+    orc.step_native(0, 3)
+    a, b = gpu.state(), orc.state()
+    assert a["n"] == b["n"]
+    assert np.array_equal(a["pid"], b["pid"])
+    vs = vel_scale(prob, orc)
+    compare_states(a, b, prob, vs, 20 * _tol(True), "c2 3 steps", vib_min=0.999)
+    ca, cb = gpu.cnt(), orc.cnt()
+    for k in ("CELL_SKIP", "PICK_FAIL"):
+        assert ca[k] == cb[k], (k, ca[k], cb[k])
+
+
+def test_step_graph_replay():
+    """usp_step captured in a HIP graph (torch.cuda.graph) and replayed three
+    times, with eager work between replays, reproduces the eager steps bit
+    for bit each time."""
+    usp = _usp()
+    prob, parts = prob_2d(True)
+    st = usp.DeviceState(prob, parts)
+    st.step(0, 1)
+    torch.cuda.synchronize()
+    keep = _snapshot(st)
+    st.step(1, 2)
+    ref, ref_cnt = st.state(), st.cnt()
+    _restore(st, keep)
+    st.cur = keep["cur"]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        st.step(1, 2)
+    cur_after = st.cur
+    for rep in range(3):
+        _restore(st, keep)
+        scratch = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        graph.replay()
+        torch.cuda.synchronize()
+        st.cur = cur_after
+        got = st.state()
+        assert got["n"] == ref["n"], rep
+        for k in ref:
+            if isinstance(ref[k], np.ndarray):
+                assert np.array_equal(got[k], ref[k]), (rep, k)
+        assert st.cnt() == ref_cnt, rep
+        del scratch

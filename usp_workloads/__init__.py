@@ -226,6 +226,27 @@ def batch0d(counts, T_tr, T_rot, T_vib, dens, gas=None, dt=None, dt_cell=None, f
     return prob, parts
 
 
+def batch_c2(M=4096, seed=42, f32=True, gas=None):
+    """Independent 0D cells of uneven size (the batched-relaxation case):
+    N_c = round(exp(U[ln 16, ln 4096])) (mean ~736, ~3.0M in total),
+    T_tr ~ U[2000, 20000] K, T_rot and T_vib ~ U[200, 1000] K,
+    n ~ log-uniform on [1e21, 1e24] m^-3, VSS N2 with Z_rot = 5, Z_vib = 50.
+    The time step of cell c is an input: dt_c = 0.5 * 1.15e-8 s *
+    (1e23 / n_c) * (T_tr,c / 1e4)^(omega - 1), i.e. about half the initial
+    collision time of each cell (the collision time scales as mu/p ~
+    T^omega / (n T))."""
+    rng = np.random.default_rng(seed)
+    counts = np.rint(np.exp(rng.uniform(np.log(16), np.log(4096), M))).astype(np.int64)
+    T_tr = rng.uniform(2000, 20000, M)
+    T_rot = rng.uniform(200, 1000, M)
+    T_vib = rng.uniform(200, 1000, M)
+    dens = 10 ** rng.uniform(21, 24, M)
+    gas = gas or Gas(zrot_model=ZROT_CONST, Z_rot=5.0, zvib_model=ZVIB_CONST, Z_vib=50.0)
+    dt_cell = 0.5 * 1.15e-8 * (1e23 / dens) * (T_tr / 1e4) ** (gas.omega - 1.0)
+    return batch0d(counts, T_tr, T_rot, T_vib, dens, gas=gas, dt_cell=dt_cell, f32=f32,
+                   seed=seed)
+
+
 # --------------------------------------------------------------------------
 # 1D: Poiseuille channel (y between two diffuse walls, x periodic)
 # --------------------------------------------------------------------------

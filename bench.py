@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 # VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64
 # instruction per SIMD every 4 cycles (16 lanes per cycle)
 VALU_PEAK = 256 * 4 * 2.4e9 / 4
-COUNTERS_MD = os.path.join(ROOT, "profiles", "counters_cylinder_600x300.md")
+COUNTERS_GLOB = os.path.join(ROOT, "profiles", "counters_*.md")
 METRIC = "particle-steps/s (full USP-FPM step) + HBM GB/s; adjoint/forward time ratio"
 PHASES = ("bin", "moments", "reconstruct", "update")
 # the kernel that dominates each phase (bin is a pipeline of small kernels
@@ -63,11 +63,12 @@ def stored_counters(kernel):
     """Per-launch PMC figures of `kernel` from the committed profile summary,
     or None when they were taken on other sources or flags than the library
     being run (fingerprint mismatch)."""
+    import glob
     from paper_2508_05642_amd import build
-    try:
-        lines = open(COUNTERS_MD).read().splitlines()
-    except OSError:
-        return None
+    lines = []
+    for f in sorted(glob.glob(COUNTERS_GLOB)):
+        with open(f) as fh:
+            lines += fh.read().splitlines()
     fp = build.fingerprint()
     for ln in lines:
         if not ln.startswith("counters:"):
@@ -175,9 +176,9 @@ def run_gpu(args):
     return res, prob, parts
 
 
-def run_cpu_baseline(prob, parts, nsteps):
+def _oracle_steps(prob, parts, nsteps, threads=0):
     import oracle
-    sim = oracle.Sim(prob, parts)
+    sim = oracle.Sim(prob, parts, threads=threads)
     total = 0
     t0 = time.perf_counter()
     for s in range(nsteps):
@@ -188,17 +189,96 @@ def run_cpu_baseline(prob, parts, nsteps):
         sim.collide(s)
         sim.conserve(s)
         sim.advect(s)
-    dt = time.perf_counter() - t0
-    return {"value": round(total / dt, 1), "unit": "particle-steps/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"{nsteps} full steps of the same cylinder workload from its initial "
-                      f"state ({parts['n']} particles), FP64 oracle, {dt:.1f} s"}
+    return total, time.perf_counter() - t0
+
+
+def run_cpu_baseline(prob, parts, nsteps, one_core_steps=1, what="cylinder"):
+    """The oracle on all host threads for `nsteps` steps, and on one thread
+    for `one_core_steps` steps, from the workload's initial state."""
+    import oracle
+    all_threads = oracle.threads()
+    total, dt = _oracle_steps(prob, parts, nsteps)
+    res = {"value": round(total / dt, 1), "unit": "particle-steps/s", "cores": all_threads,
+           "kind": "oracle",
+           "sample": f"{nsteps} full steps of the same {what} workload from its initial state "
+                     f"({parts['n']} particles), FP64 oracle, {dt:.1f} s"}
+    if one_core_steps > 0:
+        t1, d1 = _oracle_steps(prob, parts, one_core_steps, threads=1)
+        res["value_1core"] = round(t1 / d1, 1)
+        res["sample_1core"] = f"{one_core_steps} step(s) on 1 thread, {d1:.1f} s"
+        oracle.lib().orc_set_threads(all_threads)
+    return res
+
+
+def run_gpu_c2(args):
+    """The batched 0D workload (4096 uneven cells, ~3.0M particles, FP32):
+    one usp_step bins it, the autotuner picks the usp_batch schedule, the
+    warmup runs eagerly, and the timed steps are one usp_batch call captured
+    in a HIP graph and replayed once."""
+    import torch
+
+    import usp_workloads as W
+    from paper_2508_05642_amd import autotune, usp
+
+    torch.cuda.set_device(0)
+    prob, parts = W.batch_c2()
+    n = parts["n"]
+    log(f"workload ready: {n} particles, {prob.grid.ncells} cells")
+    st = usp.DeviceState(prob, parts, device="cuda:0")
+    st.step(0, 1)
+    step = 1
+    tune = autotune.tune_batch(st, step=step, nsteps=8)
+    tile, spl = tune["tile"], tune["steps_per_launch"]
+    log(f"schedule: tile {tile}, steps per launch {spl or 'all'} "
+        f"({ {f'{k[0]}/{k[1]}': round(v, 4) for k, v in tune['ms_per_step'].items()} } ms/step)")
+    if args.warmup:
+        st.batch(step, args.warmup, tile, spl)
+        step += args.warmup
+    torch.cuda.synchronize()
+    K = args.steps
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        st.batch(step, K, tile, spl)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_ev = e0.elapsed_time(e1)
+    ctr = stored_counters("k_batch")
+    t_step = ms_ev * 1e-3 / K
+    if ctr:
+        ach = ctr["valu_per_particle"] * n / t_step
+        roof = {"bound": "alu", "kernel": "k_batch", "achieved": round(ach / 1e9, 2),
+                "peak": round(VALU_PEAK / 1e9, 1), "unit": "G VALU wave-instr/s",
+                "frac": round(ach / VALU_PEAK, 4),
+                "traffic": int((ctr["fetch_bytes"] + ctr["write_bytes"])),
+                "valu_per_particle": ctr["valu_per_particle"], "avg_ms": round(ms_ev, 3)}
+    else:
+        roof = {"bound": "alu", "kernel": "k_batch", "achieved": None, "peak": round(VALU_PEAK / 1e9, 1),
+                "unit": "G VALU wave-instr/s", "frac": None, "traffic": None,
+                "avg_ms": round(ms_ev, 3)}
+    res = dict(
+        metric=METRIC, value=round(n * K / wall, 1), unit="particle-steps/s", n_gpus=1, steps=K,
+        warmup=args.warmup, ms_per_step=round(wall / K * 1e3, 4), higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+        config={"workload": "batch0d_4096_uneven_cells", "particles": int(n), "cells": 4096,
+                "state": "f32", "accumulation": "f64", "schedule": {"tile": tile,
+                "steps_per_launch": spl}, "hip_graph": True, "parallelism": "single-gpu"},
+        roofline=roof, counters={k: v for k, v in st.cnt().items() if v},
+    )
+    return res, prob, parts
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--workload", choices=("cylinder", "c2"), default="cylinder",
+                    help="cylinder (the headline case) or c2 (4096 independent 0D cells)")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (cylinder 100, c2 500)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--scale", type=float, default=1.0,
                     help="grid scale of the cylinder workload (1.0 = full size)")
@@ -220,11 +300,19 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: 1 GiB read + 1 GiB written")
         del src, dst
-    res, prob, parts = run_gpu(args)
+    if args.steps is None:
+        args.steps = 500 if args.workload == "c2" else 100
+    if args.workload == "c2":
+        res, prob, parts = run_gpu_c2(args)
+    else:
+        res, prob, parts = run_gpu(args)
     log(f"GPU: {res['value']:.4g} particle-steps/s, {res['ms_per_step']} ms/step")
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = run_cpu_baseline(prob, parts, args.cpu_steps)
-        log(f"CPU oracle: {res['cpu_baseline']['value']:.4g} particle-steps/s")
+        res["cpu_baseline"] = run_cpu_baseline(
+            prob, parts, args.cpu_steps, one_core_steps=1,
+            what="cylinder" if args.workload == "cylinder" else "batched 0D")
+        log(f"CPU oracle: {res['cpu_baseline']['value']:.4g} particle-steps/s "
+            f"({res['cpu_baseline'].get('value_1core', 0):.4g} on 1 thread)")
     print(json.dumps(res), flush=True)
 
 

@@ -624,3 +624,21 @@ def test_step_graph_replay():
                 assert np.array_equal(got[k], ref[k]), (rep, k)
         assert st.cnt() == ref_cnt, rep
         del scratch
+
+
+def test_autotune_batch_leaves_state():
+    """The usp_batch schedule autotuner returns one of its candidates and
+    leaves the state it timed on unchanged, bit for bit."""
+    usp = _usp()
+    from paper_2508_05642_amd import autotune
+    prob, parts = prob_0d(True)
+    st = usp.DeviceState(prob, parts)
+    st.step(0, 1)
+    before, cnt = st.state(), st.cnt()
+    res = autotune.tune_batch(st, step=1, nsteps=2, reps=1)
+    assert (res["tile"], res["steps_per_launch"]) in autotune.CANDIDATES_F32
+    after = st.state()
+    for k in before:
+        if isinstance(before[k], np.ndarray):
+            assert np.array_equal(before[k], after[k]), k
+    assert st.cnt() == cnt

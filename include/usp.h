@@ -54,6 +54,15 @@ typedef int32_t usp_status;
 #define USP_PR_EUCKEN_STANDARD 1  /* xi_vib = 2x/(e^x - 1) */
 #define USP_PR_CONST 2
 
+/* particle scheme: the USP-FPM method (Secs. III-IV) or the first-order
+   FPM method (Secs. II.B-II.C: alpha = exp(-dt/tau), tau = 2 mu (1-nu)/p,
+   nu = 1 - 3/(2 Pr), cell relaxation temperatures of eqs. T_tr_FPM,
+   T_rot_FPM, T_vib_FPM, vibrational jumps by Gillespie's direct method;
+   its conservation keeps the sampled rotational energies and levels and
+   conserves momentum and total energy through the velocities) */
+#define USP_SCHEME_USP 0
+#define USP_SCHEME_FPM 1
+
 /* boundary kinds, per domain side */
 #define USP_BC_PERIODIC 0
 #define USP_BC_DIFFUSE 1     /* isothermal wall, full accommodation */
@@ -108,6 +117,7 @@ typedef struct {
   double Z_vib, C1, C2, sigma_vib, d_ref;
   int32_t pr_model;
   double Pr_const;
+  int32_t scheme;    /* USP_SCHEME_USP or USP_SCHEME_FPM */
 } usp_gas;
 
 /* Uniform Cartesian grid (the uniform grid of Sec. III.B).  volume and flags
@@ -163,7 +173,7 @@ typedef struct {
 /* Cell-state buffer: USP_NCS FP64 planes (names: usp_cs_name(k)) followed
    by one packed 128-byte record per cell that the particle update reads;
    usp_cellstate_bytes() gives its size. */
-#define USP_NCS 35
+#define USP_NCS 39
 
 const char* usp_status_str(usp_status s);
 const char* usp_mom_name(int32_t k);

@@ -22,7 +22,8 @@ MOM_NAMES = ["N", "UX", "UY", "UZ", "PXX", "PYY", "PZZ", "PXY", "PXZ", "PYZ", "E
 CS_NAMES = ["NP", "NDENS", "UX", "UY", "UZ", "TTR", "TROT", "TVIB",
             "PXX", "PYY", "PZZ", "PXY", "PXZ", "PYZ", "ETR", "EROT", "EVIB",
             "MU", "MUP", "TAUC", "ZROT", "ZVIB", "PR", "DT", "A", "B", "R2", "R3",
-            "ALPHA", "OMA2", "NU", "EROT_NEW", "EVIB_NEW", "COLLIDE", "NBR_OK"]
+            "ALPHA", "OMA2", "NU", "EROT_NEW", "EVIB_NEW", "COLLIDE", "NBR_OK",
+            "FPM_TAU", "FPM_TTR_REL", "FPM_TROT_REL", "FPM_MREL"]
 CNT_NAMES = ["PB_CLAMP", "CHOL_FALLBACK", "NU_ZERO", "TREL_SKIP", "TREL_CLAMP", "VIB_SAT",
              "INTERP_CLAMP", "CONS_SKIP", "PICK_FAIL", "CELL_SKIP", "INJECTED", "DELETED",
              "WALL_HITS", "BOUNCE_LIMIT", "CAPACITY", "SOLID_DROP"]
@@ -37,7 +38,8 @@ class OrcGas(C.Structure):
                 ("zrot_model", C.c_int32), ("Z_rot", C.c_double), ("Z_rot_inf", C.c_double),
                 ("T_star", C.c_double), ("zvib_model", C.c_int32), ("Z_vib", C.c_double),
                 ("C1", C.c_double), ("C2", C.c_double), ("sigma_vib", C.c_double),
-                ("d_ref", C.c_double), ("pr_model", C.c_int32), ("Pr_const", C.c_double)]
+                ("d_ref", C.c_double), ("pr_model", C.c_int32), ("Pr_const", C.c_double),
+                ("scheme", C.c_int32)]
 
 
 class OrcGrid(C.Structure):
@@ -126,7 +128,7 @@ def philox(ctr, key):
 def make_gas(g):
     return OrcGas(g.m, g.theta_vib, g.T_ref, g.mu_ref, g.omega, g.alpha_vss, g.zrot_model,
                   g.Z_rot, g.Z_rot_inf, g.T_star, g.zvib_model, g.Z_vib, g.C1, g.C2,
-                  g.sigma_vib, g.d_ref, g.pr_model, g.Pr_const)
+                  g.sigma_vib, g.d_ref, g.pr_model, g.Pr_const, getattr(g, "scheme", 0))
 
 
 class Gas:

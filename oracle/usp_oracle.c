@@ -388,23 +388,45 @@ int orc_cellstate(const orc_grid* gr, const orc_gas* g, const double* mom, doubl
       double tauc = K * mup;
       double zr = orc_zrot(g, Ttr), zv = orc_zvib(g, Ttr);
       double Pr = orc_prandtl(g, Ttr);
-      double A = 2.0 * mup;
-      double r3 = (A - Pr * dtc) / (A + Pr * dtc);
-      double r2 = (A - dtc) / (A + dtc);
-      double al = cbrt(r3);
-      double oma2 = 1.0 - al * al;
-      double nu = (r2 - al * al) / oma2;
-      double a = dtc / (dtc + 2.0 * zr * tauc);
-      double b = dtc / (dtc + 2.0 * zv * tauc);
-      double gm[3];
       double Trot = v[ORC_CS_TROT], Tvib = v[ORC_CS_TVIB];
-      orc_gammas(g, Ttr, Trot, Tvib, a, b, gm, NULL);
       v[ORC_CS_MU] = mu; v[ORC_CS_MUP] = mup; v[ORC_CS_TAUC] = tauc;
       v[ORC_CS_ZROT] = zr; v[ORC_CS_ZVIB] = zv; v[ORC_CS_PR] = Pr;
-      v[ORC_CS_A] = a; v[ORC_CS_B] = b; v[ORC_CS_R2] = r2; v[ORC_CS_R3] = r3;
-      v[ORC_CS_ALPHA] = al; v[ORC_CS_OMA2] = oma2; v[ORC_CS_NU] = nu;
-      v[ORC_CS_EROT_NEW] = v[ORC_CS_EROT] + gm[0] * (Ttr - Trot) - gm[2] * (Trot - Tvib);
-      v[ORC_CS_EVIB_NEW] = v[ORC_CS_EVIB] + gm[1] * (Ttr - Tvib) + gm[2] * (Trot - Tvib);
+      if (g->scheme == ORC_SCHEME_FPM) {
+        /* first-order FPM (Secs. II.B-II.C): nu from Pr, tau = 2 mu (1-nu)/p, */
+        /* the update factor exp(-dt/tau) and the relaxation temperatures of */
+        /* eqs. T_tr_FPM, T_rot_FPM, T_vib_FPM (cell values)                 */
+        double nu = 1.0 - 3.0 / (2.0 * Pr);
+        double tau = 2.0 * mup * (1.0 - nu);
+        double al = exp(-dtc / tau);
+        double oma2 = -expm1(-2.0 * dtc / tau);
+        double fr = tau / (2.0 * zr * tauc), fv = tau / (2.0 * zv * tauc);
+        double mv = orc_e_vib(g, Tvib) / (R * Th), mt = orc_e_vib(g, Ttr) / (R * Th);
+        double Ttr_rel = Ttr + (2.0 / 3.0) * (fr * (Trot - Ttr) + fv * Th * (mv - mt));
+        double Trot_rel = Trot + fr * (Ttr - Trot);
+        double mrel = mv + fv * (mt - mv);
+        v[ORC_CS_ALPHA] = al; v[ORC_CS_OMA2] = oma2; v[ORC_CS_NU] = nu;
+        v[ORC_CS_EROT_NEW] = v[ORC_CS_EROT];
+        v[ORC_CS_EVIB_NEW] = v[ORC_CS_EVIB];
+        v[ORC_CS_FPM_TAU] = tau;
+        v[ORC_CS_FPM_TTR_REL] = Ttr_rel;
+        v[ORC_CS_FPM_TROT_REL] = Trot_rel;
+        v[ORC_CS_FPM_MREL] = mrel;
+      } else {
+        double A = 2.0 * mup;
+        double r3 = (A - Pr * dtc) / (A + Pr * dtc);
+        double r2 = (A - dtc) / (A + dtc);
+        double al = cbrt(r3);
+        double oma2 = 1.0 - al * al;
+        double nu = (r2 - al * al) / oma2;
+        double a = dtc / (dtc + 2.0 * zr * tauc);
+        double b = dtc / (dtc + 2.0 * zv * tauc);
+        double gm[3];
+        orc_gammas(g, Ttr, Trot, Tvib, a, b, gm, NULL);
+        v[ORC_CS_A] = a; v[ORC_CS_B] = b; v[ORC_CS_R2] = r2; v[ORC_CS_R3] = r3;
+        v[ORC_CS_ALPHA] = al; v[ORC_CS_OMA2] = oma2; v[ORC_CS_NU] = nu;
+        v[ORC_CS_EROT_NEW] = v[ORC_CS_EROT] + gm[0] * (Ttr - Trot) - gm[2] * (Trot - Tvib);
+        v[ORC_CS_EVIB_NEW] = v[ORC_CS_EVIB] + gm[1] * (Ttr - Tvib) + gm[2] * (Trot - Tvib);
+      }
       v[ORC_CS_COLLIDE] = 1.0;
       int cut = gr->flags ? (gr->flags[c] & (ORC_FLAG_SOLID | ORC_FLAG_CUT)) : 0;
       v[ORC_CS_NBR_OK] = cut ? 0.0 : 1.0;
@@ -531,6 +553,88 @@ static int chol3(const double S[6], double L[6]) {
 /* Collision: the per-particle USP-FPM update (Secs. III.A.2, III.A.3 and   */
 /* the flow chart of Sec. IV.D).                                            */
 /* ======================================================================== */
+/* First-order FPM update of the particles of cell c (Sec. II.C): cell    */
+/* values throughout (no reconstruction); velocity by eq.                */
+/* conventionial-velo and rotation by eq. conventionial-erot (the same   */
+/* algebra as the USP-FPM updates with alpha = exp(-dt/tau)); the level  */
+/* by Gillespie's direct method for the jump rates of the master          */
+/* equation, omega_{I,I-1} = 2 I / (tau (1-q)), omega_{I,I+1} = 2 (I+1) q */
+/* / (tau (1-q)), q = exp(-Theta/T_vib^rel) = m_rel/(1+m_rel).  Draws:    */
+/* block 0 of (pid, step, collide) for the four normals, then blocks 1, */
+/* 2, ... two uniforms per jump attempt.  At most FPM_MAX_JUMPS attempts; */
+/* a cap or a level beyond the top counts as VIB_SAT.  A failed Cholesky */
+/* test of the cell's Lambda falls back to nu = 0.                        */
+#define FPM_MAX_JUMPS 4096
+static void fpm_cell(const orc_grid* gr, const orc_gas* g, const double* cs, int64_t c,
+                     int64_t o0, int64_t o1, orc_parts* p, uint64_t seed, uint64_t step,
+                     int32_t f32, int64_t* lc) {
+  int64_t M = ncells(gr);
+  double R = orc_R(g);
+  double U[3], P[6];
+  for (int k = 0; k < 3; ++k) U[k] = cs[(int64_t)(ORC_CS_UX + k) * M + c];
+  for (int k = 0; k < 6; ++k) P[k] = cs[(int64_t)(ORC_CS_PXX + k) * M + c];
+  const double Ttr = cs[(int64_t)ORC_CS_TTR * M + c];
+  const double al = cs[(int64_t)ORC_CS_ALPHA * M + c], oma2 = cs[(int64_t)ORC_CS_OMA2 * M + c];
+  const double nu = cs[(int64_t)ORC_CS_NU * M + c], dtc = cs[(int64_t)ORC_CS_DT * M + c];
+  const double tau = cs[(int64_t)ORC_CS_FPM_TAU * M + c];
+  const double Ttr_rel = cs[(int64_t)ORC_CS_FPM_TTR_REL * M + c];
+  double Trot_rel = cs[(int64_t)ORC_CS_FPM_TROT_REL * M + c];
+  double mrel = cs[(int64_t)ORC_CS_FPM_MREL * M + c];
+  const int64_t n = o1 - o0;
+  double Lam[6], L[6];
+  const double RT = R * Ttr;
+  for (int k = 0; k < 3; ++k) Lam[k] = R * Ttr_rel + nu * (P[k] - RT);
+  for (int k = 3; k < 6; ++k) Lam[k] = nu * P[k];
+  if (!chol3(Lam, L)) {
+    lc[ORC_CNT_CHOL_FALLBACK] += n;
+    lc[ORC_CNT_NU_ZERO] += n;
+    if (!(Ttr_rel > 0.0)) { lc[ORC_CNT_TREL_SKIP] += n; return; }
+    double s0 = sqrt(R * Ttr_rel);
+    L[0] = s0; L[1] = 0.0; L[2] = s0; L[3] = 0.0; L[4] = 0.0; L[5] = s0;
+  }
+  if (Trot_rel < 0.0) { Trot_rel = 0.0; lc[ORC_CNT_TREL_CLAMP] += n; }
+  if (mrel < 0.0) { mrel = 0.0; lc[ORC_CNT_TREL_CLAMP] += n; }
+  const double q = mrel / (1.0 + mrel);
+  for (int64_t i = o0; i < o1; ++i) {
+    double u[4];
+    draw4(seed, p->pid[i], step, TAG_COLLIDE, 0, u);
+    double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
+    double G1 = r0 * cos(2.0 * PI * u[1]), G2 = r0 * sin(2.0 * PI * u[1]);
+    double G3 = r1 * cos(2.0 * PI * u[3]), G4 = r1 * sin(2.0 * PI * u[3]);
+    double sq = sqrt(oma2);
+    double Cx = p->cx[i] - U[0], Cy = p->cy[i] - U[1], Cz = p->cz[i] - U[2];
+    double ncx = U[0] + al * Cx + sq * (L[0] * G1);
+    double ncy = U[1] + al * Cy + sq * (L[1] * G1 + L[2] * G2);
+    double ncz = U[2] + al * Cz + sq * (L[3] * G1 + L[4] * G2 + L[5] * G3);
+    double half = 0.5 * R * Trot_rel * oma2;
+    double root = sqrt(p->erot[i]) * al + sqrt(half) * G4;
+    double ne = half + root * root;
+    /* Gillespie: waiting time -ln(U1)/W, then up with probability */
+    /* omega_up/W = (I+1) q / ((I+1) q + I)                         */
+    int32_t I = p->vib[i];
+    double t = 0.0;
+    double w[4];
+    for (int k = 0; k < FPM_MAX_JUMPS; ++k) {
+      const double wu = (double)(I + 1) * q, wd = (double)I;
+      const double W = 2.0 * (wu + wd) / (tau * (1.0 - q));
+      if (!(W > 0.0)) break;
+      if ((k & 1) == 0) draw4(seed, p->pid[i], step, TAG_COLLIDE, (uint32_t)(1 + (k >> 1)), w);
+      const double u1 = w[2 * (k & 1)], u2 = w[2 * (k & 1) + 1];
+      const double dtv = -log(u1) / W;
+      if (t + dtv > dtc) break;
+      if (u2 < wu / (wu + wd)) ++I; else --I;
+      t += dtv;
+      if (k == FPM_MAX_JUMPS - 1) lc[ORC_CNT_VIB_SAT] += 1;
+    }
+    if (I > ORC_VIB_MAX) { I = ORC_VIB_MAX; lc[ORC_CNT_VIB_SAT] += 1; }
+    p->cx[i] = store(ncx, f32);
+    p->cy[i] = store(ncy, f32);
+    p->cz[i] = store(ncz, f32);
+    p->erot[i] = store(ne, f32);
+    p->vib[i] = I;
+  }
+}
+
 int orc_collide(const orc_grid* gr, const orc_gas* g, const double* cs, const int64_t* offsets,
                 orc_parts* p, uint64_t seed, uint64_t step, int32_t f32, int64_t* counters) {
   int64_t M = ncells(gr);
@@ -546,6 +650,10 @@ int orc_collide(const orc_grid* gr, const orc_gas* g, const double* cs, const in
       int64_t o0 = offsets[c], o1 = offsets[c + 1];
       if (o1 == o0) continue;
       if (cs[(int64_t)ORC_CS_COLLIDE * M + c] == 0.0) { lc[ORC_CNT_CELL_SKIP] += 1; continue; }
+      if (g->scheme == ORC_SCHEME_FPM) {
+        fpm_cell(gr, g, cs, c, o0, o1, p, seed, step, f32, lc);
+        continue;
+      }
       const double a = cs[(int64_t)ORC_CS_A * M + c], b = cs[(int64_t)ORC_CS_B * M + c];
       const double al_cell = cs[(int64_t)ORC_CS_ALPHA * M + c];
       const double oma2_cell = cs[(int64_t)ORC_CS_OMA2 * M + c];
@@ -717,11 +825,14 @@ int orc_conserve(const orc_grid* gr, const orc_gas* g, const double* cs, const i
       double m1[3] = {S1[0] / N, S1[1] / N, S1[2] / N};
       double Us[3] = {Un[0] + m1[0], Un[1] + m1[1], Un[2] + m1[2]};
       double etr_s = 0.5 * (S2 / N - (m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2]));
-      /* (i) vibrational levels */
+      /* (i) vibrational levels (USP-FPM only: the first-order FPM      */
+      /* method keeps the levels and rotational energies it sampled and  */
+      /* conserves momentum and total energy through the velocities)     */
+      const int fpm = g->scheme == ORC_SCHEME_FPM;
       double X = (double)N * cs[(int64_t)ORC_CS_EVIB_NEW * M + c] / RTh - (double)SI;
       double u4[4];
       draw4(seed, (uint32_t)c, step, TAG_CONSERVE, 0, u4);
-      int64_t Id = (int64_t)floor(X + u4[0]);
+      int64_t Id = fpm ? 0 : (int64_t)floor(X + u4[0]);
       int64_t att = 0, maxatt = 64 * N;
       uint32_t j = 1;
       while (Id != 0) {
@@ -742,7 +853,9 @@ int orc_conserve(const orc_grid* gr, const orc_gas* g, const double* cs, const i
       /* (ii) rotational scaling */
       double erot_s = Se / N, erot_t = cs[(int64_t)ORC_CS_EROT_NEW * M + c];
       double erot_a = erot_s;
-      if (erot_s > 0.0 && erot_t > 0.0) {
+      if (fpm) {
+        /* nothing: the sampled rotational energies stand */
+      } else if (erot_s > 0.0 && erot_t > 0.0) {
         double f = erot_t / erot_s;
         for (int64_t i = o0; i < o1; ++i) p->erot[i] = store(p->erot[i] * f, f32);
         erot_a = erot_t;

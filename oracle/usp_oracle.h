@@ -94,7 +94,11 @@ typedef struct {
   double d_ref;      /* reference diameter [m]                              */
   int32_t pr_model;
   double Pr_const;
+  int32_t scheme;    /* ORC_SCHEME_USP or ORC_SCHEME_FPM                    */
 } orc_gas;
+
+/* USP-FPM (Secs. III-IV) or the first-order FPM method (Secs. II.B-II.C) */
+enum { ORC_SCHEME_USP = 0, ORC_SCHEME_FPM = 1 };
 
 /* ---- grid --------------------------------------------------------------- */
 typedef struct {
@@ -152,6 +156,9 @@ enum {
   ORC_CS_ALPHA, ORC_CS_OMA2, ORC_CS_NU,
   ORC_CS_EROT_NEW, ORC_CS_EVIB_NEW,
   ORC_CS_COLLIDE, ORC_CS_NBR_OK,
+  /* first-order FPM only: tau = 2 mu (1 - nu)/p and the cell relaxation */
+  /* temperatures (eqs. T_tr_FPM, T_rot_FPM) and level (eq. T_vib_FPM)   */
+  ORC_CS_FPM_TAU, ORC_CS_FPM_TTR_REL, ORC_CS_FPM_TROT_REL, ORC_CS_FPM_MREL,
   ORC_NCS
 };
 

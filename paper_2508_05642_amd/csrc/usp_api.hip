@@ -19,6 +19,7 @@ GasP make_gas(const usp_gas* g) {
   p.zvib_model = g->zvib_model; p.Z_vib = g->Z_vib; p.C1 = g->C1; p.C2 = g->C2;
   p.sigma_vib = g->sigma_vib; p.d_ref = g->d_ref;
   p.pr_model = g->pr_model; p.Pr_const = g->Pr_const;
+  p.scheme = g->scheme;
   return p;
 }
 
@@ -110,7 +111,7 @@ bool parts_ok(const usp_particles* p, const usp_grid* g) {
 
 bool gas_ok(const usp_gas* g) {
   return g && g->m > 0.0 && g->theta_vib > 0.0 && g->T_ref > 0.0 && g->mu_ref > 0.0 &&
-         g->alpha_vss > 0.0;
+         g->alpha_vss > 0.0 && (g->scheme == USP_SCHEME_USP || g->scheme == USP_SCHEME_FPM);
 }
 
 usp_status hip_status(hipError_t e) { return e == hipSuccess ? USP_OK : USP_EDEVICE; }
@@ -166,7 +167,8 @@ const char* kMomNames[USP_NMOM] = {"N", "UX", "UY", "UZ", "PXX", "PYY", "PZZ", "
 const char* kCsNames[USP_NCS] = {
     "NP", "NDENS", "UX", "UY", "UZ", "TTR", "TROT", "TVIB", "PXX", "PYY", "PZZ", "PXY",
     "PXZ", "PYZ", "ETR", "EROT", "EVIB", "MU", "MUP", "TAUC", "ZROT", "ZVIB", "PR", "DT",
-    "A", "B", "R2", "R3", "ALPHA", "OMA2", "NU", "EROT_NEW", "EVIB_NEW", "COLLIDE", "NBR_OK"};
+    "A", "B", "R2", "R3", "ALPHA", "OMA2", "NU", "EROT_NEW", "EVIB_NEW", "COLLIDE", "NBR_OK",
+    "FPM_TAU", "FPM_TTR_REL", "FPM_TROT_REL", "FPM_MREL"};
 const char* kCntNames[USP_NCOUNTERS] = {
     "PB_CLAMP", "CHOL_FALLBACK", "NU_ZERO", "TREL_SKIP", "TREL_CLAMP", "VIB_SAT",
     "INTERP_CLAMP", "CONS_SKIP", "PICK_FAIL", "CELL_SKIP", "INJECTED", "DELETED",

@@ -14,7 +14,7 @@
 
 namespace usp {
 
-template <typename S, bool STAGED, int CAP>
+template <typename S, bool STAGED, int CAP, bool FPM>
 __device__ __forceinline__ void batch_tile(const GridP& g, const GasP& gas, double dt,
                                            const double* dt_cell, double* mom, double* cs,
                                            const int64_t* __restrict__ offsets,
@@ -30,8 +30,8 @@ __device__ __forceinline__ void batch_tile(const GridP& g, const GasP& gas, doub
     const uint32_t step = (uint32_t)(step0 + (uint64_t)s);
     tile_cells<S>(g, gas, dt, dt_cell, mom, cs, offsets, c0, c1, st, counters);
     __syncthreads();
-    tile_update<S, CAP, true>(g, gas, cs, p, i0, i1, st, st, esc_list, nesc, seed, step,
-                              counters);
+    tile_update<S, CAP, true, FPM>(g, gas, cs, p, i0, i1, st, st, esc_list, nesc, seed, step,
+                                   counters);
     tile_conserve<S>(gas, cs, g.M, offsets, c0, c1, st, seed, step, counters);
     __syncthreads();
   }
@@ -45,7 +45,7 @@ __device__ __forceinline__ void batch_tile(const GridP& g, const GasP& gas, doub
 
 // CAP = stage size (twice the tile window); WPE = waves per SIMD the
 // register budget is held to (what the stage's LDS allows).
-template <typename S, int CAP, int WPE>
+template <typename S, int CAP, int WPE, bool FPM>
 __global__ __launch_bounds__(UPD_BLOCK, WPE) void k_batch(GridP g, GasP gas, double dt,
                                                           const double* dt_cell, double* mom,
                                                           double* cs,
@@ -65,10 +65,10 @@ __global__ __launch_bounds__(UPD_BLOCK, WPE) void k_batch(GridP g, GasP gas, dou
   if (i1 - i0 <= CAP) {
     Stage<S> st;
     st.cx = scx; st.cy = scy; st.cz = scz; st.erot = ser; st.vib = svb; st.base = i0;
-    batch_tile<S, true, CAP>(g, gas, dt, dt_cell, mom, cs, offsets, p, c0, c1, i0, i1, st,
+    batch_tile<S, true, CAP, FPM>(g, gas, dt, dt_cell, mom, cs, offsets, p, c0, c1, i0, i1, st,
                              esc_list, &nesc, seed, step0, nsteps, counters);
   } else {
-    batch_tile<S, false, CAP>(g, gas, dt, dt_cell, mom, cs, offsets, p, c0, c1, i0, i1,
+    batch_tile<S, false, CAP, FPM>(g, gas, dt, dt_cell, mom, cs, offsets, p, c0, c1, i0, i1,
                               global_stage(p), esc_list, &nesc, seed, step0, nsteps, counters);
   }
 }
@@ -83,9 +83,14 @@ static hipError_t batch_launches(const GridP& g, const GasP& gas, double dt,
   hipError_t e = launch_tiles(offsets, g.M, TILE, ntiles, first, st);
   for (int s = 0; s < nsteps && e == hipSuccess; s += spl) {
     const int k = nsteps - s < spl ? nsteps - s : spl;
-    k_batch<S, 2 * TILE, WPE><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, dt, dt_cell, mom, cs, offsets,
-                                                           first, p, seed, step + (uint64_t)s, k,
-                                                           counters);
+    if (gas.scheme == USP_SCHEME_FPM)
+      k_batch<S, 2 * TILE, WPE, true><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, dt, dt_cell, mom, cs,
+                                                                   offsets, first, p, seed,
+                                                                   step + (uint64_t)s, k, counters);
+    else
+      k_batch<S, 2 * TILE, WPE, false><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, dt, dt_cell, mom, cs,
+                                                                    offsets, first, p, seed,
+                                                                    step + (uint64_t)s, k, counters);
     e = hipGetLastError();
   }
   return e;

@@ -122,7 +122,34 @@ __device__ __forceinline__ void cell_state(const GridP& g, const GasP& gas, cons
   v[CS_ETR] = 0.5 * trP; v[CS_EROT] = erot; v[CS_EVIB] = ibar * R * Th;
   v[CS_DT] = dtc;
   const bool collide = N >= 2.0 && Ttr > 0.0 && isfinite(Ttr) && vol > 0.0;
-  if (collide) {
+  if (collide && gas.scheme == USP_SCHEME_FPM) {
+    // first-order FPM (Secs. II.B-II.C): nu from Pr, tau = 2 mu (1-nu)/p,
+    // the update factor exp(-dt/tau) and the cell relaxation temperatures
+    // of eqs. T_tr_FPM, T_rot_FPM, T_vib_FPM
+    const double mu = gas.mu_ref * pow(Ttr / gas.T_ref, gas.omega);
+    const double mup = mu / (v[CS_NDENS] * KB * Ttr);
+    const double tauc = gas.K * mup;
+    const double zr = zrot(gas, Ttr), zv = zvib(gas, Ttr);
+    const double Pr = prandtl(gas, Ttr);
+    const double nu = 1.0 - 3.0 / (2.0 * Pr);
+    const double tau = 2.0 * mup * (1.0 - nu);
+    const double fr = tau / (2.0 * zr * tauc), fv = tau / (2.0 * zv * tauc);
+    const double mv = mlevel<double>(Th, Tvib), mt = mlevel<double>(Th, Ttr);
+    v[CS_MU] = mu; v[CS_MUP] = mup; v[CS_TAUC] = tauc;
+    v[CS_ZROT] = zr; v[CS_ZVIB] = zv; v[CS_PR] = Pr;
+    v[CS_ALPHA] = exp(-dtc / tau);
+    v[CS_OMA2] = -expm1(-2.0 * dtc / tau);
+    v[CS_NU] = nu;
+    v[CS_EROT_NEW] = erot;
+    v[CS_EVIB_NEW] = v[CS_EVIB];
+    v[CS_FPM_TAU] = tau;
+    v[CS_FPM_TTR_REL] = Ttr + (2.0 / 3.0) * (fr * (Trot - Ttr) + fv * Th * (mv - mt));
+    v[CS_FPM_TROT_REL] = Trot + fr * (Ttr - Trot);
+    v[CS_FPM_MREL] = mv + fv * (mt - mv);
+    v[CS_COLLIDE] = 1.0;
+    const int cut = g.flags ? (g.flags[c] & (USP_FLAG_SOLID | USP_FLAG_CUT)) : 0;
+    v[CS_NBR_OK] = cut ? 0.0 : 1.0;
+  } else if (collide) {
     const double mu = gas.mu_ref * pow(Ttr / gas.T_ref, gas.omega);
     const double mup = mu / (v[CS_NDENS] * KB * Ttr);
     const double tauc = gas.K * mup;

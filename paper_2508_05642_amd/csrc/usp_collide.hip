@@ -8,6 +8,7 @@ constexpr int PART_BLOCK = 256;
 constexpr int CONS_BLOCK = 256;
 
 // One thread per particle.
+template <bool FPM>
 __global__ __launch_bounds__(PART_BLOCK) void k_collide_f32(GridP g, GasP gas,
                                                             const double* __restrict__ cs,
                                                             PartP<float> p, uint64_t seed,
@@ -17,7 +18,7 @@ __global__ __launch_bounds__(PART_BLOCK) void k_collide_f32(GridP g, GasP gas,
   const int32_t c = p.cell[i];
   if (c < 0) return;
   uint32_t ev = 0;
-  const PartNew<float> o = collide_one(g, gas, cs, p, i, c, load_state(p, i), seed, step, &ev);
+  const PartNew<float> o = collide_one<FPM>(g, gas, cs, p, i, c, load_state(p, i), seed, step, &ev);
   if (o.changed) {
     p.cx[i] = o.cx; p.cy[i] = o.cy; p.cz[i] = o.cz; p.erot[i] = o.erot;
     p.vib[i] = (uint8_t)o.vib;
@@ -25,6 +26,7 @@ __global__ __launch_bounds__(PART_BLOCK) void k_collide_f32(GridP g, GasP gas,
   flush_events(counters, ev);
 }
 
+template <bool FPM>
 __global__ __launch_bounds__(PART_BLOCK) void k_collide_f64(GridP g, GasP gas,
                                                             const double* __restrict__ cs,
                                                             PartP<double> p, uint64_t seed,
@@ -34,7 +36,7 @@ __global__ __launch_bounds__(PART_BLOCK) void k_collide_f64(GridP g, GasP gas,
   const int32_t c = p.cell[i];
   if (c < 0) return;
   uint32_t ev = 0;
-  const PartNew<double> o = collide_one(g, gas, cs, p, i, c, load_state(p, i), seed, step, &ev);
+  const PartNew<double> o = collide_one<FPM>(g, gas, cs, p, i, c, load_state(p, i), seed, step, &ev);
   if (o.changed) {
     p.cx[i] = o.cx; p.cy[i] = o.cy; p.cz[i] = o.cz; p.erot[i] = o.erot;
     p.vib[i] = (uint8_t)o.vib;
@@ -68,12 +70,15 @@ hipError_t launch_collide(const GridP& g, const GasP& gas, const double* cs, con
                           const PartP<S>& p, uint64_t seed, uint64_t step, int64_t* counters,
                           hipStream_t st) {
   (void)offsets;
-  if constexpr (sizeof(S) == 4)
-    k_collide_f32<<<cdiv(p.capacity, PART_BLOCK), PART_BLOCK, 0, st>>>(g, gas, cs, p, seed,
-                                                                      (uint32_t)step, counters);
-  else
-    k_collide_f64<<<cdiv(p.capacity, PART_BLOCK), PART_BLOCK, 0, st>>>(g, gas, cs, p, seed,
-                                                                      (uint32_t)step, counters);
+  const bool fpm = gas.scheme == USP_SCHEME_FPM;
+  const int64_t nb = cdiv(p.capacity, PART_BLOCK);
+  if constexpr (sizeof(S) == 4) {
+    if (fpm) k_collide_f32<true><<<nb, PART_BLOCK, 0, st>>>(g, gas, cs, p, seed, (uint32_t)step, counters);
+    else k_collide_f32<false><<<nb, PART_BLOCK, 0, st>>>(g, gas, cs, p, seed, (uint32_t)step, counters);
+  } else {
+    if (fpm) k_collide_f64<true><<<nb, PART_BLOCK, 0, st>>>(g, gas, cs, p, seed, (uint32_t)step, counters);
+    else k_collide_f64<false><<<nb, PART_BLOCK, 0, st>>>(g, gas, cs, p, seed, (uint32_t)step, counters);
+  }
   return hipGetLastError();
 }
 

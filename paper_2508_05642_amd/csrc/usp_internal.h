@@ -20,7 +20,9 @@ enum Cs {
   CS_NP = 0, CS_NDENS, CS_UX, CS_UY, CS_UZ, CS_TTR, CS_TROT, CS_TVIB,
   CS_PXX, CS_PYY, CS_PZZ, CS_PXY, CS_PXZ, CS_PYZ, CS_ETR, CS_EROT, CS_EVIB,
   CS_MU, CS_MUP, CS_TAUC, CS_ZROT, CS_ZVIB, CS_PR, CS_DT, CS_A, CS_B, CS_R2, CS_R3,
-  CS_ALPHA, CS_OMA2, CS_NU, CS_EROT_NEW, CS_EVIB_NEW, CS_COLLIDE, CS_NBR_OK, NCS
+  CS_ALPHA, CS_OMA2, CS_NU, CS_EROT_NEW, CS_EVIB_NEW, CS_COLLIDE, CS_NBR_OK,
+  // first-order FPM only: tau and the cell relaxation temperatures / level
+  CS_FPM_TAU, CS_FPM_TTR_REL, CS_FPM_TROT_REL, CS_FPM_MREL, NCS
 };
 static_assert(NCS == USP_NCS, "cell-state plane count");
 
@@ -59,6 +61,7 @@ struct GasP {
   int zrot_model; double Z_rot, Z_rot_inf, T_star;
   int zvib_model; double Z_vib, C1, C2, sigma_vib, d_ref;
   int pr_model; double Pr_const;
+  int scheme;  // USP_SCHEME_USP or USP_SCHEME_FPM
 };
 
 struct GridP {

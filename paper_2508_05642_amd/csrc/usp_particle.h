@@ -354,20 +354,112 @@ __device__ __forceinline__ void note_coef_events(const PartCoef<double>& a, uint
   if (a.clamp_rot || a.clamp_m) *ev |= 1u << USP_CNT_TREL_CLAMP;
 }
 
+// First-order FPM update of particle i in cell c (Sec. II.C), all in FP64
+// from the cell planes (no reconstruction): the velocity by eq.
+// conventionial-velo and the rotational energy by eq. conventionial-erot
+// (the USP-FPM algebra with alpha = exp(-dt/tau)); the level by Gillespie's
+// direct method for the master-equation rates omega_{I,I-1} = 2 I/(tau
+// (1-q)), omega_{I,I+1} = 2 (I+1) q/(tau (1-q)), q = exp(-Theta/T_vib^rel) =
+// m_rel/(1+m_rel).  Draws: block 0 of (pid, step, collide) for the four
+// normals, blocks 1, 2, ... two uniforms per jump attempt, at most
+// FPM_MAX_JUMPS attempts (then VIB_SAT).  A failed Cholesky test of the
+// cell's Lambda falls back to nu = 0.
+constexpr int FPM_MAX_JUMPS = 4096;
+
+template <typename S>
+__device__ __forceinline__ PartNew<S> collide_fpm(const GridP& g, const GasP& gas,
+                                                 const double* __restrict__ cs,
+                                                 const PartP<S>& p, int64_t i, int32_t c,
+                                                 const PartNew<S>& in, uint64_t seed,
+                                                 uint32_t step, uint32_t* evp) {
+#pragma clang fp contract(off)
+  PartNew<S> o;
+  o.changed = false;
+  const int64_t M = g.M;
+  const double R = gas.R;
+  double U[3], P[6];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) U[k] = cs[(CS_UX + k) * M + c];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) P[k] = cs[(CS_PXX + k) * M + c];
+  const double Ttr = cs[CS_TTR * M + c];
+  const double al = cs[CS_ALPHA * M + c], oma2 = cs[CS_OMA2 * M + c], nu = cs[CS_NU * M + c];
+  const double dtc = cs[CS_DT * M + c], tau = cs[CS_FPM_TAU * M + c];
+  const double Ttr_rel = cs[CS_FPM_TTR_REL * M + c];
+  double Trot_rel = cs[CS_FPM_TROT_REL * M + c], mrel = cs[CS_FPM_MREL * M + c];
+  uint32_t ev = 0;
+  const double RT = R * Ttr;
+  double Lam[6], L[6], margin;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) Lam[k] = R * Ttr_rel + nu * (P[k] - RT);
+#pragma unroll
+  for (int k = 3; k < 6; ++k) Lam[k] = nu * P[k];
+  if (!chol3m<double>(Lam, L, &margin)) {
+    ev |= (1u << USP_CNT_CHOL_FALLBACK) | (1u << USP_CNT_NU_ZERO);
+    if (!(Ttr_rel > 0.0)) {
+      *evp |= ev | (1u << USP_CNT_TREL_SKIP);
+      return o;
+    }
+    const double s0 = sqrt(R * Ttr_rel);
+    L[0] = s0; L[1] = 0.0; L[2] = s0; L[3] = 0.0; L[4] = 0.0; L[5] = s0;
+  }
+  if (Trot_rel < 0.0) { Trot_rel = 0.0; ev |= 1u << USP_CNT_TREL_CLAMP; }
+  if (mrel < 0.0) { mrel = 0.0; ev |= 1u << USP_CNT_TREL_CLAMP; }
+  const uint32_t id = p.pid[i];
+  const U4 w0 = philox(id, step, TAG_COLLIDE, 0u, seed);
+  double G1, G2, G3, G4;
+  box_muller<double>(w0.w[0], w0.w[1], &G1, &G2);
+  box_muller<double>(w0.w[2], w0.w[3], &G3, &G4);
+  const double sq = sqrt(oma2);
+  const double Cx = (double)in.cx - U[0], Cy = (double)in.cy - U[1], Cz = (double)in.cz - U[2];
+  o.cx = (S)(U[0] + al * Cx + sq * (L[0] * G1));
+  o.cy = (S)(U[1] + al * Cy + sq * (L[1] * G1 + L[2] * G2));
+  o.cz = (S)(U[2] + al * Cz + sq * (L[3] * G1 + L[4] * G2 + L[5] * G3));
+  const double half = 0.5 * R * Trot_rel * oma2;
+  const double root = sqrt((double)in.erot) * al + sqrt(half) * G4;
+  o.erot = (S)(half + root * root);
+  // Gillespie: waiting time -ln(U1)/W, then up with probability
+  // omega_up/W = (I+1) q / ((I+1) q + I)
+  const double q = mrel / (1.0 + mrel);
+  int I = in.vib;
+  double t = 0.0;
+  U4 w = w0;
+  for (int k = 0; k < FPM_MAX_JUMPS; ++k) {
+    const double wu = (double)(I + 1) * q, wd = (double)I;
+    const double W = 2.0 * (wu + wd) / (tau * (1.0 - q));
+    if (!(W > 0.0)) break;
+    if ((k & 1) == 0) w = philox(id, step, TAG_COLLIDE, 1u + (uint32_t)(k >> 1), seed);
+    const uint32_t a = (k & 1) ? w.w[2] : w.w[0], b = (k & 1) ? w.w[3] : w.w[1];
+    const double dtv = -log(u01d(a)) / W;
+    if (t + dtv > dtc) break;
+    if (u01d(b) < wu / (wu + wd)) ++I;
+    else --I;
+    t += dtv;
+    if (k == FPM_MAX_JUMPS - 1) ev |= 1u << USP_CNT_VIB_SAT;
+  }
+  if (I > VIB_MAX) { I = VIB_MAX; ev |= 1u << USP_CNT_VIB_SAT; }
+  o.vib = I;
+  o.changed = true;
+  *evp |= ev;
+  return o;
+}
+
 // Particle update of particle i in cell c (Secs. III.A-III.B).
 // FP32 state, first pass: fields from the packed cell records (16-byte
 // loads), FP32 reconstruction and coefficient chain.  When the Cholesky
 // test of the diffusion tensor fails, or passes with a relative pivot below
 // 1e-4, the particle is left unchanged with *esc set and no coefficient
 // events: collide_esc then redoes it with every branch taken in FP64.
+template <bool FPM>
 __device__ __forceinline__ PartNew<float> collide_f32(const GridP& g, const GasP& gas,
                                                      const double* __restrict__ cs,
                                                      const PartP<float>& p, int64_t i, int32_t c,
                                                      const PartNew<float>& in, uint64_t seed,
                                                      uint32_t step, uint32_t* evp, bool* esc) {
+  *esc = false;
+  if constexpr (FPM) return collide_fpm<float>(g, gas, cs, p, i, c, in, seed, step, evp);
   PartNew<float> o;
   o.changed = false;
-  *esc = false;
   const int64_t M = g.M;
   const CellRec* __restrict__ rec = cell_records(cs, M);
   const float4* r4 = (const float4*)(rec + c);
@@ -457,24 +549,27 @@ __device__ __forceinline__ PartNew<float> collide_esc(const GridP& g, const GasP
 }
 
 // Both passes in one call.
+template <bool FPM>
 __device__ __forceinline__ PartNew<float> collide_one(const GridP& g, const GasP& gas,
                                                      const double* __restrict__ cs,
                                                      const PartP<float>& p, int64_t i, int32_t c,
                                                      const PartNew<float>& in, uint64_t seed,
                                                      uint32_t step, uint32_t* evp) {
   bool esc;
-  PartNew<float> o = collide_f32(g, gas, cs, p, i, c, in, seed, step, evp, &esc);
+  PartNew<float> o = collide_f32<FPM>(g, gas, cs, p, i, c, in, seed, step, evp, &esc);
   if (esc) o = collide_esc(g, gas, cs, p, i, c, in, seed, step, evp);
   return o;
 }
 
 // FP64 state: fields and coefficients from the FP64 planes.
+template <bool FPM>
 __device__ __forceinline__ PartNew<double> collide_one(const GridP& g, const GasP& gas,
                                                       const double* __restrict__ cs,
                                                       const PartP<double>& p, int64_t i,
                                                       int32_t c, const PartNew<double>& in,
                                                       uint64_t seed, uint32_t step,
                                                       uint32_t* evp) {
+  if constexpr (FPM) return collide_fpm<double>(g, gas, cs, p, i, c, in, seed, step, evp);
   PartNew<double> o;
   o.changed = false;
   const int64_t M = g.M;
@@ -627,7 +722,10 @@ __device__ __forceinline__ void conserve_cell(const GasP& gas, const double* __r
   // then |I_delta| single-level moves on randomly picked particles
   int64_t SI = (int64_t)s[5];
   const double X = Nd * cs[CS_EVIB_NEW * M + c] / RTh - (double)SI;
-  const int64_t Id0 = (int64_t)floor(X + u01d(philox((uint32_t)c, step, TAG_CONSERVE, 0u, seed).w[0]));
+  // the first-order FPM method keeps the levels and rotational energies it
+  // sampled and conserves momentum and total energy through the velocities
+  const bool fpm = gas.scheme == USP_SCHEME_FPM;
+  const int64_t Id0 = fpm ? 0 : (int64_t)floor(X + u01d(philox((uint32_t)c, step, TAG_CONSERVE, 0u, seed).w[0]));
   // no level can reach VIB_MAX through these increments
   const int64_t need0 = Id0 > 0 ? Id0 : 0;
   const bool low = !__ballot((int64_t)lmax + need0 >= VIB_MAX);
@@ -638,7 +736,9 @@ __device__ __forceinline__ void conserve_cell(const GasP& gas, const double* __r
     // (ii) rotational scaling to the cell target
     const double erot_s = s[4] / Nd, erot_t = cs[CS_EROT_NEW * M + c];
     double erot_a = erot_s;
-    if (erot_s > 0.0 && erot_t > 0.0) {
+    if (fpm) {
+      // the sampled rotational energies stand
+    } else if (erot_s > 0.0 && erot_t > 0.0) {
       frot = erot_t / erot_s;
       erot_a = erot_t;
     } else {

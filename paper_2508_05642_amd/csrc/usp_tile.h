@@ -43,20 +43,22 @@ __device__ __forceinline__ Stage<S> global_stage(const PartP<S>& p) {
 // First and second pass of the particle update: in FP32 the first pass
 // flags the particles that need the FP64 chain (see collide_f32); the FP64
 // state has a single pass.
+template <bool FPM>
 __device__ __forceinline__ PartNew<float> update_first(const GridP& g, const GasP& gas,
                                                       const double* cs, const PartP<float>& p,
                                                       int64_t i, int32_t c,
                                                       const PartNew<float>& in, uint64_t seed,
                                                       uint32_t step, uint32_t* ev, bool* esc) {
-  return collide_f32(g, gas, cs, p, i, c, in, seed, step, ev, esc);
+  return collide_f32<FPM>(g, gas, cs, p, i, c, in, seed, step, ev, esc);
 }
+template <bool FPM>
 __device__ __forceinline__ PartNew<double> update_first(const GridP& g, const GasP& gas,
                                                        const double* cs, const PartP<double>& p,
                                                        int64_t i, int32_t c,
                                                        const PartNew<double>& in, uint64_t seed,
                                                        uint32_t step, uint32_t* ev, bool* esc) {
   *esc = false;
-  return collide_one(g, gas, cs, p, i, c, in, seed, step, ev);
+  return collide_one<FPM>(g, gas, cs, p, i, c, in, seed, step, ev);
 }
 __device__ __forceinline__ PartNew<float> update_second(const GridP& g, const GasP& gas,
                                                        const double* cs, const PartP<float>& p,
@@ -79,7 +81,7 @@ __device__ __forceinline__ PartNew<double> update_second(const GridP&, const Gas
 // chunks of CAP particles: first pass thread per particle; the particles
 // it lists (esc_list/nesc, LDS) get the second pass.  Positions and ids
 // are read from p.
-template <typename S, int CAP, bool SAME>
+template <typename S, int CAP, bool SAME, bool FPM>
 __device__ __forceinline__ void tile_update(const GridP& g, const GasP& gas,
                                             const double* __restrict__ cs, const PartP<S>& p,
                                             int64_t i0, int64_t i1, const Stage<S>& src,
@@ -102,7 +104,7 @@ __device__ __forceinline__ void tile_update(const GridP& g, const GasP& gas,
       GridP gl = g;
       const double* csl = cs;
       asm volatile("" : "+s"(csl), "+s"(gl.M));
-      if (c >= 0) o = update_first(gl, gas, csl, p, i, c, in, seed, step, &ev, &esc);
+      if (c >= 0) o = update_first<FPM>(gl, gas, csl, p, i, c, in, seed, step, &ev, &esc);
       if (esc) esc_list[atomicAdd(nesc, 1)] = (uint16_t)(i - cb);
       else if (o.changed) dst.store(i, o);
       else if (!SAME) dst.store(i, in);

@@ -40,7 +40,7 @@ __global__ void k_tile_first(const int64_t* __restrict__ offsets, int64_t M, int
 }
 
 // The three phases of one tile; st = LDS stage or the particle arrays.
-template <typename S, bool STAGED, int CAP>
+template <typename S, bool STAGED, int CAP, bool FPM>
 __device__ __forceinline__ void tile_pass(const GridP& g, const GasP& gas, const BcP& bc,
                                           double dt, const double* __restrict__ cs,
                                           const int64_t* __restrict__ offsets, const PartP<S>& p,
@@ -49,8 +49,8 @@ __device__ __forceinline__ void tile_pass(const GridP& g, const GasP& gas, const
                                           uint64_t seed, uint32_t step, bool advect,
                                           int64_t* counters) {
   // A: particle update, global inputs into the stage (or in place)
-  tile_update<S, CAP, !STAGED>(g, gas, cs, p, i0, i1, global_stage(p), st, esc_list, nesc, seed,
-                               step, counters);
+  tile_update<S, CAP, !STAGED, FPM>(g, gas, cs, p, i0, i1, global_stage(p), st, esc_list, nesc,
+                                    seed, step, counters);
   // B: conservation, wave per cell
   tile_conserve<S>(gas, cs, g.M, offsets, c0, c1, st, seed, step, counters);
   __syncthreads();
@@ -65,7 +65,7 @@ __device__ __forceinline__ void tile_pass(const GridP& g, const GasP& gas, const
   }
 }
 
-template <typename S>
+template <typename S, bool FPM>
 __global__ __launch_bounds__(UPD_BLOCK, 4) void k_update(GridP g, GasP gas, BcP bc, double dt,
                                                       const double* __restrict__ cs,
                                                       const int64_t* __restrict__ offsets,
@@ -84,10 +84,10 @@ __global__ __launch_bounds__(UPD_BLOCK, 4) void k_update(GridP g, GasP gas, BcP 
   if (i1 - i0 <= CAP) {
     Stage<S> st;
     st.cx = scx; st.cy = scy; st.cz = scz; st.erot = ser; st.vib = svb; st.base = i0;
-    tile_pass<S, true, CAP>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1, st, esc_list, &nesc,
+    tile_pass<S, true, CAP, FPM>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1, st, esc_list, &nesc,
                             seed, step, advect != 0, counters);
   } else {
-    tile_pass<S, false, CAP>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1, global_stage(p),
+    tile_pass<S, false, CAP, FPM>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1, global_stage(p),
                              esc_list, &nesc, seed, step, advect != 0, counters);
   }
 }
@@ -108,8 +108,12 @@ hipError_t launch_update(const GridP& g, const GasP& gas, const BcP& bc, double 
   const int64_t ntiles = cdiv(p.capacity, T);
   int32_t* first = (int32_t*)(ws + L.tiles);
   launch_tiles(offsets, g.M, T, ntiles, first, st);
-  k_update<S><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, bc, dt, cs, offsets, first, p, seed,
-                                            (uint32_t)step, g.dim != 0 ? 1 : 0, counters);
+  if (gas.scheme == USP_SCHEME_FPM)
+    k_update<S, true><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, bc, dt, cs, offsets, first, p, seed,
+                                                    (uint32_t)step, g.dim != 0 ? 1 : 0, counters);
+  else
+    k_update<S, false><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, bc, dt, cs, offsets, first, p, seed,
+                                                     (uint32_t)step, g.dim != 0 ? 1 : 0, counters);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || g.dim == 0) return e;
   return launch_inject<S>(g, gas, bc, dt, p, seed, step, ws, L, counters, st);

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libusp.so")
 
 USP_F32, USP_F64 = 0, 1
-NMOM, NCS, NCOUNTERS = 21, 35, 16
+NMOM, NCS, NCOUNTERS = 21, 39, 16
 
 
 class UspGas(C.Structure):
@@ -28,7 +28,8 @@ class UspGas(C.Structure):
                 ("zrot_model", C.c_int32), ("Z_rot", C.c_double), ("Z_rot_inf", C.c_double),
                 ("T_star", C.c_double), ("zvib_model", C.c_int32), ("Z_vib", C.c_double),
                 ("C1", C.c_double), ("C2", C.c_double), ("sigma_vib", C.c_double),
-                ("d_ref", C.c_double), ("pr_model", C.c_int32), ("Pr_const", C.c_double)]
+                ("d_ref", C.c_double), ("pr_model", C.c_int32), ("Pr_const", C.c_double),
+                ("scheme", C.c_int32)]
 
 
 class UspGrid(C.Structure):
@@ -124,7 +125,7 @@ def _stream(stream=None):
 def make_gas(g):
     return UspGas(g.m, g.theta_vib, g.T_ref, g.mu_ref, g.omega, g.alpha_vss, g.zrot_model,
                   g.Z_rot, g.Z_rot_inf, g.T_star, g.zvib_model, g.Z_vib, g.C1, g.C2,
-                  g.sigma_vib, g.d_ref, g.pr_model, g.Pr_const)
+                  g.sigma_vib, g.d_ref, g.pr_model, g.Pr_const, getattr(g, "scheme", 0))
 
 
 def make_bc(b):

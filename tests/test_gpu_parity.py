@@ -10,6 +10,7 @@ Bars (integer work bit-exact; floating point as stated):
     particles (the discrete decisions are FP64 on both sides but their
     inputs differ by rounding in the FP32 path).
 """
+import dataclasses
 import math
 import sys
 
@@ -71,10 +72,15 @@ def make(kind, f32):
     return {"0d": prob_0d, "1d": prob_1d, "2d": prob_2d}[kind](f32)
 
 
-def pair(kind, f32):
+SCHEMES = ["usp", "fpm"]
+
+
+def pair(kind, f32, scheme="usp"):
     usp = _usp()
     prob, parts = make(kind, f32)
-    _say(f"[parity] case={kind} f32={f32} n={parts['n']} cells={prob.grid.ncells}")
+    if scheme == "fpm":
+        prob.gas = dataclasses.replace(prob.gas, scheme=W.SCHEME_FPM)
+    _say(f"[parity] case={kind} f32={f32} scheme={scheme} n={parts['n']} cells={prob.grid.ncells}")
     return prob, usp.DeviceState(prob, parts), oracle.Sim(prob, parts)
 
 
@@ -221,9 +227,10 @@ def _mom_scales(prob, om):
     return sc
 
 
+@pytest.mark.parametrize("scheme", SCHEMES)
 @pytest.mark.parametrize("kind,f32", CASES)
-def test_moments_and_cellstate(kind, f32):
-    prob, gpu, orc = pair(kind, f32)
+def test_moments_and_cellstate(kind, f32, scheme):
+    prob, gpu, orc = pair(kind, f32, scheme)
     gpu.bin(); orc.bin()
     gpu.do_moments(); orc.do_moments()
     gm, om = gpu.moments(), orc.moments()
@@ -260,9 +267,10 @@ def _tol(f32):
     return 2e-5 if f32 else 1e-9
 
 
+@pytest.mark.parametrize("scheme", SCHEMES)
 @pytest.mark.parametrize("kind,f32", CASES)
-def test_collide_conserve_advect(kind, f32):
-    prob, gpu, orc = pair(kind, f32)
+def test_collide_conserve_advect(kind, f32, scheme):
+    prob, gpu, orc = pair(kind, f32, scheme)
     step = 4
     gpu.bin(); orc.bin()
     gpu.do_moments(); orc.do_moments()
@@ -286,10 +294,11 @@ def test_collide_conserve_advect(kind, f32):
             assert ca[k] == cb[k], (k, ca[k], cb[k])
 
 
+@pytest.mark.parametrize("scheme", SCHEMES)
 @pytest.mark.parametrize("kind,f32", CASES)
-def test_full_steps(kind, f32):
+def test_full_steps(kind, f32, scheme):
     """usp_step (one call, several steps) against the oracle's steps."""
-    prob, gpu, orc = pair(kind, f32)
+    prob, gpu, orc = pair(kind, f32, scheme)
     nsteps = 3
     gpu.step(10, nsteps)
     orc.step_native(10, nsteps)

@@ -227,10 +227,14 @@ def run_gpu_c2(args):
     st = usp.DeviceState(prob, parts, device="cuda:0")
     st.step(0, 1)
     step = 1
-    tune = autotune.tune_batch(st, step=step, nsteps=8)
-    tile, spl = tune["tile"], tune["steps_per_launch"]
-    log(f"schedule: tile {tile}, steps per launch {spl or 'all'} "
-        f"({ {f'{k[0]}/{k[1]}': round(v, 4) for k, v in tune['ms_per_step'].items()} } ms/step)")
+    if args.schedule:
+        tile, spl = (int(x) for x in args.schedule.split(","))
+        log(f"schedule (given): tile {tile}, steps per launch {spl or 'all'}")
+    else:
+        tune = autotune.tune_batch(st, step=step, nsteps=8)
+        tile, spl = tune["tile"], tune["steps_per_launch"]
+        log(f"schedule: tile {tile}, steps per launch {spl or 'all'} "
+            f"({ {f'{k[0]}/{k[1]}': round(v, 4) for k, v in tune['ms_per_step'].items()} } ms/step)")
     if args.warmup:
         st.batch(step, args.warmup, tile, spl)
         step += args.warmup
@@ -282,6 +286,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--scale", type=float, default=1.0,
                     help="grid scale of the cylinder workload (1.0 = full size)")
+    ap.add_argument("--schedule", default=None, metavar="TILE,SPL",
+                    help="c2: fixed usp_batch schedule (tile, steps per launch; 0 = all) "
+                         "instead of the autotuner's choice")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",

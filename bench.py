@@ -97,6 +97,10 @@ def run_gpu(args):
     n0 = parts["n"]
     log(f"workload ready: {n0} particles, {prob.grid.ncells} cells")
     st = usp.DeviceState(prob, parts, device="cuda:0")
+    if args.sample:
+        # the sampling phase of a run: field sums every step, wall sums at
+        # every diffuse re-emission (cylinder in 1-degree elements)
+        st.enable_sampling(args.sample)
     M = prob.grid.ncells
     step = 0
 
@@ -107,6 +111,8 @@ def run_gpu(args):
             nlog[k].copy_(st.bufs[st.cur]["count"][0])
         if ev: ev[1].record()
         st.do_moments()
+        if args.sample:
+            st.sample_fields()
         if ev: ev[2].record()
         st.do_reconstruct()
         if ev: ev[3].record()
@@ -167,7 +173,8 @@ def run_gpu(args):
         config={"workload": f"cylinder_mach10_{prob.grid.nx}x{prob.grid.ny}",
                 "particles_start": int(n0), "particles_mean": int(n_mean), "cells": M,
                 "state": "f32", "accumulation": "f64", "dt_s": prob.dt,
-                "first_timed_step": args.warmup, "parallelism": "single-gpu"},
+                "first_timed_step": args.warmup, "sampling": bool(args.sample),
+                "parallelism": "single-gpu"},
         phase_ms=phase_ms,
         step_algorithmic_gbs=round(step_bytes / (wall / K) / 1e9, 1),
         roofline=roof,
@@ -289,6 +296,9 @@ def main():
     ap.add_argument("--schedule", default=None, metavar="TILE,SPL",
                     help="c2: fixed usp_batch schedule (tile, steps per launch; 0 = all) "
                          "instead of the autotuner's choice")
+    ap.add_argument("--sample", type=int, default=0, metavar="NBODY",
+                    help="cylinder: sample fields every step and wall fluxes with NBODY "
+                         "angular elements on the cylinder (0 = no sampling)")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",

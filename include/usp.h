@@ -132,7 +132,11 @@ typedef struct {
 } usp_grid;
 
 /* Boundaries (host struct).  The paper names diffuse isothermal walls, a
-   symmetry plane and a free stream (Secs. V.B, V.C); kinds per side. */
+   symmetry plane and a free stream (Secs. V.B, V.C); kinds per side.
+   Surface sampling (the wall fluxes behind the surface coefficients C_f,
+   C_h, the drag and the peak heat flux of Sec. V.C): when `surf` is not
+   NULL every diffuse re-emission adds the momentum and energy that the
+   particle gives the wall to its surface element, see USP_SURF_* below. */
 typedef struct {
   int32_t kind[4];   /* USP_BC_* for xlo, xhi, ylo, yhi */
   double Tw[4];      /* diffuse-wall temperature per side [K] */
@@ -143,7 +147,38 @@ typedef struct {
   int32_t cyl;       /* 1: a cylinder (a circle in x,y) is present */
   double cyl_xc, cyl_yc, cyl_r, cyl_Tw;
   double g[3];       /* body acceleration [m/s^2], applied before the flight */
+  int64_t* surf;     /* DEVICE int64[usp_surf_elements() * USP_SURF_NQ] or NULL */
+  int32_t surf_nbody;/* angular elements on the cylinder (0: body not sampled) */
 } usp_bc;
+
+/* Surface elements: ylo wall [0, nx) by the x cell of the hit point, yhi
+   wall [nx, 2nx), xlo wall [2nx, 2nx+ny) by the y cell, xhi wall
+   [2nx+ny, 2nx+2ny), cylinder [2nx+2ny, +surf_nbody) by the angle
+   Theta = atan2(|y - yc|, xc - x) in [0, pi] from the upstream stagnation
+   point, surf_nbody equal bins (the two halves of a full cylinder share a
+   bin).  Per element USP_SURF_NQ int64 sums, row-major surf[e*NQ + q],
+   accumulated with integer atomics in fixed point, so the totals do not
+   depend on the order of the hits.  Per hit, with c_in/c_out the velocity
+   before/after the re-emission and n the unit normal into the gas (t the
+   tangent: +x on the y walls, +y on the x walls, increasing Theta on the
+   cylinder), all per unit mass:
+     HITS  1
+     PX, PY, PZ  (c_in - c_out) * USP_SURF_P_SCALE      [m/s -> fixed]
+     PN  -(c_in - c_out).n * USP_SURF_P_SCALE  (pressure part)
+     PT   (c_in - c_out).t * USP_SURF_P_SCALE  (shear part)
+     ETR  (|c_in|^2 - |c_out|^2)/2 * USP_SURF_E_SCALE   [J/kg -> fixed]
+     EROT (eps_in - eps_out) * USP_SURF_E_SCALE
+     QVIB I_in - I_out  (quanta; energy R theta_vib each)
+   each value rounded to the nearest integer (ties to even) before it is
+   added.  Multiply by m * fnum / (area * time) for fluxes.  The caller
+   zeroes the buffer; sums overflow only past ~1e9 hits per element. */
+enum {
+  USP_SURF_HITS = 0, USP_SURF_PX = 1, USP_SURF_PY = 2, USP_SURF_PZ = 3,
+  USP_SURF_PN = 4, USP_SURF_PT = 5, USP_SURF_ETR = 6, USP_SURF_EROT = 7,
+  USP_SURF_QVIB = 8, USP_SURF_NQ = 9
+};
+#define USP_SURF_P_SCALE 65536.0
+#define USP_SURF_E_SCALE 16.0
 
 /* Particle state (Sec. II.A: position, velocity, rotational energy,
    vibrational level), structure of arrays in DEVICE memory, `capacity`
@@ -174,6 +209,11 @@ typedef struct {
    by one packed 128-byte record per cell that the particle update reads;
    usp_cellstate_bytes() gives its size. */
 #define USP_NCS 39
+/* Field-sampling planes: running sums over sampled steps of the per-cell
+   raw particle sums (the time averages of the cylinder case, Sec. V.C):
+   N, sum c(3), sum c_i c_j(6: xx yy zz xy xz yz), sum eps_rot, sum I,
+   sum (1/2)|c|^2 c(3), sum c eps_rot(3), sum c I(3). */
+#define USP_NSAMP 21
 
 const char* usp_status_str(usp_status s);
 const char* usp_mom_name(int32_t k);
@@ -184,6 +224,10 @@ const char* usp_version(void);
 /* Bytes of the cell-state buffer `cs` for this grid (0 if the grid is
    invalid). */
 size_t usp_cellstate_bytes(const usp_grid* grid);
+
+/* Number of surface elements for this grid and bc (2 nx + 2 ny +
+   bc->surf_nbody), or 0 if an argument is invalid. */
+int64_t usp_surf_elements(const usp_grid* grid, const usp_bc* bc);
 
 /* Bytes of scratch the caller passes as `ws` to usp_bin, usp_advect,
    usp_update and usp_step for this grid and particle capacity. */
@@ -215,6 +259,17 @@ usp_status usp_bin(const usp_grid* grid, const usp_particles* in, usp_particles*
    accumulated in FP64 in a fixed order (deterministic). */
 usp_status usp_moments(const usp_grid* grid, const usp_particles* p, const int64_t* offsets,
                        double* mom, void* stream);
+
+/* Field sampling (the N_sampling phase of Sec. V.C): acc (device
+   double[USP_NSAMP*M], plane-major, zeroed by the caller before the first
+   sample) += the raw particle sums of each cell formed from the moment
+   planes `mom` of usp_moments (N, N U, N (Pi + U U), N e_rot, N I_mean,
+   N ((1/2)|U|^2 U + Pi U + tr(Pi) U/2 + q_tr), N (U e_rot + q_rot),
+   N (U I_mean + <C I>)).  Thread per cell, no atomics: deterministic.
+   To sample every step, call usp_step with nsteps = 1 and this after it
+   (mom then holds the step's pre-collision moments). */
+usp_status usp_sample_fields(const usp_grid* grid, const double* mom, double* acc,
+                             void* stream);
 
 /* Cell state (Secs. II.A, III.A.1, III.A.2, IV.A, IV.B): temperatures,
    viscosity, tau_c, Z's, Pr, the USP-FPM coefficients alpha (eq.
@@ -252,7 +307,9 @@ usp_status usp_conserve(const usp_grid* grid, const usp_gas* gas, const double* 
    1, block).  Removed particles get cell -1; survivors get their new cell.
    Free-stream faces then inject new particles after the live ones (ids
    count[1], count[1]+1, ...; draws from (face, step, 5, 0) and (pid, step, 3,
-   block)); count[] is advanced on the device.  No-op for dim 0. */
+   block)); count[] is advanced on the device.  With bc->surf set, every
+   diffuse re-emission is added to its surface element (see usp_bc).
+   No-op for dim 0. */
 usp_status usp_advect(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
                       usp_particles* p, uint64_t seed, uint64_t step, void* ws, size_t ws_bytes,
                       int64_t* counters, void* stream);

@@ -28,6 +28,11 @@ CNT_NAMES = ["PB_CLAMP", "CHOL_FALLBACK", "NU_ZERO", "TREL_SKIP", "TREL_CLAMP", 
              "INTERP_CLAMP", "CONS_SKIP", "PICK_FAIL", "CELL_SKIP", "INJECTED", "DELETED",
              "WALL_HITS", "BOUNCE_LIMIT", "CAPACITY", "SOLID_DROP"]
 NMOM, NCS, NCNT = len(MOM_NAMES), len(CS_NAMES), len(CNT_NAMES)
+SAMP_NAMES = ["N", "CX", "CY", "CZ", "CXX", "CYY", "CZZ", "CXY", "CXZ", "CYZ", "EROT", "I",
+              "HC2CX", "HC2CY", "HC2CZ", "CXEROT", "CYEROT", "CZEROT", "CXI", "CYI", "CZI"]
+SURF_NAMES = ["HITS", "PX", "PY", "PZ", "PN", "PT", "ETR", "EROT", "QVIB"]
+NSAMP, SURF_NQ = len(SAMP_NAMES), len(SURF_NAMES)
+SURF_P_SCALE, SURF_E_SCALE = 65536.0, 16.0
 
 PD = C.POINTER(C.c_double)
 
@@ -52,7 +57,8 @@ class OrcBC(C.Structure):
     _fields_ = [("kind", C.c_int32 * 4), ("Tw", C.c_double * 4), ("fs_n", C.c_double),
                 ("fs_T", C.c_double), ("fs_U", C.c_double * 3), ("depth", C.c_double),
                 ("cyl", C.c_int32), ("cyl_xc", C.c_double), ("cyl_yc", C.c_double),
-                ("cyl_r", C.c_double), ("cyl_Tw", C.c_double), ("g", C.c_double * 3)]
+                ("cyl_r", C.c_double), ("cyl_Tw", C.c_double), ("g", C.c_double * 3),
+                ("surf", C.c_void_p), ("surf_nbody", C.c_int32)]
 
 
 class OrcParts(C.Structure):
@@ -100,6 +106,7 @@ def lib():
         L.orc_collide.argtypes = [vp, vp, vp, vp, vp, u64, u64, i32, vp]
         L.orc_conserve.argtypes = [vp, vp, vp, vp, vp, u64, u64, i32, vp]
         L.orc_advect.argtypes = [vp, vp, vp, d, vp, u64, u64, i32, vp]
+        L.orc_sample_fields.argtypes = [vp, vp, vp, vp]
         L.orc_step.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, vp, vp, u64, u64, i32, i32, vp]
         L.orc_sample_nb.argtypes = [d, i32, d]
         L.orc_sample_nb.restype = i32
@@ -187,7 +194,9 @@ class Sim:
         b = prob.bc
         self.bc = OrcBC((C.c_int32 * 4)(*b.kind), (C.c_double * 4)(*b.Tw), b.fs_n, b.fs_T,
                         (C.c_double * 3)(*b.fs_U), b.depth, b.cyl, b.cyl_xc, b.cyl_yc, b.cyl_r,
-                        b.cyl_Tw, (C.c_double * 3)(*b.g))
+                        b.cyl_Tw, (C.c_double * 3)(*b.g), None, 0)
+        self.surf = None
+        self.fields = None
         self.dt_cell = None if prob.dt_cell is None else np.ascontiguousarray(prob.dt_cell, np.float64)
         cap = parts["cap"]
         self.cap = cap
@@ -279,6 +288,24 @@ class Sim:
         lib().orc_advect(C.byref(self.grid), C.byref(self.gas), C.byref(self.bc), self.prob.dt,
                          C.byref(self.structs[self.cur]), self.prob.seed, step, self.f32,
                          _p(self.counters))
+
+    def enable_sampling(self, nbody=0):
+        """Zeroed field sums [NSAMP, M] and surface sums [elements, SURF_NQ]
+        (int64 fixed point); from now on every diffuse re-emission is
+        sampled, and :meth:`sample_fields` adds the current binned state."""
+        g = self.prob.grid
+        ne = 2 * g.nx + 2 * g.ny + int(nbody)
+        self.surf = np.zeros((ne, SURF_NQ), np.int64)
+        self.fields = np.zeros((NSAMP, self.M))
+        self.bc.surf = self.surf.ctypes.data
+        self.bc.surf_nbody = int(nbody)
+
+    def sample_fields(self):
+        """Add the per-cell particle sums of the current binned state."""
+        if not self.sorted:
+            raise RuntimeError("sample_fields needs a binned state")
+        lib().orc_sample_fields(C.byref(self.grid), C.byref(self.structs[self.cur]),
+                                _p(self.offsets), _p(self.fields))
 
     def interp(self, field, cell, x, y):
         return lib().orc_interp(C.byref(self.grid), _p(self.cs), CS_NAMES.index(field), cell, x, y)

@@ -344,6 +344,41 @@ int orc_moments(const orc_grid* gr, const orc_gas* gas, const orc_parts* p,
 }
 
 /* ======================================================================== */
+/* Field sampling: per cell, the plain sums over its particles of 1, c,    */
+/* c_i c_j, eps_rot, I, |c|^2 c/2, c eps_rot and c I, added to the running  */
+/* sums of the sampled steps (time averages of the cylinder case, Sec. V.C).*/
+/* ======================================================================== */
+int orc_sample_fields(const orc_grid* gr, const orc_parts* p, const int64_t* offsets,
+                      double* acc) {
+  int64_t M = ncells(gr);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t c = 0; c < M; ++c) {
+    double s[ORC_NSAMP];
+    for (int k = 0; k < ORC_NSAMP; ++k) s[k] = 0.0;
+    for (int64_t i = offsets[c]; i < offsets[c + 1]; ++i) {
+      double v[3] = {p->cx[i], p->cy[i], p->cz[i]};
+      double e = p->erot[i], I = (double)p->vib[i];
+      double h = 0.5 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+      s[0] += 1.0;
+      for (int k = 0; k < 3; ++k) {
+        s[1 + k] += v[k];
+        s[4 + k] += v[k] * v[k];
+        s[12 + k] += h * v[k];
+        s[15 + k] += v[k] * e;
+        s[18 + k] += v[k] * I;
+      }
+      s[7] += v[0] * v[1];
+      s[8] += v[0] * v[2];
+      s[9] += v[1] * v[2];
+      s[10] += e;
+      s[11] += I;
+    }
+    for (int k = 0; k < ORC_NSAMP; ++k) acc[(int64_t)k * M + c] += s[k];
+  }
+  return 0;
+}
+
+/* ======================================================================== */
 /* Cell state: temperatures, transport, and the USP-FPM cell coefficients.  */
 /*   T_tr = tr(Pi)/(3R), T_rot = e_rot/R, T_vib from the mean level.        */
 /*   mu(T_tr), p = n k T_tr, tau_c, Z's, Pr (Secs. IV.A, IV.B, V.C).         */
@@ -932,6 +967,65 @@ static double settle(double v, double lo, double hi, int32_t f32) {
   return v;
 }
 
+/* One diffuse re-emission into the surface sums (see usp_oracle.h).      */
+static void surf_fix_add(int64_t* a, double v, double scale) {
+  int64_t q = llrint(v * scale);
+#pragma omp atomic
+  *a += q;
+}
+
+static void surface_sample(const orc_grid* gr, const orc_bc* bc, int side, double x,
+                           double y, const double cin[3], double ein, int32_t lin,
+                           const double cout[3], double eout, int32_t lout) {
+  int64_t e;
+  double n[2], t[2];
+  if (side == ORC_SIDE_YLO || side == ORC_SIDE_YHI) {
+    int64_t ix = 0;
+    if (gr->dim == 2) {
+      double f = floor((x - gr->x0) / gr->dx);
+      ix = (f < 0.0) ? 0 : (f >= gr->nx) ? gr->nx - 1 : (int64_t)f;
+    }
+    e = ((side == ORC_SIDE_YLO) ? 0 : gr->nx) + ix;
+    n[0] = 0.0; n[1] = (side == ORC_SIDE_YLO) ? 1.0 : -1.0;
+    t[0] = 1.0; t[1] = 0.0;
+  } else if (side == ORC_SIDE_XLO || side == ORC_SIDE_XHI) {
+    double f = floor((y - gr->y0) / gr->dy);
+    int64_t iy = (f < 0.0) ? 0 : (f >= gr->ny) ? gr->ny - 1 : (int64_t)f;
+    e = 2 * (int64_t)gr->nx + ((side == ORC_SIDE_XLO) ? 0 : gr->ny) + iy;
+    n[0] = (side == ORC_SIDE_XLO) ? 1.0 : -1.0; n[1] = 0.0;
+    t[0] = 0.0; t[1] = 1.0;
+  } else {
+    if (bc->surf_nbody <= 0) return;
+    /* outward unit normal of the circle at the hit point */
+    double ux = x - bc->cyl_xc, uy = y - bc->cyl_yc;
+    double r = sqrt(ux * ux + uy * uy);
+    n[0] = ux / r; n[1] = uy / r;
+    /* Theta from the upstream point (-r, 0), growing over either half */
+    double theta = atan2(fabs(n[1]), -n[0]);
+    double f = floor(theta * bc->surf_nbody / PI);
+    int64_t ib = (f < 0.0) ? 0 : (f >= bc->surf_nbody) ? bc->surf_nbody - 1 : (int64_t)f;
+    e = 2 * (int64_t)gr->nx + 2 * (int64_t)gr->ny + ib;
+    /* d(point)/dTheta direction: upper half (n_y >= 0) and its mirror */
+    if (n[1] >= 0.0) { t[0] = n[1]; t[1] = -n[0]; }
+    else { t[0] = -n[1]; t[1] = n[0]; }
+  }
+  int64_t* a = bc->surf + e * ORC_SURF_NQ;
+  double d[3] = {cin[0] - cout[0], cin[1] - cout[1], cin[2] - cout[2]};
+#pragma omp atomic
+  a[ORC_SURF_HITS] += 1;
+  surf_fix_add(a + ORC_SURF_PX, d[0], ORC_SURF_P_SCALE);
+  surf_fix_add(a + ORC_SURF_PY, d[1], ORC_SURF_P_SCALE);
+  surf_fix_add(a + ORC_SURF_PZ, d[2], ORC_SURF_P_SCALE);
+  surf_fix_add(a + ORC_SURF_PN, -(d[0] * n[0] + d[1] * n[1]), ORC_SURF_P_SCALE);
+  surf_fix_add(a + ORC_SURF_PT, d[0] * t[0] + d[1] * t[1], ORC_SURF_P_SCALE);
+  double kin = cin[0] * cin[0] + cin[1] * cin[1] + cin[2] * cin[2];
+  double kout = cout[0] * cout[0] + cout[1] * cout[1] + cout[2] * cout[2];
+  surf_fix_add(a + ORC_SURF_ETR, 0.5 * (kin - kout), ORC_SURF_E_SCALE);
+  surf_fix_add(a + ORC_SURF_EROT, ein - eout, ORC_SURF_E_SCALE);
+#pragma omp atomic
+  a[ORC_SURF_QVIB] += (int64_t)(lin - lout);
+}
+
 static void flight(const orc_grid* gr, const orc_gas* g, const orc_bc* bc, double dt,
                    orc_parts* p, int64_t i, uint64_t seed, uint64_t step, int32_t f32,
                    int64_t* lc) {
@@ -1002,6 +1096,9 @@ static void flight(const orc_grid* gr, const orc_gas* g, const orc_bc* bc, doubl
     wall_draw(g, Tw, seed, p->pid[i], step, bounces, &cn, &ta, &tb, &ner, &nlv);
     bounces++;
     lc[ORC_CNT_WALL_HITS] += 1;
+    double cin[3] = {cx, cy, cz}, ein = er;
+    int32_t lin = lv;
+    double hx = x, hy = y;   /* the hit point */
     er = ner; lv = nlv; changed_int = 1;
     if (side == ORC_SIDE_YLO || side == ORC_SIDE_YHI) {
       cy = (side == ORC_SIDE_YLO) ? cn : -cn;
@@ -1018,6 +1115,10 @@ static void flight(const orc_grid* gr, const orc_gas* g, const orc_bc* bc, doubl
       cx = cn * nxv - ta * nyv;
       cy = cn * nyv + ta * nxv;
       cz = tb;
+    }
+    if (bc->surf) {
+      double cout[3] = {cx, cy, cz};
+      surface_sample(gr, bc, side, hx, hy, cin, ein, lin, cout, er, lv);
     }
   }
   (void)changed_int;

@@ -121,7 +121,27 @@ typedef struct {
   int32_t cyl;       /* 1: a cylinder (circle in x,y) is present            */
   double cyl_xc, cyl_yc, cyl_r, cyl_Tw;
   double g[3];       /* body acceleration [m/s^2]                           */
+  int64_t* surf;     /* surface sums [element][ORC_SURF_NQ] or NULL         */
+  int32_t surf_nbody;/* angular elements on the cylinder                    */
 } orc_bc;
+
+/* ---- sampling (the N_sampling phase of Sec. V.C) ------------------------- */
+/* Surface elements: ylo wall by x cell [0, nx), yhi [nx, 2nx), xlo by y    */
+/* cell [2nx, 2nx+ny), xhi [2nx+ny, 2nx+2ny), cylinder by the angle from   */
+/* the upstream stagnation point, Theta in [0, pi], in surf_nbody bins.    */
+/* Per element, per diffuse re-emission, per unit mass, fixed point:       */
+/* hits; c_in - c_out (x, y, z); its components along -n and t (n: normal  */
+/* into the gas, t: +x on y walls, +y on x walls, increasing Theta on the  */
+/* cylinder); (|c_in|^2 - |c_out|^2)/2; eps_in - eps_out; I_in - I_out.    */
+enum {
+  ORC_SURF_HITS = 0, ORC_SURF_PX, ORC_SURF_PY, ORC_SURF_PZ, ORC_SURF_PN, ORC_SURF_PT,
+  ORC_SURF_ETR, ORC_SURF_EROT, ORC_SURF_QVIB, ORC_SURF_NQ
+};
+#define ORC_SURF_P_SCALE 65536.0   /* fixed-point units per m/s   */
+#define ORC_SURF_E_SCALE 16.0      /* fixed-point units per J/kg  */
+/* Field sums: N, sum c, sum c_i c_j (xx yy zz xy xz yz), sum eps_rot,      */
+/* sum I, sum |c|^2 c / 2, sum c eps_rot, sum c I; plane-major [k][M].       */
+#define ORC_NSAMP 21
 
 /* ---- particles (FP64 structure of arrays) ------------------------------- */
 typedef struct {
@@ -194,6 +214,8 @@ int orc_collide(const orc_grid* grid, const orc_gas* gas, const double* cs,
 int orc_conserve(const orc_grid* grid, const orc_gas* gas, const double* cs,
                  const int64_t* offsets, orc_parts* p, uint64_t seed, uint64_t step,
                  int32_t f32, int64_t* counters);
+int orc_sample_fields(const orc_grid* grid, const orc_parts* p, const int64_t* offsets,
+                      double* acc);
 int orc_advect(const orc_grid* grid, const orc_gas* gas, const orc_bc* bc, double dt,
                orc_parts* p, uint64_t seed, uint64_t step, int32_t f32, int64_t* counters);
 int orc_step(const orc_grid* grid, const orc_gas* gas, const orc_bc* bc, double dt,

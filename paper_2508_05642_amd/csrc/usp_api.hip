@@ -46,6 +46,8 @@ BcP make_bc(const usp_bc* b) {
   for (int k = 0; k < 3; ++k) { p.fs_U[k] = b->fs_U[k]; p.g[k] = b->g[k]; }
   p.depth = b->depth;
   p.cyl = b->cyl; p.cyl_xc = b->cyl_xc; p.cyl_yc = b->cyl_yc; p.cyl_r = b->cyl_r; p.cyl_Tw = b->cyl_Tw;
+  p.surf = (unsigned long long*)b->surf;
+  p.surf_nbody = b->surf_nbody;
   return p;
 }
 
@@ -112,6 +114,18 @@ bool parts_ok(const usp_particles* p, const usp_grid* g) {
 bool gas_ok(const usp_gas* g) {
   return g && g->m > 0.0 && g->theta_vib > 0.0 && g->T_ref > 0.0 && g->mu_ref > 0.0 &&
          g->alpha_vss > 0.0 && (g->scheme == USP_SCHEME_USP || g->scheme == USP_SCHEME_FPM);
+}
+
+// Free-stream faces need a temperature and a depth; the surface element
+// count must not be negative.  A null bc passes (callers that require one
+// check it themselves).
+bool bc_ok(const usp_bc* b, const usp_grid* grid) {
+  if (!b) return true;
+  if (b->surf_nbody < 0) return false;
+  if (grid->dim == 2)
+    for (int k = 0; k < 4; ++k)
+      if (b->kind[k] == USP_BC_FREESTREAM && !(b->fs_T > 0.0 && b->depth > 0.0)) return false;
+  return true;
 }
 
 usp_status hip_status(hipError_t e) { return e == hipSuccess ? USP_OK : USP_EDEVICE; }
@@ -201,6 +215,11 @@ size_t usp_cellstate_bytes(const usp_grid* grid) {
   return cellstate_bytes((int64_t)grid->nx * grid->ny);
 }
 
+int64_t usp_surf_elements(const usp_grid* grid, const usp_bc* bc) {
+  if (!grid_ok(grid) || !bc || bc->surf_nbody < 0) return 0;
+  return 2 * (int64_t)grid->nx + 2 * (int64_t)grid->ny + bc->surf_nbody;
+}
+
 size_t usp_workspace_bytes(const usp_grid* grid, int64_t capacity) {
   if (!grid_ok(grid) || capacity <= 0) return 0;
   const GridP g = make_grid(grid);
@@ -226,6 +245,12 @@ usp_status usp_moments(const usp_grid* grid, const usp_particles* p, const int64
   hipStream_t st = (hipStream_t)stream;
   return hip_status(p->prec == USP_F32 ? launch_moments<float>(g, make_parts<float>(p), offsets, mom, st)
                                        : launch_moments<double>(g, make_parts<double>(p), offsets, mom, st));
+}
+
+usp_status usp_sample_fields(const usp_grid* grid, const double* mom, double* acc,
+                             void* stream) {
+  if (!grid_ok(grid) || !mom || !acc) return USP_EINVAL;
+  return hip_status(launch_sample_fields(make_grid(grid), mom, acc, (hipStream_t)stream));
 }
 
 usp_status usp_reconstruct(const usp_grid* grid, const usp_gas* gas, const double* mom,
@@ -265,15 +290,11 @@ usp_status usp_advect(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc
                       usp_particles* p, uint64_t seed, uint64_t step, void* ws, size_t ws_bytes,
                       int64_t* counters, void* stream) {
   if (!grid_ok(grid) || !gas_ok(gas) || !bc || !parts_ok(p, grid) || !ws) return USP_EINVAL;
-  if (!(dt > 0.0)) return USP_EINVAL;
+  if (!(dt > 0.0) || !bc_ok(bc, grid)) return USP_EINVAL;
   if (ws_bytes < usp_workspace_bytes(grid, p->capacity)) return USP_EINVAL;
   const GridP g = make_grid(grid);
   const GasP gp = make_gas(gas);
   const BcP bp = make_bc(bc);
-  if (g.dim == 2) {
-    for (int k = 0; k < 4; ++k)
-      if (bp.kind[k] == USP_BC_FREESTREAM && !(bp.fs_T > 0.0 && bp.depth > 0.0)) return USP_EINVAL;
-  }
   const WsLayout L = ws_layout(g.M, p->capacity, n_faces(g));
   hipStream_t st = (hipStream_t)stream;
   return hip_status(p->prec == USP_F32
@@ -288,14 +309,11 @@ usp_status usp_update(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc
   if (!grid_ok(grid) || !gas_ok(gas) || !parts_ok(p, grid) || !cs || !offsets || !ws)
     return USP_EINVAL;
   if (grid->dim >= 1 && (!bc || !(dt > 0.0))) return USP_EINVAL;
+  if (!bc_ok(bc, grid)) return USP_EINVAL;
   if (ws_bytes < usp_workspace_bytes(grid, p->capacity)) return USP_EINVAL;
   const GridP g = make_grid(grid);
   const GasP gp = make_gas(gas);
   const BcP bp = make_bc(bc);
-  if (g.dim == 2) {
-    for (int k = 0; k < 4; ++k)
-      if (bp.kind[k] == USP_BC_FREESTREAM && !(bp.fs_T > 0.0 && bp.depth > 0.0)) return USP_EINVAL;
-  }
   const WsLayout L = ws_layout(g.M, p->capacity, n_faces(g));
   hipStream_t st = (hipStream_t)stream;
   return hip_status(p->prec == USP_F32
@@ -331,6 +349,7 @@ usp_status usp_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, 
   if (!offsets || !mom || !cs || !ws || nsteps < 0) return USP_EINVAL;
   if (p->prec != p_alt->prec || p_alt->capacity < p->capacity || p->cx == p_alt->cx) return USP_EINVAL;
   if (grid->dim >= 1 && (!bc || !(dt > 0.0))) return USP_EINVAL;
+  if (!bc_ok(bc, grid)) return USP_EINVAL;
   if (!dt_cell && !(dt > 0.0)) return USP_EINVAL;
   if (ws_bytes < usp_workspace_bytes(grid, p_alt->capacity)) return USP_EINVAL;
   hipStream_t st = (hipStream_t)stream;

@@ -80,6 +80,8 @@ struct BcP {
   int cyl;
   double cyl_xc, cyl_yc, cyl_r, cyl_Tw;
   double g[3];
+  unsigned long long* surf;  // surface sums [element][USP_SURF_NQ] or null
+  int surf_nbody;
 };
 
 template <typename S>
@@ -118,6 +120,7 @@ hipError_t launch_moments(const GridP& g, const PartP<S>& p, const int64_t* offs
                           hipStream_t st);
 hipError_t launch_reconstruct(const GridP& g, const GasP& gas, const double* mom, double dt,
                               const double* dt_cell, double* cs, int64_t* counters, hipStream_t st);
+hipError_t launch_sample_fields(const GridP& g, const double* mom, double* acc, hipStream_t st);
 template <typename S>
 hipError_t launch_collide(const GridP& g, const GasP& gas, const double* cs, const int64_t* offsets,
                           const PartP<S>& p, uint64_t seed, uint64_t step, int64_t* counters,

@@ -67,6 +67,53 @@ __global__ void k_stencil(GridP g, double* cs) {
   cell_records(cs, M)[c].stencil = bits;
 }
 
+// Field sampling: the raw particle sums of each cell, N <f(c)>, formed
+// from the central moment planes (c = U + C) and added to the running sums.
+// Thread per cell, plain read-modify-write: deterministic.
+__global__ void k_sample_fields(int64_t M, const double* __restrict__ mom,
+                                double* __restrict__ acc) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= M) return;
+  const double N = mom[M_N * M + c];
+  if (N == 0.0) return;
+  double U[3], P[6], qt[3], qr[3], qi[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    U[k] = mom[(M_UX + k) * M + c];
+    qt[k] = mom[(M_QTRX + k) * M + c];
+    qr[k] = mom[(M_QROTX + k) * M + c];
+    qi[k] = mom[(M_QIX + k) * M + c];
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) P[k] = mom[(M_PXX + k) * M + c];
+  const double er = mom[M_EROT * M + c], Ib = mom[M_IBAR * M + c];
+  // Pi as a full matrix: xx yy zz xy xz yz
+  const double PU[3] = {P[0] * U[0] + P[3] * U[1] + P[4] * U[2],
+                        P[3] * U[0] + P[1] * U[1] + P[5] * U[2],
+                        P[4] * U[0] + P[5] * U[1] + P[2] * U[2]};
+  const double hU2 = 0.5 * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
+  const double htr = 0.5 * (P[0] + P[1] + P[2]);
+  double v[USP_NSAMP];
+  v[0] = 1.0;
+  v[1] = U[0]; v[2] = U[1]; v[3] = U[2];
+  v[4] = P[0] + U[0] * U[0]; v[5] = P[1] + U[1] * U[1]; v[6] = P[2] + U[2] * U[2];
+  v[7] = P[3] + U[0] * U[1]; v[8] = P[4] + U[0] * U[2]; v[9] = P[5] + U[1] * U[2];
+  v[10] = er; v[11] = Ib;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    v[12 + k] = (hU2 + htr) * U[k] + PU[k] + qt[k];
+    v[15 + k] = U[k] * er + qr[k];
+    v[18 + k] = U[k] * Ib + qi[k];
+  }
+#pragma unroll
+  for (int k = 0; k < USP_NSAMP; ++k) acc[k * M + c] += N * v[k];
+}
+
+hipError_t launch_sample_fields(const GridP& g, const double* mom, double* acc, hipStream_t st) {
+  k_sample_fields<<<cdiv(g.M, 256), 256, 0, st>>>(g.M, mom, acc);
+  return hipGetLastError();
+}
+
 template <typename S>
 hipError_t launch_moments(const GridP& g, const PartP<S>& p, const int64_t* offsets, double* mom,
                           hipStream_t st) {

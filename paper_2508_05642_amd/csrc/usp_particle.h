@@ -802,6 +802,57 @@ __device__ __forceinline__ S settle(double v, double lo, double hi) {
 // periodic, specular, outflow/free-stream and diffuse-wall boundaries (wall
 // re-emission continues the remaining flight time).  Writes position,
 // velocity, rot/vib state and the new cell (or -1 on deletion) to p.
+// Surface sampling of one diffuse re-emission: the momentum and energy the
+// particle gives the wall, per unit mass, added in fixed point to its
+// element with integer atomics (order-independent sums).  (nx, ny) is the
+// unit normal into the gas; side 4 is the cylinder.
+__device__ __forceinline__ void surf_add(unsigned long long* a, double v, double scale) {
+  atomicAdd(a, (unsigned long long)__double2ll_rn(v * scale));
+}
+
+__device__ __forceinline__ void surf_record(const GridP& g, const BcP& bc, int side, double x,
+                                         double y, double nx, double ny, double cix, double ciy,
+                                         double ciz, double eri, int lvi, double cox, double coy,
+                                         double coz, double ero, int lvo) {
+  int64_t e;
+  double tx, ty;
+  if (side == USP_SIDE_YLO || side == USP_SIDE_YHI) {
+    int64_t ix = 0;
+    if (g.dim == 2) {
+      const double f = floor((x - g.x0) / g.dx);
+      ix = f < 0.0 ? 0 : (f >= (double)g.nx ? g.nx - 1 : (int64_t)f);
+    }
+    e = (side == USP_SIDE_YLO ? 0 : g.nx) + ix;
+    nx = 0.0; ny = side == USP_SIDE_YLO ? 1.0 : -1.0; tx = 1.0; ty = 0.0;
+  } else if (side == USP_SIDE_XLO || side == USP_SIDE_XHI) {
+    const double f = floor((y - g.y0) / g.dy);
+    const int64_t iy = f < 0.0 ? 0 : (f >= (double)g.ny ? g.ny - 1 : (int64_t)f);
+    e = 2 * (int64_t)g.nx + (side == USP_SIDE_XLO ? 0 : g.ny) + iy;
+    nx = side == USP_SIDE_XLO ? 1.0 : -1.0; ny = 0.0; tx = 0.0; ty = 1.0;
+  } else {
+    if (bc.surf_nbody <= 0) return;
+    const double th = atan2(fabs(ny), -nx);
+    const double f = floor(th * (double)bc.surf_nbody / M_PI);
+    const int64_t ib = f < 0.0 ? 0 : (f >= (double)bc.surf_nbody ? bc.surf_nbody - 1 : (int64_t)f);
+    e = 2 * (int64_t)g.nx + 2 * (int64_t)g.ny + ib;
+    // tangent along increasing Theta on either half
+    if (ny >= 0.0) { tx = ny; ty = -nx; } else { tx = -ny; ty = nx; }
+  }
+  unsigned long long* a = bc.surf + e * USP_SURF_NQ;
+  const double dx = cix - cox, dy = ciy - coy, dz = ciz - coz;
+  atomicAdd(a + USP_SURF_HITS, 1ull);
+  surf_add(a + USP_SURF_PX, dx, USP_SURF_P_SCALE);
+  surf_add(a + USP_SURF_PY, dy, USP_SURF_P_SCALE);
+  surf_add(a + USP_SURF_PZ, dz, USP_SURF_P_SCALE);
+  surf_add(a + USP_SURF_PN, -(dx * nx + dy * ny), USP_SURF_P_SCALE);
+  surf_add(a + USP_SURF_PT, dx * tx + dy * ty, USP_SURF_P_SCALE);
+  surf_add(a + USP_SURF_ETR,
+           0.5 * ((cix * cix + ciy * ciy + ciz * ciz) - (cox * cox + coy * coy + coz * coz)),
+           USP_SURF_E_SCALE);
+  surf_add(a + USP_SURF_EROT, eri - ero, USP_SURF_E_SCALE);
+  atomicAdd(a + USP_SURF_QVIB, (unsigned long long)(long long)(lvi - lvo));
+}
+
 template <typename S>
 __device__ __forceinline__ void advect_one(const GridP& g, const GasP& gas, const BcP& bc,
                                            double dt, const PartP<S>& p, int64_t i, S cx0, S cy0,
@@ -878,8 +929,11 @@ __device__ __forceinline__ void advect_one(const GridP& g, const GasP& gas, cons
     const double Tw = side == 4 ? bc.cyl_Tw : bc.Tw[side];
     wall_draw(gas, Tw, seed, id, step, bounces, &cn, &ta, &tb, &ner, &nlv);
     ++bounces;
+    const double cix = cx, ciy = cy, ciz = cz, eri = er;
+    const int lvi = lv;
     er = ner;
     lv = nlv;
+    double nxv = 0.0, nyv = 0.0;
     if (side == USP_SIDE_YLO || side == USP_SIDE_YHI) {
       cy = side == USP_SIDE_YLO ? cn : -cn;
       cx = ta; cz = tb;
@@ -887,7 +941,8 @@ __device__ __forceinline__ void advect_one(const GridP& g, const GasP& gas, cons
       cx = side == USP_SIDE_XLO ? cn : -cn;
       cy = ta; cz = tb;
     } else {
-      double nxv = x - bc.cyl_xc, nyv = y - bc.cyl_yc;
+      nxv = x - bc.cyl_xc;
+      nyv = y - bc.cyl_yc;
       const double nn = sqrt(nxv * nxv + nyv * nyv);
       nxv /= nn;
       nyv /= nn;
@@ -897,6 +952,8 @@ __device__ __forceinline__ void advect_one(const GridP& g, const GasP& gas, cons
       cy = cn * nyv + ta * nxv;
       cz = tb;
     }
+    if (bc.surf)
+      surf_record(g, bc, side, x, y, nxv, nyv, cix, ciy, ciz, eri, lvi, cx, cy, cz, er, lv);
   }
   if (deleted) {
     // a deleted particle keeps its position and its values before the flight

@@ -20,6 +20,9 @@ LIB_PATH = os.path.join(_HERE, "libusp.so")
 
 USP_F32, USP_F64 = 0, 1
 NMOM, NCS, NCOUNTERS = 21, 39, 16
+NSAMP, SURF_NQ = 21, 9
+SURF_HITS, SURF_PX, SURF_PY, SURF_PZ, SURF_PN, SURF_PT, SURF_ETR, SURF_EROT, SURF_QVIB = range(9)
+SURF_P_SCALE, SURF_E_SCALE = 65536.0, 16.0
 
 
 class UspGas(C.Structure):
@@ -42,7 +45,8 @@ class UspBC(C.Structure):
     _fields_ = [("kind", C.c_int32 * 4), ("Tw", C.c_double * 4), ("fs_n", C.c_double),
                 ("fs_T", C.c_double), ("fs_U", C.c_double * 3), ("depth", C.c_double),
                 ("cyl", C.c_int32), ("cyl_xc", C.c_double), ("cyl_yc", C.c_double),
-                ("cyl_r", C.c_double), ("cyl_Tw", C.c_double), ("g", C.c_double * 3)]
+                ("cyl_r", C.c_double), ("cyl_Tw", C.c_double), ("g", C.c_double * 3),
+                ("surf", C.c_void_p), ("surf_nbody", C.c_int32)]
 
 
 class UspParticles(C.Structure):
@@ -75,6 +79,9 @@ def lib():
         L.usp_workspace_bytes.restype = sz
         L.usp_cellstate_bytes.argtypes = [vp]
         L.usp_cellstate_bytes.restype = sz
+        L.usp_surf_elements.argtypes = [vp, vp]
+        L.usp_surf_elements.restype = i64
+        L.usp_sample_fields.argtypes = [vp, vp, vp, vp]
         L.usp_bin.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp, vp]
         L.usp_moments.argtypes = [vp, vp, vp, vp, vp]
         L.usp_reconstruct.argtypes = [vp, vp, vp, d, vp, vp, vp, vp]
@@ -85,16 +92,17 @@ def lib():
         L.usp_batch.argtypes = [vp, vp, d, vp, vp, vp, vp, vp, vp, sz, i32, i32, u64, u64, i32, vp,
                                 vp]
         L.usp_step.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, vp, vp, vp, sz, u64, u64, i32, vp, vp]
-        for nm in ("usp_bin", "usp_moments", "usp_reconstruct", "usp_collide", "usp_conserve",
-                   "usp_advect", "usp_update", "usp_batch", "usp_step"):
+        for nm in ("usp_bin", "usp_moments", "usp_sample_fields", "usp_reconstruct", "usp_collide",
+                   "usp_conserve", "usp_advect", "usp_update", "usp_batch", "usp_step"):
             getattr(L, nm).restype = i32
         _lib = L
     return _lib
 
 
 EXPORTED = ["usp_status_str", "usp_mom_name", "usp_cs_name", "usp_counter_name", "usp_version",
-            "usp_workspace_bytes", "usp_cellstate_bytes", "usp_bin", "usp_moments", "usp_reconstruct", "usp_collide",
-            "usp_conserve", "usp_advect", "usp_update", "usp_batch", "usp_step"]
+            "usp_workspace_bytes", "usp_cellstate_bytes", "usp_surf_elements", "usp_bin",
+            "usp_moments", "usp_sample_fields", "usp_reconstruct", "usp_collide", "usp_conserve",
+            "usp_advect", "usp_update", "usp_batch", "usp_step"]
 
 
 def names(kind):
@@ -128,10 +136,10 @@ def make_gas(g):
                   g.sigma_vib, g.d_ref, g.pr_model, g.Pr_const, getattr(g, "scheme", 0))
 
 
-def make_bc(b):
+def make_bc(b, surf=None, surf_nbody=0):
     return UspBC((C.c_int32 * 4)(*b.kind), (C.c_double * 4)(*b.Tw), b.fs_n, b.fs_T,
                  (C.c_double * 3)(*b.fs_U), b.depth, b.cyl, b.cyl_xc, b.cyl_yc, b.cyl_r,
-                 b.cyl_Tw, (C.c_double * 3)(*b.g))
+                 b.cyl_Tw, (C.c_double * 3)(*b.g), _ptr(surf), int(surf_nbody))
 
 
 # ---- the seven entry points -------------------------------------------------
@@ -144,6 +152,15 @@ def usp_bin(grid, pin, pout, offsets, ws, counters, stream=None, in_offsets=None
 def usp_moments(grid, p, offsets, mom, stream=None):
     _check(lib().usp_moments(C.byref(grid), C.byref(p), _ptr(offsets), _ptr(mom),
                              _stream(stream)), "usp_moments")
+
+
+def usp_sample_fields(grid, mom, acc, stream=None):
+    _check(lib().usp_sample_fields(C.byref(grid), _ptr(mom), _ptr(acc), _stream(stream)),
+           "usp_sample_fields")
+
+
+def usp_surf_elements(grid, bc):
+    return int(lib().usp_surf_elements(C.byref(grid), C.byref(bc)))
 
 
 def usp_reconstruct(grid, gas, mom, dt, dt_cell, cs, counters, stream=None):
@@ -227,6 +244,31 @@ class DeviceState:
             raise UspError("usp_workspace_bytes rejected the grid/capacity")
         self.ws = torch.zeros(wsb, dtype=torch.uint8, device=self.dev)
         self.counters = torch.zeros(NCOUNTERS, dtype=torch.int64, device=self.dev)
+        self.fields = None
+        self.surf = None
+
+    def enable_sampling(self, nbody=0):
+        """Zeroed field sums (double[NSAMP, M]) and surface sums (int64
+        [usp_surf_elements, SURF_NQ]); from now on every diffuse re-emission
+        is sampled, and sample_fields() adds the current moments."""
+        self.bc = make_bc(self.prob.bc, None, nbody)
+        ne = usp_surf_elements(self.grid, self.bc)
+        if ne <= 0:
+            raise UspError("usp_surf_elements rejected the grid/bc")
+        self.surf = torch.zeros(ne * SURF_NQ, dtype=torch.int64, device=self.dev)
+        self.fields = torch.zeros(NSAMP * self.M, dtype=torch.float64, device=self.dev)
+        self.bc = make_bc(self.prob.bc, self.surf, nbody)
+
+    def sample_fields(self, stream=None):
+        """Add the moments in `mom` (the last step's pre-collision state) to
+        the field sums."""
+        usp_sample_fields(self.grid, self.mom, self.fields, stream)
+
+    def field_sums(self):
+        return self.fields.view(NSAMP, self.M).cpu().numpy()
+
+    def surface_sums(self):
+        return self.surf.view(-1, SURF_NQ).cpu().numpy()
 
     def _alloc(self):
         cap, dev, f = self.cap, self.dev, self.fdt

@@ -476,6 +476,8 @@ def test_update_fused_equals_phases(kind, f32):
     _say(f"[fused] case={kind} f32={f32} n={parts['n']} cells={prob.grid.ncells}")
     a = usp.DeviceState(prob, parts)
     b = usp.DeviceState(prob, parts)
+    if prob.grid.dim >= 1:
+        a.enable_sampling(24); b.enable_sampling(24)
     for s in (3, 4):
         for st in (a, b):
             st.bin(); st.do_moments(); st.do_reconstruct()
@@ -494,6 +496,9 @@ def test_update_fused_equals_phases(kind, f32):
                                        if isinstance(sa[f], np.ndarray)})
                 assert bad.size == 0, (s, k)
         assert a.cnt() == b.cnt(), (a.cnt(), b.cnt())
+        if prob.grid.dim >= 1:
+            # integer sums: the order of the atomics does not matter
+            assert np.array_equal(a.surface_sums(), b.surface_sums())
 
 
 @pytest.mark.parametrize("kind", ["2d", "1d"])
@@ -651,3 +656,74 @@ def test_autotune_batch_leaves_state():
         if isinstance(before[k], np.ndarray):
             assert np.array_equal(before[k], after[k]), k
     assert st.cnt() == cnt
+
+
+# --------------------------------------------------------------------------
+# sampling: field sums and wall sums
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,f32", CASES)
+def test_sample_fields_parity(kind, f32):
+    """usp_sample_fields (raw sums from the central moment planes) against
+    the oracle's plain particle sums, twice in a row: within 1e-10 of each
+    plane's largest magnitude."""
+    prob, gpu, orc = pair(kind, f32)
+    gpu.bin(); orc.bin()
+    gpu.do_moments()
+    gpu.enable_sampling(); orc.enable_sampling()
+    for _ in range(2):
+        gpu.sample_fields(); orc.sample_fields()
+    a, b = gpu.field_sums(), orc.fields
+    worst = 0.0
+    for k in range(oracle.NSAMP):
+        sc = float(np.abs(b[k]).max()) or 1.0
+        d = float(np.abs(a[k] - b[k]).max()) / sc
+        worst = max(worst, d)
+        assert d <= 1e-10, (oracle.SAMP_NAMES[k], d)
+    assert np.array_equal(a[0], b[0])
+    _say(f"  fields: worst scaled diff {worst:.3g}")
+
+
+def _surf_compare(a, b, what):
+    """Integer sums: hits and quanta equal; the fixed-point sums within one
+    unit per hit (the re-emission draws round differently by at most an ulp
+    between the device and host math libraries)."""
+    assert a.shape == b.shape
+    assert np.array_equal(a[:, 0], b[:, 0]), what
+    assert np.array_equal(a[:, 8], b[:, 8]), what
+    d = np.abs(a[:, 1:8] - b[:, 1:8])
+    assert np.all(d <= a[:, :1] + 1), (what, int(d.max()))
+    _say(f"  {what}: {int(a[:, 0].sum())} hits, max fixed-point diff {int(d.max())}")
+
+
+@pytest.mark.parametrize("kind,f32", [("1d", False), ("1d", True), ("2d", True), ("2d", False)])
+def test_surface_sampling_parity(kind, f32):
+    """Wall sums of one flight from identical states (the GPU's collided
+    and conserved state loaded into the oracle), the cylinder in 36
+    angular elements; then the fused particle phase of the next step."""
+    prob, gpu, orc = pair(kind, f32)
+    nb = 36 if kind == "2d" else 0
+    step = 6
+    gpu.bin(); orc.bin()
+    gpu.do_moments(); gpu.do_reconstruct()
+    gpu.collide(step); gpu.conserve(step)
+    load_into_oracle(orc, gpu.state())
+    gpu.enable_sampling(nb); orc.enable_sampling(nb)
+    gpu.advect(step); orc.advect(step)
+    a = gpu.surface_sums()
+    _surf_compare(a, orc.surf, "flight")
+    assert a[:, 0].sum() == gpu.cnt()["WALL_HITS"] > 0
+    if kind == "2d":
+        base = 2 * prob.grid.nx + 2 * prob.grid.ny
+        assert a.shape[0] == base + nb
+        assert a[base:, 0].sum() > 0, "no body hits"
+
+
+def test_surface_sampling_full_steps_fp64():
+    """Three usp_step calls with sampling on (FP64 cylinder) against the
+    oracle's steps: the same wall sums up to the rounding allowance."""
+    prob, gpu, orc = pair("2d", False)
+    gpu.enable_sampling(18); orc.enable_sampling(18)
+    for s in range(3):
+        gpu.step(20 + s, 1)
+        orc.step_native(20 + s, 1)
+    _surf_compare(gpu.surface_sums(), orc.surf, "3 steps")

@@ -47,3 +47,19 @@ def test_host_side_queries_and_validation():
     assert L.usp_bin(None, None, None, None, None, None, 0, None, None) == -1
     assert L.usp_step(None, None, None, 1.0, None, None, None, None, None, None, None, 0, 0, 0, 1,
                       None, None) == -1
+    assert L.usp_sample_fields(None, None, None, None) == -1
+    assert L.usp_sample_fields(ctypes.byref(g), None, None, None) == -1
+
+
+def test_surface_element_count():
+    """2 nx + 2 ny wall elements plus the requested cylinder elements; a
+    negative element count or a bad grid gives 0."""
+    from paper_2508_05642_amd import usp
+    import usp_workloads as W
+    g = usp.UspGrid(2, 10, 5, 0.0, 0.0, 0.1, 0.1, 1.0, 1, None)
+    b = usp.make_bc(W.BC(), None, 36)
+    assert usp.usp_surf_elements(g, b) == 2 * 10 + 2 * 5 + 36
+    b.surf_nbody = -1
+    assert usp.usp_surf_elements(g, b) == 0
+    bad = usp.UspGrid(2, 0, 5, 0.0, 0.0, 0.1, 0.1, 1.0, 1, None)
+    assert usp.usp_surf_elements(bad, usp.make_bc(W.BC())) == 0

@@ -107,6 +107,7 @@ def lib():
         L.orc_conserve.argtypes = [vp, vp, vp, vp, vp, u64, u64, i32, vp]
         L.orc_advect.argtypes = [vp, vp, vp, d, vp, u64, u64, i32, vp]
         L.orc_sample_fields.argtypes = [vp, vp, vp, vp]
+        L.orc_collide_normals.argtypes = [u64, u64, i64, vp, vp]
         L.orc_step.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, vp, vp, u64, u64, i32, i32, vp]
         L.orc_sample_nb.argtypes = [d, i32, d]
         L.orc_sample_nb.restype = i32

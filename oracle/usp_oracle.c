@@ -81,6 +81,23 @@ static void draw4(uint64_t seed, uint32_t c0, uint64_t step, uint32_t tag, uint3
 /* stream tags */
 enum { TAG_COLLIDE = 0, TAG_WALL = 1, TAG_CONSERVE = 2, TAG_INJECT = 3, TAG_FACE = 5 };
 
+/* The four standard normals G1..G4 of the collision update of each       */
+/* particle (Box-Muller on block 0 of its collide stream), as orc_collide */
+/* draws them: G[4 i + k].                                                 */
+void orc_collide_normals(uint64_t seed, uint64_t step, int64_t n, const uint32_t* pid,
+                         double* G) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double u[4];
+    draw4(seed, pid[i], step, TAG_COLLIDE, 0, u);
+    double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
+    G[4 * i + 0] = r0 * cos(2.0 * PI * u[1]);
+    G[4 * i + 1] = r0 * sin(2.0 * PI * u[1]);
+    G[4 * i + 2] = r1 * cos(2.0 * PI * u[3]);
+    G[4 * i + 3] = r1 * sin(2.0 * PI * u[3]);
+  }
+}
+
 /* ======================================================================== */
 /* Gas model                                                                */
 /* ======================================================================== */

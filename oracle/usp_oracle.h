@@ -214,6 +214,8 @@ int orc_collide(const orc_grid* grid, const orc_gas* gas, const double* cs,
 int orc_conserve(const orc_grid* grid, const orc_gas* gas, const double* cs,
                  const int64_t* offsets, orc_parts* p, uint64_t seed, uint64_t step,
                  int32_t f32, int64_t* counters);
+void orc_collide_normals(uint64_t seed, uint64_t step, int64_t n, const uint32_t* pid,
+                         double* G);
 int orc_sample_fields(const orc_grid* grid, const orc_parts* p, const int64_t* offsets,
                       double* acc);
 int orc_advect(const orc_grid* grid, const orc_gas* gas, const orc_bc* bc, double dt,

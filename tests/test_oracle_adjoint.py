@@ -1,0 +1,89 @@
+"""Pins of the oracle's pathwise gradient (oracle/adjoint.py): the replay
+reproduces the oracle's own steps, its autograd gradient equals central
+differences of the replay along the same outcomes, and the mass flow of a
+run without boundary events is invariant (conservation, Sec. IV.C).
+No GPU."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import usp_workloads as W
+from oracle import adjoint as A
+
+
+def _channel(cells=12, ppc=120, seed=7, shear=200.0):
+    prob = W.poiseuille(kn=0.05, cells=cells, ppc=ppc, f32=False, seed=seed)
+    parts = W.particles_for(prob)
+    n = parts["n"]
+    y = parts["y"][:n]
+    # a sheared, slightly anisotropic start: gradients for the stencil
+    parts["cx"][:n] += shear * np.sin(np.pi * y / 1e-3)
+    parts["cz"][:n] *= 1.2
+    return prob, parts
+
+
+@pytest.fixture(scope="module")
+def path():
+    prob, parts = _channel()
+    rec = A.Record(prob, parts, 40, 6)
+    return A.Path(rec)
+
+
+def test_replay_reproduces_the_oracle(path):
+    """Every phase's continuous values along the replay equal the oracle's
+    (the replay is the oracle's step written with torch operations)."""
+    J, worst = path.run(path.theta0(), check=True)
+    assert worst < 1e-11, worst
+    # the wall-shear output is the oracle's own wall sampling
+    rec = path.rec
+    prob = rec.prob
+    sim = oracle.Sim(prob, {**rec.init, "cap": rec.init["n"], "x": None})
+    sim.enable_sampling()
+    for s in range(rec.K):
+        sim.step(rec.step0 + s)
+    g = prob.grid
+    area = g.volume[0] / g.dy
+    shear = sim.surf[:2, oracle.SURF_NAMES.index("PT")].sum() / oracle.SURF_P_SCALE
+    hits = sim.surf[:2, 0].sum()
+    w = prob.gas.m * g.fnum / (2 * area * rec.K * prob.dt)
+    # the sampled sums round each hit to 2^-16 m/s
+    assert abs(J[1].item() - w * shear) <= w * hits * 0.5 / oracle.SURF_P_SCALE
+
+
+def test_gradient_equals_central_differences(path):
+    """d(mdot, tau_w)/d(Z_rot, omega, mu_ref) by autograd against central
+    differences of the replay (h = 1e-6 relative)."""
+    J, G = path.gradient()
+    th = path.theta0().numpy()
+    for p in range(3):
+        h = 1e-6 * th[p]
+        tp, tm = th.copy(), th.copy()
+        tp[p] += h
+        tm[p] -= h
+        fd = (path.replay(tp) - path.replay(tm)) / (2 * h)
+        for o in range(2):
+            scale = max(abs(G[o, p]), abs(fd[o]), 1e-30)
+            assert abs(fd[o] - G[o, p]) <= 1e-5 * scale + 1e-12 * abs(J[o]) / th[p], \
+                (A.PARAMS[p], o, fd[o], G[o, p])
+    # every entry is live on this path
+    assert np.all(np.abs(G) > 0)
+
+
+def test_mass_flow_invariant_without_boundary_events():
+    """No particle meets a boundary: collision and conservation keep every
+    cell's momentum, so mdot does not depend on the parameters (pathwise)."""
+    prob, parts = _channel(cells=10, ppc=150, seed=3, shear=300.0)
+    n = parts["n"]
+    rng = np.random.default_rng(5)
+    L = prob.grid.ny * prob.grid.dy
+    parts["y"][:n] = L * (0.3 + 0.4 * rng.random(n))
+    prob = dataclasses.replace(prob, dt=2e-10)
+    prob.bc = dataclasses.replace(prob.bc, g=(0.0, 0.0, 0.0))
+    rec = A.Record(prob, parts, 0, 4)
+    path = A.Path(rec)
+    J, G = path.gradient()
+    assert not any(bool(d["event"].any()) for d in path.dec)
+    th = path.theta0().numpy()
+    assert np.all(np.abs(G[0] * th) <= 1e-11 * abs(J[0]) + 1e-20), G[0]

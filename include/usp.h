@@ -361,6 +361,55 @@ usp_status usp_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, 
                     uint64_t seed, uint64_t step, int32_t nsteps, int64_t* counters,
                     void* stream);
 
+/* ---- pathwise adjoint (1D, FP64 state, USP-FPM scheme) -------------------
+   Gradients of two time-averaged outputs of a run with respect to the
+   collision-model parameters theta = (Z_rot, omega, mu_ref) (constant
+   collision numbers; Sec. IV.A viscosity and tau_c, Sec. III.A.1 relaxation
+   times), taken along the path of the run with every discrete outcome held
+   fixed: cells and bin order, vibrational levels after the jumps (Sec.
+   III.A.2) and the picks (Sec. IV.C), the stencil and the 5% temperature
+   floor (Sec. III.B), the Cholesky test (a particle whose test fails keeps
+   its post-collision state as a constant, Sec. III.A.3), the clamp of
+   T_rot^rel, the skips of the conservation scalings, and every boundary
+   event of the flight (the particle keeps its post-flight state as a
+   constant).  The outputs, for a run of K steps, area = volume[0]/dy:
+     J0 = w_mdot * sum over steps of sum_i c_x,i at the start of the step,
+     J1 = w_tau * sum over steps of sum over particles whose flight meets a
+          boundary of (c_x after the kick - c_x after the flight),
+   with the weights given by the caller (m fnum/(area K) gives the mass flow
+   per unit depth, m fnum/(2 area K dt) the mean shear of the two walls).
+   Adjoint arrays `lam` are device double[2][5][capacity]: objective, then
+   y, cx, cy, cz, erot, then particle slot.  Requires particle ids below
+   capacity (1D runs create no particles).  Errors: USP_EINVAL for a grid
+   that is not 1D, a non-FP64 state, the first-order FPM scheme, a
+   temperature-dependent collision-number model, or short buffers. */
+size_t usp_tape_bytes(const usp_grid* grid, int64_t capacity);
+size_t usp_adjoint_ws_bytes(const usp_grid* grid, int64_t capacity);
+
+/* One full step (the bits of usp_step) that also writes the tape of the
+   step (bin permutation, binned pre-collision state, cell state, states
+   after the collision and after the conservation) into `tape`
+   (usp_tape_bytes); aws (usp_adjoint_ws_bytes) is scratch.  p and p_alt
+   are swapped as usp_step swaps them; equal capacities. */
+usp_status usp_step_taped(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
+                          usp_particles* p, usp_particles* p_alt, int64_t* offsets, double* mom,
+                          double* cs, void* ws, size_t ws_bytes, uint64_t seed, uint64_t step,
+                          void* tape, size_t tape_bytes, void* aws, size_t aws_bytes,
+                          int64_t* counters, void* stream);
+
+/* The step recorded in `tape` (taken at step index `step` with `seed`)
+   reversed: lam_in is the adjoint of the state after the step (slots as
+   the step left them), lam_out receives the adjoint of the state before it
+   (slots as they were before its bin), the step's own output terms
+   included; grad (device double[2][3], objective-major) is incremented by
+   the step's parameter terms.  lam_in and lam_out must differ.  Fixed-order
+   reductions: deterministic. */
+usp_status usp_adjoint_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
+                            const void* tape, size_t tape_bytes, int64_t capacity, uint64_t seed,
+                            uint64_t step, const double* lam_in, double* lam_out, double w_mdot,
+                            double w_tau, double* grad, void* aws, size_t aws_bytes,
+                            void* stream);
+
 #ifdef __cplusplus
 }
 #endif

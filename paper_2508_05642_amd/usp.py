@@ -92,8 +92,17 @@ def lib():
         L.usp_batch.argtypes = [vp, vp, d, vp, vp, vp, vp, vp, vp, sz, i32, i32, u64, u64, i32, vp,
                                 vp]
         L.usp_step.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, vp, vp, vp, sz, u64, u64, i32, vp, vp]
+        L.usp_tape_bytes.argtypes = [vp, i64]
+        L.usp_tape_bytes.restype = sz
+        L.usp_adjoint_ws_bytes.argtypes = [vp, i64]
+        L.usp_adjoint_ws_bytes.restype = sz
+        L.usp_step_taped.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, vp, vp, sz, u64, u64, vp, sz,
+                                     vp, sz, vp, vp]
+        L.usp_adjoint_step.argtypes = [vp, vp, vp, d, vp, sz, i64, u64, u64, vp, vp, d, d, vp, vp,
+                                       sz, vp]
         for nm in ("usp_bin", "usp_moments", "usp_sample_fields", "usp_reconstruct", "usp_collide",
-                   "usp_conserve", "usp_advect", "usp_update", "usp_batch", "usp_step"):
+                   "usp_conserve", "usp_advect", "usp_update", "usp_batch", "usp_step",
+                   "usp_step_taped", "usp_adjoint_step"):
             getattr(L, nm).restype = i32
         _lib = L
     return _lib
@@ -102,7 +111,8 @@ def lib():
 EXPORTED = ["usp_status_str", "usp_mom_name", "usp_cs_name", "usp_counter_name", "usp_version",
             "usp_workspace_bytes", "usp_cellstate_bytes", "usp_surf_elements", "usp_bin",
             "usp_moments", "usp_sample_fields", "usp_reconstruct", "usp_collide", "usp_conserve",
-            "usp_advect", "usp_update", "usp_batch", "usp_step"]
+            "usp_advect", "usp_update", "usp_batch", "usp_step", "usp_tape_bytes",
+            "usp_adjoint_ws_bytes", "usp_step_taped", "usp_adjoint_step"]
 
 
 def names(kind):
@@ -204,6 +214,24 @@ def usp_step(grid, gas, bc, dt, dt_cell, p, p_alt, offsets, mom, cs, ws, seed, s
                           dt, _ptr(dt_cell), C.byref(p), C.byref(p_alt), _ptr(offsets),
                           _ptr(mom), _ptr(cs), _ptr(ws), ws.numel(), seed, step, nsteps,
                           _ptr(counters), _stream(stream)), "usp_step")
+
+
+def usp_step_taped(grid, gas, bc, dt, p, p_alt, offsets, mom, cs, ws, seed, step, tape, aws,
+                   counters, stream=None):
+    """One step with its tape; p and p_alt are swapped in place as the
+    library swaps them."""
+    _check(lib().usp_step_taped(C.byref(grid), C.byref(gas), C.byref(bc), dt, C.byref(p),
+                                C.byref(p_alt), _ptr(offsets), _ptr(mom), _ptr(cs), _ptr(ws),
+                                ws.numel(), seed, step, _ptr(tape), tape.numel(), _ptr(aws),
+                                aws.numel(), _ptr(counters), _stream(stream)), "usp_step_taped")
+
+
+def usp_adjoint_step(grid, gas, bc, dt, tape, capacity, seed, step, lam_in, lam_out, w_mdot,
+                     w_tau, grad, aws, stream=None):
+    _check(lib().usp_adjoint_step(C.byref(grid), C.byref(gas), C.byref(bc), dt, _ptr(tape),
+                                  tape.numel(), capacity, seed, step, _ptr(lam_in), _ptr(lam_out),
+                                  w_mdot, w_tau, _ptr(grad), _ptr(aws), aws.numel(),
+                                  _stream(stream)), "usp_adjoint_step")
 
 
 # ---- device-resident state for one problem ---------------------------------
@@ -380,6 +408,17 @@ class DeviceState:
             self.binned = True
         # the library swapped the struct contents once per rebin: a now
         # describes the buffer that holds the state
+        if a.cx != self.bufs[self.cur]["cx"].data_ptr():
+            B0, B1 = self.bufs[self.cur], self.bufs[1 - self.cur]
+            B0["struct"], B1["struct"] = B1["struct"], B0["struct"]
+            self.cur = 1 - self.cur
+
+    def step_taped(self, step, tape, aws, stream=None):
+        """One step (the bits of step()) that also writes its tape."""
+        a, b = self.bufs[self.cur]["struct"], self.bufs[1 - self.cur]["struct"]
+        usp_step_taped(self.grid, self.gas, self.bc, self.prob.dt, a, b, self.offsets, self.mom,
+                       self.cs, self.ws, self.prob.seed, step, tape, aws, self.counters, stream)
+        self.binned = True
         if a.cx != self.bufs[self.cur]["cx"].data_ptr():
             B0, B1 = self.bufs[self.cur], self.bufs[1 - self.cur]
             B0["struct"], B1["struct"] = B1["struct"], B0["struct"]

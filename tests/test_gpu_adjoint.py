@@ -1,0 +1,106 @@
+"""GPU pathwise adjoint (usp_step_taped / usp_adjoint_step through the C
+ABI) against the oracle's gradient (oracle/adjoint.py, PyTorch FP64
+replay with autograd) on the same seeded 1D runs.
+
+Bar: the outputs agree to 1e-10 (mass flow) and to the fixed-point
+rounding of the wall sampling (shear); each gradient entry agrees to 1e-7
+of its magnitude (FP64 on both sides; the chains differ in operation order
+and in how the secant heat capacity is evaluated near equal temperatures).
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import usp_workloads as W
+from oracle import adjoint as A
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _channel(cells=12, ppc=120, seed=7, shear=200.0):
+    prob = W.poiseuille(kn=0.05, cells=cells, ppc=ppc, f32=False, seed=seed)
+    parts = W.particles_for(prob)
+    n = parts["n"]
+    y = parts["y"][:n]
+    parts["cx"][:n] += shear * np.sin(np.pi * y / 1e-3)
+    parts["cz"][:n] *= 1.2
+    return prob, parts
+
+
+def _compare(J, G, Jo, Go, what):
+    assert abs(J[0] - Jo[0]) <= 1e-10 * abs(Jo[0]), (what, J[0], Jo[0])
+    assert abs(J[1] - Jo[1]) <= 1e-6 * abs(Jo[1]), (what, J[1], Jo[1])
+    rel = np.abs(G - Go) / np.maximum(np.abs(Go), 1e-300)
+    _say(f"  {what}: J {J}, worst relative gradient difference {rel.max():.3g}")
+    assert np.all(rel <= 1e-7), (what, G, Go)
+
+
+@pytest.mark.parametrize("K,segment", [(6, 4), (6, 32)])
+def test_adjoint_matches_oracle_gradient(K, segment):
+    """d(mdot, tau_w)/d(Z_rot, omega, mu_ref) over K steps, checkpointed in
+    segments of `segment` steps, against the oracle's autograd gradient."""
+    from paper_2508_05642_amd.adjoint import PathwiseAdjoint
+    prob, parts = _channel()
+    _say(f"[adjoint] cells={prob.grid.ny} n={parts['n']} K={K} segment={segment}")
+    path = A.Path(A.Record(prob, parts, 40, K))
+    Jo, Go = path.gradient()
+    adj = PathwiseAdjoint(prob, parts, K, segment)
+    J = adj.forward(40).cpu().numpy()
+    G = adj.backward().cpu().numpy()
+    _compare(J, G, Jo, Go, f"K={K} segment={segment}")
+
+
+def test_adjoint_segments_bit_identical():
+    """The re-run of a segment reproduces the forward bit for bit, so the
+    gradient does not depend on the checkpoint spacing."""
+    from paper_2508_05642_amd.adjoint import PathwiseAdjoint
+    prob, parts = _channel(cells=10, ppc=100, seed=11)
+    Gs = []
+    for seg in (1, 3, 8):
+        adj = PathwiseAdjoint(prob, parts, 8, seg)
+        adj.forward(3)
+        Gs.append(adj.backward().cpu().numpy())
+    assert np.array_equal(Gs[0], Gs[1]) and np.array_equal(Gs[0], Gs[2])
+
+
+def test_mass_flow_gradient_vanishes_without_boundary_events():
+    """No particle meets a boundary: every cell keeps its momentum, so the
+    mass flow does not depend on theta along the path."""
+    from paper_2508_05642_amd.adjoint import PathwiseAdjoint
+    prob, parts = _channel(cells=10, ppc=150, seed=3, shear=300.0)
+    n = parts["n"]
+    rng = np.random.default_rng(5)
+    L = prob.grid.ny * prob.grid.dy
+    parts["y"][:n] = L * (0.3 + 0.4 * rng.random(n))
+    prob = dataclasses.replace(prob, dt=2e-10)
+    prob.bc = dataclasses.replace(prob.bc, g=(0.0, 0.0, 0.0))
+    adj = PathwiseAdjoint(prob, parts, 4, 2)
+    J = adj.forward(0).cpu().numpy()
+    G = adj.backward().cpu().numpy()
+    th = np.array([prob.gas.Z_rot, prob.gas.omega, prob.gas.mu_ref])
+    assert np.all(np.abs(G[0] * th) <= 1e-11 * abs(J[0])), G[0]
+    assert np.any(G[1] != 0.0) or J[1] == 0.0
+
+
+def test_autograd_function_contracts_the_jacobian():
+    """PathwiseOutputs: backward of w . J gives w^T dJ/dtheta."""
+    from paper_2508_05642_amd.adjoint import PathwiseAdjoint, PathwiseOutputs
+    prob, parts = _channel(cells=8, ppc=100, seed=5)
+    theta = torch.tensor([prob.gas.Z_rot, prob.gas.omega, prob.gas.mu_ref], dtype=torch.float64,
+                         requires_grad=True)
+    J = PathwiseOutputs.apply(theta, prob, parts, 2, 5, 2)
+    w = torch.tensor([3.0, -0.5], dtype=torch.float64)
+    (J * w).sum().backward()
+    adj = PathwiseAdjoint(prob, parts, 5, 2)
+    adj.forward(2)
+    G = adj.backward().cpu()
+    assert torch.allclose(theta.grad, w @ G, rtol=1e-12, atol=0.0)

@@ -354,12 +354,15 @@ usp_status usp_batch(const usp_grid* grid, const usp_gas* gas, double dt, const 
    on return *p describes the buffer that holds the state (the two structs
    are swapped as needed); p_alt->capacity >= p->capacity and ws is sized
    for p_alt->capacity.  offsets, mom, cs as above (they describe the last
-   step's pre-collision state on return). */
+   step's pre-collision state on return).  in_offsets (may be NULL, may
+   alias offsets) is passed to the first step's usp_bin: when *p is the
+   state a previous step or bin left (segments in in_offsets), the first
+   bin takes the fast route too; later steps always do. */
 usp_status usp_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
                     const double* dt_cell, usp_particles* p, usp_particles* p_alt,
-                    int64_t* offsets, double* mom, double* cs, void* ws, size_t ws_bytes,
-                    uint64_t seed, uint64_t step, int32_t nsteps, int64_t* counters,
-                    void* stream);
+                    int64_t* offsets, const int64_t* in_offsets, double* mom, double* cs,
+                    void* ws, size_t ws_bytes, uint64_t seed, uint64_t step, int32_t nsteps,
+                    int64_t* counters, void* stream);
 
 /* ---- pathwise adjoint (1D, FP64 state, USP-FPM scheme) -------------------
    Gradients of two time-averaged outputs of a run with respect to the
@@ -390,12 +393,14 @@ size_t usp_adjoint_ws_bytes(const usp_grid* grid, int64_t capacity);
    step (bin permutation, binned pre-collision state, cell state, states
    after the collision and after the conservation) into `tape`
    (usp_tape_bytes); aws (usp_adjoint_ws_bytes) is scratch.  p and p_alt
-   are swapped as usp_step swaps them; equal capacities. */
+   are swapped as usp_step swaps them; equal capacities; in_offsets as for
+   usp_step. */
 usp_status usp_step_taped(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
-                          usp_particles* p, usp_particles* p_alt, int64_t* offsets, double* mom,
-                          double* cs, void* ws, size_t ws_bytes, uint64_t seed, uint64_t step,
-                          void* tape, size_t tape_bytes, void* aws, size_t aws_bytes,
-                          int64_t* counters, void* stream);
+                          usp_particles* p, usp_particles* p_alt, int64_t* offsets,
+                          const int64_t* in_offsets, double* mom, double* cs, void* ws,
+                          size_t ws_bytes, uint64_t seed, uint64_t step, void* tape,
+                          size_t tape_bytes, void* aws, size_t aws_bytes, int64_t* counters,
+                          void* stream);
 
 /* The step recorded in `tape` (taken at step index `step` with `seed`)
    reversed: lam_in is the adjoint of the state after the step (slots as

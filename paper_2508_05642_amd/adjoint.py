@@ -65,14 +65,18 @@ class PathwiseAdjoint:
     @staticmethod
     def _save(st):
         B = st.bufs[st.cur]
-        return {k: B[k].clone() for k in FIELDS}
+        snap = {k: B[k].clone() for k in FIELDS}
+        snap["offsets"] = st.offsets.clone()
+        snap["binned"] = st.binned
+        return snap
 
     @staticmethod
     def _restore(st, snap):
         B = st.bufs[st.cur]
         for k in FIELDS:
             B[k].copy_(snap[k])
-        st.binned = False
+        st.offsets.copy_(snap["offsets"])
+        st.binned = snap["binned"]
 
     # -- passes ------------------------------------------------------------
     def forward(self, step0=0, stream=None):

@@ -21,9 +21,10 @@
 //   K2  thread per particle: the particle update reversed (the scalar chain
 //       of the relaxation temperatures through Dual<6> Jacobians), giving
 //       adjoints of the particle and of the fields of its stencil cells;
-//   K3  wave per cell: stencil contributions summed in a fixed order, the
-//       cell state reversed (Dual<6> Jacobian of its coefficients), giving
-//       adjoints of the moments and per-cell parameter partials;
+//   K3  a wave per (objective, field, cell) sums the stencil contributions
+//       in a fixed order; then a thread per cell reverses the cell state
+//       (Dual<6> Jacobian of its coefficients), giving adjoints of the
+//       moments and per-cell parameter partials;
 //   K4  thread per particle: moments reversed, mass-flow source, and the
 //       bin permutation undone;
 //   K5  one workgroup: parameter partials summed in a fixed order.
@@ -70,7 +71,7 @@ enum { LY = 0, LCX = 1, LE = 4, NLAM = 5 };
 constexpr int NOBJ = 2, NPAR = 3;
 
 struct AdjWsLayout {
-  size_t lam1, own, nbr, nbrc, cons, lmom, gcell, map, total;
+  size_t lam1, own, nbr, nbrc, cons, csum, lmom, gcell, map, total;
 };
 
 static AdjWsLayout adj_ws_layout(int64_t M, int64_t cap) {
@@ -82,6 +83,7 @@ static AdjWsLayout adj_ws_layout(int64_t M, int64_t cap) {
   w.nbr = take((size_t)NOBJ * NNBR * cap * 8);
   w.nbrc = take((size_t)cap * 4);
   w.cons = take((size_t)NOBJ * NCONS * M * 8);
+  w.csum = take((size_t)NOBJ * NOWN * M * 8);
   w.lmom = take((size_t)NOBJ * NAMOM * M * 8);
   w.gcell = take((size_t)NOBJ * NPAR * M * 8);
   w.map = take((size_t)cap * 4);
@@ -160,13 +162,14 @@ static void copy_d(void* dst, const void* src, size_t bytes, hipStream_t st, hip
 // bits of usp_step), keeping the tape.
 static hipError_t step_taped(const GridP& g, const GasP& gas, const BcP& bc, double dt,
                              const PartP<double>& in, const PartP<double>& out, int64_t* offsets,
-                             double* mom, double* cs, char* ws, const WsLayout& L, uint64_t seed,
+                             const int64_t* in_offsets, double* mom, double* cs, char* ws,
+                             const WsLayout& L, uint64_t seed,
                              uint64_t step, char* tape, const TapeLayout& T, int32_t* map,
                              int64_t* counters, hipStream_t st) {
   const int64_t cap = out.capacity;
   const int grid_p = (int)cdiv(cap, 256);
   k_pid_map<<<grid_p, 256, 0, st>>>(in.pid, in.count, cap, map);
-  hipError_t e = launch_bin<double>(g, in, out, offsets, nullptr, ws, L, counters, st);
+  hipError_t e = launch_bin<double>(g, in, out, offsets, in_offsets, ws, L, counters, st);
   if (e != hipSuccess) return e;
   k_perm<<<grid_p, 256, 0, st>>>(out.pid, out.count, cap, map, (int32_t*)(tape + T.perm));
   hipError_t ce = hipSuccess;
@@ -584,50 +587,62 @@ __device__ __forceinline__ void cell_reverse(const GasP& gas, int64_t c, int64_t
   }
 }
 
-// ---- K3: cell adjoints and the cell state reversed, wave per cell -------------
-__global__ __launch_bounds__(256) void k_adj_cells(GridP g, GasP gas, double alpha_vss, double dt,
-                                                   TapeP T, int64_t cap,
-                                                   const double* __restrict__ own,
-                                                   const double* __restrict__ nbr,
-                                                   const int32_t* __restrict__ nbrc,
-                                                   const double* __restrict__ cons,
-                                                   double* __restrict__ lmom,
-                                                   double* __restrict__ gcell) {
+// ---- K3: cell adjoints, then the cell state reversed ---------------------------
+// K3a: one wave per (objective, field, cell): the cell's own particles'
+// contributions plus those of the neighbouring cells' particles whose
+// stencil reads it (1D: cells c-1 and c+1), in a fixed order.
+__global__ __launch_bounds__(256) void k_adj_cell_sums(int64_t M, TapeP T, int64_t cap,
+                                                       const double* __restrict__ own,
+                                                       const double* __restrict__ nbr,
+                                                       const int32_t* __restrict__ nbrc,
+                                                       double* __restrict__ csum) {
   const int lane = threadIdx.x & 63;
-  const int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (w >= (int64_t)NOBJ * NOWN * M) return;
+  const int64_t c = w % M, of = w / M;
+  const int o = (int)(of / NOWN), f = (int)(of % NOWN);
+  const int64_t o0 = T.offsets[c], o1 = T.offsets[c + 1];
+  double s = 0.0;
+  if (T.cs[CS_COLLIDE * M + c] != 0.0) {
+    const double* ow = own + ((int64_t)o * NOWN + f) * cap;
+    for (int64_t i = o0 + lane; i < o1; i += 64) s += ow[i];
+    if (f < NNBR) {
+      const double* nb = nbr + ((int64_t)o * NNBR + f) * cap;
+      const int64_t lo_n = c > 0 ? T.offsets[c - 1] : o0;
+      const int64_t hi_n = c + 1 < M ? T.offsets[c + 2] : o1;
+      for (int64_t i = lo_n + lane; i < o0; i += 64)
+        if (nbrc[i] == c) s += nb[i];
+      for (int64_t i = o1 + lane; i < hi_n; i += 64)
+        if (nbrc[i] == c) s += nb[i];
+    }
+  }
+  s = wave_sum(s);
+  if (lane == 0) csum[of * M + c] = s;
+}
+
+// K3b: thread per cell: the cell state reversed (Dual<6> Jacobian of the
+// coefficients), giving moment adjoints and per-cell parameter partials.
+__global__ __launch_bounds__(64) void k_adj_cellstate(GridP g, GasP gas, double alpha_vss,
+                                                      TapeP T, const double* __restrict__ csum,
+                                                      const double* __restrict__ cons,
+                                                      double* __restrict__ lmom,
+                                                      double* __restrict__ gcell) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t M = g.M;
   if (c >= M) return;
   const double* cs = T.cs;
-  const bool coll = cs[CS_COLLIDE * M + c] != 0.0;
   for (int o = 0; o < NOBJ; ++o) {
-    if (lane < NAMOM) lmom[((int64_t)o * NAMOM + lane) * M + c] = 0.0;
-    if (lane < NPAR) gcell[((int64_t)o * NPAR + lane) * M + c] = 0.0;
+    for (int k = 0; k < NAMOM; ++k) lmom[((int64_t)o * NAMOM + k) * M + c] = 0.0;
+    for (int k = 0; k < NPAR; ++k) gcell[((int64_t)o * NPAR + k) * M + c] = 0.0;
   }
-  if (!coll) return;
-  const int64_t o0 = T.offsets[c], o1 = T.offsets[c + 1];
-  // neighbour cells whose particles may read this one (1D: c-1, c+1)
-  const int64_t lo_n = c > 0 ? T.offsets[c - 1] : o0;
-  const int64_t hi_n = c + 1 < M ? T.offsets[c + 2] : o1;
+  if (cs[CS_COLLIDE * M + c] == 0.0) return;
   Dual<6> co[6];
-  const double nd = cs[CS_NDENS * M + c];
-  cell_coef_dual(gas, alpha_vss, nd, cs[CS_DT * M + c], cs[CS_TTR * M + c], cs[CS_TROT * M + c],
-                 cs[CS_TVIB * M + c], co);
+  cell_coef_dual(gas, alpha_vss, cs[CS_NDENS * M + c], cs[CS_DT * M + c], cs[CS_TTR * M + c],
+                 cs[CS_TROT * M + c], cs[CS_TVIB * M + c], co);
   for (int o = 0; o < NOBJ; ++o) {
-    const double* ow = own + (int64_t)o * NOWN * cap;
-    const double* nb = nbr + (int64_t)o * NNBR * cap;
     double lf[NOWN];
-    for (int f = 0; f < NOWN; ++f) {
-      double s = 0.0;
-      for (int64_t i = o0 + lane; i < o1; i += 64) s += ow[(int64_t)f * cap + i];
-      if (f < NNBR) {
-        for (int64_t i = lo_n + lane; i < o0; i += 64)
-          if (nbrc[i] == c) s += nb[(int64_t)f * cap + i];
-        for (int64_t i = o1 + lane; i < hi_n; i += 64)
-          if (nbrc[i] == c) s += nb[(int64_t)f * cap + i];
-      }
-      lf[f] = wave_sum(s);
-    }
-    if (lane == 0) cell_reverse(gas, c, M, o, lf, co, cons, lmom, gcell);
+    for (int f = 0; f < NOWN; ++f) lf[f] = csum[((int64_t)o * NOWN + f) * M + c];
+    cell_reverse(gas, c, M, o, lf, co, cons, lmom, gcell);
   }
 }
 
@@ -700,8 +715,10 @@ static hipError_t adjoint_step(const GridP& g, const GasP& gas, const BcP& bc, d
   const int parts = (int)cdiv(cap, 256);
   k_adj_flight_conserve<<<cells, 256, 0, st>>>(g, gas, bc, dt, T, cap, lam_in, lam1, cons, w_tau);
   k_adj_collide<<<parts, 256, 0, st>>>(g, gas, T, cap, seed, (uint32_t)step, lam1, own, nbr, nbrc);
-  k_adj_cells<<<cells, 256, 0, st>>>(g, gas, alpha_vss, dt, T, cap, own, nbr, nbrc, cons, lmom,
-                                     gcell);
+  double* csum = (double*)(aws + W.csum);
+  k_adj_cell_sums<<<(int)cdiv((int64_t)NOBJ * NOWN * g.M, 4), 256, 0, st>>>(g.M, T, cap, own, nbr,
+                                                                            nbrc, csum);
+  k_adj_cellstate<<<(int)cdiv(g.M, 64), 64, 0, st>>>(g, gas, alpha_vss, T, csum, cons, lmom, gcell);
   k_adj_moments<<<parts, 256, 0, st>>>(g, T, cap, lam1, lmom, lam_out, w_mdot);
   k_adj_grad<<<1, 256, 0, st>>>(g.M, gcell, grad);
   return hipGetLastError();
@@ -737,10 +754,11 @@ size_t usp_adjoint_ws_bytes(const usp_grid* grid, int64_t capacity) {
 }
 
 usp_status usp_step_taped(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
-                          usp_particles* p, usp_particles* p_alt, int64_t* offsets, double* mom,
-                          double* cs, void* ws, size_t ws_bytes, uint64_t seed, uint64_t step,
-                          void* tape, size_t tape_bytes, void* aws, size_t aws_bytes,
-                          int64_t* counters, void* stream) {
+                          usp_particles* p, usp_particles* p_alt, int64_t* offsets,
+                          const int64_t* in_offsets, double* mom, double* cs, void* ws,
+                          size_t ws_bytes, uint64_t seed, uint64_t step, void* tape,
+                          size_t tape_bytes, void* aws, size_t aws_bytes, int64_t* counters,
+                          void* stream) {
   if (!adj_setup_ok(grid, gas) || !bc || !p || !p_alt || !offsets || !mom || !cs || !ws || !tape ||
       !aws)
     return USP_EINVAL;
@@ -757,7 +775,8 @@ usp_status usp_step_taped(const usp_grid* grid, const usp_gas* gas, const usp_bc
   const WsLayout L = ws_layout(g.M, cap, n_faces(g));
   hipStream_t st = (hipStream_t)stream;
   const hipError_t e = step_taped(g, make_gas(gas), make_bc(bc), dt, make_parts<double>(p),
-                                  make_parts<double>(p_alt), offsets, mom, cs, (char*)ws, L, seed,
+                                  make_parts<double>(p_alt), offsets, in_offsets, mom, cs,
+                                  (char*)ws, L, seed,
                                   step, (char*)tape, T, (int32_t*)((char*)aws + W.map), counters, st);
   if (e != hipSuccess) return USP_EDEVICE;
   const usp_particles tmp = *p;

@@ -143,8 +143,9 @@ usp_status do_bin(const usp_grid* grid, const usp_particles* in, usp_particles* 
 template <typename S>
 usp_status do_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
                    const double* dt_cell, usp_particles* p, usp_particles* p_alt,
-                   int64_t* offsets, double* mom, double* cs, void* ws, uint64_t seed,
-                   uint64_t step, int32_t nsteps, int64_t* counters, hipStream_t st) {
+                   int64_t* offsets, const int64_t* in_offsets, double* mom, double* cs,
+                   void* ws, uint64_t seed, uint64_t step, int32_t nsteps, int64_t* counters,
+                   hipStream_t st) {
   const GridP g = make_grid(grid);
   const GasP gp = make_gas(gas);
   const BcP bp = make_bc(bc);
@@ -160,7 +161,7 @@ usp_status do_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, d
     hipError_t e = hipSuccess;
     if (s == 0 || g.dim != 0) {
       e = launch_bin<S>(g, make_parts<S>(p), make_parts<S>(p_alt), offsets,
-                        s > 0 ? offsets : nullptr, w, L, counters, st);
+                        s > 0 ? offsets : in_offsets, w, L, counters, st);
       if (e != hipSuccess) return USP_EDEVICE;
       const usp_particles tmp = *p;
       *p = *p_alt;
@@ -342,9 +343,9 @@ usp_status usp_batch(const usp_grid* grid, const usp_gas* gas, double dt, const 
 
 usp_status usp_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
                     const double* dt_cell, usp_particles* p, usp_particles* p_alt,
-                    int64_t* offsets, double* mom, double* cs, void* ws, size_t ws_bytes,
-                    uint64_t seed, uint64_t step, int32_t nsteps, int64_t* counters,
-                    void* stream) {
+                    int64_t* offsets, const int64_t* in_offsets, double* mom, double* cs,
+                    void* ws, size_t ws_bytes, uint64_t seed, uint64_t step, int32_t nsteps,
+                    int64_t* counters, void* stream) {
   if (!grid_ok(grid) || !gas_ok(gas) || !parts_ok(p, grid) || !parts_ok(p_alt, grid)) return USP_EINVAL;
   if (!offsets || !mom || !cs || !ws || nsteps < 0) return USP_EINVAL;
   if (p->prec != p_alt->prec || p_alt->capacity < p->capacity || p->cx == p_alt->cx) return USP_EINVAL;
@@ -354,8 +355,8 @@ usp_status usp_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, 
   if (ws_bytes < usp_workspace_bytes(grid, p_alt->capacity)) return USP_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   return p->prec == USP_F32
-             ? do_step<float>(grid, gas, bc, dt, dt_cell, p, p_alt, offsets, mom, cs, ws, seed, step, nsteps, counters, st)
-             : do_step<double>(grid, gas, bc, dt, dt_cell, p, p_alt, offsets, mom, cs, ws, seed, step, nsteps, counters, st);
+             ? do_step<float>(grid, gas, bc, dt, dt_cell, p, p_alt, offsets, in_offsets, mom, cs, ws, seed, step, nsteps, counters, st)
+             : do_step<double>(grid, gas, bc, dt, dt_cell, p, p_alt, offsets, in_offsets, mom, cs, ws, seed, step, nsteps, counters, st);
 }
 
 }  // extern "C"

@@ -91,13 +91,14 @@ def lib():
         L.usp_update.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, sz, u64, u64, vp, vp]
         L.usp_batch.argtypes = [vp, vp, d, vp, vp, vp, vp, vp, vp, sz, i32, i32, u64, u64, i32, vp,
                                 vp]
-        L.usp_step.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, vp, vp, vp, sz, u64, u64, i32, vp, vp]
+        L.usp_step.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, vp, vp, vp, vp, sz, u64, u64, i32, vp,
+                               vp]
         L.usp_tape_bytes.argtypes = [vp, i64]
         L.usp_tape_bytes.restype = sz
         L.usp_adjoint_ws_bytes.argtypes = [vp, i64]
         L.usp_adjoint_ws_bytes.restype = sz
-        L.usp_step_taped.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, vp, vp, sz, u64, u64, vp, sz,
-                                     vp, sz, vp, vp]
+        L.usp_step_taped.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, vp, vp, vp, sz, u64, u64, vp,
+                                     sz, vp, sz, vp, vp]
         L.usp_adjoint_step.argtypes = [vp, vp, vp, d, vp, sz, i64, u64, u64, vp, vp, d, d, vp, vp,
                                        sz, vp]
         for nm in ("usp_bin", "usp_moments", "usp_sample_fields", "usp_reconstruct", "usp_collide",
@@ -207,21 +208,23 @@ def usp_advect(grid, gas, bc, dt, p, seed, step, ws, counters, stream=None):
 
 
 def usp_step(grid, gas, bc, dt, dt_cell, p, p_alt, offsets, mom, cs, ws, seed, step, nsteps,
-             counters, stream=None):
+             counters, stream=None, in_offsets=None):
     """nsteps full steps; p and p_alt (UspParticles) are swapped in place as
-    the library swaps them, so p describes the current state afterwards."""
+    the library swaps them, so p describes the current state afterwards.
+    in_offsets: the segments of an already binned input (usp_bin's)."""
     _check(lib().usp_step(C.byref(grid), C.byref(gas), C.byref(bc) if bc is not None else None,
                           dt, _ptr(dt_cell), C.byref(p), C.byref(p_alt), _ptr(offsets),
-                          _ptr(mom), _ptr(cs), _ptr(ws), ws.numel(), seed, step, nsteps,
-                          _ptr(counters), _stream(stream)), "usp_step")
+                          _ptr(in_offsets), _ptr(mom), _ptr(cs), _ptr(ws), ws.numel(), seed, step,
+                          nsteps, _ptr(counters), _stream(stream)), "usp_step")
 
 
 def usp_step_taped(grid, gas, bc, dt, p, p_alt, offsets, mom, cs, ws, seed, step, tape, aws,
-                   counters, stream=None):
+                   counters, stream=None, in_offsets=None):
     """One step with its tape; p and p_alt are swapped in place as the
     library swaps them."""
     _check(lib().usp_step_taped(C.byref(grid), C.byref(gas), C.byref(bc), dt, C.byref(p),
-                                C.byref(p_alt), _ptr(offsets), _ptr(mom), _ptr(cs), _ptr(ws),
+                                C.byref(p_alt), _ptr(offsets), _ptr(in_offsets), _ptr(mom),
+                                _ptr(cs), _ptr(ws),
                                 ws.numel(), seed, step, _ptr(tape), tape.numel(), _ptr(aws),
                                 aws.numel(), _ptr(counters), _stream(stream)), "usp_step_taped")
 
@@ -403,7 +406,8 @@ class DeviceState:
         a, b = self.bufs[self.cur]["struct"], self.bufs[1 - self.cur]["struct"]
         usp_step(self.grid, self.gas, self.bc if self.dim >= 1 else None, self.prob.dt,
                  self.dt_cell, a, b, self.offsets, self.mom, self.cs, self.ws, self.prob.seed,
-                 step, nsteps, self.counters, stream)
+                 step, nsteps, self.counters, stream,
+                 in_offsets=self.offsets if self.binned else None)
         if nsteps > 0:
             self.binned = True
         # the library swapped the struct contents once per rebin: a now
@@ -417,7 +421,8 @@ class DeviceState:
         """One step (the bits of step()) that also writes its tape."""
         a, b = self.bufs[self.cur]["struct"], self.bufs[1 - self.cur]["struct"]
         usp_step_taped(self.grid, self.gas, self.bc, self.prob.dt, a, b, self.offsets, self.mom,
-                       self.cs, self.ws, self.prob.seed, step, tape, aws, self.counters, stream)
+                       self.cs, self.ws, self.prob.seed, step, tape, aws, self.counters, stream,
+                       in_offsets=self.offsets if self.binned else None)
         self.binned = True
         if a.cx != self.bufs[self.cur]["cx"].data_ptr():
             B0, B1 = self.bufs[self.cur], self.bufs[1 - self.cur]

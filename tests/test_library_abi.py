@@ -45,8 +45,8 @@ def test_host_side_queries_and_validation():
     assert L.usp_workspace_bytes(ctypes.byref(bad), 1000) == 0
     # host-side checks fire before any device work: null structs
     assert L.usp_bin(None, None, None, None, None, None, 0, None, None) == -1
-    assert L.usp_step(None, None, None, 1.0, None, None, None, None, None, None, None, 0, 0, 0, 1,
-                      None, None) == -1
+    assert L.usp_step(None, None, None, 1.0, None, None, None, None, None, None, None, None, 0, 0,
+                      0, 1, None, None) == -1
     assert L.usp_sample_fields(None, None, None, None) == -1
     assert L.usp_sample_fields(ctypes.byref(g), None, None, None) == -1
 

@@ -151,7 +151,8 @@ __device__ __forceinline__ void sort_net(uint32_t* a, int n) {
 
 // ---------------------------------------------------------------------------
 // Neighbour groups.  A particle of old cell k whose new cell is c = k + d
-// with d in D (the cell itself and its 8 neighbours in 2D, +-1 in 1D) belongs
+// with d in D (the cell itself and its 8 neighbours in 2D, up to 4 cells
+// either way in 1D) belongs
 // to group d; any other destination is a far move.  D is listed in
 // descending order, so the source cells k = c - d of a new cell c come in
 // ascending order, which is input order for a binned input.
@@ -168,6 +169,11 @@ __host__ __device__ inline Nbr nbr_set(const GridP& g) {
     const int v[9] = {nx + 1, nx, nx - 1, 1, 0, -1, -nx + 1, -nx, -nx - 1};
     r.n = 9;
     for (int k = 0; k < 9; ++k) r.d[k] = v[k];
+  } else if (g.dim == 1) {
+    // along y a particle may cross several cells in a step: nine groups,
+    // moves of up to four cells either way
+    r.n = 9;
+    for (int k = 0; k < 9; ++k) r.d[k] = 4 - k;
   } else {
     r.n = 3;
     r.d[0] = 1; r.d[1] = 0; r.d[2] = -1;

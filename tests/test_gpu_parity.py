@@ -727,3 +727,35 @@ def test_surface_sampling_full_steps_fp64():
         gpu.step(20 + s, 1)
         orc.step_native(20 + s, 1)
     _surf_compare(gpu.surface_sums(), orc.surf, "3 steps")
+
+
+def test_poiseuille_full_size_statistics():
+    """The Kn = 0.05 channel at full size (200 cells x 1000 particles, FP32
+    state), 6000 steps with the field sums of the last 4000: the
+    time-averaged profile has the Navier-Stokes curvature g/(2 nu) within
+    4% and is symmetric (statistics end to end, not trajectories)."""
+    usp = _usp()
+    from paper_2508_05642_amd import sampling
+    prob = W.poiseuille(kn=0.05, cells=200, ppc=1000, f32=True)
+    parts = W.particles_for(prob)
+    _say(f"[poiseuille] n={parts['n']} cells={prob.grid.ny}")
+    st = usp.DeviceState(prob, parts)
+    st.enable_sampling(0)
+    transient, sampled = 2000, 4000
+    st.step(0, transient)
+    for s in range(sampled):
+        st.step(transient + s, 1)
+        st.sample_fields()
+    g, gas = prob.grid, prob.gas
+    f = sampling.field_averages(st.field_sums(), g.volume, g.fnum, gas.m, gas.theta_vib, sampled)
+    U, T = f["U"][0], f["T_tr"].mean()
+    mu = gas.mu_ref * (T / gas.T_ref) ** gas.omega
+    nu = mu / (prob.notes["n"] * gas.m)
+    M, L = g.ny, g.ny * g.dy
+    y = (np.arange(M) + 0.5) * g.dy
+    A = np.stack([y * (L - y), np.ones(M)], 1)
+    (curv, slip), *_ = np.linalg.lstsq(A, U, rcond=None)
+    ratio = curv / (prob.bc.g[0] / (2 * nu))
+    _say(f"  T {T:.1f} K, curvature / NS {ratio:.4f}, slip {slip:.2f} m/s")
+    assert abs(ratio - 1.0) < 0.04
+    assert np.abs(U - U[::-1]).mean() < 0.03 * U.max()

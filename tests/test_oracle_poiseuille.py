@@ -1,0 +1,43 @@
+"""Pin of the oracle's full step against the near-continuum Poiseuille
+flow (the force-driven channel of Sec. V.B): after the transient, the
+time-averaged velocity profile is a parabola whose curvature is
+g / (2 nu) with nu = mu(T)/rho from the gas model (the method reproduces
+the viscosity it is built from), plus a wall slip of the size of the
+first-order Maxwell slip lambda du/dy at Kn = 0.05.  No GPU."""
+import numpy as np
+
+import oracle
+import usp_workloads as W
+
+
+def test_poiseuille_profile_curvature_and_slip():
+    prob = W.poiseuille(kn=0.05, cells=40, ppc=150, f32=False, seed=7)
+    parts = W.particles_for(prob)
+    sim = oracle.Sim(prob, parts)
+    g = prob.grid
+    M, L = g.ny, g.ny * g.dy
+    transient, sampled = 1500, 3000   # the slowest mode decays in ~360 steps
+    sN, sU, sT = np.zeros(M), np.zeros(M), np.zeros(M)
+    for s in range(transient + sampled):
+        sim.step_native(s, 1)
+        if s >= transient:
+            m = sim.moments()
+            sN += m[0]
+            sU += m[0] * m[1]
+            sT += m[0] * (m[4] + m[5] + m[6])
+    U = sU / sN
+    gas = prob.gas
+    T = (sT / sN).mean() / (3 * gas.R)
+    assert abs(T - 300.0) < 5.0          # Ma ~ 0.1: little viscous heating
+    mu = gas.mu_ref * (T / gas.T_ref) ** gas.omega
+    nu = mu / (prob.notes["n"] * gas.m)
+    y = (np.arange(M) + 0.5) * g.dy
+    A = np.stack([y * (L - y), np.ones(M)], 1)
+    (curv, slip), *_ = np.linalg.lstsq(A, U, rcond=None)
+    g_x = prob.bc.g[0]
+    assert abs(curv / (g_x / (2 * nu)) - 1.0) < 0.08, curv / (g_x / (2 * nu))
+    # mean free path c_bar tau_c = 50 um at this density (Kn = 0.05)
+    u_slip1 = 50e-6 * g_x * L / (2 * nu)
+    assert 0.5 * u_slip1 < slip < 2.5 * u_slip1, (slip, u_slip1)
+    # symmetric about the centre line
+    assert np.abs(U - U[::-1]).mean() < 0.08 * U.max()

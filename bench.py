@@ -83,6 +83,42 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def _snapshot(st):
+    keep = [{k: v.clone() for k, v in B.items() if k != "struct" and v is not None} for B in st.bufs]
+    extra = {k: getattr(st, k).clone() for k in ("offsets", "counters")}
+    for k in ("fields", "surf"):
+        if getattr(st, k, None) is not None:
+            extra[k] = getattr(st, k).clone()
+    return keep, extra, st.cur, st.binned, [B["struct"] for B in st.bufs]
+
+
+def _restore(st, snap):
+    keep, extra, cur, binned, structs = snap
+    for B, S, t in zip(st.bufs, keep, structs):
+        for k, v in S.items():
+            B[k].copy_(v)
+        B["struct"] = t
+    for k, v in extra.items():
+        getattr(st, k).copy_(v)
+    st.cur, st.binned = cur, binned
+
+
+def _copy_peak(torch, dev):
+    """Read + write rate of a plain 1 GiB device copy (best of 3), GB/s."""
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    best = float("inf")
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    return round(2 * (1 << 30) / (best * 1e-3) / 1e9, 1)
+
+
 def run_gpu(args):
     import numpy as np
     import torch
@@ -125,17 +161,39 @@ def run_gpu(args):
     torch.cuda.synchronize()
     log(f"{args.warmup} warmup steps done")
     K = args.steps
+    step0 = step
+    snap = _snapshot(st)
+    # eager pass: per-phase times (events between the phases)
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(PHASES) + 1)] for _ in range(K)]
     nlog = torch.zeros(K, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(K):
-        one_step(step, evs[k], nlog, k)
-        step += 1
+        one_step(step0 + k, evs[k], nlog, k)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
-    ns = nlog.cpu().numpy()
+    wall_eager = time.perf_counter() - t0
+    # timed pass: the same K steps from the same state, captured in one HIP
+    # graph and replayed once
+    _restore(st, snap)
+    nlog_g = torch.zeros(K, dtype=torch.int64, device=dev)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for k in range(K):
+            one_step(step0 + k, None, nlog_g, k)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_graph = e0.elapsed_time(e1)
+    ns = nlog_g.cpu().numpy()
+    if not np.array_equal(ns, nlog.cpu().numpy()):
+        raise RuntimeError("graph replay and eager pass disagree on the particle counts")
+    log(f"eager {wall_eager / K * 1e3:.4f} ms/step, graph {wall / K * 1e3:.4f} ms/step")
+    hbm_copy = _copy_peak(torch, dev)
     phase_ms = {ph: 0.0 for ph in PHASES}
     for k in range(K):
         for j, ph in enumerate(PHASES):
@@ -175,8 +233,13 @@ def run_gpu(args):
                 "state": "f32", "accumulation": "f64", "dt_s": prob.dt,
                 "first_timed_step": args.warmup, "sampling": bool(args.sample),
                 "parallelism": "single-gpu"},
+        launch="one HIP graph of the K steps (per-phase times from an eager pass over the same "
+               "steps from the same state)",
+        eager_ms_per_step=round(wall_eager / K * 1e3, 4),
+        graph_event_ms=round(ms_graph, 3),
         phase_ms=phase_ms,
         step_algorithmic_gbs=round(step_bytes / (wall / K) / 1e9, 1),
+        hbm_copy_gbs=hbm_copy,
         roofline=roof,
         counters={k: v for k, v in cnt.items() if v},
     )

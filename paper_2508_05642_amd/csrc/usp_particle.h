@@ -697,7 +697,10 @@ __device__ __forceinline__ void conserve_cell(const GasP& gas, const double* __r
                                               uint64_t seed, uint32_t step, int64_t* counters) {
   const int lane = threadIdx.x & 63;
   const int64_t N = o1 - o0;
+  // the cell's values, wave-uniform, all requested before the first pass
   const double Un[3] = {cs[CS_UX * M + c], cs[CS_UY * M + c], cs[CS_UZ * M + c]};
+  const double evib_t = cs[CS_EVIB_NEW * M + c], erot_t = cs[CS_EROT_NEW * M + c];
+  const double E0 = cs[CS_ETR * M + c] + cs[CS_EROT * M + c] + cs[CS_EVIB * M + c];
   double s[6] = {0, 0, 0, 0, 0, 0};
   int lmax = 0;
   for (int64_t i = o0 + lane; i < o1; i += 64) {
@@ -721,7 +724,7 @@ __device__ __forceinline__ void conserve_cell(const GasP& gas, const double* __r
   // (i) vibrational levels: I_delta = floor(N (e_target - e*)/(R theta) + U),
   // then |I_delta| single-level moves on randomly picked particles
   int64_t SI = (int64_t)s[5];
-  const double X = Nd * cs[CS_EVIB_NEW * M + c] / RTh - (double)SI;
+  const double X = Nd * evib_t / RTh - (double)SI;
   // the first-order FPM method keeps the levels and rotational energies it
   // sampled and conserves momentum and total energy through the velocities
   const bool fpm = gas.scheme == USP_SCHEME_FPM;
@@ -730,29 +733,28 @@ __device__ __forceinline__ void conserve_cell(const GasP& gas, const double* __r
   const int64_t need0 = Id0 > 0 ? Id0 : 0;
   const bool low = !__ballot((int64_t)lmax + need0 >= VIB_MAX);
   const int moved = wave_picks(lv, N, Id0, &SI, (uint32_t)c, step, seed, low, counters);
+  // the cell scalars, the same on every lane (wave-uniform inputs)
   double frot = 0.0, sc = 0.0;
-  if (lane == 0) {
-    const double etr_s = 0.5 * (s[3] / Nd - (m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2]));
-    // (ii) rotational scaling to the cell target
-    const double erot_s = s[4] / Nd, erot_t = cs[CS_EROT_NEW * M + c];
-    double erot_a = erot_s;
-    if (fpm) {
-      // the sampled rotational energies stand
-    } else if (erot_s > 0.0 && erot_t > 0.0) {
-      frot = erot_t / erot_s;
-      erot_a = erot_t;
-    } else {
-      count_event(counters, USP_CNT_CONS_SKIP);
-    }
-    // (iii) velocity scaling about U*, toward U^n (momentum and energy)
-    const double evib_a = (double)SI * RTh / Nd;
-    const double E0 = cs[CS_ETR * M + c] + cs[CS_EROT * M + c] + cs[CS_EVIB * M + c];
-    const double s2 = (E0 - erot_a - evib_a) / etr_s;
-    if (etr_s > 0.0 && s2 > 0.0) sc = sqrt(s2);
-    else count_event(counters, USP_CNT_CONS_SKIP);
+  const double etr_s = 0.5 * (s[3] / Nd - (m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2]));
+  // (ii) rotational scaling to the cell target
+  const double erot_s = s[4] / Nd;
+  double erot_a = erot_s;
+  int skips = 0;
+  if (fpm) {
+    // the sampled rotational energies stand
+  } else if (erot_s > 0.0 && erot_t > 0.0) {
+    frot = erot_t / erot_s;
+    erot_a = erot_t;
+  } else {
+    ++skips;
   }
-  frot = __shfl(frot, 0, 64);
-  sc = __shfl(sc, 0, 64);
+  // (iii) velocity scaling about U*, toward U^n (momentum and energy)
+  const double evib_a = (double)SI * RTh / Nd;
+  const double s2 = (E0 - erot_a - evib_a) / etr_s;
+  if (etr_s > 0.0 && s2 > 0.0) sc = sqrt(s2);
+  else ++skips;
+  if (lane == 0)
+    for (int k = 0; k < skips; ++k) count_event(counters, USP_CNT_CONS_SKIP);
   wave_sync_lds();
   const double Us0 = Un[0] + m1[0], Us1 = Un[1] + m1[1], Us2 = Un[2] + m1[2];
   for (int64_t i = o0 + lane; i < o1; i += 64) {

@@ -12,6 +12,7 @@ Bars (integer work bit-exact; floating point as stated):
 """
 import dataclasses
 import math
+import os
 import sys
 
 import numpy as np
@@ -19,6 +20,8 @@ import pytest
 
 import oracle
 import usp_workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 pytestmark = pytest.mark.gpu
 
@@ -729,13 +732,33 @@ def test_surface_sampling_full_steps_fp64():
     _surf_compare(gpu.surface_sums(), orc.surf, "3 steps")
 
 
+def _golden_profile(name):
+    T, U = None, []
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            k, v = line.split()
+            if k == "T_tr":
+                T = float(v)
+            else:
+                U.append(float(v))
+    return T, np.array(U)
+
+
 def test_poiseuille_full_size_statistics():
     """The Kn = 0.05 channel at full size (200 cells x 1000 particles, FP32
-    state), 6000 steps with the field sums of the last 4000: the
-    time-averaged profile has the Navier-Stokes curvature g/(2 nu) within
-    4% and is symmetric (statistics end to end, not trajectories)."""
+    state), 6000 steps with the field sums of the last 4000, against the
+    oracle's time average of the same run (tests/golden, written by
+    make_poiseuille_profile.py).  The two trajectories part after a few
+    hundred steps (FP32 rounding order, chaotic dynamics), so what must
+    agree is the statistics: the profile cell by cell within its sampling
+    noise (about 0.35 m/s a cell), the parabola's curvature within 2% of
+    the oracle's, the temperature within 0.5 K, and the profile symmetric.
+    The curvature is also held to the Navier-Stokes value g/(2 nu) with the
+    oracle pin's 8% (both sides sit about 6% above it at this Kn and
+    resolution: the Knudsen layers at the walls are resolved here)."""
     usp = _usp()
-    from paper_2508_05642_amd import sampling
     prob = W.poiseuille(kn=0.05, cells=200, ppc=1000, f32=True)
     parts = W.particles_for(prob)
     _say(f"[poiseuille] n={parts['n']} cells={prob.grid.ny}")
@@ -747,15 +770,54 @@ def test_poiseuille_full_size_statistics():
         st.step(transient + s, 1)
         st.sample_fields()
     g, gas = prob.grid, prob.gas
-    f = sampling.field_averages(st.field_sums(), g.volume, g.fnum, gas.m, gas.theta_vib, sampled)
-    U, T = f["U"][0], f["T_tr"].mean()
-    mu = gas.mu_ref * (T / gas.T_ref) ** gas.omega
-    nu = mu / (prob.notes["n"] * gas.m)
+    F = st.field_sums()
+    N, cx = F[0], F[1]
+    U = cx / N
+    c2 = F[4] + F[5] + F[6]
+    cu = (F[1] ** 2 + F[2] ** 2 + F[3] ** 2) / N
+    T = (c2 - cu).sum() / N.sum() / (3 * gas.R)
+    To, Uo = _golden_profile("poiseuille_kn005_200x1000.txt")
     M, L = g.ny, g.ny * g.dy
+    assert Uo.size == M
     y = (np.arange(M) + 0.5) * g.dy
     A = np.stack([y * (L - y), np.ones(M)], 1)
     (curv, slip), *_ = np.linalg.lstsq(A, U, rcond=None)
-    ratio = curv / (prob.bc.g[0] / (2 * nu))
-    _say(f"  T {T:.1f} K, curvature / NS {ratio:.4f}, slip {slip:.2f} m/s")
-    assert abs(ratio - 1.0) < 0.04
+    (curv_o, slip_o), *_ = np.linalg.lstsq(A, Uo, rcond=None)
+    mu = gas.mu_ref * (T / gas.T_ref) ** gas.omega
+    ratio = curv / (prob.bc.g[0] / (2 * mu / (prob.notes["n"] * gas.m)))
+    d = np.abs(U - Uo)
+    _say(f"  T {T:.2f} K (oracle {To:.2f}), curvature / oracle {curv / curv_o:.4f}, "
+         f"/ NS {ratio:.4f}, slip {slip:.2f} (oracle {slip_o:.2f}) m/s, "
+         f"|U - U_oracle| mean {d.mean():.3f} max {d.max():.3f} m/s")
+    assert abs(T - To) < 0.5
+    assert abs(curv / curv_o - 1.0) < 0.02
+    assert d.mean() < 1.0 and d.max() < 2.5
+    assert abs(ratio - 1.0) < 0.08
     assert np.abs(U - U[::-1]).mean() < 0.03 * U.max()
+
+
+@pytest.mark.parametrize("kind,f32", CASES)
+def test_gather_pipeline_equals_copy(kind, f32):
+    """usp_bin_gather + usp_moments_gather + usp_update_gather give the bits
+    of usp_bin + usp_moments + usp_update (moments, cell state, and every
+    array of the resulting state), over two steps (the second on the fast
+    rebin route)."""
+    usp = _usp()
+    prob, parts = make(kind, f32)
+    _say(f"[gather] case={kind} f32={f32} n={parts['n']} cells={prob.grid.ncells}")
+    a = usp.DeviceState(prob, parts)
+    b = usp.DeviceState(prob, parts)
+    for s in (5, 6):
+        a.bin(); b.bin(gather=True)
+        a.do_moments(); b.do_moments()
+        assert torch.equal(a.mom, b.mom), s
+        a.do_reconstruct(); b.do_reconstruct()
+        assert torch.equal(a.cs, b.cs), s
+        a.update(s); b.update(s)
+        torch.cuda.synchronize()
+        sa, sb = a.state(), b.state()
+        assert sa["n"] == sb["n"] and sa["next_pid"] == sb["next_pid"]
+        for k in sa:
+            if isinstance(sa[k], np.ndarray):
+                assert np.array_equal(sa[k], sb[k]), (s, k)
+        assert a.cnt() == b.cnt()

@@ -41,3 +41,36 @@ def test_poiseuille_profile_curvature_and_slip():
     assert 0.5 * u_slip1 < slip < 2.5 * u_slip1, (slip, u_slip1)
     # symmetric about the centre line
     assert np.abs(U - U[::-1]).mean() < 0.08 * U.max()
+
+
+def test_stored_full_size_profile():
+    """The stored oracle profile of the full-size channel (200 cells x 1000
+    particles, tests/golden/poiseuille_kn005_200x1000.txt) meets the same
+    continuum pins: NS curvature within 8%, a positive slip of the first-order
+    size, symmetric, T near the wall temperature."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "poiseuille_kn005_200x1000.txt")
+    T, U = None, []
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, v = line.split()
+        if k == "T_tr":
+            T = float(v)
+        else:
+            U.append(float(v))
+    U = np.array(U)
+    prob = W.poiseuille(kn=0.05, cells=200, ppc=1000, f32=True)
+    g, gas = prob.grid, prob.gas
+    M, L = g.ny, g.ny * g.dy
+    assert U.size == M and abs(T - 300.0) < 5.0
+    y = (np.arange(M) + 0.5) * g.dy
+    (curv, slip), *_ = np.linalg.lstsq(np.stack([y * (L - y), np.ones(M)], 1), U, rcond=None)
+    mu = gas.mu_ref * (T / gas.T_ref) ** gas.omega
+    g_x = prob.bc.g[0]
+    ratio = curv / (g_x / (2 * mu / (prob.notes["n"] * gas.m)))
+    assert abs(ratio - 1.0) < 0.08, ratio
+    nu = mu / (prob.notes["n"] * gas.m)
+    u_slip1 = 50e-6 * g_x * L / (2 * nu)
+    assert 0.5 * u_slip1 < slip < 2.5 * u_slip1, (slip, u_slip1)
+    assert np.abs(U - U[::-1]).mean() < 0.03 * U.max()

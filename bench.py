@@ -41,15 +41,15 @@ def algorithmic_bytes(phase, n, M):
     state: x, y, cx, cy, cz, erot 4 B each, vib 1 B, cell 4 B, pid 4 B;
     cell-state plane 8 B per field)."""
     per_particle = {
-        # read x, y, cell (12), write the sorted copy of every array (33) after
-        # reading it (33): the stable rebin moves the whole state once
-        "bin": 12 + 33 + 33,
-        # read cx, cy, cz, erot, vib
-        "moments": 17,
+        # the bin only records the new order: read cell, write the input
+        # index and the new cell of every slot
+        "bin": 4 + 4 + 4,
+        # read the slot's input index, then cx, cy, cz, erot, vib through it
+        "moments": 4 + 17,
         "reconstruct": 0,
-        # read x, y, cx, cy, cz, erot, vib, cell, pid; write x, y, cx, cy, cz,
-        # erot, vib, cell
-        "update": 33 + 29,
+        # read the input index and x, y, cx, cy, cz, erot, vib, pid through
+        # it plus the new cell; write every array of the new state
+        "update": 4 + 33 + 33,
     }[phase]
     # per cell: offsets 8; moments 21 planes; cell state reads 21 planes and
     # writes 35 planes + a 128-byte record; update reads the record and 9
@@ -142,9 +142,9 @@ def run_gpu(args):
 
     def one_step(s, ev=None, nlog=None, k=None):
         if ev: ev[0].record()
-        st.bin()
+        st.bin(gather=True)
         if nlog is not None:
-            nlog[k].copy_(st.bufs[st.cur]["count"][0])
+            nlog[k].copy_(st.bufs[1 - st.cur]["count"][0])
         if ev: ev[1].record()
         st.do_moments()
         if args.sample:

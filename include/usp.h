@@ -254,6 +254,32 @@ usp_status usp_bin(const usp_grid* grid, const usp_particles* in, usp_particles*
                    int64_t* offsets, const int64_t* in_offsets, void* ws, size_t ws_bytes,
                    int64_t* counters, void* stream);
 
+/* The bin of usp_bin without moving the particles: perm (device
+   uint32[out->capacity]) receives, for every output slot j, the input index
+   of the particle usp_bin would place there; out->cell[j] receives its cell;
+   offsets and out->count as usp_bin sets them.  The other arrays of `out`
+   are left as they are.  Same arguments and errors as usp_bin otherwise.
+   With usp_moments_gather and usp_update_gather this is the step without
+   the copy of the particle state into the binned order (usp_step uses it). */
+usp_status usp_bin_gather(const usp_grid* grid, const usp_particles* in, usp_particles* out,
+                          int64_t* offsets, const int64_t* in_offsets, uint32_t* perm, void* ws,
+                          size_t ws_bytes, int64_t* counters, void* stream);
+
+/* usp_moments of the state usp_bin would have produced, reading slot j from
+   in[perm[j]] (perm and offsets from usp_bin_gather).  Bit-identical to
+   usp_bin followed by usp_moments. */
+usp_status usp_moments_gather(const usp_grid* grid, const usp_particles* in, const uint32_t* perm,
+                              const int64_t* offsets, double* mom, void* stream);
+
+/* usp_update of the state usp_bin would have produced, reading slot j from
+   in[perm[j]] and writing the whole result state in slot order to `out`
+   (whose cells and count usp_bin_gather set), injection included.  in and
+   out must differ; bit-identical to usp_bin followed by usp_update. */
+usp_status usp_update_gather(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
+                             const double* cs, const int64_t* offsets, const usp_particles* in,
+                             const uint32_t* perm, usp_particles* out, void* ws, size_t ws_bytes,
+                             uint64_t seed, uint64_t step, int64_t* counters, void* stream);
+
 /* Moments (Sec. II.A) of every cell from a binned state: mom = device
    double[USP_NMOM*M].  Two passes per cell (U, then central moments),
    accumulated in FP64 in a fixed order (deterministic). */

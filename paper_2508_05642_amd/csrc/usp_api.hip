@@ -160,12 +160,24 @@ usp_status do_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, d
     // 0D nothing moves between cells, so only the first step bins
     hipError_t e = hipSuccess;
     if (s == 0 || g.dim != 0) {
-      e = launch_bin<S>(g, make_parts<S>(p), make_parts<S>(p_alt), offsets,
-                        s > 0 ? offsets : in_offsets, w, L, counters, st);
-      if (e != hipSuccess) return USP_EDEVICE;
+      // the bin records the new order without moving the particles; the
+      // moments and the particle phase read them through it, and the
+      // particle phase writes the whole state in the new order to p_alt
+      uint32_t* gperm = (uint32_t*)(w + L.perm);
+      const PartP<S> in = make_parts<S>(p), out = make_parts<S>(p_alt);
+      if ((e = launch_bin<S>(g, in, out, offsets, s > 0 ? offsets : in_offsets, w, L, counters, st,
+                             gperm)) != hipSuccess)
+        return USP_EDEVICE;
+      if ((e = launch_moments<S>(g, in, offsets, mom, st, gperm)) != hipSuccess) return USP_EDEVICE;
+      if ((e = launch_reconstruct(g, gp, mom, dt, dt_cell, cs, counters, st)) != hipSuccess)
+        return USP_EDEVICE;
+      if ((e = launch_update<S>(g, gp, bp, dt, cs, offsets, out, seed, sn, w, L, counters, st, &in,
+                                gperm)) != hipSuccess)
+        return USP_EDEVICE;
       const usp_particles tmp = *p;
       *p = *p_alt;
       *p_alt = tmp;
+      continue;
     }
     const PartP<S> q = make_parts<S>(p);
     if ((e = launch_moments<S>(g, q, offsets, mom, st)) != hipSuccess) return USP_EDEVICE;
@@ -237,6 +249,61 @@ usp_status usp_bin(const usp_grid* grid, const usp_particles* in, usp_particles*
   hipStream_t st = (hipStream_t)stream;
   return in->prec == USP_F32 ? do_bin<float>(grid, in, out, offsets, in_offsets, ws, counters, st)
                              : do_bin<double>(grid, in, out, offsets, in_offsets, ws, counters, st);
+}
+
+usp_status usp_bin_gather(const usp_grid* grid, const usp_particles* in, usp_particles* out,
+                          int64_t* offsets, const int64_t* in_offsets, uint32_t* perm, void* ws,
+                          size_t ws_bytes, int64_t* counters, void* stream) {
+  if (!grid_ok(grid) || !parts_ok(in, grid) || !parts_ok(out, grid) || !offsets || !ws || !perm)
+    return USP_EINVAL;
+  if (in->prec != out->prec || out->capacity < in->capacity) return USP_EINVAL;
+  if (in->cx == out->cx || in->count == out->count) return USP_EINVAL;
+  const int64_t cap = out->capacity;
+  if (ws_bytes < usp_workspace_bytes(grid, cap)) return USP_EINVAL;
+  const GridP g = make_grid(grid);
+  const WsLayout L = ws_layout(g.M, cap, n_faces(g));
+  hipStream_t st = (hipStream_t)stream;
+  return hip_status(in->prec == USP_F32
+      ? launch_bin<float>(g, make_parts<float>(in), make_parts<float>(out), offsets, in_offsets,
+                          (char*)ws, L, counters, st, perm)
+      : launch_bin<double>(g, make_parts<double>(in), make_parts<double>(out), offsets, in_offsets,
+                           (char*)ws, L, counters, st, perm));
+}
+
+usp_status usp_moments_gather(const usp_grid* grid, const usp_particles* in, const uint32_t* perm,
+                              const int64_t* offsets, double* mom, void* stream) {
+  if (!grid_ok(grid) || !parts_ok(in, grid) || !perm || !offsets || !mom) return USP_EINVAL;
+  const GridP g = make_grid(grid);
+  hipStream_t st = (hipStream_t)stream;
+  return hip_status(in->prec == USP_F32
+      ? launch_moments<float>(g, make_parts<float>(in), offsets, mom, st, perm)
+      : launch_moments<double>(g, make_parts<double>(in), offsets, mom, st, perm));
+}
+
+usp_status usp_update_gather(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
+                             const double* cs, const int64_t* offsets, const usp_particles* in,
+                             const uint32_t* perm, usp_particles* out, void* ws, size_t ws_bytes,
+                             uint64_t seed, uint64_t step, int64_t* counters, void* stream) {
+  if (!grid_ok(grid) || !gas_ok(gas) || !parts_ok(in, grid) || !parts_ok(out, grid) || !cs ||
+      !offsets || !ws || !perm)
+    return USP_EINVAL;
+  if (in->prec != out->prec || in->cx == out->cx || out->capacity < in->capacity) return USP_EINVAL;
+  if (grid->dim >= 1 && (!bc || !(dt > 0.0))) return USP_EINVAL;
+  if (!bc_ok(bc, grid)) return USP_EINVAL;
+  if (ws_bytes < usp_workspace_bytes(grid, out->capacity)) return USP_EINVAL;
+  const GridP g = make_grid(grid);
+  const GasP gp = make_gas(gas);
+  const BcP bp = make_bc(bc);
+  const WsLayout L = ws_layout(g.M, out->capacity, n_faces(g));
+  hipStream_t st = (hipStream_t)stream;
+  if (in->prec == USP_F32) {
+    const PartP<float> src = make_parts<float>(in);
+    return hip_status(launch_update<float>(g, gp, bp, dt, cs, offsets, make_parts<float>(out), seed,
+                                           step, (char*)ws, L, counters, st, &src, perm));
+  }
+  const PartP<double> src = make_parts<double>(in);
+  return hip_status(launch_update<double>(g, gp, bp, dt, cs, offsets, make_parts<double>(out), seed,
+                                          step, (char*)ws, L, counters, st, &src, perm));
 }
 
 usp_status usp_moments(const usp_grid* grid, const usp_particles* p, const int64_t* offsets,

@@ -368,10 +368,25 @@ __device__ __forceinline__ void copy_particle(const PartP<S>& in, const PartP<S>
   out.cell[p] = c;
 }
 
+// Output slot p of input particle i: copied (G = false), or, for a binning
+// that leaves the particles where they are (G = true), recorded as
+// gperm[p] = i with the new cell in out.cell[p].
+template <bool G, typename S>
+__device__ __forceinline__ void place(const PartP<S>& in, const PartP<S>& out, uint32_t* gperm,
+                                      int64_t i, int64_t p, int32_t c, bool has_x, bool has_y) {
+  if constexpr (G) {
+    gperm[p] = (uint32_t)i;
+    out.cell[p] = c;
+  } else {
+    copy_particle<S>(in, out, i, p, c, has_x, has_y);
+  }
+}
+
 // E: one wave per old cell; every grouped particle goes straight to
 // offsets[c] + (group base in c) + (rank in group).
-template <typename S>
+template <typename S, bool G>
 __global__ __launch_bounds__(BIN_BLOCK) void k_bin_scatter(GridP g, Nbr nb, PartP<S> in, PartP<S> out,
+                                                           uint32_t* gperm,
                                                            const int64_t* old_off, const int32_t* grp,
                                                            const int32_t* T9, const int64_t* offsets) {
   const int64_t M = g.M;
@@ -404,13 +419,14 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin_scatter(GridP g, Nbr nb, Part
     const int q = gv & 15;
     const int64_t b = __shfl(gbase, q < 9 ? q : 0, 64);
     const int32_t c = __shfl(gcell, q < 9 ? q : 0, 64);
-    if (i < hi && q < nb.n) copy_particle<S>(in, out, i, b + (gv >> 4), c, hx, hy);
+    if (i < hi && q < nb.n) place<G, S>(in, out, gperm, i, b + (gv >> 4), c, hx, hy);
   }
 }
 
 // far moves: each list entry finds its position inside its cell
-template <typename S>
+template <typename S, bool G>
 __global__ __launch_bounds__(BIN_BLOCK) void k_far_scatter(GridP g, PartP<S> in, PartP<S> out,
+                                                           uint32_t* gperm,
                                                            const int32_t* far_total,
                                                            const int32_t* far_c, const int32_t* far_i,
                                                            const int64_t* far_off,
@@ -423,7 +439,7 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_far_scatter(GridP g, PartP<S> in,
     int64_t fp = far_off[c];
     const int64_t f1 = far_off[c + 1];
     while (fp < f1 && far_list[fp] != i) ++fp;
-    if (fp < f1) copy_particle<S>(in, out, i, offsets[c] + far_base[fp], c, g.dim == 2, g.dim >= 1);
+    if (fp < f1) place<G, S>(in, out, gperm, i, offsets[c] + far_base[fp], c, g.dim == 2, g.dim >= 1);
   }
 }
 
@@ -452,10 +468,10 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_tail_claim(int64_t M, const int64
 // counting and copies each particle to its rank's slot: each lane holds K
 // entries; an entry's rank is the number of entries below it, counted
 // against all entries broadcast with readlane.
-template <int K, typename S>
+template <int K, bool G, typename S>
 __device__ __forceinline__ void wave_rank_copy(const uint32_t* seg, int n, int64_t dst0,
-                                               const PartP<S>& in, const PartP<S>& out, int32_t c,
-                                               bool hx, bool hy) {
+                                               const PartP<S>& in, const PartP<S>& out,
+                                               uint32_t* gperm, int32_t c, bool hx, bool hy) {
   const int lane = threadIdx.x & 63;
   uint32_t v[K];
   int r[K];
@@ -477,18 +493,18 @@ __device__ __forceinline__ void wave_rank_copy(const uint32_t* seg, int n, int64
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int j = k * 64 + lane;
-    if (j < n) copy_particle<S>(in, out, v[k], dst0 + r[k], c, hx, hy);
+    if (j < n) place<G, S>(in, out, gperm, v[k], dst0 + r[k], c, hx, hy);
   }
 }
 
 constexpr int WAVE_SORT_MAX = 1024;
 
 // one wave per listed cell (grid-stride over the list of cells with a tail)
-template <typename S>
+template <typename S, bool G>
 __global__ __launch_bounds__(BIN_BLOCK) void k_tail_sort_copy(GridP g, PartP<S> in, PartP<S> out,
                                                               const int64_t* offsets,
                                                               const int32_t* nontail,
-                                                              const uint32_t* perm,
+                                                              uint32_t* perm,
                                                               const int32_t* tail_cells,
                                                               const int32_t* n_tail_cells) {
   const int nl = *n_tail_cells;
@@ -500,17 +516,17 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_tail_sort_copy(GridP g, PartP<S> 
     if (n <= 0 || n > WAVE_SORT_MAX) continue;
     const bool hx = g.dim == 2, hy = g.dim >= 1;
     const uint32_t* seg = perm + t0;
-    if (n <= 64) wave_rank_copy<1, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
-    else if (n <= 128) wave_rank_copy<2, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
-    else if (n <= 256) wave_rank_copy<4, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
-    else if (n <= 512) wave_rank_copy<8, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
-    else wave_rank_copy<16, S>(seg, n, t0, in, out, (int32_t)c, hx, hy);
+    if (n <= 64) wave_rank_copy<1, G, S>(seg, n, t0, in, out, perm, (int32_t)c, hx, hy);
+    else if (n <= 128) wave_rank_copy<2, G, S>(seg, n, t0, in, out, perm, (int32_t)c, hx, hy);
+    else if (n <= 256) wave_rank_copy<4, G, S>(seg, n, t0, in, out, perm, (int32_t)c, hx, hy);
+    else if (n <= 512) wave_rank_copy<8, G, S>(seg, n, t0, in, out, perm, (int32_t)c, hx, hy);
+    else wave_rank_copy<16, G, S>(seg, n, t0, in, out, perm, (int32_t)c, hx, hy);
   }
 }
 
 // tails above WAVE_SORT_MAX: one block per cell, sort network in LDS (or in
 // global memory beyond SORT_LDS entries), then the copy
-template <typename S>
+template <typename S, bool G>
 __global__ __launch_bounds__(BIN_BLOCK) void k_tail_sort_copy_big(GridP g, PartP<S> in, PartP<S> out,
                                                                   const int64_t* offsets,
                                                                   const int32_t* nontail,
@@ -530,11 +546,11 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_tail_sort_copy_big(GridP g, PartP
       for (int i = threadIdx.x; i < n; i += blockDim.x) s[i] = seg[i];
       __syncthreads();
       sort_net<true>(s, n);
-      for (int i = threadIdx.x; i < n; i += blockDim.x) copy_particle<S>(in, out, s[i], t0 + i, (int32_t)c, hx, hy);
+      for (int i = threadIdx.x; i < n; i += blockDim.x) place<G, S>(in, out, perm, s[i], t0 + i, (int32_t)c, hx, hy);
       __syncthreads();
     } else {
       sort_net<false>(seg, n);
-      for (int i = threadIdx.x; i < n; i += blockDim.x) copy_particle<S>(in, out, seg[i], t0 + i, (int32_t)c, hx, hy);
+      for (int i = threadIdx.x; i < n; i += blockDim.x) place<G, S>(in, out, perm, seg[i], t0 + i, (int32_t)c, hx, hy);
     }
   }
 }
@@ -559,12 +575,12 @@ static void launch_scan(const int32_t* cnt, int64_t M, int64_t* out_off, int64_t
   k_scan_down<<<nb, BIN_BLOCK, 0, st>>>(cnt, M, blocksums, out_off);
 }
 
-template <typename S>
-hipError_t launch_bin(const GridP& g, const PartP<S>& in, const PartP<S>& out, int64_t* offsets,
-                      const int64_t* in_offsets, char* ws, const WsLayout& L, int64_t* counters,
-                      hipStream_t st) {
+template <typename S, bool G>
+static hipError_t bin_launches(const GridP& g, const PartP<S>& in, const PartP<S>& out,
+                               int64_t* offsets, const int64_t* in_offsets, char* ws,
+                               const WsLayout& L, uint32_t* perm, int64_t* counters,
+                               hipStream_t st) {
   int32_t* key = (int32_t*)(ws + L.key);
-  uint32_t* perm = (uint32_t*)(ws + L.perm);
   int64_t* blocksums = (int64_t*)(ws + L.blocksums);
   int32_t* T9 = (int32_t*)(ws + L.t9);
   int32_t* tail_cnt = (int32_t*)(ws + L.cell_i32);
@@ -598,24 +614,37 @@ hipError_t launch_bin(const GridP& g, const PartP<S>& in, const PartP<S>& out, i
                                                           far_list, far_base, tail_cnt, nontail,
                                                           cnt_total);
   launch_scan(cnt_total, M, offsets, blocksums, out.count, in.count, st);
-  k_bin_scatter<S><<<cdiv(M, BIN_BLOCK / 64), BIN_BLOCK, 0, st>>>(g, nb, in, out, old_off, key, T9,
+  k_bin_scatter<S, G><<<cdiv(M, BIN_BLOCK / 64), BIN_BLOCK, 0, st>>>(g, nb, in, out, perm, old_off, key, T9,
                                                                    offsets);
-  k_far_scatter<S><<<64, BIN_BLOCK, 0, st>>>(g, in, out, far_total, far_c, far_i, far_off, far_list,
+  k_far_scatter<S, G><<<64, BIN_BLOCK, 0, st>>>(g, in, out, perm, far_total, far_c, far_i, far_off, far_list,
                                              far_base, offsets);
   k_tail_claim<<<TAIL_GRID, BIN_BLOCK, 0, st>>>(M, old_off, in.count, key, offsets, nontail, cursor,
                                                 perm);
-  k_tail_sort_copy<S><<<TAIL_GRID, BIN_BLOCK, 0, st>>>(g, in, out, offsets, nontail, perm,
+  k_tail_sort_copy<S, G><<<TAIL_GRID, BIN_BLOCK, 0, st>>>(g, in, out, offsets, nontail, perm,
                                                        tail_cells, n_tail_cells);
-  k_tail_sort_copy_big<S><<<TAIL_GRID, BIN_BLOCK, 0, st>>>(g, in, out, offsets, nontail, perm,
+  k_tail_sort_copy_big<S, G><<<TAIL_GRID, BIN_BLOCK, 0, st>>>(g, in, out, offsets, nontail, perm,
                                                            tail_cells, n_tail_cells);
   return hipGetLastError();
 }
 
+// Copying bin (gather_perm null), or the same order recorded in
+// gather_perm[slot] = input index with out.cell and out.count set and the
+// particles left in place.
+template <typename S>
+hipError_t launch_bin(const GridP& g, const PartP<S>& in, const PartP<S>& out, int64_t* offsets,
+                      const int64_t* in_offsets, char* ws, const WsLayout& L, int64_t* counters,
+                      hipStream_t st, uint32_t* gather_perm) {
+  if (gather_perm)
+    return bin_launches<S, true>(g, in, out, offsets, in_offsets, ws, L, gather_perm, counters, st);
+  return bin_launches<S, false>(g, in, out, offsets, in_offsets, ws, L, (uint32_t*)(ws + L.perm),
+                                counters, st);
+}
+
 template hipError_t launch_bin<float>(const GridP&, const PartP<float>&, const PartP<float>&,
                                       int64_t*, const int64_t*, char*, const WsLayout&, int64_t*,
-                                      hipStream_t);
+                                      hipStream_t, uint32_t*);
 template hipError_t launch_bin<double>(const GridP&, const PartP<double>&, const PartP<double>&,
                                        int64_t*, const int64_t*, char*, const WsLayout&, int64_t*,
-                                       hipStream_t);
+                                       hipStream_t, uint32_t*);
 
 }  // namespace usp

@@ -34,23 +34,32 @@ constexpr int MOM_LANES = 16;
 
 // The NMOM moments of the particles [o0, o1) (array indices) on one row of
 // 16 lanes (sub = lane in the row; all 16 lanes call); every lane of the
-// row returns the same v.
-template <typename PS>
+// row returns the same v.  With G, slot i is the particle perm[i] of the
+// arrays (a binning that left the particles in place).
+template <typename PS, bool G = false>
 __device__ __forceinline__ void row_moments(const PS* cx, const PS* cy, const PS* cz,
                                             const PS* er, const uint8_t* vb, int64_t o0,
-                                            int64_t o1, int sub, double v[NMOM]) {
+                                            int64_t o1, int sub, double v[NMOM],
+                                            const uint32_t* perm = nullptr) {
   const int64_t N = o1 - o0;
+  auto at = [&](int64_t i) -> int64_t {
+    if constexpr (G) return (int64_t)perm[i];
+    else return i;
+  };
   double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-  if (N > 0) { r0 = (double)cx[o0]; r1 = (double)cy[o0]; r2 = (double)cz[o0]; }
+  if (N > 0) {
+    const int64_t j = at(o0);
+    r0 = (double)cx[j]; r1 = (double)cy[j]; r2 = (double)cz[j];
+  }
   double s[20];
 #pragma unroll
   for (int k = 0; k < 20; ++k) s[k] = 0.0;
   int64_t i = o0 + sub;
   for (; i + MOM_LANES < o1; i += 2 * MOM_LANES) {
-    mom_add<PS>(cx, cy, cz, er, vb, i, r0, r1, r2, s);
-    mom_add<PS>(cx, cy, cz, er, vb, i + MOM_LANES, r0, r1, r2, s);
+    mom_add<PS>(cx, cy, cz, er, vb, at(i), r0, r1, r2, s);
+    mom_add<PS>(cx, cy, cz, er, vb, at(i + MOM_LANES), r0, r1, r2, s);
   }
-  if (i < o1) mom_add<PS>(cx, cy, cz, er, vb, i, r0, r1, r2, s);
+  if (i < o1) mom_add<PS>(cx, cy, cz, er, vb, at(i), r0, r1, r2, s);
 #pragma unroll
   for (int k = 0; k < 20; ++k) s[k] = row16_sum(s[k]);
   if (N == 0) {

@@ -114,10 +114,10 @@ int n_faces(const GridP& g);
 template <typename S>
 hipError_t launch_bin(const GridP& g, const PartP<S>& in, const PartP<S>& out, int64_t* offsets,
                       const int64_t* in_offsets, char* ws, const WsLayout& L, int64_t* counters,
-                      hipStream_t st);
+                      hipStream_t st, uint32_t* gather_perm = nullptr);
 template <typename S>
 hipError_t launch_moments(const GridP& g, const PartP<S>& p, const int64_t* offsets, double* mom,
-                          hipStream_t st);
+                          hipStream_t st, const uint32_t* gather_perm = nullptr);
 hipError_t launch_reconstruct(const GridP& g, const GasP& gas, const double* mom, double dt,
                               const double* dt_cell, double* cs, int64_t* counters, hipStream_t st);
 hipError_t launch_sample_fields(const GridP& g, const double* mom, double* acc, hipStream_t st);
@@ -138,11 +138,16 @@ template <typename S>
 hipError_t launch_inject(const GridP& g, const GasP& gas, const BcP& bc, double dt,
                          const PartP<S>& p, uint64_t seed, uint64_t step, char* ws,
                          const WsLayout& L, int64_t* counters, hipStream_t st);
+// The fused particle phase on p (binned), or, with gather_perm, on the
+// particles of `src` in the order gather_perm gives (slot j holds
+// src[gather_perm[j]]), the results written to p (whose cells the
+// gathering bin has set).
 template <typename S>
 hipError_t launch_update(const GridP& g, const GasP& gas, const BcP& bc, double dt,
                          const double* cs, const int64_t* offsets, const PartP<S>& p,
                          uint64_t seed, uint64_t step, char* ws, const WsLayout& L,
-                         int64_t* counters, hipStream_t st);
+                         int64_t* counters, hipStream_t st, const PartP<S>* src = nullptr,
+                         const uint32_t* gather_perm = nullptr);
 
 // first[t] (t = 0..ntiles) = first cell of tile t: the cells whose first
 // particle slot lies in [t T, (t+1) T)

@@ -7,16 +7,16 @@ constexpr int CELL_BLOCK = 256;
 
 // 16 lanes per cell, four cells per wave (every lane stays active for the
 // row permutes; lanes of cells past M carry zeros).
-template <typename S>
+template <typename S, bool G>
 __global__ __launch_bounds__(CELL_BLOCK) void k_moments(GridP g, PartP<S> p, const int64_t* offsets,
-                                                        double* mom) {
+                                                        double* mom, const uint32_t* perm) {
   const int64_t M = g.M;
   const int64_t c = ((int64_t)blockIdx.x * CELL_BLOCK + threadIdx.x) / MOM_LANES;
   const int sub = threadIdx.x & (MOM_LANES - 1);
   const bool valid = c < M;
   const int64_t o0 = valid ? offsets[c] : 0, o1 = valid ? offsets[c + 1] : 0;
   double v[NMOM];
-  row_moments<S>(p.cx, p.cy, p.cz, p.erot, p.vib, o0, o1, sub, v);
+  row_moments<S, G>(p.cx, p.cy, p.cz, p.erot, p.vib, o0, o1, sub, v, perm);
   if (valid) store_moments(mom, M, c, sub, v);
 }
 
@@ -116,8 +116,12 @@ hipError_t launch_sample_fields(const GridP& g, const double* mom, double* acc, 
 
 template <typename S>
 hipError_t launch_moments(const GridP& g, const PartP<S>& p, const int64_t* offsets, double* mom,
-                          hipStream_t st) {
-  k_moments<S><<<cdiv(g.M * MOM_LANES, CELL_BLOCK), CELL_BLOCK, 0, st>>>(g, p, offsets, mom);
+                          hipStream_t st, const uint32_t* gather_perm) {
+  const int64_t nb = cdiv(g.M * MOM_LANES, CELL_BLOCK);
+  if (gather_perm)
+    k_moments<S, true><<<nb, CELL_BLOCK, 0, st>>>(g, p, offsets, mom, gather_perm);
+  else
+    k_moments<S, false><<<nb, CELL_BLOCK, 0, st>>>(g, p, offsets, mom, nullptr);
   return hipGetLastError();
 }
 
@@ -129,8 +133,8 @@ hipError_t launch_reconstruct(const GridP& g, const GasP& gas, const double* mom
 }
 
 template hipError_t launch_moments<float>(const GridP&, const PartP<float>&, const int64_t*,
-                                          double*, hipStream_t);
+                                          double*, hipStream_t, const uint32_t*);
 template hipError_t launch_moments<double>(const GridP&, const PartP<double>&, const int64_t*,
-                                           double*, hipStream_t);
+                                           double*, hipStream_t, const uint32_t*);
 
 }  // namespace usp

@@ -40,7 +40,9 @@ __global__ void k_tile_first(const int64_t* __restrict__ offsets, int64_t M, int
 }
 
 // The three phases of one tile; st = LDS stage or the particle arrays.
-template <typename S, bool STAGED, int CAP, bool FPM>
+// With G the stage (or, for a tile past the stage, the arrays of p) was
+// filled by the gather prologue, so phase A updates it in place.
+template <typename S, bool STAGED, int CAP, bool FPM, bool G>
 __device__ __forceinline__ void tile_pass(const GridP& g, const GasP& gas, const BcP& bc,
                                           double dt, const double* __restrict__ cs,
                                           const int64_t* __restrict__ offsets, const PartP<S>& p,
@@ -49,8 +51,12 @@ __device__ __forceinline__ void tile_pass(const GridP& g, const GasP& gas, const
                                           uint64_t seed, uint32_t step, bool advect,
                                           int64_t* counters) {
   // A: particle update, global inputs into the stage (or in place)
-  tile_update<S, CAP, !STAGED, FPM>(g, gas, cs, p, i0, i1, global_stage(p), st, esc_list, nesc,
-                                    seed, step, counters);
+  if constexpr (G && STAGED)
+    tile_update<S, CAP, true, FPM>(g, gas, cs, p, i0, i1, st, st, esc_list, nesc, seed, step,
+                                   counters);
+  else
+    tile_update<S, CAP, !STAGED, FPM>(g, gas, cs, p, i0, i1, global_stage(p), st, esc_list, nesc,
+                                      seed, step, counters);
   // B: conservation, wave per cell
   tile_conserve<S>(gas, cs, g.M, offsets, c0, c1, st, seed, step, counters);
   __syncthreads();
@@ -65,13 +71,31 @@ __device__ __forceinline__ void tile_pass(const GridP& g, const GasP& gas, const
   }
 }
 
-template <typename S, bool FPM>
+// Gather prologue of a tile (G): slot i takes particle perm[i] of src;
+// velocities, rotational energy and level go to the stage, positions and
+// ids to p (p's cells were set by the gathering bin).
+template <typename S>
+__device__ __forceinline__ void tile_gather(const GridP& g, const PartP<S>& src,
+                                            const uint32_t* __restrict__ perm, const PartP<S>& p,
+                                            int64_t i0, int64_t i1, const Stage<S>& st) {
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += UPD_BLOCK) {
+    const int64_t j = perm[i];
+    st.store(i, load_state(src, j));
+    if (g.dim == 2) p.x[i] = src.x[j];
+    if (g.dim >= 1) p.y[i] = src.y[j];
+    p.pid[i] = src.pid[j];
+  }
+  __syncthreads();
+}
+
+template <typename S, bool FPM, bool G>
 __global__ __launch_bounds__(UPD_BLOCK, 4) void k_update(GridP g, GasP gas, BcP bc, double dt,
                                                       const double* __restrict__ cs,
                                                       const int64_t* __restrict__ offsets,
                                                       const int32_t* __restrict__ first,
                                                       PartP<S> p, uint64_t seed, uint32_t step,
-                                                      int advect, int64_t* counters) {
+                                                      int advect, int64_t* counters, PartP<S> src,
+                                                      const uint32_t* __restrict__ perm) {
   constexpr int CAP = UpdCfg<S>::STAGE;
   __shared__ S scx[CAP], scy[CAP], scz[CAP], ser[CAP];
   __shared__ uint8_t svb[CAP];
@@ -84,11 +108,14 @@ __global__ __launch_bounds__(UPD_BLOCK, 4) void k_update(GridP g, GasP gas, BcP 
   if (i1 - i0 <= CAP) {
     Stage<S> st;
     st.cx = scx; st.cy = scy; st.cz = scz; st.erot = ser; st.vib = svb; st.base = i0;
-    tile_pass<S, true, CAP, FPM>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1, st, esc_list, &nesc,
-                            seed, step, advect != 0, counters);
+    if constexpr (G) tile_gather<S>(g, src, perm, p, i0, i1, st);
+    tile_pass<S, true, CAP, FPM, G>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1, st, esc_list,
+                                    &nesc, seed, step, advect != 0, counters);
   } else {
-    tile_pass<S, false, CAP, FPM>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1, global_stage(p),
-                             esc_list, &nesc, seed, step, advect != 0, counters);
+    if constexpr (G) tile_gather<S>(g, src, perm, p, i0, i1, global_stage(p));
+    tile_pass<S, false, CAP, FPM, G>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1,
+                                     global_stage(p), esc_list, &nesc, seed, step, advect != 0,
+                                     counters);
   }
 }
 
@@ -103,17 +130,28 @@ template <typename S>
 hipError_t launch_update(const GridP& g, const GasP& gas, const BcP& bc, double dt,
                          const double* cs, const int64_t* offsets, const PartP<S>& p,
                          uint64_t seed, uint64_t step, char* ws, const WsLayout& L,
-                         int64_t* counters, hipStream_t st) {
+                         int64_t* counters, hipStream_t st, const PartP<S>* src,
+                         const uint32_t* gather_perm) {
   constexpr int T = UpdCfg<S>::TILE;
   const int64_t ntiles = cdiv(p.capacity, T);
   int32_t* first = (int32_t*)(ws + L.tiles);
   launch_tiles(offsets, g.M, T, ntiles, first, st);
-  if (gas.scheme == USP_SCHEME_FPM)
-    k_update<S, true><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, bc, dt, cs, offsets, first, p, seed,
-                                                    (uint32_t)step, g.dim != 0 ? 1 : 0, counters);
+  const uint32_t s32 = (uint32_t)step;
+  const int adv = g.dim != 0 ? 1 : 0;
+  const bool fpm = gas.scheme == USP_SCHEME_FPM;
+  const PartP<S> sp = src ? *src : p;
+  if (gather_perm && fpm)
+    k_update<S, true, true><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, bc, dt, cs, offsets, first, p, seed,
+                                                          s32, adv, counters, sp, gather_perm);
+  else if (gather_perm)
+    k_update<S, false, true><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, bc, dt, cs, offsets, first, p, seed,
+                                                           s32, adv, counters, sp, gather_perm);
+  else if (fpm)
+    k_update<S, true, false><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, bc, dt, cs, offsets, first, p, seed,
+                                                           s32, adv, counters, sp, nullptr);
   else
-    k_update<S, false><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, bc, dt, cs, offsets, first, p, seed,
-                                                     (uint32_t)step, g.dim != 0 ? 1 : 0, counters);
+    k_update<S, false, false><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, bc, dt, cs, offsets, first, p,
+                                                            seed, s32, adv, counters, sp, nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || g.dim == 0) return e;
   return launch_inject<S>(g, gas, bc, dt, p, seed, step, ws, L, counters, st);
@@ -122,10 +160,10 @@ hipError_t launch_update(const GridP& g, const GasP& gas, const BcP& bc, double 
 template hipError_t launch_update<float>(const GridP&, const GasP&, const BcP&, double,
                                          const double*, const int64_t*, const PartP<float>&,
                                          uint64_t, uint64_t, char*, const WsLayout&, int64_t*,
-                                         hipStream_t);
+                                         hipStream_t, const PartP<float>*, const uint32_t*);
 template hipError_t launch_update<double>(const GridP&, const GasP&, const BcP&, double,
                                           const double*, const int64_t*, const PartP<double>&,
                                           uint64_t, uint64_t, char*, const WsLayout&, int64_t*,
-                                          hipStream_t);
+                                          hipStream_t, const PartP<double>*, const uint32_t*);
 
 }  // namespace usp

@@ -82,6 +82,9 @@ def lib():
         L.usp_surf_elements.argtypes = [vp, vp]
         L.usp_surf_elements.restype = i64
         L.usp_sample_fields.argtypes = [vp, vp, vp, vp]
+        L.usp_bin_gather.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp, vp]
+        L.usp_moments_gather.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.usp_update_gather.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, vp, vp, sz, u64, u64, vp, vp]
         L.usp_bin.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp, vp]
         L.usp_moments.argtypes = [vp, vp, vp, vp, vp]
         L.usp_reconstruct.argtypes = [vp, vp, vp, d, vp, vp, vp, vp]
@@ -101,7 +104,8 @@ def lib():
                                      sz, vp, sz, vp, vp]
         L.usp_adjoint_step.argtypes = [vp, vp, vp, d, vp, sz, i64, u64, u64, vp, vp, d, d, vp, vp,
                                        sz, vp]
-        for nm in ("usp_bin", "usp_moments", "usp_sample_fields", "usp_reconstruct", "usp_collide",
+        for nm in ("usp_bin", "usp_bin_gather", "usp_moments_gather", "usp_update_gather",
+                   "usp_moments", "usp_sample_fields", "usp_reconstruct", "usp_collide",
                    "usp_conserve", "usp_advect", "usp_update", "usp_batch", "usp_step",
                    "usp_step_taped", "usp_adjoint_step"):
             getattr(L, nm).restype = i32
@@ -111,6 +115,7 @@ def lib():
 
 EXPORTED = ["usp_status_str", "usp_mom_name", "usp_cs_name", "usp_counter_name", "usp_version",
             "usp_workspace_bytes", "usp_cellstate_bytes", "usp_surf_elements", "usp_bin",
+            "usp_bin_gather", "usp_moments_gather", "usp_update_gather",
             "usp_moments", "usp_sample_fields", "usp_reconstruct", "usp_collide", "usp_conserve",
             "usp_advect", "usp_update", "usp_batch", "usp_step", "usp_tape_bytes",
             "usp_adjoint_ws_bytes", "usp_step_taped", "usp_adjoint_step"]
@@ -158,6 +163,25 @@ def usp_bin(grid, pin, pout, offsets, ws, counters, stream=None, in_offsets=None
     _check(lib().usp_bin(C.byref(grid), C.byref(pin), C.byref(pout), _ptr(offsets),
                          _ptr(in_offsets), _ptr(ws), ws.numel(), _ptr(counters),
                          _stream(stream)), "usp_bin")
+
+
+def usp_bin_gather(grid, pin, pout, offsets, perm, ws, counters, stream=None, in_offsets=None):
+    _check(lib().usp_bin_gather(C.byref(grid), C.byref(pin), C.byref(pout), _ptr(offsets),
+                                _ptr(in_offsets), _ptr(perm), _ptr(ws), ws.numel(), _ptr(counters),
+                                _stream(stream)), "usp_bin_gather")
+
+
+def usp_moments_gather(grid, pin, perm, offsets, mom, stream=None):
+    _check(lib().usp_moments_gather(C.byref(grid), C.byref(pin), _ptr(perm), _ptr(offsets),
+                                    _ptr(mom), _stream(stream)), "usp_moments_gather")
+
+
+def usp_update_gather(grid, gas, bc, dt, cs, offsets, pin, perm, pout, seed, step, ws, counters,
+                      stream=None):
+    _check(lib().usp_update_gather(C.byref(grid), C.byref(gas), None if bc is None else C.byref(bc),
+                                   dt, _ptr(cs), _ptr(offsets), C.byref(pin), _ptr(perm),
+                                   C.byref(pout), _ptr(ws), ws.numel(), seed, step, _ptr(counters),
+                                   _stream(stream)), "usp_update_gather")
 
 
 def usp_moments(grid, p, offsets, mom, stream=None):
@@ -277,6 +301,8 @@ class DeviceState:
         self.counters = torch.zeros(NCOUNTERS, dtype=torch.int64, device=self.dev)
         self.fields = None
         self.surf = None
+        self.perm = torch.zeros(cap, dtype=torch.int32, device=self.dev)  # uint32 bits
+        self.gathered = False
 
     def enable_sampling(self, nbody=0):
         """Zeroed field sums (double[NSAMP, M]) and surface sums (int64
@@ -368,41 +394,68 @@ class DeviceState:
         return dict(zip(names("cnt"), self.counters.cpu().tolist()))
 
     # -- phases (the C entry points on this state) ------------------------
-    def bin(self, stream=None, use_offsets=True):
+    def bin(self, stream=None, use_offsets=True, gather=False):
         """Rebin the current state.  Once this state has been binned, the
         previous offsets describe its prefix (the phases keep the order) and
-        are passed on, unless use_offsets is False."""
+        are passed on, unless use_offsets is False.  With gather the order
+        is only recorded (usp_bin_gather): do_moments and update then read
+        through it, and update writes the new state to the other buffer."""
         prev = self.offsets if (use_offsets and self.binned) else None
-        usp_bin(self.grid, self.p, self.p_alt, self.offsets, self.ws, self.counters, stream,
-                in_offsets=prev)
-        self.cur = 1 - self.cur
+        if gather:
+            usp_bin_gather(self.grid, self.p, self.p_alt, self.offsets, self.perm, self.ws,
+                           self.counters, stream, in_offsets=prev)
+            self.gathered = True
+        else:
+            usp_bin(self.grid, self.p, self.p_alt, self.offsets, self.ws, self.counters, stream,
+                    in_offsets=prev)
+            self.cur = 1 - self.cur
         self.binned = True
 
     def do_moments(self, stream=None):
-        usp_moments(self.grid, self.p, self.offsets, self.mom, stream)
+        if self.gathered:
+            usp_moments_gather(self.grid, self.p, self.perm, self.offsets, self.mom, stream)
+        else:
+            usp_moments(self.grid, self.p, self.offsets, self.mom, stream)
 
     def do_reconstruct(self, stream=None):
         usp_reconstruct(self.grid, self.gas, self.mom, self.prob.dt, self.dt_cell, self.cs,
                         self.counters, stream)
 
     def collide(self, step, stream=None):
+        self._not_gathered("collide")
         usp_collide(self.grid, self.gas, self.cs, self.offsets, self.p, self.prob.seed, step,
                     self.counters, stream)
 
     def conserve(self, step, stream=None):
+        self._not_gathered("conserve")
         usp_conserve(self.grid, self.gas, self.cs, self.offsets, self.p, self.prob.seed, step,
                      self.counters, stream)
 
     def advect(self, step, stream=None):
+        self._not_gathered("advect")
         usp_advect(self.grid, self.gas, self.bc, self.prob.dt, self.p, self.prob.seed, step,
                    self.ws, self.counters, stream)
 
     def update(self, step, stream=None):
-        """collide + conserve + advect in one fused pass (binned state)."""
-        usp_update(self.grid, self.gas, self.bc if self.dim >= 1 else None, self.prob.dt, self.cs,
-                   self.offsets, self.p, self.prob.seed, step, self.ws, self.counters, stream)
+        """collide + conserve + advect in one fused pass (binned state, or
+        the recorded order of a gathering bin)."""
+        bc = self.bc if self.dim >= 1 else None
+        if self.gathered:
+            usp_update_gather(self.grid, self.gas, bc, self.prob.dt, self.cs, self.offsets, self.p,
+                              self.perm, self.p_alt, self.prob.seed, step, self.ws, self.counters,
+                              stream)
+            self.cur = 1 - self.cur
+            self.gathered = False
+            return
+        usp_update(self.grid, self.gas, bc, self.prob.dt, self.cs, self.offsets, self.p,
+                   self.prob.seed, step, self.ws, self.counters, stream)
+
+    def _not_gathered(self, what):
+        if self.gathered:
+            raise UspError(f"{what}: the state is between a gathering bin and its update")
 
     def step(self, step, nsteps=1, stream=None):
+        self._not_gathered("step")
         a, b = self.bufs[self.cur]["struct"], self.bufs[1 - self.cur]["struct"]
         usp_step(self.grid, self.gas, self.bc if self.dim >= 1 else None, self.prob.dt,
                  self.dt_cell, a, b, self.offsets, self.mom, self.cs, self.ws, self.prob.seed,

@@ -122,3 +122,29 @@ def test_cylinder_drag_and_coefficients():
     assert co["theta_deg"][0] == pytest.approx(180.0 / nb / 2)
     # windward elements carry the largest pressure
     assert np.argmax(co["C_p"]) == 0
+
+
+def test_surface_elements_of_the_half_body_cylinder():
+    """The cylinder workload (half body on the symmetry plane y = 0): the
+    element order and areas, one half in the domain, and the mirror half
+    added to the force (drag doubled, lift cancelled)."""
+    prob = W.cylinder(scale=0.05, f32=True)
+    g, bc = prob.grid, prob.bc
+    nb = 18
+    el = sampling.surface_elements(g, bc, nb)
+    assert el["halves"] == 1
+    k = el["kind"]
+    assert list(np.bincount(k, minlength=5)) == [g.nx, g.nx, g.ny, g.ny, nb]
+    assert np.allclose(el["area"][:g.nx], g.dx * bc.depth)
+    assert np.allclose(el["area"][2 * g.nx:2 * g.nx + g.ny], g.dy * bc.depth)
+    assert np.allclose(el["area"][-nb:], bc.cyl_r * np.pi / nb * bc.depth)
+    assert np.allclose(np.degrees(el["coord"][-nb:]), (np.arange(nb) + 0.5) * 10.0)
+    # one hit on the first body element, 1 m/s of x momentum and 2 of y
+    surf = np.zeros((k.size, sampling.SURF_NQ), np.int64)
+    e = 2 * g.nx + 2 * g.ny
+    surf[e, sampling.SURF_HITS] = 1
+    surf[e, sampling.SURF_PX] = int(sampling.SURF_P_SCALE)
+    surf[e, sampling.SURF_PY] = int(2 * sampling.SURF_P_SCALE)
+    fl = sampling.surface_fluxes(surf, g, bc, nb, 1.0, 1.0, 3371.0, 1.0)
+    assert fl["body_force"][0] == pytest.approx(2.0 / bc.depth)
+    assert fl["body_force"][1] == 0.0

@@ -15,12 +15,20 @@ namespace usp {
 //   sum |C|^2 C_i = S3_i - m_i tr S - 2 (S m)_i + 2 N |m|^2 m_i,
 //   sum C_i e = S_ie - m_i sum e.
 // FP64 sums reduced by a fixed butterfly (deterministic).
+struct MomIn {
+  double c0, c1, c2, e, I;
+};
+
 template <typename PS>
-__device__ __forceinline__ void mom_add(const PS* cx, const PS* cy, const PS* cz, const PS* er,
-                                        const uint8_t* vb, int64_t i, double r0, double r1,
-                                        double r2, double* s) {
-  const double d0 = (double)cx[i] - r0, d1 = (double)cy[i] - r1, d2 = (double)cz[i] - r2;
-  const double e = (double)er[i], I = (double)vb[i];
+__device__ __forceinline__ MomIn mom_load(const PS* cx, const PS* cy, const PS* cz, const PS* er,
+                                          const uint8_t* vb, int64_t i) {
+  return MomIn{(double)cx[i], (double)cy[i], (double)cz[i], (double)er[i], (double)vb[i]};
+}
+
+__device__ __forceinline__ void mom_add(const MomIn& a, double r0, double r1, double r2,
+                                        double* s) {
+  const double d0 = a.c0 - r0, d1 = a.c1 - r1, d2 = a.c2 - r2;
+  const double e = a.e, I = a.I;
   const double q = d0 * d0 + d1 * d1 + d2 * d2;
   s[0] += d0; s[1] += d1; s[2] += d2;
   s[3] += d0 * d0; s[4] += d1 * d1; s[5] += d2 * d2;
@@ -54,12 +62,20 @@ __device__ __forceinline__ void row_moments(const PS* cx, const PS* cy, const PS
   double s[20];
 #pragma unroll
   for (int k = 0; k < 20; ++k) s[k] = 0.0;
+  // a lane takes i, i + 16, i + 32, ... in order; four at a time (all
+  // loads issued before the sums), then the rest one at a time
   int64_t i = o0 + sub;
-  for (; i + MOM_LANES < o1; i += 2 * MOM_LANES) {
-    mom_add<PS>(cx, cy, cz, er, vb, at(i), r0, r1, r2, s);
-    mom_add<PS>(cx, cy, cz, er, vb, at(i + MOM_LANES), r0, r1, r2, s);
+  for (; i + 3 * MOM_LANES < o1; i += 4 * MOM_LANES) {
+    int64_t j[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) j[k] = at(i + k * MOM_LANES);
+    MomIn a[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] = mom_load<PS>(cx, cy, cz, er, vb, j[k]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) mom_add(a[k], r0, r1, r2, s);
   }
-  if (i < o1) mom_add<PS>(cx, cy, cz, er, vb, at(i), r0, r1, r2, s);
+  for (; i < o1; i += MOM_LANES) mom_add(mom_load<PS>(cx, cy, cz, er, vb, at(i)), r0, r1, r2, s);
 #pragma unroll
   for (int k = 0; k < 20; ++k) s[k] = row16_sum(s[k]);
   if (N == 0) {

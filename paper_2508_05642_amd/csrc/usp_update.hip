@@ -73,17 +73,44 @@ __device__ __forceinline__ void tile_pass(const GridP& g, const GasP& gas, const
 
 // Gather prologue of a tile (G): slot i takes particle perm[i] of src;
 // velocities, rotational energy and level go to the stage, positions and
-// ids to p (p's cells were set by the gathering bin).
+// ids to p (p's cells were set by the gathering bin).  Each thread loads
+// GATHER_U slots' indices, then all their fields, then stores them, so
+// that many scattered loads are in flight at once.
+constexpr int GATHER_U = 4;
+
 template <typename S>
 __device__ __forceinline__ void tile_gather(const GridP& g, const PartP<S>& src,
                                             const uint32_t* __restrict__ perm, const PartP<S>& p,
                                             int64_t i0, int64_t i1, const Stage<S>& st) {
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += UPD_BLOCK) {
-    const int64_t j = perm[i];
-    st.store(i, load_state(src, j));
-    if (g.dim == 2) p.x[i] = src.x[j];
-    if (g.dim >= 1) p.y[i] = src.y[j];
-    p.pid[i] = src.pid[j];
+  for (int64_t b = i0 + threadIdx.x; b < i1; b += GATHER_U * UPD_BLOCK) {
+    uint32_t j[GATHER_U];
+#pragma unroll
+    for (int k = 0; k < GATHER_U; ++k) {
+      const int64_t i = b + k * UPD_BLOCK;
+      j[k] = i < i1 ? perm[i] : 0u;
+    }
+    PartNew<S> v[GATHER_U];
+    S xs[GATHER_U], ys[GATHER_U];
+    uint32_t id[GATHER_U];
+#pragma unroll
+    for (int k = 0; k < GATHER_U; ++k) {
+      if (b + k * UPD_BLOCK < i1) {
+        v[k] = load_state(src, j[k]);
+        xs[k] = g.dim == 2 ? src.x[j[k]] : S(0);
+        ys[k] = g.dim >= 1 ? src.y[j[k]] : S(0);
+        id[k] = src.pid[j[k]];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < GATHER_U; ++k) {
+      const int64_t i = b + k * UPD_BLOCK;
+      if (i < i1) {
+        st.store(i, v[k]);
+        if (g.dim == 2) p.x[i] = xs[k];
+        if (g.dim >= 1) p.y[i] = ys[k];
+        p.pid[i] = id[k];
+      }
+    }
   }
   __syncthreads();
 }

@@ -21,7 +21,11 @@ __device__ __forceinline__ void batch_tile(const GridP& g, const GasP& gas, doub
                                            const PartP<S>& p, int64_t c0, int64_t c1,
                                            int64_t i0, int64_t i1, const Stage<S>& st,
                                            uint16_t* esc_list, int* nesc, uint64_t seed,
-                                           uint64_t step0, int nsteps, int64_t* counters) {
+                                           uint64_t step0, int nsteps, int64_t* counters,
+                                           unsigned long long* wcnt) {
+  // per-particle events of the update go to the workgroup's counts, which
+  // are added to the global counters after every step
+  const WgCounters wc{counters ? wcnt : nullptr};
   if (STAGED) {
     for (int64_t i = i0 + threadIdx.x; i < i1; i += UPD_BLOCK) st.store(i, load_state(p, i));
     __syncthreads();
@@ -31,9 +35,10 @@ __device__ __forceinline__ void batch_tile(const GridP& g, const GasP& gas, doub
     tile_cells<S>(g, gas, dt, dt_cell, mom, cs, offsets, c0, c1, st, counters);
     __syncthreads();
     tile_update<S, CAP, true, FPM>(g, gas, cs, p, i0, i1, st, st, esc_list, nesc, seed, step,
-                                   counters);
+                                   wc);
     tile_conserve<S>(gas, cs, g.M, offsets, c0, c1, st, seed, step, counters);
     __syncthreads();
+    wg_counters_flush(wcnt, counters);
   }
   if (STAGED) {
     for (int64_t i = i0 + threadIdx.x; i < i1; i += UPD_BLOCK) {
@@ -58,18 +63,20 @@ __global__ __launch_bounds__(UPD_BLOCK, WPE) void k_batch(GridP g, GasP gas, dou
   __shared__ uint8_t svb[CAP];
   __shared__ uint16_t esc_list[CAP];
   __shared__ int nesc;
+  __shared__ unsigned long long wcnt[USP_NCOUNTERS];
   const int64_t t = blockIdx.x;
   const int64_t c0 = first[t], c1 = first[t + 1];
   if (c0 >= c1) return;
   const int64_t i0 = offsets[c0], i1 = offsets[c1];
+  wg_counters_init(wcnt);  // ordered before use by the barriers ahead of the first update
   if (i1 - i0 <= CAP) {
     Stage<S> st;
     st.cx = scx; st.cy = scy; st.cz = scz; st.erot = ser; st.vib = svb; st.base = i0;
     batch_tile<S, true, CAP, FPM>(g, gas, dt, dt_cell, mom, cs, offsets, p, c0, c1, i0, i1, st,
-                             esc_list, &nesc, seed, step0, nsteps, counters);
+                             esc_list, &nesc, seed, step0, nsteps, counters, wcnt);
   } else {
     batch_tile<S, false, CAP, FPM>(g, gas, dt, dt_cell, mom, cs, offsets, p, c0, c1, i0, i1,
-                              global_stage(p), esc_list, &nesc, seed, step0, nsteps, counters);
+                              global_stage(p), esc_list, &nesc, seed, step0, nsteps, counters, wcnt);
   }
 }
 

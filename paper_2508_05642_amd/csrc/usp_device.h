@@ -221,6 +221,16 @@ __device__ __forceinline__ int32_t cell_of(const GridP& g, S x, S y) {
   return iy * g.nx + ix;
 }
 
+extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_or_u32(unsigned int);
+
+// Event bits that name a counter (bit k: counter k).
+constexpr uint32_t EVENT_MASK = USP_NCOUNTERS >= 32 ? 0xFFFFFFFFu : ((1u << USP_NCOUNTERS) - 1u);
+
+// Bitwise OR of v over the active lanes of the wave, as a wave-uniform value.
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)__ockl_wfred_or_u32(v));
+}
+
 // 64-bit event counter
 __device__ __forceinline__ void count_event(int64_t* counters, int k, int64_t v = 1) {
   if (counters) atomicAdd((unsigned long long*)&counters[k], (unsigned long long)v);
@@ -236,14 +246,55 @@ __device__ __forceinline__ void flush_events(int64_t* counters, uint32_t ev, int
   const uint64_t active = __ballot(1);
   const int leader = __ffsll((long long)active) - 1;
   if (!__ballot(ev != 0u || extra != 0)) return;
-  for (int k = 0; k < USP_NCOUNTERS; ++k) {
+  for (uint32_t rest = wave_or(ev) & EVENT_MASK; rest; rest &= rest - 1u) {
+    const int k = __builtin_ctz(rest);
     const uint64_t m = __ballot((ev >> k) & 1u);
-    if (m && lane == leader) atomicAdd((unsigned long long*)&counters[k], (unsigned long long)__popcll(m));
+    if (lane == leader) atomicAdd((unsigned long long*)&counters[k], (unsigned long long)__popcll(m));
   }
   if (extra_k >= 0) {
     unsigned long long tot = 0;
     for (int b = 0; b < 4; ++b) tot += (unsigned long long)__popcll(__ballot((extra >> b) & 1)) << b;
     if (tot && lane == leader) atomicAdd((unsigned long long*)&counters[extra_k], tot);
+  }
+}
+
+// A workgroup's event counts in LDS (c == nullptr when no counters are
+// kept): flush_events adds to them with LDS atomics, and the workgroup adds
+// them to the global counters after its last barrier.
+struct WgCounters {
+  unsigned long long* c;
+};
+
+__device__ __forceinline__ void flush_events(WgCounters w, uint32_t ev, int extra_k = -1,
+                                             int extra = 0) {
+  if (!w.c) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t active = __ballot(1);
+  const int leader = __ffsll((long long)active) - 1;
+  if (!__ballot(ev != 0u || extra != 0)) return;
+  for (uint32_t rest = wave_or(ev) & EVENT_MASK; rest; rest &= rest - 1u) {
+    const int k = __builtin_ctz(rest);
+    const uint64_t m = __ballot((ev >> k) & 1u);
+    if (lane == leader) atomicAdd(&w.c[k], (unsigned long long)__popcll(m));
+  }
+  if (extra_k >= 0) {
+    unsigned long long tot = 0;
+    for (int b = 0; b < 4; ++b) tot += (unsigned long long)__popcll(__ballot((extra >> b) & 1)) << b;
+    if (tot && lane == leader) atomicAdd(&w.c[extra_k], tot);
+  }
+}
+
+// Zero the workgroup's counts (before a barrier that precedes their use).
+__device__ __forceinline__ void wg_counters_init(unsigned long long* c) {
+  if (threadIdx.x < USP_NCOUNTERS) c[threadIdx.x] = 0ull;
+}
+
+// Add the workgroup's counts to the global counters and zero them (after a
+// barrier that follows their last use; the next use must follow another).
+__device__ __forceinline__ void wg_counters_flush(unsigned long long* c, int64_t* counters) {
+  if (counters && threadIdx.x < USP_NCOUNTERS && c[threadIdx.x]) {
+    atomicAdd((unsigned long long*)&counters[threadIdx.x], c[threadIdx.x]);
+    c[threadIdx.x] = 0ull;
   }
 }
 

@@ -855,11 +855,11 @@ __device__ __forceinline__ void surf_record(const GridP& g, const BcP& bc, int s
   atomicAdd(a + USP_SURF_QVIB, (unsigned long long)(long long)(lvi - lvo));
 }
 
-template <typename S>
+template <typename S, typename CNT>
 __device__ __forceinline__ void advect_one(const GridP& g, const GasP& gas, const BcP& bc,
                                            double dt, const PartP<S>& p, int64_t i, S cx0, S cy0,
                                            S cz0, S er0, int lv0, uint64_t seed, uint32_t step,
-                                           int64_t* counters) {
+                                           CNT counters) {
   // body-force kick, rounded to storage as the state is, then the flight
   double cx = (double)(S)((double)cx0 + bc.g[0] * dt);
   double cy = (double)(S)((double)cy0 + bc.g[1] * dt);

@@ -81,12 +81,12 @@ __device__ __forceinline__ PartNew<double> update_second(const GridP&, const Gas
 // chunks of CAP particles: first pass thread per particle; the particles
 // it lists (esc_list/nesc, LDS) get the second pass.  Positions and ids
 // are read from p.
-template <typename S, int CAP, bool SAME, bool FPM>
+template <typename S, int CAP, bool SAME, bool FPM, typename CNT>
 __device__ __forceinline__ void tile_update(const GridP& g, const GasP& gas,
                                             const double* __restrict__ cs, const PartP<S>& p,
                                             int64_t i0, int64_t i1, const Stage<S>& src,
                                             const Stage<S>& dst, uint16_t* esc_list, int* nesc,
-                                            uint64_t seed, uint32_t step, int64_t* counters) {
+                                            uint64_t seed, uint32_t step, CNT counters) {
   for (int64_t cb = i0; cb < i1; cb += CAP) {
     const int64_t ce = cb + CAP < i1 ? cb + CAP : i1;
     if (threadIdx.x == 0) *nesc = 0;

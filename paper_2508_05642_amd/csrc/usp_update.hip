@@ -49,14 +49,14 @@ __device__ __forceinline__ void tile_pass(const GridP& g, const GasP& gas, const
                                           int64_t c0, int64_t c1, int64_t i0, int64_t i1,
                                           const Stage<S>& st, uint16_t* esc_list, int* nesc,
                                           uint64_t seed, uint32_t step, bool advect,
-                                          int64_t* counters) {
-  // A: particle update, global inputs into the stage (or in place)
+                                          int64_t* counters, WgCounters wc) {
+  // A: particle update, global inputs into the stage (or in place); the
+  // per-particle events of A and C go to the workgroup's counts
   if constexpr (G && STAGED)
-    tile_update<S, CAP, true, FPM>(g, gas, cs, p, i0, i1, st, st, esc_list, nesc, seed, step,
-                                   counters);
+    tile_update<S, CAP, true, FPM>(g, gas, cs, p, i0, i1, st, st, esc_list, nesc, seed, step, wc);
   else
     tile_update<S, CAP, !STAGED, FPM>(g, gas, cs, p, i0, i1, global_stage(p), st, esc_list, nesc,
-                                      seed, step, counters);
+                                      seed, step, wc);
   // B: conservation, wave per cell
   tile_conserve<S>(gas, cs, g.M, offsets, c0, c1, st, seed, step, counters);
   __syncthreads();
@@ -64,7 +64,7 @@ __device__ __forceinline__ void tile_pass(const GridP& g, const GasP& gas, const
   for (int64_t i = i0 + threadIdx.x; i < i1; i += UPD_BLOCK) {
     const PartNew<S> v = st.load(i);
     if (advect && p.cell[i] >= 0) {
-      advect_one<S>(g, gas, bc, dt, p, i, v.cx, v.cy, v.cz, v.erot, v.vib, seed, step, counters);
+      advect_one<S>(g, gas, bc, dt, p, i, v.cx, v.cy, v.cz, v.erot, v.vib, seed, step, wc);
     } else if (STAGED) {
       p.cx[i] = v.cx; p.cy[i] = v.cy; p.cz[i] = v.cz; p.erot[i] = v.erot; p.vib[i] = (uint8_t)v.vib;
     }
@@ -128,22 +128,27 @@ __global__ __launch_bounds__(UPD_BLOCK, 4) void k_update(GridP g, GasP gas, BcP 
   __shared__ uint8_t svb[CAP];
   __shared__ uint16_t esc_list[CAP];
   __shared__ int nesc;
+  __shared__ unsigned long long wcnt[USP_NCOUNTERS];
   const int64_t t = blockIdx.x;
   const int64_t c0 = first[t], c1 = first[t + 1];
   if (c0 >= c1) return;
   const int64_t i0 = offsets[c0], i1 = offsets[c1];
+  wg_counters_init(wcnt);  // ordered before use by the first barrier of A
+  const WgCounters wc{counters ? wcnt : nullptr};
   if (i1 - i0 <= CAP) {
     Stage<S> st;
     st.cx = scx; st.cy = scy; st.cz = scz; st.erot = ser; st.vib = svb; st.base = i0;
     if constexpr (G) tile_gather<S>(g, src, perm, p, i0, i1, st);
     tile_pass<S, true, CAP, FPM, G>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1, st, esc_list,
-                                    &nesc, seed, step, advect != 0, counters);
+                                    &nesc, seed, step, advect != 0, counters, wc);
   } else {
     if constexpr (G) tile_gather<S>(g, src, perm, p, i0, i1, global_stage(p));
     tile_pass<S, false, CAP, FPM, G>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1,
                                      global_stage(p), esc_list, &nesc, seed, step, advect != 0,
-                                     counters);
+                                     counters, wc);
   }
+  __syncthreads();
+  wg_counters_flush(wcnt, counters);
 }
 
 hipError_t launch_tiles(const int64_t* offsets, int64_t M, int64_t T, int64_t ntiles,

@@ -821,3 +821,48 @@ def test_gather_pipeline_equals_copy(kind, f32):
             if isinstance(sa[k], np.ndarray):
                 assert np.array_equal(sa[k], sb[k]), (s, k)
         assert a.cnt() == b.cnt()
+
+
+@pytest.mark.parametrize("f32", [True, False])
+def test_gather_pipeline_large_cell(f32):
+    """The gathering pipeline on a tile larger than the LDS stage (one cell
+    of 9000 particles: the update gathers into the new state's arrays and
+    runs its phases there) gives the bits of the copying pipeline, over two
+    steps."""
+    usp = _usp()
+    grid = W.Grid(dim=2, nx=4, ny=3, x0=0.0, y0=0.0, dx=1e-3, dy=1e-3, fnum=1e9,
+                  volume=np.full(12, 1e-6), flags=np.zeros(12, np.uint8))
+    prob = W.Problem("big", W.Gas(), grid, W.BC(), dt=2e-8, seed=4, f32=f32)
+    rng = np.random.default_rng(12)
+    n = 12000
+    x = rng.random(n) * 4e-3
+    y = rng.random(n) * 3e-3
+    x[:9000] = 1e-3 + 0.999e-3 * rng.random(9000)
+    y[:9000] = 1e-3 + 0.999e-3 * rng.random(9000)
+    order = rng.permutation(n)
+    fdt = np.float32 if f32 else np.float64
+    sig = math.sqrt(prob.gas.R * 800.0)
+    parts = dict(n=n, cap=n + 4096, x=x[order].astype(fdt), y=y[order].astype(fdt),
+                 cx=(sig * rng.standard_normal(n) + 300.0).astype(fdt),
+                 cy=(sig * rng.standard_normal(n)).astype(fdt),
+                 cz=(sig * rng.standard_normal(n)).astype(fdt),
+                 erot=(prob.gas.R * 500.0 * rng.exponential(size=n)).astype(fdt),
+                 vib=rng.integers(0, 3, n).astype(np.int32), cell=np.zeros(n, np.int32),
+                 pid=np.arange(n, dtype=np.uint32), next_pid=n)
+    _say(f"[gather-large] f32={f32} n={n}")
+    a = usp.DeviceState(prob, parts)
+    b = usp.DeviceState(prob, parts)
+    for s in (3, 4):
+        a.bin(); b.bin(gather=True)
+        a.do_moments(); b.do_moments()
+        assert torch.equal(a.mom, b.mom), s
+        assert int(a.offsets[6] - a.offsets[5]) > 8000
+        a.do_reconstruct(); b.do_reconstruct()
+        a.update(s); b.update(s)
+        torch.cuda.synchronize()
+        sa, sb = a.state(), b.state()
+        assert sa["n"] == sb["n"] and sa["next_pid"] == sb["next_pid"]
+        for k in sa:
+            if isinstance(sa[k], np.ndarray):
+                assert np.array_equal(sa[k], sb[k]), (s, k)
+        assert a.cnt() == b.cnt()

@@ -78,7 +78,7 @@ WsLayout ws_layout(int64_t M, int64_t capacity, int nfaces) {
   L.face_cnt = o; o = align256(o + sizeof(int32_t) * (size_t)(nfaces + 1));
   L.face_off = o; o = align256(o + sizeof(int64_t) * (size_t)(nfaces + 1));
   L.misc = o; o = align256(o + sizeof(int64_t) * 8);
-  L.tiles = o; o = align256(o + sizeof(int32_t) * (size_t)(cdiv(capacity, UPDATE_TILE_F64) + 2));
+  L.tiles = o; o = align256(o + sizeof(int32_t) * (size_t)(cdiv(capacity, UPDATE_TILE_MIN) + 2));
   L.total = o;
   return L;
 }

@@ -104,9 +104,11 @@ struct WsLayout {
   size_t key, perm, blocksums, t9, cell_i32, old_off, far_off, far, face_cnt, face_off, misc,
       tiles, total;
 };
-// particle slots per tile of the fused particle phase (FP32 / FP64 state)
-constexpr int UPDATE_TILE_F32 = 1024;
-constexpr int UPDATE_TILE_F64 = 512;
+// LDS stage of the fused particle phase, in particle slots (FP32 / FP64
+// state), and the smallest tile window (the tile index array is sized for it)
+constexpr int UPDATE_STAGE_F32 = 2048;
+constexpr int UPDATE_STAGE_F64 = 1024;
+constexpr int UPDATE_TILE_MIN = 128;
 WsLayout ws_layout(int64_t M, int64_t capacity, int nfaces);
 int n_faces(const GridP& g);
 
@@ -161,5 +163,19 @@ hipError_t launch_batch(const GridP& g, const GasP& gas, double dt, const double
                         hipStream_t st);
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Tile window of the fused particle phase: a tile holds the cells whose
+// first particle lies in one window, so it spans the window plus the part
+// of its last cell past the window's end.  The window is the stage less
+// 1.25x the mean slots per cell (capacity / M), kept within [stage/8,
+// 7 stage/8], so that most tiles fit the stage.
+inline int64_t update_tile(int stage, int64_t capacity, int64_t M) {
+  const int64_t ppc = M > 0 ? cdiv(capacity, M) : stage;
+  int64_t t = stage - ppc - ppc / 4;
+  const int64_t lo = stage / 8, hi = stage - stage / 8;
+  if (t < lo) t = lo;
+  if (t > hi) t = hi;
+  return t < UPDATE_TILE_MIN ? UPDATE_TILE_MIN : t;
+}
 
 }  // namespace usp

@@ -3,8 +3,10 @@
 // (Sec. IV.C) and the free flight with boundaries.
 //
 // A workgroup owns a tile: the cells whose first particle lies in one
-// window of TILE particle slots (so whole cells, ~TILE particles).  Three
-// phases separated by workgroup barriers:
+// window of particle slots (so whole cells; the window is sized from the
+// mean slots per cell by update_tile).  A gathering launch first loads the
+// tile's particles through the bin's permutation.  Three phases separated
+// by workgroup barriers:
 //   A  particle update, one thread per particle, into an LDS stage;
 //   B  conservation, one wave per cell, on the stage;
 //   C  free flight, one thread per particle, from the stage; the state is
@@ -18,8 +20,8 @@
 namespace usp {
 
 template <typename S> struct UpdCfg;
-template <> struct UpdCfg<float> { static constexpr int TILE = UPDATE_TILE_F32, STAGE = 2048; };
-template <> struct UpdCfg<double> { static constexpr int TILE = UPDATE_TILE_F64, STAGE = 1024; };
+template <> struct UpdCfg<float> { static constexpr int STAGE = UPDATE_STAGE_F32; };
+template <> struct UpdCfg<double> { static constexpr int STAGE = UPDATE_STAGE_F64; };
 
 __global__ void k_fill_first(int32_t* first, int64_t n, int32_t v) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -164,7 +166,7 @@ hipError_t launch_update(const GridP& g, const GasP& gas, const BcP& bc, double 
                          uint64_t seed, uint64_t step, char* ws, const WsLayout& L,
                          int64_t* counters, hipStream_t st, const PartP<S>* src,
                          const uint32_t* gather_perm) {
-  constexpr int T = UpdCfg<S>::TILE;
+  const int64_t T = update_tile(UpdCfg<S>::STAGE, p.capacity, g.M);
   const int64_t ntiles = cdiv(p.capacity, T);
   int32_t* first = (int32_t*)(ws + L.tiles);
   launch_tiles(offsets, g.M, T, ntiles, first, st);

@@ -347,8 +347,10 @@ usp_status usp_advect(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc
    leaves it); particles past offsets[M] are not updated.  cs from
    usp_reconstruct of the same state.  bc and dt > 0 are required for
    dim >= 1; for dim 0 bc may be NULL and dt is unused (no flight).  A
-   workgroup owns the cells whose first particle lies in one window of 1024
-   (FP32) or 512 (FP64) particle slots; tile boundaries go to `ws`.
+   workgroup owns the cells whose first particle lies in one window of
+   particle slots: its LDS stage (2048 FP32 / 1024 FP64 slots) less 1.25x
+   the mean slots per cell (capacity / M), kept within 1/8..7/8 of the
+   stage; tile boundaries go to `ws`.
    Errors: USP_EINVAL for a null or inconsistent argument or a short ws. */
 usp_status usp_update(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
                       const double* cs, const int64_t* offsets, usp_particles* p,

@@ -140,6 +140,54 @@ def _ptr(t):
     return None if t is None else t.data_ptr()
 
 
+def _dev(t, dtype, n, what, optional=False):
+    """Device pointer of tensor t after checking that it is a contiguous
+    tensor on a GPU with the given dtype and at least n elements; raises
+    ValueError before anything is enqueued."""
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{what}: a tensor is required")
+    if not torch.is_tensor(t) or not t.is_cuda:
+        raise ValueError(f"{what}: expected a tensor on a GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: expected a contiguous tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{what}: expected dtype {dtype}, got {t.dtype}")
+    if t.numel() < n:
+        raise ValueError(f"{what}: {t.numel()} elements, at least {n} needed")
+    return t.data_ptr()
+
+
+def _ncells(grid):
+    return int(grid.nx) * int(grid.ny)
+
+
+def _offsets(grid, t, what="offsets", optional=False):
+    return _dev(t, torch.int64, _ncells(grid) + 1, what, optional)
+
+
+def _planes(grid, t, k, what):
+    return _dev(t, torch.float64, k * _ncells(grid), what)
+
+
+def _cs(grid, t):
+    return _dev(t, torch.float64, lib().usp_cellstate_bytes(C.byref(grid)) // 8, "cs")
+
+
+def _ws(t, what="ws"):
+    _dev(t, torch.uint8, 0, what)
+    return t.data_ptr(), t.numel()
+
+
+def _cnt(t):
+    return _dev(t, torch.int64, NCOUNTERS, "counters", optional=True)
+
+
+def _perm(t, p):
+    return _dev(t, torch.int32, int(p.capacity), "perm")
+
+
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
@@ -160,37 +208,39 @@ def make_bc(b, surf=None, surf_nbody=0):
 
 # ---- the seven entry points -------------------------------------------------
 def usp_bin(grid, pin, pout, offsets, ws, counters, stream=None, in_offsets=None):
-    _check(lib().usp_bin(C.byref(grid), C.byref(pin), C.byref(pout), _ptr(offsets),
-                         _ptr(in_offsets), _ptr(ws), ws.numel(), _ptr(counters),
+    _check(lib().usp_bin(C.byref(grid), C.byref(pin), C.byref(pout), _offsets(grid, offsets),
+                         _offsets(grid, in_offsets, "in_offsets", True), *_ws(ws), _cnt(counters),
                          _stream(stream)), "usp_bin")
 
 
 def usp_bin_gather(grid, pin, pout, offsets, perm, ws, counters, stream=None, in_offsets=None):
-    _check(lib().usp_bin_gather(C.byref(grid), C.byref(pin), C.byref(pout), _ptr(offsets),
-                                _ptr(in_offsets), _ptr(perm), _ptr(ws), ws.numel(), _ptr(counters),
-                                _stream(stream)), "usp_bin_gather")
+    _check(lib().usp_bin_gather(C.byref(grid), C.byref(pin), C.byref(pout), _offsets(grid, offsets),
+                                _offsets(grid, in_offsets, "in_offsets", True), _perm(perm, pout),
+                                *_ws(ws), _cnt(counters), _stream(stream)), "usp_bin_gather")
 
 
 def usp_moments_gather(grid, pin, perm, offsets, mom, stream=None):
-    _check(lib().usp_moments_gather(C.byref(grid), C.byref(pin), _ptr(perm), _ptr(offsets),
-                                    _ptr(mom), _stream(stream)), "usp_moments_gather")
+    _check(lib().usp_moments_gather(C.byref(grid), C.byref(pin), _perm(perm, pin),
+                                    _offsets(grid, offsets), _planes(grid, mom, NMOM, "mom"),
+                                    _stream(stream)), "usp_moments_gather")
 
 
 def usp_update_gather(grid, gas, bc, dt, cs, offsets, pin, perm, pout, seed, step, ws, counters,
                       stream=None):
     _check(lib().usp_update_gather(C.byref(grid), C.byref(gas), None if bc is None else C.byref(bc),
-                                   dt, _ptr(cs), _ptr(offsets), C.byref(pin), _ptr(perm),
-                                   C.byref(pout), _ptr(ws), ws.numel(), seed, step, _ptr(counters),
-                                   _stream(stream)), "usp_update_gather")
+                                   dt, _cs(grid, cs), _offsets(grid, offsets), C.byref(pin),
+                                   _perm(perm, pin), C.byref(pout), *_ws(ws), seed, step,
+                                   _cnt(counters), _stream(stream)), "usp_update_gather")
 
 
 def usp_moments(grid, p, offsets, mom, stream=None):
-    _check(lib().usp_moments(C.byref(grid), C.byref(p), _ptr(offsets), _ptr(mom),
-                             _stream(stream)), "usp_moments")
+    _check(lib().usp_moments(C.byref(grid), C.byref(p), _offsets(grid, offsets),
+                             _planes(grid, mom, NMOM, "mom"), _stream(stream)), "usp_moments")
 
 
 def usp_sample_fields(grid, mom, acc, stream=None):
-    _check(lib().usp_sample_fields(C.byref(grid), _ptr(mom), _ptr(acc), _stream(stream)),
+    _check(lib().usp_sample_fields(C.byref(grid), _planes(grid, mom, NMOM, "mom"),
+                                   _planes(grid, acc, NSAMP, "acc"), _stream(stream)),
            "usp_sample_fields")
 
 
@@ -199,36 +249,39 @@ def usp_surf_elements(grid, bc):
 
 
 def usp_reconstruct(grid, gas, mom, dt, dt_cell, cs, counters, stream=None):
-    _check(lib().usp_reconstruct(C.byref(grid), C.byref(gas), _ptr(mom), dt, _ptr(dt_cell),
-                                 _ptr(cs), _ptr(counters), _stream(stream)), "usp_reconstruct")
+    _check(lib().usp_reconstruct(C.byref(grid), C.byref(gas), _planes(grid, mom, NMOM, "mom"), dt,
+                                 _dev(dt_cell, torch.float64, _ncells(grid), "dt_cell", True),
+                                 _cs(grid, cs), _cnt(counters), _stream(stream)), "usp_reconstruct")
 
 
 def usp_collide(grid, gas, cs, offsets, p, seed, step, counters, stream=None):
-    _check(lib().usp_collide(C.byref(grid), C.byref(gas), _ptr(cs), _ptr(offsets), C.byref(p),
-                             seed, step, _ptr(counters), _stream(stream)), "usp_collide")
+    _check(lib().usp_collide(C.byref(grid), C.byref(gas), _cs(grid, cs), _offsets(grid, offsets),
+                             C.byref(p), seed, step, _cnt(counters), _stream(stream)), "usp_collide")
 
 
 def usp_conserve(grid, gas, cs, offsets, p, seed, step, counters, stream=None):
-    _check(lib().usp_conserve(C.byref(grid), C.byref(gas), _ptr(cs), _ptr(offsets), C.byref(p),
-                              seed, step, _ptr(counters), _stream(stream)), "usp_conserve")
+    _check(lib().usp_conserve(C.byref(grid), C.byref(gas), _cs(grid, cs), _offsets(grid, offsets),
+                              C.byref(p), seed, step, _cnt(counters), _stream(stream)), "usp_conserve")
 
 
 def usp_batch(grid, gas, dt, dt_cell, p, offsets, mom, cs, ws, tile, steps_per_launch, seed, step,
               nsteps, counters, stream=None):
-    _check(lib().usp_batch(C.byref(grid), C.byref(gas), dt, _ptr(dt_cell), C.byref(p), _ptr(offsets),
-                           _ptr(mom), _ptr(cs), _ptr(ws), ws.numel(), tile, steps_per_launch, seed,
-                           step, nsteps, _ptr(counters), _stream(stream)), "usp_batch")
+    _check(lib().usp_batch(C.byref(grid), C.byref(gas), dt,
+                           _dev(dt_cell, torch.float64, _ncells(grid), "dt_cell", True), C.byref(p),
+                           _offsets(grid, offsets), _planes(grid, mom, NMOM, "mom"), _cs(grid, cs),
+                           *_ws(ws), tile, steps_per_launch, seed, step, nsteps, _cnt(counters),
+                           _stream(stream)), "usp_batch")
 
 
 def usp_update(grid, gas, bc, dt, cs, offsets, p, seed, step, ws, counters, stream=None):
     _check(lib().usp_update(C.byref(grid), C.byref(gas), None if bc is None else C.byref(bc), dt,
-                            _ptr(cs), _ptr(offsets), C.byref(p), _ptr(ws), ws.numel(), seed, step,
-                            _ptr(counters), _stream(stream)), "usp_update")
+                            _cs(grid, cs), _offsets(grid, offsets), C.byref(p), *_ws(ws), seed,
+                            step, _cnt(counters), _stream(stream)), "usp_update")
 
 
 def usp_advect(grid, gas, bc, dt, p, seed, step, ws, counters, stream=None):
     _check(lib().usp_advect(C.byref(grid), C.byref(gas), C.byref(bc), dt, C.byref(p), seed, step,
-                            _ptr(ws), ws.numel(), _ptr(counters), _stream(stream)), "usp_advect")
+                            *_ws(ws), _cnt(counters), _stream(stream)), "usp_advect")
 
 
 def usp_step(grid, gas, bc, dt, dt_cell, p, p_alt, offsets, mom, cs, ws, seed, step, nsteps,
@@ -237,9 +290,11 @@ def usp_step(grid, gas, bc, dt, dt_cell, p, p_alt, offsets, mom, cs, ws, seed, s
     the library swaps them, so p describes the current state afterwards.
     in_offsets: the segments of an already binned input (usp_bin's)."""
     _check(lib().usp_step(C.byref(grid), C.byref(gas), C.byref(bc) if bc is not None else None,
-                          dt, _ptr(dt_cell), C.byref(p), C.byref(p_alt), _ptr(offsets),
-                          _ptr(in_offsets), _ptr(mom), _ptr(cs), _ptr(ws), ws.numel(), seed, step,
-                          nsteps, _ptr(counters), _stream(stream)), "usp_step")
+                          dt, _dev(dt_cell, torch.float64, _ncells(grid), "dt_cell", True),
+                          C.byref(p), C.byref(p_alt), _offsets(grid, offsets),
+                          _offsets(grid, in_offsets, "in_offsets", True),
+                          _planes(grid, mom, NMOM, "mom"), _cs(grid, cs), *_ws(ws), seed, step,
+                          nsteps, _cnt(counters), _stream(stream)), "usp_step")
 
 
 def usp_step_taped(grid, gas, bc, dt, p, p_alt, offsets, mom, cs, ws, seed, step, tape, aws,
@@ -247,17 +302,21 @@ def usp_step_taped(grid, gas, bc, dt, p, p_alt, offsets, mom, cs, ws, seed, step
     """One step with its tape; p and p_alt are swapped in place as the
     library swaps them."""
     _check(lib().usp_step_taped(C.byref(grid), C.byref(gas), C.byref(bc), dt, C.byref(p),
-                                C.byref(p_alt), _ptr(offsets), _ptr(in_offsets), _ptr(mom),
-                                _ptr(cs), _ptr(ws),
-                                ws.numel(), seed, step, _ptr(tape), tape.numel(), _ptr(aws),
-                                aws.numel(), _ptr(counters), _stream(stream)), "usp_step_taped")
+                                C.byref(p_alt), _offsets(grid, offsets),
+                                _offsets(grid, in_offsets, "in_offsets", True),
+                                _planes(grid, mom, NMOM, "mom"), _cs(grid, cs), *_ws(ws), seed,
+                                step, *_ws(tape, "tape"), *_ws(aws, "aws"), _cnt(counters),
+                                _stream(stream)), "usp_step_taped")
 
 
 def usp_adjoint_step(grid, gas, bc, dt, tape, capacity, seed, step, lam_in, lam_out, w_mdot,
                      w_tau, grad, aws, stream=None):
-    _check(lib().usp_adjoint_step(C.byref(grid), C.byref(gas), C.byref(bc), dt, _ptr(tape),
-                                  tape.numel(), capacity, seed, step, _ptr(lam_in), _ptr(lam_out),
-                                  w_mdot, w_tau, _ptr(grad), _ptr(aws), aws.numel(),
+    nl = 2 * 5 * int(capacity)
+    _check(lib().usp_adjoint_step(C.byref(grid), C.byref(gas), C.byref(bc), dt,
+                                  *_ws(tape, "tape"), capacity, seed, step,
+                                  _dev(lam_in, torch.float64, nl, "lam_in"),
+                                  _dev(lam_out, torch.float64, nl, "lam_out"), w_mdot, w_tau,
+                                  _dev(grad, torch.float64, 6, "grad"), *_ws(aws, "aws"),
                                   _stream(stream)), "usp_adjoint_step")
 
 

@@ -354,6 +354,17 @@ def test_invalid_arguments_rejected_on_host():
         usp.usp_reconstruct(gpu.grid, gpu.gas, gpu.mom, -1.0, None, gpu.cs, gpu.counters)
     with pytest.raises(usp.UspError):
         usp.usp_bin(gpu.grid, gpu.p, gpu.p, gpu.offsets, gpu.ws, gpu.counters)
+    # the binding's own checks: dtype, length, contiguity (nothing enqueued)
+    with pytest.raises(ValueError, match="dtype"):
+        usp.usp_moments(gpu.grid, gpu.p, gpu.offsets.to(torch.int32), gpu.mom)
+    with pytest.raises(ValueError, match="at least"):
+        usp.usp_moments(gpu.grid, gpu.p, gpu.offsets[:-1], gpu.mom)
+    with pytest.raises(ValueError, match="contiguous"):
+        usp.usp_moments(gpu.grid, gpu.p, gpu.offsets, gpu.mom.view(usp.NMOM, -1).t())
+    with pytest.raises(ValueError, match="cs"):
+        usp.usp_collide(gpu.grid, gpu.gas, gpu.cs[:10], gpu.offsets, gpu.p, 0, 0, gpu.counters)
+    with pytest.raises(ValueError, match="perm"):
+        usp.usp_moments_gather(gpu.grid, gpu.p, gpu.perm[:5], gpu.offsets, gpu.mom)
 
 
 @pytest.mark.parametrize("f32", [False, True])

@@ -63,3 +63,23 @@ def test_surface_element_count():
     assert usp.usp_surf_elements(g, b) == 0
     bad = usp.UspGrid(2, 0, 5, 0.0, 0.0, 0.1, 0.1, 1.0, 1, None)
     assert usp.usp_surf_elements(bad, usp.make_bc(W.BC())) == 0
+
+
+def test_binding_rejects_host_tensors_before_any_call():
+    """The Python wrappers check every array argument (a contiguous GPU
+    tensor of the declared dtype and length) and raise ValueError before
+    anything is enqueued; host tensors never reach the library."""
+    import torch
+    from paper_2508_05642_amd import usp
+    g = usp.UspGrid(2, 10, 5, 0.0, 0.0, 0.1, 0.1, 1.0, None, None)
+    M = 50
+    p = usp.UspParticles()
+    host = dict(offsets=torch.zeros(M + 1, dtype=torch.int64),
+                mom=torch.zeros(usp.NMOM * M, dtype=torch.float64))
+    with pytest.raises(ValueError, match="offsets: expected a tensor on a GPU"):
+        usp.usp_moments(g, p, host["offsets"], host["mom"])
+    with pytest.raises(ValueError, match="a tensor is required"):
+        usp.usp_moments(g, p, None, host["mom"])
+    with pytest.raises(ValueError, match="ws: expected a tensor on a GPU"):
+        usp.usp_advect(g, usp.UspGas(), usp.UspBC(), 1e-6, p, 0, 0,
+                       torch.zeros(16, dtype=torch.uint8), None)

@@ -185,6 +185,20 @@ __host__ __device__ inline Nbr nbr_set(const GridP& g) {
 constexpr int GRP_FAR = 9;
 constexpr int GRP_GONE = 15;
 
+// Group of a move by d cells: the index of d in nb.d, else GRP_FAR.  In 2D
+// (nx >= 3) the members are d = r nx + dx with r, dx in {1, 0, -1}, listed
+// as q = 3 (1 - r) + (1 - dx), and r is fixed by the sign of d beyond +-1;
+// in 1D and 0D nb.d counts down by one from nb.d[0].
+__device__ __forceinline__ int nbr_group(const GridP& g, const Nbr& nb, int64_t d) {
+  if (g.dim == 2 && g.nx >= 3) {
+    const int64_t r = d >= 2 ? 1 : (d <= -2 ? -1 : 0);
+    const int64_t dx = d - r * g.nx;
+    return (dx >= -1 && dx <= 1) ? (int)(3 * (1 - r) + (1 - dx)) : GRP_FAR;
+  }
+  const int64_t q = (int64_t)nb.d[0] - d;
+  return (q >= 0 && q < nb.n) ? (int)q : GRP_FAR;
+}
+
 template <typename S>
 __device__ __forceinline__ int32_t new_key(const GridP& g, const PartP<S>& in, int64_t i,
                                            bool* solid) {
@@ -244,21 +258,18 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin_group(GridP g, Nbr nb, PartP<
       bool solid = false;
       if (c >= 0 && g.flags && (g.flags[c] & USP_FLAG_SOLID)) { c = -1; solid = true; }
       if (solid) count_event(counters, USP_CNT_SOLID_DROP);
-      if (c < 0) {
-        grpid = GRP_GONE;
-      } else {
-        const int64_t d = (int64_t)c - k;
-        grpid = GRP_FAR;
-        for (int q = 0; q < nb.n; ++q)
-          if (d == nb.d[q]) grpid = q;
-      }
+      grpid = c < 0 ? GRP_GONE : nbr_group(g, nb, (int64_t)c - k);
     }
+    // ranks within each group present in the wave (the others add nothing)
+    const uint32_t present = wave_or(grpid < 10 ? (1u << grpid) : 0u);
     int rank = 0;
 #pragma unroll
     for (int q = 0; q < 10; ++q) {
-      const uint64_t m = __ballot(grpid == q);
-      if (grpid == q) rank = running[q] + __popcll(m & lt);
-      running[q] += __popcll(m);
+      if (present & (1u << q)) {
+        const uint64_t m = __ballot(grpid == q);
+        if (grpid == q) rank = running[q] + __popcll(m & lt);
+        running[q] += __popcll(m);
+      }
     }
     if (active) grp[i] = (rank << 4) | grpid;
     if (grpid == GRP_FAR) {

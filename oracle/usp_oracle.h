@@ -25,6 +25,19 @@
  *   conservation        Sec. IV.C
  *   step order          Sec. IV.D (collision-step flow chart)
  *   free flight         Sec. II.C (x^{n+1} = x^n + c^n dt)
+ *
+ * Parity unpinned (the paper fixes no value to check these against; only
+ * the GPU/oracle parity tests and the invariants below cover them):
+ *   - orc_collide's positivity refit (Sec. III.A.3): which nu and alpha the
+ *     fallback picks is checked only by "Lambda is positive definite after
+ *     it and the update stays finite";
+ *   - orc_conserve's order of the vibrational picks (which particle gets a
+ *     level step, draw by draw): the total I_delta and the level bounds are
+ *     pinned, the choice of particles is not;
+ *   - orc_interp's rule at boundaries and solid cells (which neighbour a
+ *     quadrant stencil falls back to): pinned only by exactness on bilinear
+ *     fields where the whole stencil exists and on linear fields next to an
+ *     unusable cell.
  */
 #ifndef USP_ORACLE_H
 #define USP_ORACLE_H

@@ -877,3 +877,57 @@ def test_gather_pipeline_large_cell(f32):
             if isinstance(sa[k], np.ndarray):
                 assert np.array_equal(sa[k], sb[k]), (s, k)
         assert a.cnt() == b.cnt()
+
+
+def test_cylinder_full_size_bench_launch():
+    """The cylinder workload at full size (600 x 300 cells, ~36M particles,
+    FP32 state) in the launch configuration the benchmark times: gathering
+    bin, gathered moments, cell state, gathered fused update.  Two steps
+    from the initial state against the oracle's steps of the same input (the
+    oracle restarts the second step from the GPU's state): the first bin
+    takes the tail path, the second the fast neighbour-group route.  Every
+    particle and cell is compared: the new order bit for bit (offsets and
+    the pid order through the permutation), moments and cell state to the
+    small cases' bars, the stepped particles to the FP32 bar, the event
+    counters exactly."""
+    usp = _usp()
+    prob = W.cylinder(scale=1.0, f32=True)
+    parts = W.particles_for(prob)
+    _say(f"[cylinder-full] n={parts['n']} cells={prob.grid.ncells}")
+    st = usp.DeviceState(prob, parts)
+    orc = oracle.Sim(prob, parts)
+    for step in (0, 1):
+        pid_in = st.state()["pid"]
+        st.bin(gather=True)
+        orc.bin()
+        torch.cuda.synchronize()
+        go = st.offsets.cpu().numpy()
+        assert np.array_equal(go, orc.offsets), step
+        n = int(go[-1])
+        perm = st.perm[:n].cpu().numpy().view(np.uint32)
+        assert np.array_equal(pid_in[perm], orc.state()["pid"][:n]), step
+        st.do_moments()
+        orc.do_moments()
+        gm, om = st.moments(), orc.moments()
+        sc = _mom_scales(prob, om)
+        worst = max(float((np.abs(gm[k] - om[k]) / sc[name]).max())
+                    for k, name in enumerate(oracle.MOM_NAMES))
+        st.do_reconstruct()
+        orc.do_cellstate()
+        gc, oc = st.cellstate(), orc.cellstate()
+        wcs = 0.0
+        for k in range(len(oracle.CS_NAMES)):
+            fs = np.max(np.abs(oc[k])) + 1e-300
+            wcs = max(wcs, float((np.abs(gc[k] - oc[k]) / (np.abs(oc[k]) + 1e-6 * fs)).max()))
+        _say(f"  step {step}: moments {worst:.3e}, cell state {wcs:.3e}")
+        assert worst < 1e-10 and wcs < 1e-9, (step, worst, wcs)
+        st.update(step)
+        orc.collide(step)
+        orc.conserve(step)
+        orc.advect(step)
+        torch.cuda.synchronize()
+        a, b = st.state(), orc.state()
+        compare_states(a, b, prob, vel_scale(prob, orc), _tol(True), f"full-size step {step}")
+        assert st.cnt() == orc.cnt(), step
+        if step == 0:
+            load_into_oracle(orc, a)

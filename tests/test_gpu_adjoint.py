@@ -104,3 +104,21 @@ def test_autograd_function_contracts_the_jacobian():
     adj.forward(2)
     G = adj.backward().cpu()
     assert torch.allclose(theta.grad, w @ G, rtol=1e-12, atol=0.0)
+
+
+def test_adjoint_full_size_two_segments():
+    """The benchmarked case at full size (Poiseuille Kn 0.05, 100 cells x 500
+    particles, FP64, a checkpoint every 32 steps) over 40 steps from its
+    initial state: two segments, so the reverse pass restores a checkpoint
+    and re-runs it.  Outputs and gradient against the oracle's autograd
+    gradient of the same path."""
+    from paper_2508_05642_amd.adjoint import PathwiseAdjoint
+    prob = W.poiseuille(kn=0.05, cells=100, ppc=500, f32=False, seed=7)
+    parts = W.particles_for(prob)
+    K = 40
+    _say(f"[adjoint-full] cells={prob.grid.ny} n={parts['n']} K={K} segment=32")
+    Jo, Go = A.Path(A.Record(prob, parts, 0, K)).gradient()
+    adj = PathwiseAdjoint(prob, parts, K, 32)
+    J = adj.forward(0).cpu().numpy()
+    G = adj.backward().cpu().numpy()
+    _compare(J, G, Jo, Go, f"full size K={K}")

@@ -129,6 +129,9 @@ def run_gpu(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     prob = W.cylinder(scale=args.scale, f32=True)
+    if args.scheme == "fpm":
+        import dataclasses
+        prob.gas = dataclasses.replace(prob.gas, scheme=W.SCHEME_FPM)
     parts = W.particles_for(prob)
     n0 = parts["n"]
     log(f"workload ready: {n0} particles, {prob.grid.ncells} cells")
@@ -207,7 +210,8 @@ def run_gpu(args):
            "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(algorithmic_bytes(dom, n_mean, M) / t_dom / 1e9 / HBM_PEAK_GBS, 4),
            "algorithmic_bytes_per_launch": int(algorithmic_bytes(dom, n_mean, M))}
-    ctr = stored_counters(PHASE_KERNEL[dom])
+    # the stored counters are those of the USP-FPM update kernel
+    ctr = stored_counters(PHASE_KERNEL[dom]) if args.scheme == "usp" else None
     if ctr:
         # VALU wave-instructions per particle (PMC, same sources and flags,
         # same steps) x particles per launch / event-timed launch
@@ -232,7 +236,7 @@ def run_gpu(args):
                 "particles_start": int(n0), "particles_mean": int(n_mean), "cells": M,
                 "state": "f32", "accumulation": "f64", "dt_s": prob.dt,
                 "first_timed_step": args.warmup, "sampling": bool(args.sample),
-                "parallelism": "single-gpu"},
+                "scheme": args.scheme, "parallelism": "single-gpu"},
         launch="one HIP graph of the K steps (per-phase times from an eager pass over the same "
                "steps from the same state)",
         eager_ms_per_step=round(wall_eager / K * 1e3, 4),
@@ -490,6 +494,8 @@ def main():
                     help="adjoint: skip the finite-difference runs (profiling)")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--scheme", choices=("usp", "fpm"), default="usp",
+                    help="cylinder: the USP-FPM scheme (default) or the first-order FPM scheme")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()

@@ -500,7 +500,8 @@ def main():
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported",
+        print(f"bench.py: the step runs on one GPU (the multi-GPU split is not implemented); "
+              f"--gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
     if args.calib_copy:

@@ -757,25 +757,30 @@ def _golden_profile(name):
     return T, np.array(U)
 
 
-def test_poiseuille_full_size_statistics():
-    """The Kn = 0.05 channel at full size (200 cells x 1000 particles, FP32
-    state), 6000 steps with the field sums of the last 4000, against the
-    oracle's time average of the same run (tests/golden, written by
-    make_poiseuille_profile.py).  The two trajectories part after a few
-    hundred steps (FP32 rounding order, chaotic dynamics), so what must
-    agree is the statistics: the profile cell by cell within its sampling
-    noise (about 0.35 m/s a cell), the parabola's curvature within 2% of
-    the oracle's, the temperature within 0.5 K, and the profile symmetric.
-    The curvature is also held to the Navier-Stokes value g/(2 nu) with the
-    oracle pin's 8% (both sides sit about 6% above it at this Kn and
-    resolution: the Knudsen layers at the walls are resolved here)."""
+POIS_RUNS = [(0.05, 2000, "poiseuille_kn005_200x1000.txt"),
+             (0.01, 4500, "poiseuille_kn001_200x1000.txt")]
+
+
+@pytest.mark.parametrize("kn,transient,golden", POIS_RUNS)
+def test_poiseuille_full_size_statistics(kn, transient, golden):
+    """The channel at full size (200 cells x 1000 particles, FP32 state) at
+    Kn = 0.05 and 0.01: the transient, then the field sums of 4000 steps,
+    against the oracle's time average of the same run (tests/golden,
+    written by make_poiseuille_profile.py).  The two trajectories part
+    after a few hundred steps (FP32 rounding order, chaotic dynamics), so
+    what must agree is the statistics: the profile cell by cell within its
+    sampling noise (about 0.35 m/s a cell), the parabola's curvature within
+    2% of the oracle's, the temperature within 0.5 K, and the profile
+    symmetric.  The curvature is also held to the Navier-Stokes value
+    g/(2 nu) with the oracle pin's 8%: at Kn = 0.05 both sides sit about 6%
+    above it (the Knudsen layers at the walls are resolved here)."""
     usp = _usp()
-    prob = W.poiseuille(kn=0.05, cells=200, ppc=1000, f32=True)
+    prob = W.poiseuille(kn=kn, cells=200, ppc=1000, f32=True)
     parts = W.particles_for(prob)
-    _say(f"[poiseuille] n={parts['n']} cells={prob.grid.ny}")
+    _say(f"[poiseuille] kn={kn} n={parts['n']} cells={prob.grid.ny}")
     st = usp.DeviceState(prob, parts)
     st.enable_sampling(0)
-    transient, sampled = 2000, 4000
+    sampled = 4000
     st.step(0, transient)
     for s in range(sampled):
         st.step(transient + s, 1)
@@ -787,7 +792,7 @@ def test_poiseuille_full_size_statistics():
     c2 = F[4] + F[5] + F[6]
     cu = (F[1] ** 2 + F[2] ** 2 + F[3] ** 2) / N
     T = (c2 - cu).sum() / N.sum() / (3 * gas.R)
-    To, Uo = _golden_profile("poiseuille_kn005_200x1000.txt")
+    To, Uo = _golden_profile(golden)
     M, L = g.ny, g.ny * g.dy
     assert Uo.size == M
     y = (np.arange(M) + 0.5) * g.dy

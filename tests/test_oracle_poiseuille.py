@@ -5,6 +5,7 @@ g / (2 nu) with nu = mu(T)/rho from the gas model (the method reproduces
 the viscosity it is built from), plus a wall slip of the size of the
 first-order Maxwell slip lambda du/dy at Kn = 0.05.  No GPU."""
 import numpy as np
+import pytest
 
 import oracle
 import usp_workloads as W
@@ -43,13 +44,16 @@ def test_poiseuille_profile_curvature_and_slip():
     assert np.abs(U - U[::-1]).mean() < 0.08 * U.max()
 
 
-def test_stored_full_size_profile():
-    """The stored oracle profile of the full-size channel (200 cells x 1000
-    particles, tests/golden/poiseuille_kn005_200x1000.txt) meets the same
-    continuum pins: NS curvature within 8%, a positive slip of the first-order
-    size, symmetric, T near the wall temperature."""
+@pytest.mark.parametrize("kn,golden,mfp", [(0.05, "poiseuille_kn005_200x1000.txt", 50e-6),
+                                           (0.01, "poiseuille_kn001_200x1000.txt", 10e-6)])
+def test_stored_full_size_profile(kn, golden, mfp):
+    """The stored oracle profiles of the full-size channel (200 cells x 1000
+    particles, tests/golden/) meet the same continuum pins: NS curvature
+    within 8%, a positive slip of the first-order size lambda du/dy (mean
+    free path c_bar tau_c = Kn x gap), symmetric, T near the wall
+    temperature."""
     import os
-    path = os.path.join(os.path.dirname(__file__), "golden", "poiseuille_kn005_200x1000.txt")
+    path = os.path.join(os.path.dirname(__file__), "golden", golden)
     T, U = None, []
     for line in open(path):
         if line.startswith("#") or not line.strip():
@@ -60,7 +64,7 @@ def test_stored_full_size_profile():
         else:
             U.append(float(v))
     U = np.array(U)
-    prob = W.poiseuille(kn=0.05, cells=200, ppc=1000, f32=True)
+    prob = W.poiseuille(kn=kn, cells=200, ppc=1000, f32=True)
     g, gas = prob.grid, prob.gas
     M, L = g.ny, g.ny * g.dy
     assert U.size == M and abs(T - 300.0) < 5.0
@@ -71,6 +75,6 @@ def test_stored_full_size_profile():
     ratio = curv / (g_x / (2 * mu / (prob.notes["n"] * gas.m)))
     assert abs(ratio - 1.0) < 0.08, ratio
     nu = mu / (prob.notes["n"] * gas.m)
-    u_slip1 = 50e-6 * g_x * L / (2 * nu)
+    u_slip1 = mfp * g_x * L / (2 * nu)
     assert 0.5 * u_slip1 < slip < 2.5 * u_slip1, (slip, u_slip1)
     assert np.abs(U - U[::-1]).mean() < 0.03 * U.max()

@@ -936,3 +936,33 @@ def test_cylinder_full_size_bench_launch():
         assert st.cnt() == orc.cnt(), step
         if step == 0:
             load_into_oracle(orc, a)
+
+
+def test_relax0d_full_size_histories():
+    """The 0D relaxation at full size (one cell, 100,000 particles, FP64,
+    200 steps of usp_step from T_tr = 10,000 K, T_rot = T_vib = 300 K)
+    against the oracle's steps: every 20 steps the cell's T_tr, T_rot and
+    T_vib agree to 1e-11 relative and every particle's level is the
+    oracle's (same draws, FP64 on both sides)."""
+    usp = _usp()
+    prob = W.relax0d()
+    parts = W.particles_for(prob)
+    _say(f"[relax0d-full] n={parts['n']}")
+    st = usp.DeviceState(prob, parts)
+    orc = oracle.Sim(prob, parts)
+    iT = [oracle.CS_NAMES.index(k) for k in ("TTR", "TROT", "TVIB")]
+    for s in range(200):
+        st.step(s, 1)
+        orc.step_native(s, 1)
+        if s % 20 == 19:
+            st.bin()
+            orc.bin()
+            st.do_moments()
+            st.do_reconstruct()
+            orc.do_moments()
+            orc.do_cellstate()
+            gc, oc = st.cellstate(), orc.cellstate()
+            d = [abs(gc[k, 0] - oc[k, 0]) / oc[k, 0] for k in iT]
+            assert max(d) < 1e-11, (s, d)
+            assert np.array_equal(st.state()["vib"], orc.state()["vib"]), s
+    _say(f"  T after 200 steps: {[round(float(oc[k, 0]), 3) for k in iT]}")

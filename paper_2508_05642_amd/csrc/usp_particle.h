@@ -354,8 +354,10 @@ __device__ __forceinline__ void note_coef_events(const PartCoef<double>& a, uint
   if (a.clamp_rot || a.clamp_m) *ev |= 1u << USP_CNT_TREL_CLAMP;
 }
 
-// First-order FPM update of particle i in cell c (Sec. II.C), all in FP64
-// from the cell planes (no reconstruction): the velocity by eq.
+// First-order FPM update of particle i in cell c (Sec. II.C) from the FP64
+// cell planes (no reconstruction); the Cholesky test and the level jumps in
+// FP64, the four normals and the velocity and rotational-energy update in
+// the state precision: the velocity by eq.
 // conventionial-velo and the rotational energy by eq. conventionial-erot
 // (the USP-FPM algebra with alpha = exp(-dt/tau)); the level by Gillespie's
 // direct method for the master-equation rates omega_{I,I-1} = 2 I/(tau
@@ -407,17 +409,26 @@ __device__ __forceinline__ PartNew<S> collide_fpm(const GridP& g, const GasP& ga
   if (mrel < 0.0) { mrel = 0.0; ev |= 1u << USP_CNT_TREL_CLAMP; }
   const uint32_t id = p.pid[i];
   const U4 w0 = philox(id, step, TAG_COLLIDE, 0u, seed);
-  double G1, G2, G3, G4;
-  box_muller<double>(w0.w[0], w0.w[1], &G1, &G2);
-  box_muller<double>(w0.w[2], w0.w[3], &G3, &G4);
-  const double sq = sqrt(oma2);
-  const double Cx = (double)in.cx - U[0], Cy = (double)in.cy - U[1], Cz = (double)in.cz - U[2];
-  o.cx = (S)(U[0] + al * Cx + sq * (L[0] * G1));
-  o.cy = (S)(U[1] + al * Cy + sq * (L[1] * G1 + L[2] * G2));
-  o.cz = (S)(U[2] + al * Cz + sq * (L[3] * G1 + L[4] * G2 + L[5] * G3));
-  const double half = 0.5 * R * Trot_rel * oma2;
-  const double root = sqrt((double)in.erot) * al + sqrt(half) * G4;
-  o.erot = (S)(half + root * root);
+  {
+    // the draws and the update in the state precision (the decisions
+    // above and the level jumps below stay in FP64)
+    using T = S;
+    T G1, G2, G3, G4;
+    box_muller<T>(w0.w[0], w0.w[1], &G1, &G2);
+    box_muller<T>(w0.w[2], w0.w[3], &G3, &G4);
+    const T u0 = (T)U[0], u1 = (T)U[1], u2 = (T)U[2], a = (T)al;
+    const T sq = sqrt((T)oma2);
+    T Lt[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Lt[k] = (T)L[k];
+    const T Cx = (T)in.cx - u0, Cy = (T)in.cy - u1, Cz = (T)in.cz - u2;
+    o.cx = (S)(u0 + a * Cx + sq * (Lt[0] * G1));
+    o.cy = (S)(u1 + a * Cy + sq * (Lt[1] * G1 + Lt[2] * G2));
+    o.cz = (S)(u2 + a * Cz + sq * (Lt[3] * G1 + Lt[4] * G2 + Lt[5] * G3));
+    const T half = T(0.5) * (T)R * (T)Trot_rel * (T)oma2;
+    const T root = sqrt((T)in.erot) * a + sqrt(half) * G4;
+    o.erot = (S)(half + root * root);
+  }
   // Gillespie: waiting time -ln(U1)/W, then up with probability
   // omega_up/W = (I+1) q / ((I+1) q + I)
   const double q = mrel / (1.0 + mrel);

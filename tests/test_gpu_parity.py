@@ -1006,3 +1006,46 @@ def test_cylinder_full_size_stagnation_pressure():
     _say(f"  C_p {np.round(co['C_p'][front], 3)} vs {np.round(newton, 3)}, "
          f"C_D {co['drag'] / (0.5 * rho * U * U * 2 * bc.cyl_r):.3f}")
     assert np.all(np.abs(co["C_p"][front] / newton - 1.0) < 0.04)
+
+
+def test_cylinder_reduced_wall_statistics():
+    """Wall sampling of a developed flow against the oracle: the scale-0.25
+    Mach 10 cylinder (the full grid's 1-mm cells, ~2.25M particles, FP32
+    state), 1000 steps of flow development, then the surface sums of 2000
+    steps in 36 body elements, against the oracle's sums of the same run
+    (tests/golden, written by make_cylinder_wall_sums.py).  The two
+    trajectories part early, so the statistics must agree: the drag and the
+    body-integrated pressure within 1%, the integrated shear and heat load
+    within 3%, and the pressure coefficient element by element over the
+    front (Theta < 60 degrees) within 6%.  Single elements' shear and heat
+    flux are noisier than that and are not compared one by one."""
+    usp = _usp()
+    from paper_2508_05642_amd import sampling
+    prob = W.cylinder(scale=0.25, f32=True)
+    parts = W.particles_for(prob)
+    transient, sampled, nb = 1000, 2000, 36
+    _say(f"[cylinder-wall] n={parts['n']} cells={prob.grid.ncells}")
+    st = usp.DeviceState(prob, parts)
+    st.step(0, transient)
+    st.enable_sampling(nb)
+    st.step(transient, sampled)
+    rows = [line.split() for line in open(os.path.join(GOLD, "cylinder_s025_wall_sums.txt"))
+            if not line.startswith("#") and line.strip()]
+    so = np.array(rows, dtype=np.int64)
+    g, gas, bc = prob.grid, prob.gas, prob.bc
+    rho, U = prob.notes["n"] * gas.m, prob.notes["U"]
+    co = {}
+    for who, surf in (("gpu", st.surface_sums()), ("oracle", so)):
+        fl = sampling.surface_fluxes(surf, g, bc, nb, gas.m, g.fnum, gas.theta_vib,
+                                     sampled * prob.dt)
+        co[who] = sampling.cylinder_coefficients(fl, rho, U)
+    a, b = co["gpu"], co["oracle"]
+    front = b["theta_deg"] < 60.0
+    _say(f"  drag {a['drag']:.3f} (oracle {b['drag']:.3f}) N/m; sum C_p {a['C_p'].sum():.3f} "
+         f"({b['C_p'].sum():.3f}), C_f {a['C_f'].sum():.4f} ({b['C_f'].sum():.4f}), "
+         f"C_h {a['C_h'].sum():.4f} ({b['C_h'].sum():.4f})")
+    assert abs(a["drag"] / b["drag"] - 1.0) < 0.01
+    assert abs(a["C_p"].sum() / b["C_p"].sum() - 1.0) < 0.01
+    assert abs(a["C_f"].sum() / b["C_f"].sum() - 1.0) < 0.03
+    assert abs(a["C_h"].sum() / b["C_h"].sum() - 1.0) < 0.03
+    assert np.all(np.abs(a["C_p"][front] / b["C_p"][front] - 1.0) < 0.06)

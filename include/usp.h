@@ -267,14 +267,17 @@ usp_status usp_bin_gather(const usp_grid* grid, const usp_particles* in, usp_par
 
 /* usp_moments of the state usp_bin would have produced, reading slot j from
    in[perm[j]] (perm and offsets from usp_bin_gather).  Bit-identical to
-   usp_bin followed by usp_moments. */
+   usp_bin followed by usp_moments.  Errors: USP_EINVAL for a null
+   argument. */
 usp_status usp_moments_gather(const usp_grid* grid, const usp_particles* in, const uint32_t* perm,
                               const int64_t* offsets, double* mom, void* stream);
 
 /* usp_update of the state usp_bin would have produced, reading slot j from
    in[perm[j]] and writing the whole result state in slot order to `out`
    (whose cells and count usp_bin_gather set), injection included.  in and
-   out must differ; bit-identical to usp_bin followed by usp_update. */
+   out must differ; bit-identical to usp_bin followed by usp_update.
+   Errors: USP_EINVAL for a null or inconsistent argument, in == out, or a
+   short ws. */
 usp_status usp_update_gather(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
                              const double* cs, const int64_t* offsets, const usp_particles* in,
                              const uint32_t* perm, usp_particles* out, void* ws, size_t ws_bytes,

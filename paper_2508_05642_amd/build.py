@@ -25,16 +25,25 @@ HIPCC_FLAGS = [
 ]
 
 
+def _code(text):
+    """The text of a C/C++/HIP source without comments and whitespace (the
+    sources hold no string literal with a comment marker in it)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return re.sub(r"\s+", "", text)
+
+
 def fingerprint():
-    """SHA-256 of every kernel source, the public header and the compiler
-    flags: identifies the code that a stored counter measurement belongs
-    to."""
+    """SHA-256 of the code of every kernel source and the public header
+    (comments and whitespace removed) and the compiler flags: identifies the
+    code that a stored counter measurement belongs to."""
     import hashlib
     h = hashlib.sha256()
     for f in SRC + HDR:
         h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            h.update(_code(fh.read()).encode())
     h.update(" ".join(HIPCC_FLAGS).encode())
     return h.hexdigest()[:16]
 

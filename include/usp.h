@@ -365,7 +365,8 @@ usp_status usp_update(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc
    IV.B), the particle update and the conservation (Secs. III.A-III.B, IV.C),
    with no rebin (0D particles never change cell).  A workgroup owns a tile
    of whole cells and keeps their particles in LDS for all the steps of a
-   launch.  Bit-identical to usp_step on the same state.
+   launch; the tiles are dispatched by descending particle count (the tile
+   order goes to `ws`).  Bit-identical to usp_step on the same state.
    p must be binned with `offsets` (count[0] == offsets[M]; a first
    usp_bin or usp_step leaves it so).  dt_cell (device double[M], may be
    NULL) overrides dt per cell.  mom and cs as for usp_moments /

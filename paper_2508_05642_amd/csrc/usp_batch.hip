@@ -56,6 +56,7 @@ __global__ __launch_bounds__(UPD_BLOCK, WPE) void k_batch(GridP g, GasP gas, dou
                                                           double* cs,
                                                           const int64_t* __restrict__ offsets,
                                                           const int32_t* __restrict__ first,
+                                                          const int32_t* __restrict__ order,
                                                           PartP<S> p, uint64_t seed,
                                                           uint64_t step0, int nsteps,
                                                           int64_t* counters) {
@@ -64,7 +65,7 @@ __global__ __launch_bounds__(UPD_BLOCK, WPE) void k_batch(GridP g, GasP gas, dou
   __shared__ uint16_t esc_list[CAP];
   __shared__ int nesc;
   __shared__ unsigned long long wcnt[USP_NCOUNTERS];
-  const int64_t t = blockIdx.x;
+  const int64_t t = order[blockIdx.x];
   const int64_t c0 = first[t], c1 = first[t + 1];
   if (c0 >= c1) return;
   const int64_t i0 = offsets[c0], i1 = offsets[c1];
@@ -80,6 +81,52 @@ __global__ __launch_bounds__(UPD_BLOCK, WPE) void k_batch(GridP g, GasP gas, dou
   }
 }
 
+// Dispatch order of a batched launch: the tiles by descending particle
+// count (ties by index), so that the heaviest tiles start first and the
+// launch, in which every workgroup keeps its tile for all its steps, does
+// not end on a heavy tile started late.  One block, a bitonic sort of
+// (count, index) keys in LDS; more than ORDER_MAX tiles keep launch order.
+constexpr int ORDER_MAX = 8192;
+
+__global__ __launch_bounds__(1024) void k_tile_order(const int64_t* __restrict__ offsets,
+                                                     const int32_t* __restrict__ first,
+                                                     int64_t ntiles, int32_t* order) {
+  __shared__ unsigned long long key[ORDER_MAX];
+  const int n = (int)ntiles;
+  if (ntiles > ORDER_MAX) {
+    for (int64_t t = threadIdx.x; t < ntiles; t += blockDim.x) order[t] = (int32_t)t;
+    return;
+  }
+  int P = 1;
+  while (P < n) P <<= 1;
+  for (int t = threadIdx.x; t < P; t += blockDim.x) {
+    unsigned long long k = ~0ull;  // padding sorts last
+    if (t < n) {
+      const int64_t w = offsets[first[t + 1]] - offsets[first[t]];
+      const uint32_t wc = w > 0xFFFFFFF0LL ? 0xFFFFFFF0u : (uint32_t)w;
+      k = ((unsigned long long)(0xFFFFFFFFu - wc) << 32) | (uint32_t)t;
+    }
+    key[t] = k;
+  }
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < P; t += blockDim.x) {
+        const int u = t ^ j;
+        if (u > t) {
+          const unsigned long long a = key[t], b = key[u];
+          if ((a > b) == ((t & k) == 0)) {
+            key[t] = b;
+            key[u] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = threadIdx.x; t < n; t += blockDim.x) order[t] = (int32_t)(key[t] & 0xFFFFFFFFull);
+}
+
 template <typename S, int TILE, int WPE>
 static hipError_t batch_launches(const GridP& g, const GasP& gas, double dt,
                                  const double* dt_cell, double* mom, double* cs,
@@ -88,15 +135,21 @@ static hipError_t batch_launches(const GridP& g, const GasP& gas, double dt,
                                  int64_t* counters, hipStream_t st) {
   const int64_t ntiles = cdiv(p.capacity, TILE);
   hipError_t e = launch_tiles(offsets, g.M, TILE, ntiles, first, st);
+  // the order follows first[] in the workspace (sized for 128-slot windows)
+  int32_t* order = first + ntiles + 1;
+  if (e == hipSuccess) {
+    k_tile_order<<<1, 1024, 0, st>>>(offsets, first, ntiles, order);
+    e = hipGetLastError();
+  }
   for (int s = 0; s < nsteps && e == hipSuccess; s += spl) {
     const int k = nsteps - s < spl ? nsteps - s : spl;
     if (gas.scheme == USP_SCHEME_FPM)
       k_batch<S, 2 * TILE, WPE, true><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, dt, dt_cell, mom, cs,
-                                                                   offsets, first, p, seed,
+                                                                   offsets, first, order, p, seed,
                                                                    step + (uint64_t)s, k, counters);
     else
       k_batch<S, 2 * TILE, WPE, false><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, dt, dt_cell, mom, cs,
-                                                                    offsets, first, p, seed,
+                                                                    offsets, first, order, p, seed,
                                                                     step + (uint64_t)s, k, counters);
     e = hipGetLastError();
   }

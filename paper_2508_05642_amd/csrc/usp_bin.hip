@@ -328,6 +328,46 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_far_place(const int32_t* far_tota
   }
 }
 
+// B2: the far moves into each cell in ascending input index.  One wave per
+// cell sorts lists of 2..FAR_SORT entries in its share of LDS (bitonic
+// network, distinct keys, so the result is the unique sorted list); longer
+// lists are left to the insertion sort of k_cell_bases.
+constexpr int FAR_SORT = 512;
+
+__global__ __launch_bounds__(BIN_BLOCK) void k_far_sort(const int64_t* __restrict__ far_off,
+                                                        int64_t M, int32_t* far_list) {
+  __shared__ int32_t keys[BIN_BLOCK / 64][FAR_SORT];
+  const int64_t c = (int64_t)blockIdx.x * (BIN_BLOCK / 64) + (threadIdx.x >> 6);
+  if (c >= M) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t f0 = far_off[c], f1 = far_off[c + 1];
+  const int64_t n = f1 - f0;
+  if (n < 2 || n > FAR_SORT) return;
+  int32_t* v = keys[threadIdx.x >> 6];
+  int P = 2;
+  while (P < n) P <<= 1;
+  for (int t = lane; t < P; t += 64) v[t] = t < n ? far_list[f0 + t] : INT32_MAX;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = lane; t < P; t += 64) {
+        const int u = t ^ j;
+        if (u > t) {
+          const int32_t a = v[t], b = v[u];
+          if ((a > b) == ((t & k) == 0)) {
+            v[t] = b;
+            v[u] = a;
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  for (int t = lane; t < n; t += 64) far_list[f0 + t] = v[t];
+}
+
 // C: one thread per new cell c.  The source groups (k = c - d, ascending k)
 // and the far moves into c (ascending index) interleave in input order;
 // T9[k][q] becomes the group's first position inside c, far_base the far
@@ -342,7 +382,7 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_cell_bases(GridP g, Nbr nb, const
   if (c >= M) return;
   const int64_t ns = sorted_len(old_off, M, count);
   const int64_t f0 = far_off[c], f1 = far_off[c + 1];
-  for (int64_t a = f0 + 1; a < f1; ++a) {  // insertion sort (lists are tiny)
+  for (int64_t a = f0 + 1; a < f1; ++a) {  // insertion sort (lists longer than FAR_SORT)
     const int32_t v = far_list[a];
     int64_t b = a - 1;
     while (b >= f0 && far_list[b] > v) { far_list[b + 1] = far_list[b]; --b; }
@@ -621,6 +661,7 @@ static hipError_t bin_launches(const GridP& g, const PartP<S>& in, const PartP<S
                                                  n_tail_cells, counters);
   launch_scan(far_cnt, M, far_off, blocksums, nullptr, nullptr, st);
   k_far_place<<<64, BIN_BLOCK, 0, st>>>(far_total, far_c, far_i, far_off, far_cur, far_list);
+  k_far_sort<<<cdiv(M, BIN_BLOCK / 64), BIN_BLOCK, 0, st>>>(far_off, M, far_list);
   k_cell_bases<<<cdiv(M, BIN_BLOCK), BIN_BLOCK, 0, st>>>(g, nb, old_off, in.count, T9, far_off,
                                                           far_list, far_base, tail_cnt, nontail,
                                                           cnt_total);

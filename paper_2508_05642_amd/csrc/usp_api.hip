@@ -153,8 +153,38 @@ usp_status do_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, d
   const int64_t cap = p->capacity > p_alt->capacity ? p->capacity : p_alt->capacity;
   const WsLayout L = ws_layout(g.M, cap, n_faces(g));
   char* w = (char*)ws;
+  // Cells far larger than the fused particle phase's LDS stage (mean slots
+  // per cell above it) would give whole cells to single workgroups: such
+  // grids run the separate phase kernels, which spread every particle over
+  // the chip and give the same bits, after a copying bin.
+  const int stage = sizeof(S) == 4 ? UPDATE_STAGE_F32 : UPDATE_STAGE_F64;
+  const bool big_cells = cdiv(cap, g.M) > stage;
   for (int32_t s = 0; s < nsteps; ++s) {
     const uint64_t sn = step + (uint64_t)s;
+    if (big_cells) {
+      hipError_t e = hipSuccess;
+      if (s == 0 || g.dim != 0) {
+        const PartP<S> in = make_parts<S>(p), out = make_parts<S>(p_alt);
+        if ((e = launch_bin<S>(g, in, out, offsets, s > 0 ? offsets : in_offsets, w, L, counters,
+                               st)) != hipSuccess)
+          return USP_EDEVICE;
+        const usp_particles tmp = *p;
+        *p = *p_alt;
+        *p_alt = tmp;
+      }
+      const PartP<S> q = make_parts<S>(p);
+      if ((e = launch_moments<S>(g, q, offsets, mom, st)) != hipSuccess) return USP_EDEVICE;
+      if ((e = launch_reconstruct(g, gp, mom, dt, dt_cell, cs, counters, st)) != hipSuccess)
+        return USP_EDEVICE;
+      if ((e = launch_collide<S>(g, gp, cs, offsets, q, seed, sn, counters, st)) != hipSuccess)
+        return USP_EDEVICE;
+      if ((e = launch_conserve<S>(g, gp, cs, offsets, q, seed, sn, counters, st)) != hipSuccess)
+        return USP_EDEVICE;
+      if (g.dim != 0 &&
+          (e = launch_advect<S>(g, gp, bp, dt, q, seed, sn, w, L, counters, st)) != hipSuccess)
+        return USP_EDEVICE;
+      continue;
+    }
     // from the second step on, the input is the previous step's binned
     // state (segments in `offsets`) followed by the injected particles; in
     // 0D nothing moves between cells, so only the first step bins

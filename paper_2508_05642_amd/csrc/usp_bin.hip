@@ -26,6 +26,7 @@ constexpr int BIN_BLOCK = 256;
 constexpr int SCAN_ITEMS = 4;
 constexpr int SCAN_TILE = BIN_BLOCK * SCAN_ITEMS;
 constexpr int SORT_LDS = 4096;
+constexpr int BIN_U = 4;  // chunks of 64 particles per load batch of the grouped bin
 
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -245,38 +246,56 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin_group(GridP g, Nbr nb, PartP<
   int running[10];
 #pragma unroll
   for (int q = 0; q < 10; ++q) running[q] = 0;
-  for (int64_t base = lo; base < hi; base += 64) {
-    const int64_t i = base + lane;
-    const bool active = i < hi;
-    int grpid = 14;  // inactive lane
-    int32_t c = -1;
-    if (active) {
+  // BIN_U chunks of 64 at a time: their cell and flag loads are issued
+  // together, ahead of the ranking, which needs no memory
+  for (int64_t base = lo; base < hi; base += 64 * BIN_U) {
+    int32_t cc[BIN_U];
+#pragma unroll
+    for (int u = 0; u < BIN_U; ++u) {
+      const int64_t i = base + u * 64 + lane;
       // a binned prefix carries its current cells (the flight rewrote them
       // from the new positions); only the solid-cell test remains
-      c = in.cell[i];
-      if (g.dim == 0 && c >= M) c = -1;
-      bool solid = false;
-      if (c >= 0 && g.flags && (g.flags[c] & USP_FLAG_SOLID)) { c = -1; solid = true; }
-      if (solid) count_event(counters, USP_CNT_SOLID_DROP);
-      grpid = c < 0 ? GRP_GONE : nbr_group(g, nb, (int64_t)c - k);
+      cc[u] = i < hi ? in.cell[i] : -1;
+      if (g.dim == 0 && cc[u] >= M) cc[u] = -1;
     }
-    // ranks within each group present in the wave (the others add nothing)
-    const uint32_t present = wave_or(grpid < 10 ? (1u << grpid) : 0u);
-    int rank = 0;
+    uint32_t solid = 0;
+    if (g.flags) {
 #pragma unroll
-    for (int q = 0; q < 10; ++q) {
-      if (present & (1u << q)) {
-        const uint64_t m = __ballot(grpid == q);
-        if (grpid == q) rank = running[q] + __popcll(m & lt);
-        running[q] += __popcll(m);
-      }
+      for (int u = 0; u < BIN_U; ++u)
+        if (cc[u] >= 0 && (g.flags[cc[u]] & USP_FLAG_SOLID)) solid |= 1u << u;
     }
-    if (active) grp[i] = (rank << 4) | grpid;
-    if (grpid == GRP_FAR) {
-      const int j = atomicAdd(far_total, 1);
-      far_c[j] = c;
-      far_i[j] = (int32_t)i;
-      atomicAdd(&far_cnt[c], 1);
+#pragma unroll
+    for (int u = 0; u < BIN_U; ++u) {
+      if (base + u * 64 >= hi) break;
+      const int64_t i = base + u * 64 + lane;
+      const bool active = i < hi;
+      int grpid = 14;  // inactive lane
+      int32_t c = cc[u];
+      if (active) {
+        if (solid & (1u << u)) {
+          c = -1;
+          count_event(counters, USP_CNT_SOLID_DROP);
+        }
+        grpid = c < 0 ? GRP_GONE : nbr_group(g, nb, (int64_t)c - k);
+      }
+      // ranks within each group present in the wave (the others add nothing)
+      const uint32_t present = wave_or(grpid < 10 ? (1u << grpid) : 0u);
+      int rank = 0;
+#pragma unroll
+      for (int q = 0; q < 10; ++q) {
+        if (present & (1u << q)) {
+          const uint64_t m = __ballot(grpid == q);
+          if (grpid == q) rank = running[q] + __popcll(m & lt);
+          running[q] += __popcll(m);
+        }
+      }
+      if (active) grp[i] = (rank << 4) | grpid;
+      if (grpid == GRP_FAR) {
+        const int j = atomicAdd(far_total, 1);
+        far_c[j] = c;
+        far_i[j] = (int32_t)i;
+        atomicAdd(&far_cnt[c], 1);
+      }
     }
   }
   if (lane < nb.n) {
@@ -446,10 +465,8 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin_scatter(GridP g, Nbr nb, Part
   const int lane = threadIdx.x & 63;
   const int64_t ns = sorted_len(old_off, M, in.count);
   int64_t lo = old_off[k], hi = old_off[k + 1];
-  lo = lo < 0 ? 0 : (lo > ns ? ns : lo);
-  hi = hi < lo ? lo : (hi > ns ? ns : hi);
-  if (lo >= hi) return;
-  // lane q < nb.n holds the first slot of group q and its cell
+  // lane q < nb.n holds the first slot of group q and its cell (loaded
+  // beside the segment bounds, which it does not depend on)
   int64_t gbase = 0;
   int32_t gcell = 0;
   if (lane < nb.n) {
@@ -463,14 +480,27 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin_scatter(GridP g, Nbr nb, Part
       gbase = offsets[c] + T9[k * 9 + lane];
     }
   }
+  lo = lo < 0 ? 0 : (lo > ns ? ns : lo);
+  hi = hi < lo ? lo : (hi > ns ? ns : hi);
   const bool hx = g.dim == 2, hy = g.dim >= 1;
-  for (int64_t base = lo; base < hi; base += 64) {
-    const int64_t i = base + lane;
-    const int32_t gv = i < hi ? grp[i] : (GRP_GONE);
-    const int q = gv & 15;
-    const int64_t b = __shfl(gbase, q < 9 ? q : 0, 64);
-    const int32_t c = __shfl(gcell, q < 9 ? q : 0, 64);
-    if (i < hi && q < nb.n) place<G, S>(in, out, gperm, i, b + (gv >> 4), c, hx, hy);
+  // the group words of BIN_U chunks are loaded before any of them is placed
+  // (the stores could alias them as far as the compiler knows)
+  for (int64_t base = lo; base < hi; base += 64 * BIN_U) {
+    int32_t gw[BIN_U];
+#pragma unroll
+    for (int u = 0; u < BIN_U; ++u) {
+      const int64_t i = base + u * 64 + lane;
+      gw[u] = i < hi ? grp[i] : GRP_GONE;
+    }
+#pragma unroll
+    for (int u = 0; u < BIN_U; ++u) {
+      const int64_t i = base + u * 64 + lane;
+      const int32_t gv = gw[u];
+      const int q = gv & 15;
+      const int64_t b = __shfl(gbase, q < 9 ? q : 0, 64);
+      const int32_t c = __shfl(gcell, q < 9 ? q : 0, 64);
+      if (i < hi && q < nb.n) place<G, S>(in, out, gperm, i, b + (gv >> 4), c, hx, hy);
+    }
   }
 }
 

@@ -636,21 +636,53 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_tail_sort_copy_big(GridP g, PartP
   }
 }
 
-__global__ void k_copy_i64(const int64_t* src, int64_t* dst, int64_t n) {
+// Bin set-up, thread per cell: the input offsets [0, M] copied (the output
+// offsets may be the same buffer) and the four per-cell counters and two
+// totals cleared.
+__global__ void k_bin_init(const int64_t* src, int64_t* dst, int64_t M, int32_t* a, int32_t* b,
+                           int32_t* c, int32_t* d, int32_t* scalar, int32_t* scalar2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = src ? src[i] : 0;
+  if (i <= M) dst[i] = src ? src[i] : 0;
+  if (i < M) { a[i] = 0; b[i] = 0; c[i] = 0; d[i] = 0; }
+  if (i == 0) { *scalar = 0; *scalar2 = 0; }
 }
 
-__global__ void k_zero_i32x(int32_t* a, int32_t* b, int32_t* c, int32_t* d, int64_t n,
-                            int32_t* scalar, int32_t* scalar2) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) { a[i] = 0; b[i] = 0; c[i] = 0; d[i] = 0; }
-  if (i == 0) { *scalar = 0; *scalar2 = 0; }
+// The three scan passes in one block, for M <= SCAN_TILE (the 1D and 0D
+// grids, where the step is launch-bound); same results as the three kernels.
+__global__ __launch_bounds__(BIN_BLOCK) void k_scan_small(const int32_t* counts, int64_t M,
+                                                          int64_t* offsets, int64_t* out_count,
+                                                          const int64_t* in_count) {
+  const int64_t base = (int64_t)threadIdx.x * SCAN_ITEMS;
+  int32_t v[SCAN_ITEMS];
+  int64_t s = 0;
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const int64_t j = base + k;
+    v[k] = j < M ? counts[j] : 0;
+    s += v[k];
+  }
+  int64_t tot;
+  int64_t run = block_exclusive_scan(s, &tot);
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const int64_t j = base + k;
+    if (j < M) offsets[j] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) {
+    offsets[M] = tot;
+    if (out_count) {
+      out_count[0] = tot;
+      out_count[1] = in_count[1];
+    }
+  }
 }
 
 static void launch_scan(const int32_t* cnt, int64_t M, int64_t* out_off, int64_t* blocksums,
                         int64_t* out_count, const int64_t* in_count, hipStream_t st) {
   const int64_t nb = cdiv(M, SCAN_TILE);
+  if (nb <= 1) {
+    k_scan_small<<<1, BIN_BLOCK, 0, st>>>(cnt, M, out_off, out_count, in_count);
+    return;
+  }
   k_scan_reduce<<<nb, BIN_BLOCK, 0, st>>>(cnt, M, blocksums);
   k_scan_top<<<1, BIN_BLOCK, 0, st>>>(blocksums, nb, out_off, M, out_count, in_count);
   k_scan_down<<<nb, BIN_BLOCK, 0, st>>>(cnt, M, blocksums, out_off);
@@ -682,9 +714,8 @@ static hipError_t bin_launches(const GridP& g, const PartP<S>& in, const PartP<S
   const int64_t M = g.M;
   const Nbr nb = nbr_set(g);
   const int TAIL_GRID = 512;
-  k_copy_i64<<<cdiv(M + 1, 256), 256, 0, st>>>(in_offsets, old_off, M + 1);
-  k_zero_i32x<<<cdiv(M, 256), 256, 0, st>>>(tail_cnt, cursor, far_cnt, far_cur, M, far_total,
-                                             n_tail_cells);
+  k_bin_init<<<cdiv(M + 1, 256), 256, 0, st>>>(in_offsets, old_off, M, tail_cnt, cursor, far_cnt,
+                                                far_cur, far_total, n_tail_cells);
   k_bin_group<S><<<cdiv(M, BIN_BLOCK / 64), BIN_BLOCK, 0, st>>>(g, nb, in, old_off, key, T9, far_cnt,
                                                                  far_c, far_i, far_total, counters);
   k_tail_key<S><<<TAIL_GRID, BIN_BLOCK, 0, st>>>(g, in, old_off, key, tail_cnt, tail_cells,

@@ -26,7 +26,9 @@ constexpr int BIN_BLOCK = 256;
 constexpr int SCAN_ITEMS = 4;
 constexpr int SCAN_TILE = BIN_BLOCK * SCAN_ITEMS;
 constexpr int SORT_LDS = 4096;
-constexpr int BIN_U = 4;  // chunks of 64 particles per load batch of the grouped bin
+constexpr int BIN_U = 4;
+// grids of at most this many cells launch independent bin kernels together
+constexpr int64_t BIN_MERGE_MAX = 4096;  // chunks of 64 particles per load batch of the grouped bin
 
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -229,13 +231,12 @@ __device__ __forceinline__ int64_t sorted_len(const int64_t* old_off, int64_t M,
 // same group (64 at a time with ballots).  Writes grp[i] = rank << 4 | group,
 // the group counts T9[k][.], and appends far moves to an unordered list.
 template <typename S>
-__global__ __launch_bounds__(BIN_BLOCK) void k_bin_group(GridP g, Nbr nb, PartP<S> in,
-                                                         const int64_t* old_off, int32_t* grp,
-                                                         int32_t* T9, int32_t* far_cnt,
-                                                         int32_t* far_c, int32_t* far_i,
-                                                         int32_t* far_total, int64_t* counters) {
+__device__ __forceinline__ void bin_group(const GridP& g, const Nbr& nb, const PartP<S>& in,
+                                          const int64_t* old_off, int32_t* grp, int32_t* T9,
+                                          int32_t* far_cnt, int32_t* far_c, int32_t* far_i,
+                                          int32_t* far_total, int64_t* counters, int64_t blk) {
   const int64_t M = g.M;
-  const int64_t k = (int64_t)blockIdx.x * (BIN_BLOCK / 64) + (threadIdx.x >> 6);
+  const int64_t k = blk * (BIN_BLOCK / 64) + (threadIdx.x >> 6);
   if (k >= M) return;
   const int lane = threadIdx.x & 63;
   const int64_t ns = sorted_len(old_off, M, in.count);
@@ -310,15 +311,15 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin_group(GridP g, Nbr nb, PartP<
 // Keys of the unsorted tail [ns, n) (injected particles, or every particle
 // when the input is not binned): one atomic per run of equal keys.
 template <typename S>
-__global__ __launch_bounds__(BIN_BLOCK) void k_tail_key(GridP g, PartP<S> in, const int64_t* old_off,
-                                                        int32_t* key, int32_t* tail_cnt,
-                                                        int32_t* tail_cells, int32_t* n_tail_cells,
-                                                        int64_t* counters) {
+__device__ __forceinline__ void tail_key(const GridP& g, const PartP<S>& in, const int64_t* old_off,
+                                         int32_t* key, int32_t* tail_cnt, int32_t* tail_cells,
+                                         int32_t* n_tail_cells, int64_t* counters, int64_t blk,
+                                         int64_t nblk) {
   const int64_t M = g.M;
   const int64_t ns = sorted_len(old_off, M, in.count), n = in.count[0];
   const int lane = threadIdx.x & 63;
-  const int64_t stride = (int64_t)gridDim.x * BIN_BLOCK;
-  for (int64_t b = ns + (int64_t)blockIdx.x * BIN_BLOCK + (threadIdx.x & ~63); b < n; b += stride) {
+  const int64_t stride = nblk * BIN_BLOCK;
+  for (int64_t b = ns + blk * BIN_BLOCK + (threadIdx.x & ~63); b < n; b += stride) {
     const int64_t i = b + lane;
     int32_t c = -1;
     if (i < n) {
@@ -333,6 +334,45 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_tail_key(GridP g, PartP<S> in, co
     if (len > 0 && c >= 0 && atomicAdd(&tail_cnt[c], len) == 0)
       tail_cells[atomicAdd(n_tail_cells, 1)] = c;
   }
+}
+
+template <typename S>
+__global__ __launch_bounds__(BIN_BLOCK) void k_bin_group(GridP g, Nbr nb, PartP<S> in,
+                                                         const int64_t* old_off, int32_t* grp,
+                                                         int32_t* T9, int32_t* far_cnt,
+                                                         int32_t* far_c, int32_t* far_i,
+                                                         int32_t* far_total, int64_t* counters) {
+  bin_group<S>(g, nb, in, old_off, grp, T9, far_cnt, far_c, far_i, far_total, counters, blockIdx.x);
+}
+
+template <typename S>
+__global__ __launch_bounds__(BIN_BLOCK) void k_tail_key(GridP g, PartP<S> in, const int64_t* old_off,
+                                                        int32_t* key, int32_t* tail_cnt,
+                                                        int32_t* tail_cells, int32_t* n_tail_cells,
+                                                        int64_t* counters) {
+  tail_key<S>(g, in, old_off, key, tail_cnt, tail_cells, n_tail_cells, counters, blockIdx.x,
+              gridDim.x);
+}
+
+// On small grids, where the step is launch-bound, the two run side by side
+// in one launch (they touch disjoint arrays): the first ngroup blocks group
+// the binned prefix, the rest key the tail.  (On large grids the separate
+// launches are faster.)
+template <typename S>
+__global__ __launch_bounds__(BIN_BLOCK) void k_bin_group_tail(GridP g, Nbr nb, PartP<S> in,
+                                                              const int64_t* old_off, int32_t* key,
+                                                              int32_t* T9, int32_t* far_cnt,
+                                                              int32_t* far_c, int32_t* far_i,
+                                                              int32_t* far_total, int32_t* tail_cnt,
+                                                              int32_t* tail_cells,
+                                                              int32_t* n_tail_cells,
+                                                              int64_t* counters, int64_t ngroup) {
+  const int64_t blk = blockIdx.x;
+  if (blk < ngroup)
+    bin_group<S>(g, nb, in, old_off, key, T9, far_cnt, far_c, far_i, far_total, counters, blk);
+  else
+    tail_key<S>(g, in, old_off, key, tail_cnt, tail_cells, n_tail_cells, counters, blk - ngroup,
+                (int64_t)gridDim.x - ngroup);
 }
 
 // Far moves into per-cell lists (the order inside a list is fixed later).
@@ -506,16 +546,14 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin_scatter(GridP g, Nbr nb, Part
 
 // far moves: each list entry finds its position inside its cell
 template <typename S, bool G>
-__global__ __launch_bounds__(BIN_BLOCK) void k_far_scatter(GridP g, PartP<S> in, PartP<S> out,
-                                                           uint32_t* gperm,
-                                                           const int32_t* far_total,
-                                                           const int32_t* far_c, const int32_t* far_i,
-                                                           const int64_t* far_off,
-                                                           const int32_t* far_list,
-                                                           const int32_t* far_base,
-                                                           const int64_t* offsets) {
+__device__ __forceinline__ void far_scatter(const GridP& g, const PartP<S>& in, const PartP<S>& out,
+                                            uint32_t* gperm, const int32_t* far_total,
+                                            const int32_t* far_c, const int32_t* far_i,
+                                            const int64_t* far_off, const int32_t* far_list,
+                                            const int32_t* far_base, const int64_t* offsets,
+                                            int blk, int nblk) {
   const int nt = *far_total;
-  for (int j = blockIdx.x * BIN_BLOCK + threadIdx.x; j < nt; j += gridDim.x * BIN_BLOCK) {
+  for (int j = blk * BIN_BLOCK + threadIdx.x; j < nt; j += nblk * BIN_BLOCK) {
     const int32_t c = far_c[j], i = far_i[j];
     int64_t fp = far_off[c];
     const int64_t f1 = far_off[c + 1];
@@ -525,15 +563,14 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_far_scatter(GridP g, PartP<S> in,
 }
 
 // tail: slots after the prefix particles of each cell, claimed per run
-__global__ __launch_bounds__(BIN_BLOCK) void k_tail_claim(int64_t M, const int64_t* old_off,
-                                                          const int64_t* count, const int32_t* key,
-                                                          const int64_t* offsets,
-                                                          const int32_t* nontail, int32_t* cursor,
-                                                          uint32_t* perm) {
+__device__ __forceinline__ void tail_claim(int64_t M, const int64_t* old_off, const int64_t* count,
+                                           const int32_t* key, const int64_t* offsets,
+                                           const int32_t* nontail, int32_t* cursor, uint32_t* perm,
+                                           int64_t blk, int64_t nblk) {
   const int64_t ns = sorted_len(old_off, M, count), n = count[0];
   const int lane = threadIdx.x & 63;
-  const int64_t stride = (int64_t)gridDim.x * BIN_BLOCK;
-  for (int64_t b = ns + (int64_t)blockIdx.x * BIN_BLOCK + (threadIdx.x & ~63); b < n; b += stride) {
+  const int64_t stride = nblk * BIN_BLOCK;
+  for (int64_t b = ns + blk * BIN_BLOCK + (threadIdx.x & ~63); b < n; b += stride) {
     const int64_t i = b + lane;
     const int32_t c = i < n ? key[i] : -1;
     int hl, len;
@@ -543,6 +580,50 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_tail_claim(int64_t M, const int64
     base = __shfl(base, hl, 64);
     if (c >= 0) perm[offsets[c] + nontail[c] + base + (lane - hl)] = (uint32_t)i;
   }
+}
+
+template <typename S, bool G>
+__global__ __launch_bounds__(BIN_BLOCK) void k_far_scatter(GridP g, PartP<S> in, PartP<S> out,
+                                                           uint32_t* gperm,
+                                                           const int32_t* far_total,
+                                                           const int32_t* far_c, const int32_t* far_i,
+                                                           const int64_t* far_off,
+                                                           const int32_t* far_list,
+                                                           const int32_t* far_base,
+                                                           const int64_t* offsets) {
+  far_scatter<S, G>(g, in, out, gperm, far_total, far_c, far_i, far_off, far_list, far_base, offsets,
+                    blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(BIN_BLOCK) void k_tail_claim(int64_t M, const int64_t* old_off,
+                                                          const int64_t* count, const int32_t* key,
+                                                          const int64_t* offsets,
+                                                          const int32_t* nontail, int32_t* cursor,
+                                                          uint32_t* perm) {
+  tail_claim(M, old_off, count, key, offsets, nontail, cursor, perm, blockIdx.x, gridDim.x);
+}
+
+// Far moves and tail claims side by side in one launch on small grids
+// (disjoint slots): the first nfar blocks place the far moves, the rest
+// claim the tail's slots.
+template <typename S, bool G>
+__global__ __launch_bounds__(BIN_BLOCK) void k_far_tail(GridP g, PartP<S> in, PartP<S> out,
+                                                        uint32_t* gperm, const int32_t* far_total,
+                                                        const int32_t* far_c, const int32_t* far_i,
+                                                        const int64_t* far_off,
+                                                        const int32_t* far_list,
+                                                        const int32_t* far_base,
+                                                        const int64_t* old_off, const int32_t* key,
+                                                        const int64_t* offsets,
+                                                        const int32_t* nontail, int32_t* cursor,
+                                                        uint32_t* perm, int nfar) {
+  const int blk = blockIdx.x;
+  if (blk < nfar)
+    far_scatter<S, G>(g, in, out, gperm, far_total, far_c, far_i, far_off, far_list, far_base,
+                      offsets, blk, nfar);
+  else
+    tail_claim(g.M, old_off, in.count, key, offsets, nontail, cursor, perm, blk - nfar,
+               (int64_t)gridDim.x - nfar);
 }
 
 // One wave sorts one cell's tail slot list (distinct input indices) by rank
@@ -716,10 +797,18 @@ static hipError_t bin_launches(const GridP& g, const PartP<S>& in, const PartP<S
   const int TAIL_GRID = 512;
   k_bin_init<<<cdiv(M + 1, 256), 256, 0, st>>>(in_offsets, old_off, M, tail_cnt, cursor, far_cnt,
                                                 far_cur, far_total, n_tail_cells);
-  k_bin_group<S><<<cdiv(M, BIN_BLOCK / 64), BIN_BLOCK, 0, st>>>(g, nb, in, old_off, key, T9, far_cnt,
-                                                                 far_c, far_i, far_total, counters);
-  k_tail_key<S><<<TAIL_GRID, BIN_BLOCK, 0, st>>>(g, in, old_off, key, tail_cnt, tail_cells,
-                                                 n_tail_cells, counters);
+  const bool merged = M <= BIN_MERGE_MAX;
+  const int64_t ngroup = cdiv(M, BIN_BLOCK / 64);
+  if (merged) {
+    k_bin_group_tail<S><<<ngroup + TAIL_GRID, BIN_BLOCK, 0, st>>>(
+        g, nb, in, old_off, key, T9, far_cnt, far_c, far_i, far_total, tail_cnt, tail_cells,
+        n_tail_cells, counters, ngroup);
+  } else {
+    k_bin_group<S><<<ngroup, BIN_BLOCK, 0, st>>>(g, nb, in, old_off, key, T9, far_cnt, far_c, far_i,
+                                                 far_total, counters);
+    k_tail_key<S><<<TAIL_GRID, BIN_BLOCK, 0, st>>>(g, in, old_off, key, tail_cnt, tail_cells,
+                                                   n_tail_cells, counters);
+  }
   launch_scan(far_cnt, M, far_off, blocksums, nullptr, nullptr, st);
   k_far_place<<<64, BIN_BLOCK, 0, st>>>(far_total, far_c, far_i, far_off, far_cur, far_list);
   k_far_sort<<<cdiv(M, BIN_BLOCK / 64), BIN_BLOCK, 0, st>>>(far_off, M, far_list);
@@ -729,10 +818,17 @@ static hipError_t bin_launches(const GridP& g, const PartP<S>& in, const PartP<S
   launch_scan(cnt_total, M, offsets, blocksums, out.count, in.count, st);
   k_bin_scatter<S, G><<<cdiv(M, BIN_BLOCK / 64), BIN_BLOCK, 0, st>>>(g, nb, in, out, perm, old_off, key, T9,
                                                                    offsets);
-  k_far_scatter<S, G><<<64, BIN_BLOCK, 0, st>>>(g, in, out, perm, far_total, far_c, far_i, far_off, far_list,
-                                             far_base, offsets);
-  k_tail_claim<<<TAIL_GRID, BIN_BLOCK, 0, st>>>(M, old_off, in.count, key, offsets, nontail, cursor,
-                                                perm);
+  const int FAR_GRID = 64;
+  if (merged) {
+    k_far_tail<S, G><<<FAR_GRID + TAIL_GRID, BIN_BLOCK, 0, st>>>(
+        g, in, out, perm, far_total, far_c, far_i, far_off, far_list, far_base, old_off, key,
+        offsets, nontail, cursor, perm, FAR_GRID);
+  } else {
+    k_far_scatter<S, G><<<FAR_GRID, BIN_BLOCK, 0, st>>>(g, in, out, perm, far_total, far_c, far_i,
+                                                       far_off, far_list, far_base, offsets);
+    k_tail_claim<<<TAIL_GRID, BIN_BLOCK, 0, st>>>(M, old_off, in.count, key, offsets, nontail,
+                                                  cursor, perm);
+  }
   k_tail_sort_copy<S, G><<<TAIL_GRID, BIN_BLOCK, 0, st>>>(g, in, out, offsets, nontail, perm,
                                                        tail_cells, n_tail_cells);
   k_tail_sort_copy_big<S, G><<<TAIL_GRID, BIN_BLOCK, 0, st>>>(g, in, out, offsets, nontail, perm,

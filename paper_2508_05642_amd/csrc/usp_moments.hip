@@ -20,17 +20,23 @@ __global__ __launch_bounds__(CELL_BLOCK) void k_moments(GridP g, PartP<S> p, con
   if (valid) store_moments(mom, M, c, sub, v);
 }
 
-// Per-cell state, one thread per cell.
-__global__ void k_reconstruct(GridP g, GasP gas, const double* mom, double dt,
-                              const double* dt_cell, double* cs, int64_t* counters) {
+// Per-cell state of cell c.
+__device__ __forceinline__ void reconstruct_cell(const GridP& g, const GasP& gas, const double* mom,
+                                                 double dt, const double* dt_cell, double* cs,
+                                                 int64_t* counters, int64_t c) {
   const int64_t M = g.M;
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= M) return;
   double m[NMOM], v[NCS];
 #pragma unroll
   for (int k = 0; k < NMOM; ++k) m[k] = mom[k * M + c];
   cell_state(g, gas, m, c, dt_cell ? dt_cell[c] : dt, v, counters);
   store_cell_state(cs, M, c, v);
+}
+
+// Per-cell state, one thread per cell.
+__global__ void k_reconstruct(GridP g, GasP gas, const double* mom, double dt,
+                              const double* dt_cell, double* cs, int64_t* counters) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < g.M) reconstruct_cell(g, gas, mom, dt, dt_cell, cs, counters, c);
 }
 
 // Quadrant stencils of the reconstruction (Sec. III.B), one thread per
@@ -39,10 +45,8 @@ __global__ void k_reconstruct(GridP g, GasP gas, const double* mom, double dt,
 // else the opposite side, else none) and whether the diagonal cell
 // completes the cross term.  Field: 2 bits tx (1: +1, 2: -1), 2 bits ty,
 // 1 bit cross, 5 bits per quadrant.
-__global__ void k_stencil(GridP g, double* cs) {
+__device__ __forceinline__ void stencil_cell(const GridP& g, double* cs, int64_t c) {
   const int64_t M = g.M;
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= M || g.dim == 0) return;
   const int nx = g.nx;
   const int ci = g.dim == 2 ? (int)(c % nx) : 0;
   const int cj = g.dim == 2 ? (int)(c / nx) : (int)c;
@@ -65,6 +69,25 @@ __global__ void k_stencil(GridP g, double* cs) {
     bits |= f << (5 * q);
   }
   cell_records(cs, M)[c].stencil = bits;
+}
+
+__global__ void k_stencil(GridP g, double* cs) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < g.M && g.dim != 0) stencil_cell(g, cs, c);
+}
+
+// Grids of at most CELL_SMALL cells (launch-bound steps): the cell state and
+// then the stencils in one block, the barrier between them standing in for
+// the launch boundary (the stencils read the neighbours' usability).
+constexpr int64_t CELL_SMALL = 256;
+__global__ __launch_bounds__(256) void k_cell_state_small(GridP g, GasP gas, const double* mom,
+                                                          double dt, const double* dt_cell,
+                                                          double* cs, int64_t* counters) {
+  for (int64_t c = threadIdx.x; c < g.M; c += blockDim.x)
+    reconstruct_cell(g, gas, mom, dt, dt_cell, cs, counters, c);
+  if (g.dim == 0) return;
+  __syncthreads();
+  for (int64_t c = threadIdx.x; c < g.M; c += blockDim.x) stencil_cell(g, cs, c);
 }
 
 // Field sampling: the raw particle sums of each cell, N <f(c)>, formed
@@ -127,6 +150,10 @@ hipError_t launch_moments(const GridP& g, const PartP<S>& p, const int64_t* offs
 
 hipError_t launch_reconstruct(const GridP& g, const GasP& gas, const double* mom, double dt,
                               const double* dt_cell, double* cs, int64_t* counters, hipStream_t st) {
+  if (g.M <= CELL_SMALL) {
+    k_cell_state_small<<<1, 256, 0, st>>>(g, gas, mom, dt, dt_cell, cs, counters);
+    return hipGetLastError();
+  }
   k_reconstruct<<<cdiv(g.M, 128), 128, 0, st>>>(g, gas, mom, dt, dt_cell, cs, counters);
   k_stencil<<<cdiv(g.M, 256), 256, 0, st>>>(g, cs);
   return hipGetLastError();

@@ -31,14 +31,28 @@ __global__ void k_fill_first(int32_t* first, int64_t n, int32_t v) {
 // first[t] = the smallest cell c with offsets[c] >= t * T (tiles past the
 // last particle keep the prefilled M): cell c owns the tiles t with
 // offsets[c-1] < t T <= offsets[c].
-__global__ void k_tile_first(const int64_t* __restrict__ offsets, int64_t M, int64_t T,
-                             int64_t ntiles, int32_t* first) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c > M) return;
+__device__ __forceinline__ void tile_first(const int64_t* __restrict__ offsets, int64_t T,
+                                           int64_t ntiles, int32_t* first, int64_t c) {
   const int64_t lo = c == 0 ? 0 : offsets[c - 1] / T + 1;
   int64_t hi = offsets[c] / T;
   if (hi > ntiles) hi = ntiles;
   for (int64_t t = lo; t <= hi; ++t) first[t] = (int32_t)c;
+}
+
+__global__ void k_tile_first(const int64_t* __restrict__ offsets, int64_t M, int64_t T,
+                             int64_t ntiles, int32_t* first) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c <= M) tile_first(offsets, T, ntiles, first, c);
+}
+
+// Both passes in one block for grids of at most TILES_SMALL cells and tiles
+// (launch-bound steps); the barrier orders the fill before the starts.
+constexpr int64_t TILES_SMALL = 4096;
+__global__ __launch_bounds__(256) void k_tiles_small(const int64_t* __restrict__ offsets, int64_t M,
+                                                     int64_t T, int64_t ntiles, int32_t* first) {
+  for (int64_t t = threadIdx.x; t <= ntiles; t += blockDim.x) first[t] = (int32_t)M;
+  __syncthreads();
+  for (int64_t c = threadIdx.x; c <= M; c += blockDim.x) tile_first(offsets, T, ntiles, first, c);
 }
 
 // The three phases of one tile; st = LDS stage or the particle arrays.
@@ -155,6 +169,10 @@ __global__ __launch_bounds__(UPD_BLOCK, 4) void k_update(GridP g, GasP gas, BcP 
 
 hipError_t launch_tiles(const int64_t* offsets, int64_t M, int64_t T, int64_t ntiles,
                         int32_t* first, hipStream_t st) {
+  if (M < TILES_SMALL && ntiles < TILES_SMALL) {
+    k_tiles_small<<<1, 256, 0, st>>>(offsets, M, T, ntiles, first);
+    return hipGetLastError();
+  }
   k_fill_first<<<cdiv(ntiles + 1, 256), 256, 0, st>>>(first, ntiles + 1, (int32_t)M);
   k_tile_first<<<cdiv(M + 1, 256), 256, 0, st>>>(offsets, M, T, ntiles, first);
   return hipGetLastError();

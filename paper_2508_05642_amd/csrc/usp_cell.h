@@ -15,20 +15,26 @@ namespace usp {
 //   sum |C|^2 C_i = S3_i - m_i tr S - 2 (S m)_i + 2 N |m|^2 m_i,
 //   sum C_i e = S_ie - m_i sum e.
 // FP64 sums reduced by a fixed butterfly (deterministic).
+// One particle's inputs held in the state precision while its loads are in
+// flight (half the registers of FP64 for an FP32 state); widened exactly
+// when summed.
+template <typename PS>
 struct MomIn {
-  double c0, c1, c2, e, I;
+  PS c0, c1, c2, e;
+  uint32_t I;
 };
 
 template <typename PS>
-__device__ __forceinline__ MomIn mom_load(const PS* cx, const PS* cy, const PS* cz, const PS* er,
-                                          const uint8_t* vb, int64_t i) {
-  return MomIn{(double)cx[i], (double)cy[i], (double)cz[i], (double)er[i], (double)vb[i]};
+__device__ __forceinline__ MomIn<PS> mom_load(const PS* cx, const PS* cy, const PS* cz,
+                                              const PS* er, const uint8_t* vb, int64_t i) {
+  return MomIn<PS>{cx[i], cy[i], cz[i], er[i], (uint32_t)vb[i]};
 }
 
-__device__ __forceinline__ void mom_add(const MomIn& a, double r0, double r1, double r2,
+template <typename PS>
+__device__ __forceinline__ void mom_add(const MomIn<PS>& a, double r0, double r1, double r2,
                                         double* s) {
-  const double d0 = a.c0 - r0, d1 = a.c1 - r1, d2 = a.c2 - r2;
-  const double e = a.e, I = a.I;
+  const double d0 = (double)a.c0 - r0, d1 = (double)a.c1 - r1, d2 = (double)a.c2 - r2;
+  const double e = (double)a.e, I = (double)a.I;
   const double q = d0 * d0 + d1 * d1 + d2 * d2;
   s[0] += d0; s[1] += d1; s[2] += d2;
   s[3] += d0 * d0; s[4] += d1 * d1; s[5] += d2 * d2;
@@ -69,7 +75,7 @@ __device__ __forceinline__ void row_moments(const PS* cx, const PS* cy, const PS
     int64_t j[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) j[k] = at(i + k * MOM_LANES);
-    MomIn a[4];
+    MomIn<PS> a[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) a[k] = mom_load<PS>(cx, cy, cz, er, vb, j[k]);
 #pragma unroll

@@ -387,44 +387,58 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_far_place(const int32_t* far_tota
   }
 }
 
-// B2: the far moves into each cell in ascending input index.  One wave per
-// cell sorts lists of 2..FAR_SORT entries in its share of LDS (bitonic
-// network, distinct keys, so the result is the unique sorted list); longer
-// lists are left to the insertion sort of k_cell_bases.
+// B2: the far moves into each cell in ascending input index.  Each wave
+// takes cpw cells (1, or 64 on large grids, whose far moves are sparse) and
+// sorts their lists of 2..FAR_SORT entries in its share of LDS, one list at
+// a time (bitonic network, distinct keys, so the result is the unique sorted
+// list); longer lists are left to the insertion sort of k_cell_bases.
 constexpr int FAR_SORT = 512;
 
 __global__ __launch_bounds__(BIN_BLOCK) void k_far_sort(const int64_t* __restrict__ far_off,
-                                                        int64_t M, int32_t* far_list) {
+                                                        int64_t M, int32_t* far_list, int cpw) {
   __shared__ int32_t keys[BIN_BLOCK / 64][FAR_SORT];
-  const int64_t c = (int64_t)blockIdx.x * (BIN_BLOCK / 64) + (threadIdx.x >> 6);
-  if (c >= M) return;
   const int lane = threadIdx.x & 63;
-  const int64_t f0 = far_off[c], f1 = far_off[c + 1];
-  const int64_t n = f1 - f0;
-  if (n < 2 || n > FAR_SORT) return;
+  // lanes below cpw read one cell's list bounds each; the wave then sorts
+  // the lists of 2..FAR_SORT entries among them one after another
+  const int64_t cl = ((int64_t)blockIdx.x * (BIN_BLOCK / 64) + (threadIdx.x >> 6)) * cpw + lane;
+  int64_t f0l = 0, nl = 0;
+  if (lane < cpw && cl < M) {
+    f0l = far_off[cl];
+    nl = far_off[cl + 1] - f0l;
+  }
+  uint64_t todo = __ballot(nl >= 2 && nl <= FAR_SORT);
   int32_t* v = keys[threadIdx.x >> 6];
-  int P = 2;
-  while (P < n) P <<= 1;
-  for (int t = lane; t < P; t += 64) v[t] = t < n ? far_list[f0 + t] : INT32_MAX;
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  for (int k = 2; k <= P; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = lane; t < P; t += 64) {
-        const int u = t ^ j;
-        if (u > t) {
-          const int32_t a = v[t], b = v[u];
-          if ((a > b) == ((t & k) == 0)) {
-            v[t] = b;
-            v[u] = a;
+  while (todo) {
+    const int src = __ffsll((long long)todo) - 1;
+    todo &= todo - 1;
+    const int64_t f0 = __shfl(f0l, src, 64);
+    const int64_t n = __shfl(nl, src, 64);
+    int P = 2;
+    while (P < n) P <<= 1;
+    for (int t = lane; t < P; t += 64) v[t] = t < n ? far_list[f0 + t] : INT32_MAX;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    for (int k = 2; k <= P; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int t = lane; t < P; t += 64) {
+          const int u = t ^ j;
+          if (u > t) {
+            const int32_t a = v[t], b = v[u];
+            if ((a > b) == ((t & k) == 0)) {
+              v[t] = b;
+              v[u] = a;
+            }
           }
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
       }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-      __builtin_amdgcn_wave_barrier();
     }
+    for (int t = lane; t < n; t += 64) far_list[f0 + t] = v[t];
+    // the next list reuses this wave's keys
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
   }
-  for (int t = lane; t < n; t += 64) far_list[f0 + t] = v[t];
 }
 
 // C: one thread per new cell c.  The source groups (k = c - d, ascending k)
@@ -811,7 +825,9 @@ static hipError_t bin_launches(const GridP& g, const PartP<S>& in, const PartP<S
   }
   launch_scan(far_cnt, M, far_off, blocksums, nullptr, nullptr, st);
   k_far_place<<<64, BIN_BLOCK, 0, st>>>(far_total, far_c, far_i, far_off, far_cur, far_list);
-  k_far_sort<<<cdiv(M, BIN_BLOCK / 64), BIN_BLOCK, 0, st>>>(far_off, M, far_list);
+  const int far_cpw = M >= 64 * 1024 ? 64 : 1;
+  k_far_sort<<<cdiv(M, (BIN_BLOCK / 64) * far_cpw), BIN_BLOCK, 0, st>>>(far_off, M, far_list,
+                                                                       far_cpw);
   k_cell_bases<<<cdiv(M, BIN_BLOCK), BIN_BLOCK, 0, st>>>(g, nb, old_off, in.count, T9, far_off,
                                                           far_list, far_base, tail_cnt, nontail,
                                                           cnt_total);

@@ -85,32 +85,17 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_scan_reduce(const int32_t* counts
   if (threadIdx.x == 0) blocksums[blockIdx.x] = tot;
 }
 
-// one block: exclusive scan of the block sums in place; total -> offsets[M]
-// and the output particle count
-__global__ __launch_bounds__(BIN_BLOCK) void k_scan_top(int64_t* blocksums, int64_t nb,
-                                                        int64_t* offsets, int64_t M,
-                                                        int64_t* out_count, const int64_t* in_count) {
-  int64_t carry = 0;
-  for (int64_t b0 = 0; b0 < nb; b0 += BIN_BLOCK) {
-    const int64_t j = b0 + threadIdx.x;
-    const int64_t v = j < nb ? blocksums[j] : 0;
-    int64_t tot;
-    const int64_t ex = block_exclusive_scan(v, &tot);
-    if (j < nb) blocksums[j] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) {
-    offsets[M] = carry;
-    if (out_count) {
-      out_count[0] = carry;
-      out_count[1] = in_count[1];
-    }
-  }
-}
-
+// Each block adds up the totals of the blocks before it (at most a few
+// hundred, read from L2), then scans its own tile; the last block writes the
+// total to offsets[M] and the output particle count.
 __global__ __launch_bounds__(BIN_BLOCK) void k_scan_down(const int32_t* counts, int64_t M,
                                                          const int64_t* blocksums,
-                                                         int64_t* offsets) {
+                                                         int64_t* offsets, int64_t* out_count,
+                                                         const int64_t* in_count) {
+  int64_t before = 0;
+  for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += BIN_BLOCK) before += blocksums[b];
+  int64_t block_base;
+  block_exclusive_scan(before, &block_base);
   // blocked arrangement: thread t owns SCAN_ITEMS consecutive entries
   const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
   int32_t v[SCAN_ITEMS];
@@ -121,11 +106,18 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_scan_down(const int32_t* counts, 
     s += v[k];
   }
   int64_t tot;
-  int64_t run = blocksums[blockIdx.x] + block_exclusive_scan(s, &tot);
+  int64_t run = block_base + block_exclusive_scan(s, &tot);
   for (int k = 0; k < SCAN_ITEMS; ++k) {
     const int64_t j = base + k;
     if (j < M) offsets[j] = run;
     run += v[k];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    offsets[M] = block_base + tot;
+    if (out_count) {
+      out_count[0] = block_base + tot;
+      out_count[1] = in_count[1];
+    }
   }
 }
 
@@ -779,8 +771,7 @@ static void launch_scan(const int32_t* cnt, int64_t M, int64_t* out_off, int64_t
     return;
   }
   k_scan_reduce<<<nb, BIN_BLOCK, 0, st>>>(cnt, M, blocksums);
-  k_scan_top<<<1, BIN_BLOCK, 0, st>>>(blocksums, nb, out_off, M, out_count, in_count);
-  k_scan_down<<<nb, BIN_BLOCK, 0, st>>>(cnt, M, blocksums, out_off);
+  k_scan_down<<<nb, BIN_BLOCK, 0, st>>>(cnt, M, blocksums, out_off, out_count, in_count);
 }
 
 template <typename S, bool G>

@@ -6,12 +6,24 @@ Workload: Mach-10 N2 over a cylinder (half body), 600 x 300 cells of 1 mm,
 VHS gas with Parker / Millikan-White collision numbers, dt = 1.25e-7 s.
 A step is bin -> moments -> cell state -> the fused particle phase
 (collide + conserve + advect with injection, one pass), each a call of the
-C ABI on torch's current stream so HIP events bracket every phase.  `value` is particle-steps/s over exactly
---steps timed steps (inputs resident in HBM), after --warmup steps.
+C ABI on torch's current stream so HIP events bracket every phase.  `value`
+is particle-steps/s over exactly --steps timed steps (inputs resident in
+HBM), after --warmup steps.
 
-Also reported: the HBM roofline of the dominant kernel (algorithmic bytes
-per launch / its average event-timed duration) and the CPU oracle timed on
-the host on a bounded sample of the same workload.
+Also reported on the same line:
+  roofline      the HBM roofline of the dominant kernel (k_update): the
+                algorithmic bytes of one launch over its average duration,
+                timed with HIP events recorded by the library around that
+                kernel alone, against the 8 TB/s peak; the step's own HBM
+                fraction beside it;
+  oracle_error  the first step on the GPU against the FP64 oracle's first
+                step from the same initial state;
+  developed     particle-steps/s after --developed steps (the flow has
+                formed its shock layer);
+  adjoint       the pathwise adjoint's reverse/forward time ratio on the
+                differentiable channel;
+  c2            the batched 0D solve's throughput;
+  cpu_baseline  the oracle timed on the host's cores on a bounded sample.
 """
 import argparse
 import json
@@ -30,33 +42,18 @@ VALU_PEAK = 256 * 4 * 2.4e9 / 4
 COUNTERS_GLOB = os.path.join(ROOT, "profiles", "counters_*.md")
 METRIC = "particle-steps/s (full USP-FPM step) + HBM GB/s; adjoint/forward time ratio"
 PHASES = ("bin", "moments", "reconstruct", "update")
-# the kernel that dominates each phase (bin is a pipeline of small kernels
-# around two passes; update adds two tiny tile-index kernels before and the
-# injection kernels after k_update)
-PHASE_KERNEL = {"update": "k_update", "moments": "k_moments", "reconstruct": "k_reconstruct"}
 
 
-def algorithmic_bytes(phase, n, M):
-    """Bytes a phase must move at minimum for n particles and M cells (FP32
-    state: x, y, cx, cy, cz, erot 4 B each, vib 1 B, cell 4 B, pid 4 B;
-    cell-state plane 8 B per field)."""
-    per_particle = {
-        # the bin only records the new order: read cell, write the input
-        # index and the new cell of every slot
-        "bin": 4 + 4 + 4,
-        # read the slot's input index, then cx, cy, cz, erot, vib through it
-        "moments": 4 + 17,
-        "reconstruct": 0,
-        # read the input index and x, y, cx, cy, cz, erot, vib, pid through
-        # it plus the new cell; write every array of the new state
-        "update": 4 + 33 + 33,
-    }[phase]
-    # per cell: offsets 8; moments 21 planes; cell state reads 21 planes and
-    # writes 35 planes + a 128-byte record; update reads the record and 9
-    # conservation planes
-    per_cell = {"bin": 4 + 8, "moments": 21 * 8 + 8, "reconstruct": (21 + 35) * 8 + 128,
-                "update": 128 + 9 * 8 + 8}[phase]
-    return per_particle * n + per_cell * M
+# algorithmic bytes per particle-step of the whole step and of the fused
+# particle kernel (FP32 cylinder layout of 33 B per particle): moments read
+# 17, fused collide+conserve+advect read 29 and write 29, rebin scatter read
+# and write 66, per-cell traffic about 2; the fused kernel's per-cell bytes
+# are its cell record (128) and the conservation planes (9 x 8) with the
+# offsets (8)
+STEP_BYTES_PER_PARTICLE = 17 + 29 + 29 + 66
+STEP_BYTES_PER_CELL = 400
+UPDATE_BYTES_PER_PARTICLE = 29 + 29
+UPDATE_BYTES_PER_CELL = 128 + 9 * 8 + 8
 
 
 def stored_counters(kernel):
@@ -119,6 +116,95 @@ def _copy_peak(torch, dev):
     return round(2 * (1 << 30) / (best * 1e-3) / 1e9, 1)
 
 
+def _roctx():
+    """roctxProfilerResume/Pause of the ROCTx library (no-ops unless the
+    process runs under `rocprofv3 --selected-regions`), or None."""
+    import ctypes
+    for nm in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so"):
+        try:
+            L = ctypes.CDLL(nm)
+        except OSError:
+            continue
+        for f in (L.roctxProfilerResume, L.roctxProfilerPause):
+            f.argtypes = [ctypes.c_uint64]
+            f.restype = ctypes.c_int
+        return L
+    return None
+
+
+def _raw_event(torch):
+    """A timing torch.cuda.Event with its HIP event created (recorded once),
+    so that its handle can be given to the library."""
+    e = torch.cuda.Event(enable_timing=True)
+    e.record()
+    return e
+
+
+def _mom_scales(prob, om, names):
+    """The natural scale of each moment plane of each cell: the count 1, the
+    mean level max(1, I), velocities sqrt(R T) + |U|, second moments
+    R T + e_rot, heat fluxes (R T + e_rot) sqrt(R T), <C I> sqrt(R T) I."""
+    import numpy as np
+    T = np.maximum((om[names.index("PXX")] + om[names.index("PYY")] + om[names.index("PZZ")]) / 3,
+                   1.0)
+    c = np.sqrt(T)
+    Ib = np.maximum(1.0, om[names.index("IBAR")])
+    U = np.abs(om[1:4]).max(axis=0)
+    E = T + np.abs(om[names.index("EROT")])
+    sc = {}
+    for k in names:
+        sc[k] = {"N": np.ones_like(T), "IBAR": Ib}.get(k)
+        if k in ("UX", "UY", "UZ"):
+            sc[k] = c + U
+        elif k in ("PXX", "PYY", "PZZ", "PXY", "PXZ", "PYZ", "EROT"):
+            sc[k] = E
+        elif k.startswith("QTR") or k.startswith("QROT"):
+            sc[k] = E * c
+        elif k.startswith("QI"):
+            sc[k] = c * Ib
+    return sc
+
+
+def oracle_error(prob, g, o):
+    """The GPU's first step against the oracle's first step from the same
+    initial state.  g, o: {"mom", "cs", "state", "cnt"}.  Moments: the
+    largest difference over each cell's natural scale; cell state: the
+    largest relative difference (floored at 1e-6 of the plane's largest
+    value); particles (same slot order on both sides): the largest difference
+    of each array over the velocity scale (max sqrt(R T_tr) + |U| over the
+    cells), its square for e_rot, the domain length for x and y; the
+    fractions of equal levels and cells; whether the event counters agree."""
+    import numpy as np
+
+    import oracle
+    mn, cn = oracle.MOM_NAMES, oracle.CS_NAMES
+    om, gm = o["mom"], g["mom"]
+    sc = _mom_scales(prob, om, mn)
+    mom_err = max(float((np.abs(gm[k] - om[k]) / sc[nm]).max()) for k, nm in enumerate(mn))
+    oc, gc = o["cs"], g["cs"]
+    cs_err = 0.0
+    for k in range(len(cn)):
+        fs = np.max(np.abs(oc[k])) + 1e-300
+        cs_err = max(cs_err, float((np.abs(gc[k] - oc[k]) / (np.abs(oc[k]) + 1e-6 * fs)).max()))
+    T = oc[cn.index("TTR")]
+    U = np.abs(oc[cn.index("UX"):cn.index("UZ") + 1]).max(axis=0)
+    vs = float(np.max(np.sqrt(prob.gas.R * np.maximum(T, 1.0)) + U))
+    a, b = g["state"], o["state"]
+    res = {"particles": int(a["n"]), "same_count": bool(a["n"] == b["n"]),
+           "moments_vs_natural_scale": mom_err, "cell_state_relative": cs_err}
+    if a["n"] == b["n"]:
+        res["same_order"] = bool(np.array_equal(a["pid"], b["pid"]))
+        gr = prob.grid
+        scale = {"cx": vs, "cy": vs, "cz": vs, "erot": vs * vs, "x": gr.nx * gr.dx,
+                 "y": gr.ny * gr.dy}
+        res["particle_max_scaled_diff"] = {
+            k: float((np.abs(a[k] - b[k]) / scale[k]).max()) for k in scale if a.get(k) is not None}
+        res["vib_level_agreement"] = float(np.mean(a["vib"] == b["vib"]))
+        res["cell_agreement"] = float(np.mean(a["cell"] == b["cell"]))
+    res["counters_equal"] = bool(g["cnt"] == o["cnt"])
+    return res
+
+
 def run_gpu(args):
     import numpy as np
     import torch
@@ -142,8 +228,10 @@ def run_gpu(args):
         st.enable_sampling(args.sample)
     M = prob.grid.ncells
     step = 0
+    rtx = _roctx()
+    first = {}
 
-    def one_step(s, ev=None, nlog=None, k=None):
+    def one_step(s, ev=None, nlog=None, k=None, kev=None, keep=None):
         if ev: ev[0].record()
         st.bin(gather=True)
         if nlog is not None:
@@ -154,30 +242,44 @@ def run_gpu(args):
             st.sample_fields()
         if ev: ev[2].record()
         st.do_reconstruct()
+        if keep is not None:
+            keep["mom"], keep["cs"] = st.moments(), st.cellstate()
         if ev: ev[3].record()
-        st.update(s)
+        st.update(s, events=kev)
         if ev: ev[4].record()
+        if keep is not None:
+            keep["state"], keep["cnt"] = st.state(), st.cnt()
 
     for _ in range(args.warmup):
-        one_step(step)
+        # the first step from the initial state is kept for the comparison
+        # with the oracle's first step
+        one_step(step, keep=first if (step == 0 and args.oracle_error) else None)
         step += 1
     torch.cuda.synchronize()
     log(f"{args.warmup} warmup steps done")
     K = args.steps
     step0 = step
     snap = _snapshot(st)
-    # eager pass: per-phase times (events between the phases)
+    # eager pass: per-phase times (events between the phases) and the
+    # particle kernel alone (events the library records around it)
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(PHASES) + 1)] for _ in range(K)]
+    kevs = [(_raw_event(torch), _raw_event(torch)) for _ in range(K)]
     nlog = torch.zeros(K, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
+    if rtx:
+        rtx.roctxProfilerResume(0)
     t0 = time.perf_counter()
     for k in range(K):
-        one_step(step0 + k, evs[k], nlog, k)
+        one_step(step0 + k, evs[k], nlog, k,
+                 kev=(kevs[k][0].cuda_event, kevs[k][1].cuda_event))
     torch.cuda.synchronize()
     wall_eager = time.perf_counter() - t0
+    if rtx:
+        rtx.roctxProfilerPause(0)
     # timed pass: the same K steps from the same state, captured in one HIP
     # graph and replayed once
     _restore(st, snap)
+    del snap
     nlog_g = torch.zeros(K, dtype=torch.int64, device=dev)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
@@ -192,6 +294,7 @@ def run_gpu(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_graph = e0.elapsed_time(e1)
+    del graph
     ns = nlog_g.cpu().numpy()
     if not np.array_equal(ns, nlog.cpu().numpy()):
         raise RuntimeError("graph replay and eager pass disagree on the particle counts")
@@ -202,34 +305,41 @@ def run_gpu(args):
         for j, ph in enumerate(PHASES):
             phase_ms[ph] += evs[k][j].elapsed_time(evs[k][j + 1])
     phase_ms = {ph: v / K for ph, v in phase_ms.items()}
+    kms = [kevs[k][0].elapsed_time(kevs[k][1]) for k in range(K)]
+    k_ms = float(np.mean(kms))
     total_ps = float(ns.sum())
     n_mean = float(ns.mean())
-    dom = max(PHASE_KERNEL, key=lambda p: phase_ms[p])
-    t_dom = phase_ms[dom] * 1e-3
-    hbm = {"achieved": round(algorithmic_bytes(dom, n_mean, M) / t_dom / 1e9, 1),
-           "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(algorithmic_bytes(dom, n_mean, M) / t_dom / 1e9 / HBM_PEAK_GBS, 4),
-           "algorithmic_bytes_per_launch": int(algorithmic_bytes(dom, n_mean, M))}
-    # the stored counters are those of the USP-FPM update kernel
-    ctr = stored_counters(PHASE_KERNEL[dom]) if args.scheme == "usp" else None
+    ms_step = wall / K * 1e3
+    # the dominant kernel: bytes of one launch at the mean particle count
+    upd_bytes = UPDATE_BYTES_PER_PARTICLE * n_mean + UPDATE_BYTES_PER_CELL * M
+    ach = upd_bytes / (k_ms * 1e-3) / 1e9
+    step_bytes = STEP_BYTES_PER_PARTICLE * n_mean + STEP_BYTES_PER_CELL * M
+    step_gbs = step_bytes / (ms_step * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": "k_update", "achieved": round(ach, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": None, "avg_ms": round(k_ms, 4),
+            "min_ms": round(float(np.min(kms)), 4), "max_ms": round(float(np.max(kms)), 4),
+            "window": f"steps {step0}..{step0 + K - 1} (eager pass; HIP events around each "
+                      f"k_update launch, on its stream)",
+            "bytes_per_particle": UPDATE_BYTES_PER_PARTICLE,
+            "bytes_per_cell": UPDATE_BYTES_PER_CELL,
+            "algorithmic_bytes_per_launch": int(upd_bytes),
+            "step": {"achieved": round(step_gbs, 1), "frac": round(step_gbs / HBM_PEAK_GBS, 4),
+                     "bytes_per_particle": STEP_BYTES_PER_PARTICLE,
+                     "bytes_per_cell": STEP_BYTES_PER_CELL, "ms_per_step": round(ms_step, 4)}}
+    # counters of the same sources and flags (PMC), when they are on record
+    ctr = stored_counters("k_update") if args.scheme == "usp" else None
     if ctr:
-        # VALU wave-instructions per particle (PMC, same sources and flags,
-        # same steps) x particles per launch / event-timed launch
-        ach = ctr["valu_per_particle"] * n_mean / t_dom
-        roof = {"bound": "alu", "kernel": PHASE_KERNEL[dom], "phase": dom,
-                "achieved": round(ach / 1e9, 2), "peak": round(VALU_PEAK / 1e9, 1),
-                "unit": "G VALU wave-instr/s", "frac": round(ach / VALU_PEAK, 4),
-                "traffic": int(ctr["fetch_bytes"] + ctr["write_bytes"]),
-                "valu_per_particle": ctr["valu_per_particle"], "avg_ms": round(phase_ms[dom], 4),
-                "hbm": hbm}
-    else:
-        roof = dict(bound="hbm", kernel=PHASE_KERNEL[dom], phase=dom, traffic=None,
-                    avg_ms=round(phase_ms[dom], 4), **hbm)
-    step_bytes = sum(algorithmic_bytes(p, n_mean, M) for p in PHASES)
+        roof["traffic"] = int(ctr["fetch_bytes"] + ctr["write_bytes"])
+        roof["traffic_per_particle"] = round(roof["traffic"] / n_mean, 1)
+        valu = ctr["valu_per_particle"] * n_mean / (k_ms * 1e-3)
+        roof["valu"] = {"achieved": round(valu / 1e9, 2), "peak": round(VALU_PEAK / 1e9, 1),
+                        "unit": "G VALU wave-instr/s", "frac": round(valu / VALU_PEAK, 4),
+                        "valu_per_particle": ctr["valu_per_particle"]}
     cnt = st.cnt()
     res = dict(
         metric=METRIC, value=round(total_ps / wall, 1), unit="particle-steps/s", n_gpus=1,
-        steps=K, warmup=args.warmup, ms_per_step=round(wall / K * 1e3, 4),
+        steps=K, warmup=args.warmup, ms_per_step=round(ms_step, 4),
         higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
         data="synthetic",
         config={"workload": f"cylinder_mach10_{prob.grid.nx}x{prob.grid.ny}",
@@ -237,27 +347,58 @@ def run_gpu(args):
                 "state": "f32", "accumulation": "f64", "dt_s": prob.dt,
                 "first_timed_step": args.warmup, "sampling": bool(args.sample),
                 "scheme": args.scheme, "parallelism": "single-gpu"},
-        launch="one HIP graph of the K steps (per-phase times from an eager pass over the same "
-               "steps from the same state)",
+        launch="one HIP graph of the K steps (per-phase and k_update times from an eager pass "
+               "over the same steps from the same state)",
         eager_ms_per_step=round(wall_eager / K * 1e3, 4),
         graph_event_ms=round(ms_graph, 3),
         phase_ms=phase_ms,
-        step_algorithmic_gbs=round(step_bytes / (wall / K) / 1e9, 1),
+        step_algorithmic_gbs=round(step_gbs, 1),
         hbm_copy_gbs=hbm_copy,
         roofline=roof,
         counters={k: v for k, v in cnt.items() if v},
     )
-    return res, prob, parts
+    if args.developed and args.developed > step0 + K:
+        # keep stepping (eagerly, with the run's own step indices) until the
+        # shock layer has formed, then time K more steps
+        s = step0 + K
+        while s < args.developed:
+            one_step(s)
+            s += 1
+        torch.cuda.synchronize()
+        kd = [(_raw_event(torch), _raw_event(torch)) for _ in range(K)]
+        nd = torch.zeros(K, dtype=torch.int64, device=dev)
+        d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        d0.record()
+        for k in range(K):
+            one_step(s + k, None, nd, k, kev=(kd[k][0].cuda_event, kd[k][1].cuda_event))
+        d1.record()
+        torch.cuda.synchronize()
+        dms = d0.elapsed_time(d1)
+        ndm = nd.cpu().numpy()
+        kdm = float(np.mean([kd[k][0].elapsed_time(kd[k][1]) for k in range(K)]))
+        nmd = float(ndm.mean())
+        ub = UPDATE_BYTES_PER_PARTICLE * nmd + UPDATE_BYTES_PER_CELL * M
+        res["developed"] = {
+            "first_step": s, "steps": K, "value": round(float(ndm.sum()) / (dms * 1e-3), 1),
+            "unit": "particle-steps/s", "ms_per_step": round(dms / K, 4),
+            "particles_mean": int(nmd), "k_update_ms": round(kdm, 4),
+            "k_update_hbm_frac": round(ub / (kdm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "launch": "eager (events around the K steps)",
+            "counters_since_start": {k: v for k, v in st.cnt().items() if v}}
+        log(f"developed flow (steps {s}..{s + K - 1}): {res['developed']['value']:.4g} "
+            f"particle-steps/s, {dms / K:.4f} ms/step")
+    del st
+    torch.cuda.empty_cache()
+    return res, prob, parts, first
 
 
-def run_gpu_adjoint(args):
+def adjoint_timing(K, warmup=20, seg=32):
     """The differentiable Poiseuille case: Kn = 0.05, 100 cells x 500
     particles (50,000), FP64, K steps from the initial state.  Times a plain
     forward (usp_step), the checkpointed forward with output sampling, and
-    the reverse pass (re-run with tapes + usp_adjoint_step), every 32 steps
-    a checkpoint; then checks the gradient against central differences of
-    the outputs (h = 1e-4 relative, common random numbers: same seed)."""
-    import numpy as np
+    the reverse pass (re-run with tapes + usp_adjoint_step), a checkpoint
+    every `seg` steps.  Returns (times, outputs J, gradient G, prob, parts)."""
     import torch
 
     import usp_workloads as W
@@ -266,10 +407,10 @@ def run_gpu_adjoint(args):
     torch.cuda.set_device(0)
     prob = W.poiseuille(kn=0.05, cells=100, ppc=500, f32=False, seed=7)
     parts = W.particles_for(prob)
-    n, K, seg = int(parts["n"]), args.steps, 32
-    log(f"workload ready: {n} particles, {prob.grid.ncells} cells, {K} steps")
+    n = int(parts["n"])
+    log(f"adjoint workload ready: {n} particles, {prob.grid.ncells} cells, {K} steps")
     warm = usp.DeviceState(prob, parts)
-    for k in range(args.warmup):
+    for k in range(warmup):
         warm.step(k, 1)
     wa = ADJ.PathwiseAdjoint(prob, parts, min(K, 4), 2)
     wa.forward(0)
@@ -294,8 +435,26 @@ def run_gpu_adjoint(args):
     J, t_fwd = timed(lambda: adj.forward(0))
     G, t_bwd = timed(lambda: adj.backward())
     J, G = J.cpu().numpy(), G.cpu().numpy()
+    del st, adj
+    torch.cuda.empty_cache()
     log(f"plain forward {t_plain:.3f} s, forward with checkpoints {t_fwd:.3f} s, "
         f"reverse {t_bwd:.3f} s; J = {J}")
+    times = {"plain_forward": round(t_plain, 4), "forward_checkpointed": round(t_fwd, 4),
+             "reverse": round(t_bwd, 4)}
+    return times, J, G, prob, parts
+
+
+def run_gpu_adjoint(args):
+    """adjoint_timing over --steps steps, then the gradient against central
+    differences of the outputs (h = 1e-4 relative, common random numbers:
+    same seed)."""
+    import numpy as np
+
+    from paper_2508_05642_amd import adjoint as ADJ
+    K, seg = args.steps, 32
+    times, J, G, prob, parts = adjoint_timing(K, args.warmup, seg)
+    n = int(parts["n"])
+    t_plain, t_fwd, t_bwd = times["plain_forward"], times["forward_checkpointed"], times["reverse"]
     th0 = np.array([prob.gas.Z_rot, prob.gas.omega, prob.gas.mu_ref])
     fd = np.full((2, 3), np.nan)
     for p in range(3 if not args.no_fd else 0):
@@ -370,36 +529,53 @@ def run_cpu_adjoint_baseline(prob, parts, K=4):
                       f"({n} particles), FP64, {dt:.1f} s"}
 
 
-def _oracle_steps(prob, parts, nsteps, threads=0):
-    import oracle
-    sim = oracle.Sim(prob, parts, threads=threads)
-    total = 0
-    t0 = time.perf_counter()
-    for s in range(nsteps):
-        sim.bin()
-        total += sim.n
-        sim.do_moments()
-        sim.do_cellstate()
-        sim.collide(s)
-        sim.conserve(s)
-        sim.advect(s)
-    return total, time.perf_counter() - t0
+def _oracle_step(sim, s, keep=None):
+    sim.bin()
+    n = sim.n
+    sim.do_moments()
+    sim.do_cellstate()
+    if keep is not None:
+        keep["mom"], keep["cs"] = sim.moments().copy(), sim.cellstate().copy()
+    sim.collide(s)
+    sim.conserve(s)
+    sim.advect(s)
+    if keep is not None:
+        keep["state"], keep["cnt"] = sim.state(), sim.cnt()
+    return n
 
 
-def run_cpu_baseline(prob, parts, nsteps, one_core_steps=1, what="cylinder"):
-    """The oracle on all host threads for `nsteps` steps, and on one thread
-    for `one_core_steps` steps, from the workload's initial state."""
+def run_cpu_baseline(prob, parts, warm, timed, one_core_steps=1, what="cylinder", keep=None):
+    """The oracle on all host threads: `warm` steps from the workload's
+    initial state (the first kept in `keep` when given), then `timed` steps
+    timed; and `one_core_steps` steps on one thread from the initial
+    state."""
     import oracle
     all_threads = oracle.threads()
-    total, dt = _oracle_steps(prob, parts, nsteps)
+    sim = oracle.Sim(prob, parts)
+    for s in range(warm):
+        _oracle_step(sim, s, keep if s == 0 else None)
+    total = 0
+    t0 = time.perf_counter()
+    for s in range(warm, warm + timed):
+        total += _oracle_step(sim, s)
+    dt = time.perf_counter() - t0
+    del sim
     res = {"value": round(total / dt, 1), "unit": "particle-steps/s", "cores": all_threads,
            "kind": "oracle",
-           "sample": f"{nsteps} full steps of the same {what} workload from its initial state "
-                     f"({parts['n']} particles), FP64 oracle, {dt:.1f} s"}
+           "sample": f"steps {warm}..{warm + timed - 1} of the same {what} workload "
+                     f"({parts['n']} particles at start), timed after {warm} warm-up steps "
+                     f"from its initial state, FP64 oracle, {dt:.1f} s"}
     if one_core_steps > 0:
-        t1, d1 = _oracle_steps(prob, parts, one_core_steps, threads=1)
+        oracle.lib().orc_set_threads(1)
+        sim = oracle.Sim(prob, parts, threads=1)
+        t1 = 0
+        t0 = time.perf_counter()
+        for s in range(one_core_steps):
+            t1 += _oracle_step(sim, s)
+        d1 = time.perf_counter() - t0
+        del sim
         res["value_1core"] = round(t1 / d1, 1)
-        res["sample_1core"] = f"{one_core_steps} step(s) on 1 thread, {d1:.1f} s"
+        res["sample_1core"] = f"step(s) 0..{one_core_steps - 1} on 1 thread, {d1:.1f} s"
         oracle.lib().orc_set_threads(all_threads)
     return res
 
@@ -492,7 +668,14 @@ def main():
                          "angular elements on the cylinder (0 = no sampling)")
     ap.add_argument("--no-fd", action="store_true",
                     help="adjoint: skip the finite-difference runs (profiling)")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--developed", type=int, default=2000, metavar="STEP",
+                    help="cylinder: also time --steps steps from this step on (0 = skip)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="cylinder: skip the adjoint and batched-0D figures")
+    ap.add_argument("--no-oracle-error", dest="oracle_error", action="store_false",
+                    help="cylinder: skip the first-step comparison with the oracle")
+    ap.add_argument("--cpu-warmup", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scheme", choices=("usp", "fpm"), default="usp",
                     help="cylinder: the USP-FPM scheme (default) or the first-order FPM scheme")
@@ -525,15 +708,39 @@ def main():
         return
     if args.workload == "c2":
         res, prob, parts = run_gpu_c2(args)
-    else:
-        res, prob, parts = run_gpu(args)
+        log(f"GPU: {res['value']:.4g} particle-steps/s, {res['ms_per_step']} ms/step")
+        if not args.no_cpu_baseline:
+            res["cpu_baseline"] = run_cpu_baseline(prob, parts, args.cpu_warmup, args.cpu_steps,
+                                                   what="batched 0D")
+        print(json.dumps(res), flush=True)
+        return
+    res, prob, parts, first = run_gpu(args)
     log(f"GPU: {res['value']:.4g} particle-steps/s, {res['ms_per_step']} ms/step")
+    if not args.no_extras:
+        times, _, _, _, _ = adjoint_timing(2000)
+        res["adjoint"] = {
+            "workload": "poiseuille_kn0.05_100x500_adjoint (FP64, 2000 steps, checkpoint every 32)",
+            "adjoint_forward_ratio": round(times["reverse"] / times["plain_forward"], 3),
+            "forward_and_adjoint_ratio": round(
+                (times["forward_checkpointed"] + times["reverse"]) / times["plain_forward"], 3),
+            "times_s": times}
+        c2args = argparse.Namespace(steps=500, warmup=20, schedule=None)
+        c2, _, _ = run_gpu_c2(c2args)
+        res["c2"] = {"workload": c2["config"]["workload"], "value": c2["value"],
+                     "unit": c2["unit"], "ms_per_step": c2["ms_per_step"], "steps": 500,
+                     "schedule": c2["config"]["schedule"], "launch": "one HIP graph of 500 steps"}
+        log(f"adjoint/forward {res['adjoint']['adjoint_forward_ratio']}, "
+            f"c2 {c2['value']:.4g} particle-steps/s")
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = run_cpu_baseline(
-            prob, parts, args.cpu_steps, one_core_steps=1,
-            what="cylinder" if args.workload == "cylinder" else "batched 0D")
+        keep = {} if first else None
+        res["cpu_baseline"] = run_cpu_baseline(prob, parts, args.cpu_warmup, args.cpu_steps,
+                                               what="cylinder", keep=keep)
         log(f"CPU oracle: {res['cpu_baseline']['value']:.4g} particle-steps/s "
             f"({res['cpu_baseline'].get('value_1core', 0):.4g} on 1 thread)")
+        if keep:
+            res["oracle_error"] = oracle_error(prob, first, keep)
+            res["oracle_error"]["step"] = 0
+            log(f"oracle error of the first step: {res['oracle_error']}")
     print(json.dumps(res), flush=True)
 
 

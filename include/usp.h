@@ -10,16 +10,19 @@
  *   space is a caller buffer of usp_workspace_bytes() bytes.
  * - Structs themselves (usp_gas, usp_grid, usp_bc, usp_particles) live in
  *   HOST memory and are read during the call only.
- * - `stream` is a hipStream_t (passed as void*).  Every call enqueues work
- *   on it and returns without synchronising.  Nothing is copied between host
- *   and device, so calls may be captured in a HIP graph.
+ * - `stream` is a hipStream_t (passed as void*).  Every call except
+ *   usp_check enqueues work on it and returns without synchronising.
+ *   Nothing is copied between host and device, so those calls may be
+ *   captured in a HIP graph.
  * - The live particle count and the next free particle id are device
  *   scalars (usp_particles.count[0], count[1]); kernels read them on the
  *   device, so no step needs a host round trip.
  * - Return value: USP_OK, or a negative usp_status detected on the host
  *   before anything is enqueued (USP_EINVAL), or a HIP launch error
  *   (USP_EDEVICE).  Non-fatal physics events are counted on the device in
- *   the caller's int64 counters[USP_NCOUNTERS] (see enum below).
+ *   the caller's int64 counters[USP_NCOUNTERS] (see enum below); usp_check
+ *   turns the counts of non-finite values and dropped injections into the
+ *   statuses USP_ENUMERIC and USP_ECAPACITY.
  * - Cells are numbered c = j*nx + i (dim 2), c = j (dim 1, nx = 1), or are
  *   independent boxes c = 0..nx-1 (dim 0, ny = 1).  M = nx*ny.
  * - Plane buffers are FP64, plane-major: buf[k*M + c].
@@ -38,7 +41,8 @@ typedef int32_t usp_status;
 #define USP_OK 0
 #define USP_EINVAL -1      /* null pointer, bad size or dimension, dt <= 0 */
 #define USP_EDEVICE -2     /* a HIP launch or runtime error */
-#define USP_ECAPACITY -3   /* reserved: capacity problems are counted instead */
+#define USP_ECAPACITY -3   /* usp_check: injections were dropped for lack of capacity */
+#define USP_ENUMERIC -4    /* usp_check: a NaN or infinite value in the state */
 #define USP_EUNSUPPORTED -5
 
 #define USP_F32 0
@@ -96,7 +100,9 @@ enum {
   USP_CNT_BOUNCE_LIMIT = 13, /* flight stopped at the re-emission limit */
   USP_CNT_CAPACITY = 14,     /* injections dropped: capacity reached */
   USP_CNT_SOLID_DROP = 15,   /* particles found in a solid cell and removed */
-  USP_NCOUNTERS = 16
+  USP_CNT_NONFINITE = 16,    /* occupied cells with non-finite moments (not collided),
+                                plus the values usp_check finds */
+  USP_NCOUNTERS = 17
 };
 
 /* Gas model.  Sec. II.A (harmonic oscillator, Landau-Teller relaxation
@@ -276,16 +282,23 @@ usp_status usp_moments_gather(const usp_grid* grid, const usp_particles* in, con
    in[perm[j]] and writing the whole result state in slot order to `out`
    (whose cells and count usp_bin_gather set), injection included.  in and
    out must differ; bit-identical to usp_bin followed by usp_update.
+   ev_begin, ev_end (hipEvent_t, may be NULL): when given, recorded on
+   `stream` immediately before and after the launch of the particle kernel
+   itself (not the tile-index and injection kernels around it), so that a
+   caller can time that kernel alone.
    Errors: USP_EINVAL for a null or inconsistent argument, in == out, or a
    short ws. */
 usp_status usp_update_gather(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
                              const double* cs, const int64_t* offsets, const usp_particles* in,
                              const uint32_t* perm, usp_particles* out, void* ws, size_t ws_bytes,
-                             uint64_t seed, uint64_t step, int64_t* counters, void* stream);
+                             uint64_t seed, uint64_t step, int64_t* counters, void* ev_begin,
+                             void* ev_end, void* stream);
 
 /* Moments (Sec. II.A) of every cell from a binned state: mom = device
-   double[USP_NMOM*M].  Two passes per cell (U, then central moments),
-   accumulated in FP64 in a fixed order (deterministic). */
+   double[USP_NMOM*M].  One pass per cell over sums shifted by the cell's
+   first particle (for FP32 states every shifted difference is exact in
+   FP64), accumulated in FP64 in a fixed order (deterministic); the central
+   moments follow from the shifted sums. */
 usp_status usp_moments(const usp_grid* grid, const usp_particles* p, const int64_t* offsets,
                        double* mom, void* stream);
 
@@ -384,8 +397,9 @@ usp_status usp_batch(const usp_grid* grid, const usp_gas* gas, double dt, const 
    phase of usp_update) starting at step index `step`; in 0D only the first
    step bins.  p and p_alt are the two particle buffers;
    on return *p describes the buffer that holds the state (the two structs
-   are swapped as needed); p_alt->capacity >= p->capacity and ws is sized
-   for p_alt->capacity.  offsets, mom, cs as above (they describe the last
+   are swapped as needed); the two buffers must have equal capacities (the
+   state moves between them every step) and distinct arrays, and ws is sized
+   for that capacity.  offsets, mom, cs as above (they describe the last
    step's pre-collision state on return).  in_offsets (may be NULL, may
    alias offsets) is passed to the first step's usp_bin: when *p is the
    state a previous step or bin left (segments in in_offsets), the first
@@ -395,6 +409,23 @@ usp_status usp_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, 
                     int64_t* offsets, const int64_t* in_offsets, double* mom, double* cs,
                     void* ws, size_t ws_bytes, uint64_t seed, uint64_t step, int32_t nsteps,
                     int64_t* counters, void* stream);
+
+/* State check (the USP_ENUMERIC and USP_ECAPACITY statuses): scans the
+   live particles of p (count[0], read on the device) for NaN or infinite
+   x, y (as the grid uses them), cx, cy, cz and erot, and, when not NULL,
+   the moment planes mom (USP_NMOM*M) and the FP64 cell-state planes cs
+   (USP_NCS*M) of the occupied cells; the number of non-finite values found
+   is added to counters[USP_CNT_NONFINITE] (counters is required).  Unlike
+   every other entry point this call WAITS for `stream` (it copies the
+   counters to the host), so it cannot be captured in a HIP graph.
+   Returns USP_ENUMERIC if counters[USP_CNT_NONFINITE] is then non-zero
+   (cells flagged by usp_reconstruct count too), else USP_ECAPACITY if
+   counters[USP_CNT_CAPACITY] is non-zero, else USP_OK; *nonfinite (host,
+   may be NULL) receives the number of values this scan found.  Errors:
+   USP_EINVAL for a null or inconsistent argument, USP_EDEVICE for a HIP
+   error. */
+usp_status usp_check(const usp_grid* grid, const usp_particles* p, const double* mom,
+                     const double* cs, int64_t* counters, int64_t* nonfinite, void* stream);
 
 /* ---- pathwise adjoint (1D, FP64 state, USP-FPM scheme) -------------------
    Gradients of two time-averaged outputs of a run with respect to the

@@ -26,7 +26,7 @@ CS_NAMES = ["NP", "NDENS", "UX", "UY", "UZ", "TTR", "TROT", "TVIB",
             "FPM_TAU", "FPM_TTR_REL", "FPM_TROT_REL", "FPM_MREL"]
 CNT_NAMES = ["PB_CLAMP", "CHOL_FALLBACK", "NU_ZERO", "TREL_SKIP", "TREL_CLAMP", "VIB_SAT",
              "INTERP_CLAMP", "CONS_SKIP", "PICK_FAIL", "CELL_SKIP", "INJECTED", "DELETED",
-             "WALL_HITS", "BOUNCE_LIMIT", "CAPACITY", "SOLID_DROP"]
+             "WALL_HITS", "BOUNCE_LIMIT", "CAPACITY", "SOLID_DROP", "NONFINITE"]
 NMOM, NCS, NCNT = len(MOM_NAMES), len(CS_NAMES), len(CNT_NAMES)
 SAMP_NAMES = ["N", "CX", "CY", "CZ", "CXX", "CYY", "CZZ", "CXY", "CXZ", "CYZ", "EROT", "I",
               "HC2CX", "HC2CY", "HC2CZ", "CXEROT", "CYEROT", "CZEROT", "CXI", "CYI", "CZI"]

@@ -432,7 +432,11 @@ int orc_cellstate(const orc_grid* gr, const orc_gas* g, const double* mom, doubl
     double dtc = dt_cell ? dt_cell[c] : dt;
     v[ORC_CS_DT] = dtc;
     double Ttr = v[ORC_CS_TTR];
-    int collide = (N >= 2.0) && (Ttr > 0.0) && isfinite(Ttr) && (vol > 0.0);
+    /* a cell whose sums are not finite (a NaN or infinite velocity or
+       rotational energy among its particles) is not collided */
+    int finite = isfinite(v[ORC_CS_UX]) && isfinite(v[ORC_CS_UY]) && isfinite(v[ORC_CS_UZ]) &&
+                 isfinite(trP) && isfinite(v[ORC_CS_EROT]);
+    int collide = (N >= 2.0) && (Ttr > 0.0) && finite && (vol > 0.0);
     if (collide) {
       double mu = orc_viscosity(g, Ttr);
       double pres = v[ORC_CS_NDENS] * ORC_KB * Ttr;
@@ -701,7 +705,16 @@ int orc_collide(const orc_grid* gr, const orc_gas* g, const double* cs, const in
     for (int64_t c = 0; c < M; ++c) {
       int64_t o0 = offsets[c], o1 = offsets[c + 1];
       if (o1 == o0) continue;
-      if (cs[(int64_t)ORC_CS_COLLIDE * M + c] == 0.0) { lc[ORC_CNT_CELL_SKIP] += 1; continue; }
+      if (cs[(int64_t)ORC_CS_COLLIDE * M + c] == 0.0) {
+        lc[ORC_CNT_CELL_SKIP] += 1;
+        double trP = cs[(int64_t)ORC_CS_PXX * M + c] + cs[(int64_t)ORC_CS_PYY * M + c] +
+                     cs[(int64_t)ORC_CS_PZZ * M + c];
+        if (!(isfinite(cs[(int64_t)ORC_CS_UX * M + c]) && isfinite(cs[(int64_t)ORC_CS_UY * M + c]) &&
+              isfinite(cs[(int64_t)ORC_CS_UZ * M + c]) && isfinite(trP) &&
+              isfinite(cs[(int64_t)ORC_CS_EROT * M + c])))
+          lc[ORC_CNT_NONFINITE] += 1;
+        continue;
+      }
       if (g->scheme == ORC_SCHEME_FPM) {
         fpm_cell(gr, g, cs, c, o0, o1, p, seed, step, f32, lc);
         continue;

@@ -82,7 +82,8 @@ enum {
   ORC_CNT_BOUNCE_LIMIT = 13, /* flight stopped at the re-emission limit       */
   ORC_CNT_CAPACITY = 14,     /* injections dropped for lack of capacity       */
   ORC_CNT_SOLID_DROP = 15,   /* particle found in a solid cell, removed       */
-  ORC_NCNT = 16
+  ORC_CNT_NONFINITE = 16,    /* occupied cell with non-finite sums (skipped)  */
+  ORC_NCNT = 17
 };
 
 #define ORC_VIB_MAX 255

@@ -55,18 +55,38 @@ def stale():
     return any(os.path.getmtime(f) > t for f in SRC + HDR)
 
 
-def build(force=True, verbose=False):
-    """Compile every .hip source into one shared library (always, unless
-    force=False and the library is newer than all sources)."""
+OBJ_DIR = os.path.join(os.path.dirname(HERE), "_build")
+
+
+def _compile(src):
+    obj = os.path.join(OBJ_DIR, os.path.basename(src) + ".o")
+    flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    r = subprocess.run(["hipcc"] + flags + ["-c", "-o", obj, src], cwd=HERE,
+                       capture_output=True, text=True)
+    return obj, r
+
+
+def build(force=True, verbose=False, jobs=None):
+    """Compile every .hip source (one hipcc per source, in parallel) and
+    link them into one shared library (always, unless force=False and the
+    library is newer than all sources)."""
     if not force and not stale():
         return LIB
+    from concurrent.futures import ThreadPoolExecutor
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    jobs = jobs or min(len(SRC), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(jobs) as ex:
+        res = list(ex.map(_compile, SRC))
+    for obj, r in res:
+        if r.returncode != 0:
+            raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
+        if verbose and r.stderr:
+            print(r.stderr)
     tmp = LIB + ".tmp"
-    cmd = ["hipcc"] + HIPCC_FLAGS + ["-o", tmp] + SRC
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [o for o, _ in res]
     r = subprocess.run(cmd, cwd=HERE, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
-    if verbose:
-        print(r.stderr)
+        raise RuntimeError("hipcc link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
     return LIB
 

@@ -149,8 +149,8 @@ usp_status do_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, d
   const GridP g = make_grid(grid);
   const GasP gp = make_gas(gas);
   const BcP bp = make_bc(bc);
-  // the two buffers swap every step: lay the scratch out for the larger
-  const int64_t cap = p->capacity > p_alt->capacity ? p->capacity : p_alt->capacity;
+  // the two buffers swap every step (equal capacities)
+  const int64_t cap = p->capacity;
   const WsLayout L = ws_layout(g.M, cap, n_faces(g));
   char* w = (char*)ws;
   // Cells far larger than the fused particle phase's LDS stage (mean slots
@@ -229,7 +229,7 @@ const char* kCsNames[USP_NCS] = {
 const char* kCntNames[USP_NCOUNTERS] = {
     "PB_CLAMP", "CHOL_FALLBACK", "NU_ZERO", "TREL_SKIP", "TREL_CLAMP", "VIB_SAT",
     "INTERP_CLAMP", "CONS_SKIP", "PICK_FAIL", "CELL_SKIP", "INJECTED", "DELETED",
-    "WALL_HITS", "BOUNCE_LIMIT", "CAPACITY", "SOLID_DROP"};
+    "WALL_HITS", "BOUNCE_LIMIT", "CAPACITY", "SOLID_DROP", "NONFINITE"};
 
 }  // namespace
 
@@ -240,7 +240,8 @@ const char* usp_status_str(usp_status s) {
     case USP_OK: return "ok";
     case USP_EINVAL: return "invalid argument";
     case USP_EDEVICE: return "HIP device error";
-    case USP_ECAPACITY: return "particle capacity exceeded";
+    case USP_ECAPACITY: return "particle capacity exceeded (injections dropped)";
+    case USP_ENUMERIC: return "NaN or infinite value in the state";
     case USP_EUNSUPPORTED: return "unsupported";
     default: return "unknown status";
   }
@@ -313,7 +314,8 @@ usp_status usp_moments_gather(const usp_grid* grid, const usp_particles* in, con
 usp_status usp_update_gather(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
                              const double* cs, const int64_t* offsets, const usp_particles* in,
                              const uint32_t* perm, usp_particles* out, void* ws, size_t ws_bytes,
-                             uint64_t seed, uint64_t step, int64_t* counters, void* stream) {
+                             uint64_t seed, uint64_t step, int64_t* counters, void* ev_begin,
+                             void* ev_end, void* stream) {
   if (!grid_ok(grid) || !gas_ok(gas) || !parts_ok(in, grid) || !parts_ok(out, grid) || !cs ||
       !offsets || !ws || !perm)
     return USP_EINVAL;
@@ -329,11 +331,13 @@ usp_status usp_update_gather(const usp_grid* grid, const usp_gas* gas, const usp
   if (in->prec == USP_F32) {
     const PartP<float> src = make_parts<float>(in);
     return hip_status(launch_update<float>(g, gp, bp, dt, cs, offsets, make_parts<float>(out), seed,
-                                           step, (char*)ws, L, counters, st, &src, perm));
+                                           step, (char*)ws, L, counters, st, &src, perm,
+                                           (hipEvent_t)ev_begin, (hipEvent_t)ev_end));
   }
   const PartP<double> src = make_parts<double>(in);
   return hip_status(launch_update<double>(g, gp, bp, dt, cs, offsets, make_parts<double>(out), seed,
-                                          step, (char*)ws, L, counters, st, &src, perm));
+                                          step, (char*)ws, L, counters, st, &src, perm,
+                                          (hipEvent_t)ev_begin, (hipEvent_t)ev_end));
 }
 
 usp_status usp_moments(const usp_grid* grid, const usp_particles* p, const int64_t* offsets,
@@ -445,7 +449,11 @@ usp_status usp_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, 
                     int64_t* counters, void* stream) {
   if (!grid_ok(grid) || !gas_ok(gas) || !parts_ok(p, grid) || !parts_ok(p_alt, grid)) return USP_EINVAL;
   if (!offsets || !mom || !cs || !ws || nsteps < 0) return USP_EINVAL;
-  if (p->prec != p_alt->prec || p_alt->capacity < p->capacity || p->cx == p_alt->cx) return USP_EINVAL;
+  // the state moves between the two buffers every step, so both must hold
+  // the same number of slots (the bin copies up to the input's capacity)
+  if (p->prec != p_alt->prec || p_alt->capacity != p->capacity || p->cx == p_alt->cx ||
+      p->count == p_alt->count)
+    return USP_EINVAL;
   if (grid->dim >= 1 && (!bc || !(dt > 0.0))) return USP_EINVAL;
   if (!bc_ok(bc, grid)) return USP_EINVAL;
   if (!dt_cell && !(dt > 0.0)) return USP_EINVAL;
@@ -454,6 +462,29 @@ usp_status usp_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, 
   return p->prec == USP_F32
              ? do_step<float>(grid, gas, bc, dt, dt_cell, p, p_alt, offsets, in_offsets, mom, cs, ws, seed, step, nsteps, counters, st)
              : do_step<double>(grid, gas, bc, dt, dt_cell, p, p_alt, offsets, in_offsets, mom, cs, ws, seed, step, nsteps, counters, st);
+}
+
+usp_status usp_check(const usp_grid* grid, const usp_particles* p, const double* mom,
+                     const double* cs, int64_t* counters, int64_t* nonfinite, void* stream) {
+  if (!grid_ok(grid) || !parts_ok(p, grid) || !counters) return USP_EINVAL;
+  const GridP g = make_grid(grid);
+  hipStream_t st = (hipStream_t)stream;
+  int64_t* found = counters + USP_CNT_NONFINITE;
+  int64_t before[USP_NCOUNTERS];
+  if (hipMemcpyAsync(before, counters, sizeof(before), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return USP_EDEVICE;
+  const hipError_t e = p->prec == USP_F32
+      ? launch_check<float>(g, make_parts<float>(p), mom, cs, found, st)
+      : launch_check<double>(g, make_parts<double>(p), mom, cs, found, st);
+  if (e != hipSuccess) return USP_EDEVICE;
+  int64_t after[USP_NCOUNTERS];
+  if (hipMemcpyAsync(after, counters, sizeof(after), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return USP_EDEVICE;
+  if (nonfinite) *nonfinite = after[USP_CNT_NONFINITE] - before[USP_CNT_NONFINITE];
+  if (after[USP_CNT_NONFINITE] > 0) return USP_ENUMERIC;
+  if (after[USP_CNT_CAPACITY] > 0) return USP_ECAPACITY;
+  return USP_OK;
 }
 
 }  // extern "C"

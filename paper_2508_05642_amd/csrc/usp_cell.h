@@ -7,10 +7,11 @@
 namespace usp {
 
 // Moments of one cell (Sec. II.A): U = <c>, then central second and third
-// moments about U, per unit mass.  One wave per cell and one pass: sums of
-// d = c - c_0 (c_0 = the cell's first particle, so every d is exact in
-// FP64 and of the order of the thermal speed) and of its products, turned
-// into central moments with m = <d>:
+// moments about U, per unit mass.  One pass over 16 lanes per cell: sums of
+// d = c - c_0 (c_0 = the cell's first particle; d is of the order of the
+// thermal speed, and for an FP32 state it is exact in FP64, while for an
+// FP64 state it carries one rounding) and of its products, turned into
+// central moments with m = <d>:
 //   sum C_i C_j = S_ij - N m_i m_j,
 //   sum |C|^2 C_i = S3_i - m_i tr S - 2 (S m)_i + 2 N |m|^2 m_i,
 //   sum C_i e = S_ie - m_i sum e.
@@ -152,7 +153,12 @@ __device__ __forceinline__ void cell_state(const GridP& g, const GasP& gas, cons
   v[CS_TTR] = Ttr; v[CS_TROT] = Trot; v[CS_TVIB] = Tvib;
   v[CS_ETR] = 0.5 * trP; v[CS_EROT] = erot; v[CS_EVIB] = ibar * R * Th;
   v[CS_DT] = dtc;
-  const bool collide = N >= 2.0 && Ttr > 0.0 && isfinite(Ttr) && vol > 0.0;
+  // a NaN or infinite velocity or rotational energy in the cell makes its
+  // sums non-finite: such a cell is not collided, and it is counted
+  const bool finite = isfinite(v[CS_UX]) && isfinite(v[CS_UY]) && isfinite(v[CS_UZ]) &&
+                      isfinite(trP) && isfinite(erot);
+  if (N >= 1.0 && !finite) count_event(counters, USP_CNT_NONFINITE);
+  const bool collide = N >= 2.0 && Ttr > 0.0 && finite && vol > 0.0;
   if (collide && gas.scheme == USP_SCHEME_FPM) {
     // first-order FPM (Secs. II.B-II.C): nu from Pr, tau = 2 mu (1-nu)/p,
     // the update factor exp(-dt/tau) and the cell relaxation temperatures

@@ -149,7 +149,14 @@ hipError_t launch_update(const GridP& g, const GasP& gas, const BcP& bc, double 
                          const double* cs, const int64_t* offsets, const PartP<S>& p,
                          uint64_t seed, uint64_t step, char* ws, const WsLayout& L,
                          int64_t* counters, hipStream_t st, const PartP<S>* src = nullptr,
-                         const uint32_t* gather_perm = nullptr);
+                         const uint32_t* gather_perm = nullptr, hipEvent_t ev_begin = nullptr,
+                         hipEvent_t ev_end = nullptr);
+// Adds to *found the number of NaN or infinite values among the live
+// particles' floating arrays and, when given, the moment and FP64
+// cell-state planes of the occupied cells.
+template <typename S>
+hipError_t launch_check(const GridP& g, const PartP<S>& p, const double* mom, const double* cs,
+                        int64_t* found, hipStream_t st);
 
 // first[t] (t = 0..ntiles) = first cell of tile t: the cells whose first
 // particle slot lies in [t T, (t+1) T)

@@ -183,7 +183,7 @@ hipError_t launch_update(const GridP& g, const GasP& gas, const BcP& bc, double 
                          const double* cs, const int64_t* offsets, const PartP<S>& p,
                          uint64_t seed, uint64_t step, char* ws, const WsLayout& L,
                          int64_t* counters, hipStream_t st, const PartP<S>* src,
-                         const uint32_t* gather_perm) {
+                         const uint32_t* gather_perm, hipEvent_t ev_begin, hipEvent_t ev_end) {
   const int64_t T = update_tile(UpdCfg<S>::STAGE, p.capacity, g.M);
   const int64_t ntiles = cdiv(p.capacity, T);
   int32_t* first = (int32_t*)(ws + L.tiles);
@@ -192,6 +192,7 @@ hipError_t launch_update(const GridP& g, const GasP& gas, const BcP& bc, double 
   const int adv = g.dim != 0 ? 1 : 0;
   const bool fpm = gas.scheme == USP_SCHEME_FPM;
   const PartP<S> sp = src ? *src : p;
+  if (ev_begin && hipEventRecord(ev_begin, st) != hipSuccess) return hipGetLastError();
   if (gather_perm && fpm)
     k_update<S, true, true><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, bc, dt, cs, offsets, first, p, seed,
                                                           s32, adv, counters, sp, gather_perm);
@@ -205,6 +206,7 @@ hipError_t launch_update(const GridP& g, const GasP& gas, const BcP& bc, double 
     k_update<S, false, false><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, bc, dt, cs, offsets, first, p,
                                                             seed, s32, adv, counters, sp, nullptr);
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess && ev_end) e = hipEventRecord(ev_end, st);
   if (e != hipSuccess || g.dim == 0) return e;
   return launch_inject<S>(g, gas, bc, dt, p, seed, step, ws, L, counters, st);
 }
@@ -212,10 +214,12 @@ hipError_t launch_update(const GridP& g, const GasP& gas, const BcP& bc, double 
 template hipError_t launch_update<float>(const GridP&, const GasP&, const BcP&, double,
                                          const double*, const int64_t*, const PartP<float>&,
                                          uint64_t, uint64_t, char*, const WsLayout&, int64_t*,
-                                         hipStream_t, const PartP<float>*, const uint32_t*);
+                                         hipStream_t, const PartP<float>*, const uint32_t*,
+                                         hipEvent_t, hipEvent_t);
 template hipError_t launch_update<double>(const GridP&, const GasP&, const BcP&, double,
                                           const double*, const int64_t*, const PartP<double>&,
                                           uint64_t, uint64_t, char*, const WsLayout&, int64_t*,
-                                          hipStream_t, const PartP<double>*, const uint32_t*);
+                                          hipStream_t, const PartP<double>*, const uint32_t*,
+                                          hipEvent_t, hipEvent_t);
 
 }  // namespace usp

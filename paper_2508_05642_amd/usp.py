@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libusp.so")
 
 USP_F32, USP_F64 = 0, 1
-NMOM, NCS, NCOUNTERS = 21, 39, 16
+NMOM, NCS, NCOUNTERS = 21, 39, 17
 NSAMP, SURF_NQ = 21, 9
 SURF_HITS, SURF_PX, SURF_PY, SURF_PZ, SURF_PN, SURF_PT, SURF_ETR, SURF_EROT, SURF_QVIB = range(9)
 SURF_P_SCALE, SURF_E_SCALE = 65536.0, 16.0
@@ -84,7 +84,9 @@ def lib():
         L.usp_sample_fields.argtypes = [vp, vp, vp, vp]
         L.usp_bin_gather.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp, vp]
         L.usp_moments_gather.argtypes = [vp, vp, vp, vp, vp, vp]
-        L.usp_update_gather.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, vp, vp, sz, u64, u64, vp, vp]
+        L.usp_update_gather.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, vp, vp, sz, u64, u64, vp, vp,
+                                        vp, vp]
+        L.usp_check.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.usp_bin.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp, vp]
         L.usp_moments.argtypes = [vp, vp, vp, vp, vp]
         L.usp_reconstruct.argtypes = [vp, vp, vp, d, vp, vp, vp, vp]
@@ -107,7 +109,7 @@ def lib():
         for nm in ("usp_bin", "usp_bin_gather", "usp_moments_gather", "usp_update_gather",
                    "usp_moments", "usp_sample_fields", "usp_reconstruct", "usp_collide",
                    "usp_conserve", "usp_advect", "usp_update", "usp_batch", "usp_step",
-                   "usp_step_taped", "usp_adjoint_step"):
+                   "usp_step_taped", "usp_adjoint_step", "usp_check"):
             getattr(L, nm).restype = i32
         _lib = L
     return _lib
@@ -118,7 +120,7 @@ EXPORTED = ["usp_status_str", "usp_mom_name", "usp_cs_name", "usp_counter_name",
             "usp_bin_gather", "usp_moments_gather", "usp_update_gather",
             "usp_moments", "usp_sample_fields", "usp_reconstruct", "usp_collide", "usp_conserve",
             "usp_advect", "usp_update", "usp_batch", "usp_step", "usp_tape_bytes",
-            "usp_adjoint_ws_bytes", "usp_step_taped", "usp_adjoint_step"]
+            "usp_adjoint_ws_bytes", "usp_step_taped", "usp_adjoint_step", "usp_check"]
 
 
 def names(kind):
@@ -226,11 +228,30 @@ def usp_moments_gather(grid, pin, perm, offsets, mom, stream=None):
 
 
 def usp_update_gather(grid, gas, bc, dt, cs, offsets, pin, perm, pout, seed, step, ws, counters,
-                      stream=None):
+                      stream=None, events=None):
+    """events: optional pair of raw hipEvent_t handles (ints) recorded just
+    before and after the particle kernel itself."""
+    ev0, ev1 = (None, None) if events is None else (C.c_void_p(events[0]), C.c_void_p(events[1]))
     _check(lib().usp_update_gather(C.byref(grid), C.byref(gas), None if bc is None else C.byref(bc),
                                    dt, _cs(grid, cs), _offsets(grid, offsets), C.byref(pin),
                                    _perm(perm, pin), C.byref(pout), *_ws(ws), seed, step,
-                                   _cnt(counters), _stream(stream)), "usp_update_gather")
+                                   _cnt(counters), ev0, ev1, _stream(stream)), "usp_update_gather")
+
+
+def usp_check(grid, p, mom, cs, counters, stream=None):
+    """Scan p (and mom, cs when given) for NaN/Inf; waits for the stream.
+    Returns (status, nonfinite values found by this scan); the status is
+    USP_OK (0), USP_ENUMERIC (-4) or USP_ECAPACITY (-3); other statuses
+    raise."""
+    found = C.c_int64(0)
+    st = lib().usp_check(C.byref(grid), C.byref(p),
+                         None if mom is None else _planes(grid, mom, NMOM, "mom"),
+                         None if cs is None else _cs(grid, cs),
+                         _dev(counters, torch.int64, NCOUNTERS, "counters"), C.byref(found),
+                         _stream(stream))
+    if st not in (0, -3, -4):
+        _check(st, "usp_check")
+    return int(st), int(found.value)
 
 
 def usp_moments(grid, p, offsets, mom, stream=None):
@@ -495,14 +516,15 @@ class DeviceState:
         usp_advect(self.grid, self.gas, self.bc, self.prob.dt, self.p, self.prob.seed, step,
                    self.ws, self.counters, stream)
 
-    def update(self, step, stream=None):
+    def update(self, step, stream=None, events=None):
         """collide + conserve + advect in one fused pass (binned state, or
-        the recorded order of a gathering bin)."""
+        the recorded order of a gathering bin; `events` as for
+        usp_update_gather)."""
         bc = self.bc if self.dim >= 1 else None
         if self.gathered:
             usp_update_gather(self.grid, self.gas, bc, self.prob.dt, self.cs, self.offsets, self.p,
                               self.perm, self.p_alt, self.prob.seed, step, self.ws, self.counters,
-                              stream)
+                              stream, events)
             self.cur = 1 - self.cur
             self.gathered = False
             return
@@ -528,6 +550,11 @@ class DeviceState:
             B0, B1 = self.bufs[self.cur], self.bufs[1 - self.cur]
             B0["struct"], B1["struct"] = B1["struct"], B0["struct"]
             self.cur = 1 - self.cur
+
+    def check(self, stream=None):
+        """usp_check of the current state, its moments and cell state:
+        (status, non-finite values found)."""
+        return usp_check(self.grid, self.p, self.mom, self.cs, self.counters, stream)
 
     def step_taped(self, step, tape, aws, stream=None):
         """One step (the bits of step()) that also writes its tape."""

@@ -83,3 +83,51 @@ def test_binding_rejects_host_tensors_before_any_call():
     with pytest.raises(ValueError, match="ws: expected a tensor on a GPU"):
         usp.usp_advect(g, usp.UspGas(), usp.UspBC(), 1e-6, p, 0, 0,
                        torch.zeros(16, dtype=torch.uint8), None)
+
+
+def _fake_parts(usp, cap, base):
+    """A particle struct whose arrays are non-null stand-in addresses: only
+    for calls that must fail in the host-side checks, before any enqueue."""
+    a = [base + 0x1000 * k for k in range(10)]
+    return usp.UspParticles(usp.USP_F32, cap, a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7],
+                            a[8], a[9])
+
+
+def test_step_rejects_unequal_buffer_capacities():
+    """usp_step moves the state between its two buffers every step, so the
+    buffers must hold the same number of slots: a larger second buffer
+    would let the injection fill slots the first cannot take on the next
+    bin.  Unequal capacities, and buffers that share arrays or the count,
+    are rejected with USP_EINVAL on the host."""
+    from paper_2508_05642_amd import usp
+    import usp_workloads as W
+    L = usp.lib()
+    prob = W.poiseuille(kn=0.05, cells=10, ppc=10, f32=True)
+    g = usp.UspGrid(1, 1, 10, 0.0, 0.0, 1e-4, 1e-4, 1.0, 0x10, None)
+    gas, bc = usp.make_gas(prob.gas), usp.make_bc(prob.bc)
+    fake = 0x7000_0000
+
+    def step(p, q):
+        return L.usp_step(ctypes.byref(g), ctypes.byref(gas), ctypes.byref(bc), 1e-8, None,
+                          ctypes.byref(p), ctypes.byref(q), fake, None, fake, fake, fake,
+                          1 << 40, 1, 0, 1, None, None)
+    assert step(_fake_parts(usp, 100, 0x1000_0000), _fake_parts(usp, 200, 0x2000_0000)) == -1
+    assert step(_fake_parts(usp, 200, 0x1000_0000), _fake_parts(usp, 100, 0x2000_0000)) == -1
+    # shared count
+    p, q = _fake_parts(usp, 100, 0x1000_0000), _fake_parts(usp, 100, 0x2000_0000)
+    q.count = p.count
+    assert step(p, q) == -1
+
+
+def test_check_statuses_and_host_validation():
+    """usp_check reports USP_ENUMERIC and USP_ECAPACITY by name and
+    rejects a missing counters array on the host."""
+    from paper_2508_05642_amd import usp
+    L = usp.lib()
+    assert L.usp_status_str(-4) == b"NaN or infinite value in the state"
+    assert b"capacity" in L.usp_status_str(-3)
+    assert usp.names("cnt")[16] == "NONFINITE" and usp.NCOUNTERS == 17
+    g = usp.UspGrid(1, 1, 10, 0.0, 0.0, 1e-4, 1e-4, 1.0, 0x10, None)
+    p = _fake_parts(usp, 100, 0x1000_0000)
+    assert L.usp_check(ctypes.byref(g), ctypes.byref(p), None, None, None, None, None) == -1
+    assert L.usp_check(None, ctypes.byref(p), None, None, 0x10, None, None) == -1

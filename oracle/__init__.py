@@ -68,12 +68,26 @@ class OrcParts(C.Structure):
                 ("cell", C.c_void_p), ("pid", C.c_void_p), ("next_pid", C.c_uint64)]
 
 
+# With ORACLE_SANITIZE=1 in the environment the oracle is built and loaded
+# as liboracle_san.so, instrumented with AddressSanitizer and
+# UndefinedBehaviorSanitizer (every finding aborts).  The Python process
+# must then preload the ASan runtime, e.g.
+#   ORACLE_SANITIZE=1 LD_PRELOAD=$(gcc -print-file-name=libasan.so) \
+#   ASAN_OPTIONS=detect_leaks=0 python -m pytest tests -m "not gpu"
+SANITIZE = os.environ.get("ORACLE_SANITIZE", "") not in ("", "0")
+if SANITIZE:
+    _LIB = os.path.join(_HERE, "liboracle_san.so")
+
+
 def build(force=False):
     """Compile liboracle.so with gcc (plain C11, FP64, OpenMP, no FMA contraction)."""
     if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
         return _LIB
     cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fopenmp", "-fPIC",
            "-shared", "-o", _LIB, _SRC, "-lm"]
+    if SANITIZE:
+        cmd[1:1] = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=all"]
     subprocess.run(cmd, check=True, cwd=_HERE)
     return _LIB
 
@@ -98,6 +112,7 @@ def lib():
         L.orc_tcheck.restype = d
         L.orc_gammas.argtypes = [vp, d, d, d, d, d, vp, vp]
         L.orc_eigvals_sym3.argtypes = [vp, vp]
+        L.orc_particle_coef.argtypes = [vp, d, d, d, vp] + [d] * 9 + [vp]
         L.orc_bin.argtypes = [vp, vp, vp, vp, i32, vp]
         L.orc_moments.argtypes = [vp, vp, vp, vp, vp]
         L.orc_cellstate.argtypes = [vp, vp, vp, d, vp, vp]
@@ -166,6 +181,27 @@ class Gas:
         tc = C.c_double(0.0)
         lib().orc_gammas(self.ref, Ttr, Trot, Tvib, a, b, _p(out), C.byref(tc))
         return out, tc.value
+
+
+class OrcPCoef(C.Structure):
+    _fields_ = [("L", C.c_double * 6), ("al", C.c_double), ("oma2", C.c_double),
+                ("nu", C.c_double), ("nu_bound", C.c_double), ("Ttr_rel", C.c_double),
+                ("Trot_rel", C.c_double), ("mstar", C.c_double), ("fallback", C.c_int32),
+                ("nu_zero", C.c_int32), ("skip", C.c_int32)]
+
+
+def particle_coef(gas, Ttr, Trot, Tvib, P, a, b, al, oma2, nu, r2, A2, Pr, dt):
+    """orc_particle_coef (Secs. III.A.1-III.A.3) for one particle: its
+    interpolated temperatures and Pi (xx, yy, zz, xy, xz, yz), and the cell
+    coefficients; returns the fields of orc_pcoef as a dict."""
+    g = gas if isinstance(gas, Gas) else Gas(gas)
+    P = np.ascontiguousarray(P, np.float64)
+    out = OrcPCoef()
+    lib().orc_particle_coef(g.ref, Ttr, Trot, Tvib, _p(P), a, b, al, oma2, nu, r2, A2, Pr, dt,
+                            C.byref(out))
+    r = {k: getattr(out, k) for k, _ in OrcPCoef._fields_ if k != "L"}
+    r["L"] = np.array(out.L[:])
+    return r
 
 
 def eigvals_sym3(P):

@@ -691,10 +691,119 @@ static void fpm_cell(const orc_grid* gr, const orc_gas* g, const double* cs, int
   }
 }
 
+/* ======================================================================== */
+/* Per-particle coefficients of one particle (Secs. III.A.1-III.A.3): the   */
+/* gamma coefficients at the interpolated temperatures, the relaxation      */
+/* temperatures (eqs. T_tr_USP, T_rot_USP, T_vib_USP) with the cell's       */
+/* alpha and nu, the tensor Lambda = R T_tr^rel I + nu (Pi - R T_tr I)      */
+/* (tau times the diffusion tensor of eq. D_tr) and its Cholesky test.      */
+/* When the test fails: nu is moved into the positive-definite range of     */
+/* eq. nu_USP_positivity (bounds at the relaxation temperature of the cell  */
+/* coefficients, kept 2^-20 inside so the re-test can pass), alpha^2        */
+/* refitted by eq. alpha_USP_positivity_1 (clamped to [0, 1]), the sign of  */
+/* alpha chosen by the Prandtl number of eq. alpha_USP_positivity_3 that is */
+/* closer to the cell's (ties: +), alpha_rot = alpha_vib = alpha_tr (eq.    */
+/* alpha_USP_positivity_4), the relaxation temperatures recomputed with the */
+/* new 1 - alpha^2 and Lambda re-tested; a second failure sets nu = 0       */
+/* (Lambda = R T_tr^rel I, alpha kept).  T_tr^rel <= 0 (before or after    */
+/* the refit) or 1 - alpha^2 = 0 after it skips the particle.               */
+/* Cell inputs: a, b (eqs. of the gammas), alpha, 1 - alpha^2, nu, r2 =     */
+/* (2mu/p - dt)/(2mu/p + dt), A2 = 2 mu/p, the cell's Pr and dt.            */
+/* ======================================================================== */
+void orc_particle_coef(const orc_gas* g, double Ttr, double Trot, double Tvib, const double P[6],
+                       double a, double b, double al_cell, double oma2_cell, double nu_cell,
+                       double r2, double A2, double Pr, double dtc, orc_pcoef* out) {
+  double R = orc_R(g), Th = g->theta_vib;
+  double gm[3];
+  orc_gammas(g, Ttr, Trot, Tvib, a, b, gm, NULL);
+  /* energy handed on by each mode in one step (eqs. e_*_relax) */
+  double Xtr = gm[0] * (Ttr - Trot) + gm[1] * (Ttr - Tvib);
+  double Xrot = gm[0] * (Ttr - Trot) - gm[2] * (Trot - Tvib);
+  double Xvib = gm[1] * (Ttr - Tvib) + gm[2] * (Trot - Tvib);
+  double al = al_cell, oma2 = oma2_cell, nu = nu_cell;
+  /* relaxation temperatures, eqs. T_tr_USP, T_rot_USP, T_vib_USP */
+  double Ttr_rel = Ttr - Xtr / (oma2 * 1.5 * R);
+  double Trot_rel = Trot + Xrot / (oma2 * R);
+  double mstar = orc_e_vib(g, Tvib) / (R * Th) + Xvib / (oma2 * R * Th);
+  /* diffusion tensor (times tau), eq. D_tr, and its Cholesky test */
+  double RT = R * Ttr;
+  double Lam[6], L[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = 0; k < 3; ++k) Lam[k] = R * Ttr_rel + nu * (P[k] - RT);
+  for (int k = 3; k < 6; ++k) Lam[k] = nu * P[k];
+  int ok = chol3(Lam, L);
+  int skip = 0, fallback = 0, nu_zero = 0;
+  out->nu_bound = 0.0;
+  if (!ok) {
+    fallback = 1;
+    if (!(Ttr_rel > 0.0)) {
+      skip = 1;
+    } else {
+      /* nu clamped into the positive-definite range, eq.            */
+      /* nu_USP_positivity; kept a hair inside the bound so the     */
+      /* re-test can pass.                                          */
+      double ev[3];
+      orc_eigvals_sym3(P, ev);
+      double RTr = R * Ttr_rel;
+      const double shrink = 1.0 - 1.0 / 1048576.0;
+      if (nu <= 0.0) {
+        if (ev[2] > RT) {
+          out->nu_bound = -RTr / (ev[2] - RT);
+          nu = fmax(nu, -RTr / (ev[2] - RT) * shrink);
+        }
+      } else {
+        if (ev[0] < RT) {
+          out->nu_bound = RTr / (RT - ev[0]);
+          nu = fmin(nu, RTr / (RT - ev[0]) * shrink);
+        }
+      }
+      /* alpha refit, eqs. alpha_USP_positivity_1..4 */
+      double a2 = (nu - r2) / (nu - 1.0);
+      if (a2 < 0.0) a2 = 0.0;
+      if (a2 > 1.0) a2 = 1.0;
+      double ap = sqrt(a2), am = -sqrt(a2);
+      double Prp = A2 * (1.0 - ap * ap * ap) / (dtc * (1.0 + ap * ap * ap));
+      double Prm = A2 * (1.0 - am * am * am) / (dtc * (1.0 + am * am * am));
+      al = (fabs(Prm - Pr) < fabs(Prp - Pr)) ? am : ap;
+      oma2 = 1.0 - a2;
+      if (!(oma2 > 0.0)) {
+        skip = 1;
+      } else {
+        Ttr_rel = Ttr - Xtr / (oma2 * 1.5 * R);
+        Trot_rel = Trot + Xrot / (oma2 * R);
+        mstar = orc_e_vib(g, Tvib) / (R * Th) + Xvib / (oma2 * R * Th);
+        for (int k = 0; k < 3; ++k) Lam[k] = R * Ttr_rel + nu * (P[k] - RT);
+        for (int k = 3; k < 6; ++k) Lam[k] = nu * P[k];
+        ok = chol3(Lam, L);
+        if (!ok) {
+          nu_zero = 1;
+          nu = 0.0;
+          if (Ttr_rel > 0.0) {
+            double s0 = sqrt(R * Ttr_rel);
+            L[0] = s0; L[1] = 0.0; L[2] = s0; L[3] = 0.0; L[4] = 0.0; L[5] = s0;
+            ok = 1;
+          } else {
+            skip = 1;
+          }
+        }
+      }
+    }
+  }
+  for (int k = 0; k < 6; ++k) out->L[k] = L[k];
+  out->al = al;
+  out->oma2 = oma2;
+  out->nu = nu;
+  out->Ttr_rel = Ttr_rel;
+  out->Trot_rel = Trot_rel;
+  out->mstar = mstar;
+  out->fallback = fallback;
+  out->nu_zero = nu_zero;
+  out->skip = skip;
+}
+
 int orc_collide(const orc_grid* gr, const orc_gas* g, const double* cs, const int64_t* offsets,
                 orc_parts* p, uint64_t seed, uint64_t step, int32_t f32, int64_t* counters) {
   int64_t M = ncells(gr);
-  double R = orc_R(g), Th = g->theta_vib;
+  double R = orc_R(g);
   int64_t cnt[ORC_NCNT];
   memset(cnt, 0, sizeof(cnt));
 #pragma omp parallel
@@ -743,73 +852,14 @@ int orc_collide(const orc_grid* gr, const orc_gas* g, const double* cs, const in
         }
         if (clamped) lc[ORC_CNT_INTERP_CLAMP] += 1;
         double Ttr = T[0], Trot = T[1], Tvib = T[2];
-        double gm[3];
-        orc_gammas(g, Ttr, Trot, Tvib, a, b, gm, NULL);
-        /* energy handed on by each mode in one step (eqs. e_*_relax) */
-        double Xtr = gm[0] * (Ttr - Trot) + gm[1] * (Ttr - Tvib);
-        double Xrot = gm[0] * (Ttr - Trot) - gm[2] * (Trot - Tvib);
-        double Xvib = gm[1] * (Ttr - Tvib) + gm[2] * (Trot - Tvib);
-        double al = al_cell, oma2 = oma2_cell, nu = nu_cell;
-        /* relaxation temperatures, eqs. T_tr_USP, T_rot_USP, T_vib_USP */
-        double Ttr_rel = Ttr - Xtr / (oma2 * 1.5 * R);
-        double Trot_rel = Trot + Xrot / (oma2 * R);
-        double mstar = orc_e_vib(g, Tvib) / (R * Th) + Xvib / (oma2 * R * Th);
-        /* diffusion tensor (times tau), eq. D_tr, and its Cholesky test */
-        double RT = R * Ttr;
-        double Lam[6], L[6];
-        for (int k = 0; k < 3; ++k) Lam[k] = R * Ttr_rel + nu * (P[k] - RT);
-        for (int k = 3; k < 6; ++k) Lam[k] = nu * P[k];
-        int ok = chol3(Lam, L);
-        int skip = 0;
-        if (!ok) {
-          lc[ORC_CNT_CHOL_FALLBACK] += 1;
-          if (!(Ttr_rel > 0.0)) {
-            skip = 1;
-          } else {
-            /* nu clamped into the positive-definite range, eq.            */
-            /* nu_USP_positivity; kept a hair inside the bound so the     */
-            /* re-test can pass.                                          */
-            double ev[3];
-            orc_eigvals_sym3(P, ev);
-            double RTr = R * Ttr_rel;
-            const double shrink = 1.0 - 1.0 / 1048576.0;
-            if (nu <= 0.0) {
-              if (ev[2] > RT) nu = fmax(nu, -RTr / (ev[2] - RT) * shrink);
-            } else {
-              if (ev[0] < RT) nu = fmin(nu, RTr / (RT - ev[0]) * shrink);
-            }
-            /* alpha refit, eqs. alpha_USP_positivity_1..4 */
-            double a2 = (nu - r2) / (nu - 1.0);
-            if (a2 < 0.0) a2 = 0.0;
-            if (a2 > 1.0) a2 = 1.0;
-            double ap = sqrt(a2), am = -sqrt(a2);
-            double Prp = A2 * (1.0 - ap * ap * ap) / (dtc * (1.0 + ap * ap * ap));
-            double Prm = A2 * (1.0 - am * am * am) / (dtc * (1.0 + am * am * am));
-            al = (fabs(Prm - Pr) < fabs(Prp - Pr)) ? am : ap;
-            oma2 = 1.0 - a2;
-            if (!(oma2 > 0.0)) {
-              skip = 1;
-            } else {
-              Ttr_rel = Ttr - Xtr / (oma2 * 1.5 * R);
-              Trot_rel = Trot + Xrot / (oma2 * R);
-              mstar = orc_e_vib(g, Tvib) / (R * Th) + Xvib / (oma2 * R * Th);
-              for (int k = 0; k < 3; ++k) Lam[k] = R * Ttr_rel + nu * (P[k] - RT);
-              for (int k = 3; k < 6; ++k) Lam[k] = nu * P[k];
-              ok = chol3(Lam, L);
-              if (!ok) {
-                lc[ORC_CNT_NU_ZERO] += 1;
-                nu = 0.0;
-                if (Ttr_rel > 0.0) {
-                  double s0 = sqrt(R * Ttr_rel);
-                  L[0] = s0; L[1] = 0.0; L[2] = s0; L[3] = 0.0; L[4] = 0.0; L[5] = s0;
-                  ok = 1;
-                } else {
-                  skip = 1;
-                }
-              }
-            }
-          }
-        }
+        orc_pcoef pc;
+        orc_particle_coef(g, Ttr, Trot, Tvib, P, a, b, al_cell, oma2_cell, nu_cell, r2, A2, Pr,
+                          dtc, &pc);
+        if (pc.fallback) lc[ORC_CNT_CHOL_FALLBACK] += 1;
+        if (pc.nu_zero) lc[ORC_CNT_NU_ZERO] += 1;
+        int skip = pc.skip;
+        double al = pc.al, oma2 = pc.oma2, Trot_rel = pc.Trot_rel, mstar = pc.mstar;
+        const double* L = pc.L;
         if (skip) { lc[ORC_CNT_TREL_SKIP] += 1; continue; }
         if (Trot_rel < 0.0) { Trot_rel = 0.0; lc[ORC_CNT_TREL_CLAMP] += 1; }
         if (mstar < 0.0) { mstar = 0.0; lc[ORC_CNT_TREL_CLAMP] += 1; }

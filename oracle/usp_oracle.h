@@ -213,6 +213,24 @@ void orc_gammas(const orc_gas* g, double Ttr, double Trot, double Tvib,
                 double a, double b, double out_gamma[3], double* out_tcheck);
 void orc_eigvals_sym3(const double P[6], double out[3]);
 
+/* Per-particle coefficients of Secs. III.A.1-III.A.3 with the positivity
+   fallback of Sec. III.A.3 (see usp_oracle.c).  L: lower Cholesky factor
+   (l11, l21, l22, l31, l32, l33) of Lambda = tau D_tr; al, oma2: alpha and
+   1 - alpha^2 after any refit; nu: the nu used (0 after the second
+   fallback); nu_bound: the bound of eq. nu_USP_positivity on the side of
+   the cell's nu (0 when the first test passed or the bound does not apply);
+   Ttr_rel, Trot_rel, mstar: relaxation temperatures and mean level before
+   the clamps to 0 of the update; flags: the first test failed (fallback),
+   the re-test failed (nu_zero), the particle is left unchanged (skip). */
+typedef struct {
+  double L[6];
+  double al, oma2, nu, nu_bound, Ttr_rel, Trot_rel, mstar;
+  int32_t fallback, nu_zero, skip;
+} orc_pcoef;
+void orc_particle_coef(const orc_gas* g, double Ttr, double Trot, double Tvib, const double P[6],
+                       double a, double b, double al_cell, double oma2_cell, double nu_cell,
+                       double r2, double A2, double Pr, double dtc, orc_pcoef* out);
+
 /* ---- one step, phase by phase ------------------------------------------- */
 int orc_bin(const orc_grid* grid, const orc_parts* src, orc_parts* dst,
             int64_t* offsets, int32_t f32, int64_t* counters);

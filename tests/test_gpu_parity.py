@@ -5,8 +5,8 @@ Bars (integer work bit-exact; floating point as stated):
   * bin: cell indices, offsets and permutation identical;
   * moments, cell state (FP64): within 1e-10 of each moment's natural scale;
   * collide/conserve/advect: FP64 state within 1e-9 of the velocity /
-    energy / length scale; FP32 state within 2e-5 of that scale (the update
-    runs in single precision); vibrational levels equal on >= 99.99% of
+    energy / length scale; FP32 state within 1e-5 of that scale (the update
+    runs in single precision), 4e-4 after several full steps; vibrational levels equal on >= 99.99% of
     particles (the discrete decisions are FP64 on both sides but their
     inputs differ by rounding in the FP32 path).
 """
@@ -267,7 +267,15 @@ def usp_name(k, kind):
 # collide, conserve, advect -- each on identical inputs
 # --------------------------------------------------------------------------
 def _tol(f32):
-    return 2e-5 if f32 else 1e-9
+    """One phase on identical inputs: the FP32 update's ~20-operation chain
+    (a few ulp of 1.2e-7 each, transcendentals included) on values of the
+    velocity scale stays within 1e-5 of it; FP64 within 1e-9."""
+    return 1e-5 if f32 else 1e-9
+
+
+# several full steps compound the one-phase differences (and the FP32
+# trajectories of cells whose FP64 decisions differ part more)
+MULTI_STEP = 40
 
 
 @pytest.mark.parametrize("scheme", SCHEMES)
@@ -315,7 +323,7 @@ def test_full_steps(kind, f32, scheme):
             b[k] = b[k][ib]
     vs = vel_scale(prob, orc)
     # a few steps compound the single-step differences
-    compare_states(a, b, prob, vs, 20 * _tol(f32), f"{nsteps} steps", vib_min=0.999)
+    compare_states(a, b, prob, vs, MULTI_STEP * _tol(f32), f"{nsteps} steps", vib_min=0.999)
     ca, cb = gpu.cnt(), orc.cnt()
     for k in ("INJECTED", "SOLID_DROP"):
         assert ca[k] == cb[k], (k, ca[k], cb[k])
@@ -619,7 +627,7 @@ def test_batch_c2_full_size(tile):
     assert a["n"] == b["n"]
     assert np.array_equal(a["pid"], b["pid"])
     vs = vel_scale(prob, orc)
-    compare_states(a, b, prob, vs, 20 * _tol(True), "c2 3 steps", vib_min=0.999)
+    compare_states(a, b, prob, vs, MULTI_STEP * _tol(True), "c2 3 steps", vib_min=0.999)
     ca, cb = gpu.cnt(), orc.cnt()
     for k in ("CELL_SKIP", "PICK_FAIL"):
         assert ca[k] == cb[k], (k, ca[k], cb[k])
@@ -775,9 +783,10 @@ def test_poiseuille_full_size_statistics(kn, transient, golden):
     what must agree is the statistics: the profile cell by cell within its
     sampling noise (about 0.35 m/s a cell), the parabola's curvature within
     2% of the oracle's, the temperature within 0.5 K, and the profile
-    symmetric.  The curvature is also held to the Navier-Stokes value
-    g/(2 nu) with the oracle pin's 8%: at Kn = 0.05 both sides sit about 6%
-    above it (the Knudsen layers at the walls are resolved here)."""
+    symmetric.  The curvature fitted over the cells more than two mean free
+    paths from the walls (outside the Knudsen layers) is also held to the
+    Navier-Stokes value g/(2 nu) with the oracle pin's 5% (the oracle's
+    stored profiles sit at 1.042 and 0.974 of it)."""
     usp = _usp()
     prob = W.poiseuille(kn=kn, cells=200, ppc=1000, f32=True)
     parts = W.particles_for(prob)
@@ -803,8 +812,12 @@ def test_poiseuille_full_size_statistics(kn, transient, golden):
     A = np.stack([y * (L - y), np.ones(M)], 1)
     (curv, slip), *_ = np.linalg.lstsq(A, U, rcond=None)
     (curv_o, slip_o), *_ = np.linalg.lstsq(A, Uo, rcond=None)
+    # the bulk, outside two mean free paths (c_bar tau_c = Kn x gap) from the walls
+    mfp = kn * M * g.dy
+    bulk = (y > 2 * mfp) & (y < M * g.dy - 2 * mfp)
+    (curv_b, _), *_ = np.linalg.lstsq(A[bulk], U[bulk], rcond=None)
     mu = gas.mu_ref * (T / gas.T_ref) ** gas.omega
-    ratio = curv / (prob.bc.g[0] / (2 * mu / (prob.notes["n"] * gas.m)))
+    ratio = curv_b / (prob.bc.g[0] / (2 * mu / (prob.notes["n"] * gas.m)))
     d = np.abs(U - Uo)
     _say(f"  T {T:.2f} K (oracle {To:.2f}), curvature / oracle {curv / curv_o:.4f}, "
          f"/ NS {ratio:.4f}, slip {slip:.2f} (oracle {slip_o:.2f}) m/s, "
@@ -812,7 +825,7 @@ def test_poiseuille_full_size_statistics(kn, transient, golden):
     assert abs(T - To) < 0.5
     assert abs(curv / curv_o - 1.0) < 0.02
     assert d.mean() < 1.0 and d.max() < 2.5
-    assert abs(ratio - 1.0) < 0.08
+    assert abs(ratio - 1.0) < 0.05
     assert np.abs(U - U[::-1]).mean() < 0.03 * U.max()
 
 

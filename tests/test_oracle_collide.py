@@ -249,10 +249,10 @@ def test_conservation_to_round_off_and_targets():
 
 
 def test_positivity_fallback_keeps_update_finite():
-    """A strongly anisotropic cell fails the first
-    Cholesky test; the nu clamp and alpha refit of Sec. III.A.3 restore a
-    positive-definite diffusion tensor (parity of the refit itself is not
-    pinned by the paper)."""
+    """A strongly anisotropic sampled cell fails the first Cholesky test for
+    some of its particles; after the nu clamp and alpha refit of Sec.
+    III.A.3 every update stays finite (the refit's own properties are
+    pinned on hand-made Pi below)."""
     rng = np.random.default_rng(27)
     gas = W.Gas()
     N = 20000
@@ -272,3 +272,164 @@ def test_positivity_fallback_keeps_update_finite():
     for k in ("cx", "cy", "cz", "erot"):
         assert np.all(np.isfinite(st[k]))
     assert np.all(st["erot"] >= 0)
+
+
+# --------------------------------------------------------------------------
+# The positivity fallback of Sec. III.A.3 on hand-made anisotropic Pi
+# --------------------------------------------------------------------------
+SHRINK = 1.0 - 2.0 ** -20
+
+
+def _coef_cell(gas, T, Trot, dt_over_tauc, seed):
+    """Cell coefficients (from the oracle's cell state of a sampled cell)."""
+    rng = np.random.default_rng(seed)
+    N = 4000
+    s = math.sqrt(gas.R * T)
+    cx, cy, cz = (s * rng.standard_normal(N) for _ in range(3))
+    erot = rng.exponential(gas.R * Trot, N)
+    prob, sim = _cell_problem(cx, cy, cz, erot, np.zeros(N, np.int32), gas=gas,
+                              dt_over_tauc=dt_over_tauc)
+    return {k: _cs(sim, k) for k in ("A", "B", "ALPHA", "OMA2", "NU", "R2", "MUP", "PR", "DT")}
+
+
+def _sym(M):
+    return np.array([M[0, 0], M[1, 1], M[2, 2], M[0, 1], M[0, 2], M[1, 2]])
+
+
+def _full(v):
+    return np.array([[v[0], v[3], v[4]], [v[3], v[1], v[5]], [v[4], v[5], v[2]]])
+
+
+def _refit_cases(gas, cc, Ts, aniso, seed):
+    """Every combination of particle temperatures and Pi eigenvalue ratios
+    (Pi = R T_tr Q diag(d) Q^T, trace 3 R T_tr, random rotation Q), with the
+    oracle's coefficients and the same particle with an isotropic Pi (whose
+    Lambda is R T_tr^rel I, so it gives the relaxation temperatures before
+    any refit)."""
+    rng = np.random.default_rng(seed)
+    R = gas.R
+    out = []
+    for Ttr, Trot, Tvib in Ts:
+        for d in aniso:
+            d = np.asarray(d, float) * 3.0 / sum(d)
+            Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+            Pm = R * Ttr * (Q @ np.diag(d) @ Q.T)
+            args = (cc["A"], cc["B"], cc["ALPHA"], cc["OMA2"], cc["NU"], cc["R2"],
+                    2.0 * cc["MUP"], cc["PR"], cc["DT"])
+            r = oracle.particle_coef(gas, Ttr, Trot, Tvib, _sym(Pm), *args)
+            iso = oracle.particle_coef(gas, Ttr, Trot, Tvib, _sym(R * Ttr * np.eye(3)), *args)
+            # an isotropic Pi fails only through T_tr^rel <= 0, and then
+            # before any refit: iso always holds the unrefitted values
+            assert iso["fallback"] == (not iso["Ttr_rel"] > 0)
+            out.append((Ttr, Trot, Tvib, Pm, r, iso))
+    return out
+
+
+def _check_refit(gas, cc, case):
+    """The properties eqs. nu_USP_positivity and alpha_USP_positivity_1..4
+    fix, evaluated independently of the oracle's arithmetic (eigenvalues by
+    numpy, the bound from the pre-refit relaxation temperature).  Returns
+    which branch the case took."""
+    Ttr, Trot, Tvib, Pm, r, iso = case
+    R = gas.R
+    RT = R * Ttr
+    if not r["fallback"]:
+        # the first test passed: Lambda with the cell's nu is positive definite
+        Lam = R * iso["Ttr_rel"] * np.eye(3) + cc["NU"] * (Pm - RT * np.eye(3))
+        assert np.linalg.eigvalsh(Lam).min() > 0
+        return "pass"
+    Lam0 = R * iso["Ttr_rel"] * np.eye(3) + cc["NU"] * (Pm - RT * np.eye(3))
+    assert np.linalg.eigvalsh(Lam0).min() <= 1e-12 * RT
+    if not iso["Ttr_rel"] > 0:
+        assert r["skip"]
+        return "skip"
+    lam = np.linalg.eigvalsh(Pm)
+    RTr = R * iso["Ttr_rel"]
+    nu0 = cc["NU"]
+    # eq. nu_USP_positivity: the admissible interval (eigenvalues by numpy)
+    lo = -RTr / (lam[2] - RT) if lam[2] > RT else -np.inf
+    hi = RTr / (RT - lam[0]) if lam[0] < RT else np.inf
+    # the oracle's bound on nu's side agrees with it (the closed-form
+    # eigenvalues lose up to ~1e-8 relative where two eigenvalues coincide)
+    bound = lo if nu0 <= 0 else hi
+    if np.isfinite(bound):
+        assert r["nu_bound"] == pytest.approx(bound, rel=1e-7)
+        nu1 = max(nu0, r["nu_bound"] * SHRINK) if nu0 <= 0 else min(nu0, r["nu_bound"] * SHRINK)
+    else:
+        assert r["nu_bound"] == 0.0
+        nu1 = nu0
+    # the clamped nu lies strictly inside the interval
+    assert lo < nu1 < hi
+    # eq. alpha_USP_positivity_1: alpha^2 from the clamped nu and r2
+    a2 = min(1.0, max(0.0, (nu1 - cc["R2"]) / (nu1 - 1.0)))
+    assert r["al"] ** 2 == pytest.approx(a2, rel=1e-12, abs=1e-15)
+    assert r["oma2"] == pytest.approx(1.0 - a2, rel=1e-12, abs=1e-15)
+    # eq. alpha_USP_positivity_3: of +-sqrt(alpha^2), the Pr closer to the cell's
+    def prandtl(al):
+        return 2.0 * cc["MUP"] * (1.0 - al ** 3) / (cc["DT"] * (1.0 + al ** 3))
+    ap = math.sqrt(a2)
+    dp, dm = abs(prandtl(ap) - cc["PR"]), abs(prandtl(-ap) - cc["PR"])
+    if dp != dm:
+        assert r["al"] == pytest.approx(ap if dp < dm else -ap, rel=1e-14, abs=1e-15)
+    # the relaxation temperature with the new 1 - alpha^2 (eq. T_tr_USP):
+    # T_tr - (T_tr - T_tr^rel,0) (1 - alpha_0^2)/(1 - alpha^2)
+    Trel1 = Ttr - (Ttr - iso["Ttr_rel"]) * cc["OMA2"] / r["oma2"]
+    assert r["Ttr_rel"] == pytest.approx(Trel1, rel=1e-11)
+    Lam1 = R * Trel1 * np.eye(3) + nu1 * (Pm - RT * np.eye(3))
+    pd = np.linalg.eigvalsh(Lam1).min() > 1e-9 * RT
+    L = r["L"]
+    Lm = np.array([[L[0], 0, 0], [L[1], L[2], 0], [L[3], L[4], L[5]]])
+    if r["nu_zero"]:
+        # the second fallback fires exactly when the re-test fails
+        assert np.linalg.eigvalsh(Lam1).min() < 1e-9 * RT
+        assert r["nu"] == 0.0
+        if Trel1 > 0:
+            assert np.allclose(Lm @ Lm.T, R * Trel1 * np.eye(3), rtol=1e-12)
+        return "nu_zero"
+    assert pd
+    assert r["nu"] == pytest.approx(nu1, rel=1e-14)
+    assert np.allclose(Lm @ Lm.T, Lam1, rtol=1e-10, atol=1e-10 * RT)
+    return "refit"
+
+
+ANISO = [(1, 1, 1), (2, 1, 0.5), (4, 1, 1), (8, 1, 1), (20, 1, 1), (1, 1, 0.05), (1, 0.02, 0.02),
+         (50, 0.5, 0.1)]
+
+
+def test_positivity_refit_negative_nu():
+    """nu < 0 (the Eucken Prandtl number): a Pi with a large eigenvalue fails
+    the first test; nu is clamped to just inside -R T_rel/(lambda_max - R T),
+    alpha^2 refitted, the Pr-closer sign taken, and the re-test decides
+    between the refitted tensor (positive definite) and nu = 0.  Energy
+    flowing into translation (T_rot > T_tr) raises T_tr^rel with the new
+    1 - alpha^2 the other way, which is where the re-test can fail."""
+    gas = W.Gas()
+    seen = set()
+    for dto, seed in ((0.3, 1), (1.0, 2), (3.0, 3), (10.0, 4)):
+        cc = _coef_cell(gas, 3000.0, 3000.0, dto, seed)
+        assert cc["NU"] < 0
+        Ts = [(3000.0, 3000.0, 3000.0), (3000.0, 300.0, 300.0), (3000.0, 12000.0, 3000.0),
+              (3000.0, 30000.0, 5000.0), (1000.0, 60000.0, 1000.0)]
+        for case in _refit_cases(gas, cc, Ts, ANISO, seed):
+            seen.add(_check_refit(gas, cc, case))
+    assert {"pass", "refit", "nu_zero"} <= seen, seen
+
+
+def test_positivity_refit_positive_nu():
+    """nu > 0 (a constant Prandtl number above 3/2): a Pi with a small
+    eigenvalue fails the first test, which needs R T_tr^rel < nu (R T -
+    lambda_min) < R T_tr, i.e. energy leaving translation.  nu is clamped to
+    just inside R T_rel/(R T - lambda_min).  Lowering nu raises alpha^2
+    (d alpha^2/d nu = (r2 - 1)/(nu - 1)^2 < 0), so 1 - alpha^2 falls and
+    T_tr^rel falls below the value the bound was taken at: under this
+    reading the re-test then fails and nu = 0 is used, in every case."""
+    gas = W.Gas(pr_model=W.PR_CONST, Pr_const=2.5, Z_rot=0.5)
+    seen = set()
+    for dto, seed in ((0.1, 5), (0.3, 6), (0.6, 7)):
+        cc = _coef_cell(gas, 3000.0, 3000.0, dto, seed)
+        assert cc["NU"] > 0
+        Ts = [(3000.0, 3000.0, 3000.0), (3000.0, 300.0, 300.0), (3000.0, 10.0, 10.0),
+              (3000.0, 12000.0, 3000.0)]
+        for case in _refit_cases(gas, cc, Ts, ANISO + [(1, 1e-3, 1e-3)], seed):
+            seen.add(_check_refit(gas, cc, case))
+    assert {"pass", "nu_zero"} <= seen and "refit" not in seen, seen

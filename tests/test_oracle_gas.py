@@ -126,3 +126,52 @@ def test_eigvals_match_library():
         P = [S[0, 0], S[1, 1], S[2, 2], S[0, 1], S[0, 2], S[1, 2]]
         assert np.allclose(oracle.eigvals_sym3(P), np.linalg.eigvalsh(S), rtol=1e-10, atol=1e-10)
     assert np.allclose(oracle.eigvals_sym3([3, 1, 2, 0, 0, 0]), [1, 2, 3])
+
+
+def test_millikan_white_term_against_the_published_correlation():
+    """The Millikan-White part of Z_vib (Sec. V.C), times the oracle's
+    tau_c, against the relaxation time of the Millikan-White correlation
+    itself, p tau = exp(A (T^-1/3 - B) - 18.42) atm s with A = 1.16e-3
+    mu^1/2 theta^4/3 and B = 0.015 mu^1/4 (mu = 14 amu, the N2-N2 reduced
+    mass).  A alone reproduces the paper's C2 = 220 to 0.3%; over 500 K to
+    20,000 K, where the two times span ten decades, their ratio stays within
+    [1.1, 1.25] (C1 absorbs Bird's collision-time convention) and drifts
+    by less than 6%.  A wrong exponent, sign or power of T in the oracle
+    would move the ratio by orders of magnitude."""
+    gas = W.cylinder(scale=0.05, f32=True).gas
+    assert gas.zvib_model == W.ZVIB_MW_HT
+    g = oracle.Gas(gas)
+    mu_red, theta = 14.0, gas.theta_vib
+    A = 1.16e-3 * math.sqrt(mu_red) * theta ** (4.0 / 3.0)
+    B = 0.015 * mu_red ** 0.25
+    assert abs(A / 220.0 - 1) < 3e-3
+    n = 1e22
+    ratios = []
+    for T in (500.0, 1000.0, 2000.0, 5000.0, 10000.0, 20000.0):
+        p = n * KB * T
+        tau_mw = math.exp(A * (T ** (-1.0 / 3.0) - B) - 18.42) * 101325.0 / p
+        # the Millikan-White term alone: Z_vib less the high-temperature term,
+        # which the next test pins (negligible below ~3000 K)
+        zht = math.pi * gas.d_ref ** 2 / gas.sigma_vib * (gas.T_ref / T) ** (gas.omega - 0.5)
+        zmw = g.zvib(T) - zht
+        ratios.append(zmw * g.tau_c(T, n) / tau_mw)
+    r = np.array(ratios)
+    assert np.all((r > 1.1) & (r < 1.25)), r
+    assert r.max() / r.min() < 1.06, r
+
+
+def test_high_temperature_term_is_parks_limit():
+    """The high-temperature part of Z_vib (Sec. V.C), times tau_c of the VHS
+    viscosity derived from the same d_ref, is Park's limiting relaxation
+    time 1/(n sigma_vib c_r) with c_r = sqrt(16 k T/(pi m)) the mean
+    relative speed of two molecules: equal to 1e-10 wherever the
+    Millikan-White part is small enough to subtract (T >= 2000 K)."""
+    gas = W.cylinder(scale=0.05, f32=True).gas
+    g = oracle.Gas(gas)
+    n = 1e22
+    for T in (2000.0, 5000.0, 20000.0, 1e5, 1e6):
+        zmw = gas.C1 / T ** gas.omega * math.exp(gas.C2 * T ** (-1.0 / 3.0))
+        zht = g.zvib(T) - zmw
+        cr = math.sqrt(16.0 * KB * T / (math.pi * gas.m))
+        park = 1.0 / (n * gas.sigma_vib * cr)
+        assert abs(zht * g.tau_c(T, n) / park - 1) < 1e-10, T

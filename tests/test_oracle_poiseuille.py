@@ -3,12 +3,26 @@ flow (the force-driven channel of Sec. V.B): after the transient, the
 time-averaged velocity profile is a parabola whose curvature is
 g / (2 nu) with nu = mu(T)/rho from the gas model (the method reproduces
 the viscosity it is built from), plus a wall slip of the size of the
-first-order Maxwell slip lambda du/dy at Kn = 0.05.  No GPU."""
+first-order Maxwell slip lambda du/dy at Kn = 0.05.  The parabola is fitted
+over the cells more than two mean free paths from either wall: the
+Knudsen layers next to the walls follow no Navier-Stokes profile.  No GPU."""
 import numpy as np
 import pytest
 
 import oracle
 import usp_workloads as W
+
+
+def bulk_fit(y, U, L, mfp, walls=2.0):
+    """Least-squares U = curv y (L - y) + slip over the cells farther than
+    `walls` mean free paths from both walls; returns (curv, slip) and the
+    standard error of curv from the residuals."""
+    m = (y > walls * mfp) & (y < L - walls * mfp)
+    A = np.stack([y[m] * (L - y[m]), np.ones(m.sum())], 1)
+    coef, *_ = np.linalg.lstsq(A, U[m], rcond=None)
+    r = U[m] - A @ coef
+    cov = (r @ r) / (m.sum() - 2) * np.linalg.inv(A.T @ A)
+    return coef, float(np.sqrt(cov[0, 0]))
 
 
 def test_poiseuille_profile_curvature_and_slip():
@@ -33,9 +47,9 @@ def test_poiseuille_profile_curvature_and_slip():
     mu = gas.mu_ref * (T / gas.T_ref) ** gas.omega
     nu = mu / (prob.notes["n"] * gas.m)
     y = (np.arange(M) + 0.5) * g.dy
-    A = np.stack([y * (L - y), np.ones(M)], 1)
-    (curv, slip), *_ = np.linalg.lstsq(A, U, rcond=None)
+    (curv, slip), sd = bulk_fit(y, U, L, 50e-6)
     g_x = prob.bc.g[0]
+    # 4500 steps of 6000 particles: the fit's own noise is ~5% (sd)
     assert abs(curv / (g_x / (2 * nu)) - 1.0) < 0.08, curv / (g_x / (2 * nu))
     # mean free path c_bar tau_c = 50 um at this density (Kn = 0.05)
     u_slip1 = 50e-6 * g_x * L / (2 * nu)
@@ -49,9 +63,11 @@ def test_poiseuille_profile_curvature_and_slip():
 def test_stored_full_size_profile(kn, golden, mfp):
     """The stored oracle profiles of the full-size channel (200 cells x 1000
     particles, tests/golden/) meet the same continuum pins: NS curvature
-    within 8%, a positive slip of the first-order size lambda du/dy (mean
-    free path c_bar tau_c = Kn x gap), symmetric, T near the wall
-    temperature."""
+    over the bulk within 5% (measured 1.042 +- 0.005 at Kn = 0.05, where
+    the O(Kn^2) departures from Navier-Stokes are largest, and 0.974 +-
+    0.004 at Kn = 0.01, whose step is 1.9 tau_c), a positive slip of the
+    first-order size lambda du/dy (mean free path c_bar tau_c = Kn x gap),
+    symmetric, T near the wall temperature."""
     import os
     path = os.path.join(os.path.dirname(__file__), "golden", golden)
     T, U = None, []
@@ -69,11 +85,12 @@ def test_stored_full_size_profile(kn, golden, mfp):
     M, L = g.ny, g.ny * g.dy
     assert U.size == M and abs(T - 300.0) < 5.0
     y = (np.arange(M) + 0.5) * g.dy
-    (curv, slip), *_ = np.linalg.lstsq(np.stack([y * (L - y), np.ones(M)], 1), U, rcond=None)
+    (curv, slip), sd = bulk_fit(y, U, L, mfp)
     mu = gas.mu_ref * (T / gas.T_ref) ** gas.omega
     g_x = prob.bc.g[0]
     ratio = curv / (g_x / (2 * mu / (prob.notes["n"] * gas.m)))
-    assert abs(ratio - 1.0) < 0.08, ratio
+    assert abs(ratio - 1.0) < 0.05, ratio
+    assert sd < 0.01 * curv
     nu = mu / (prob.notes["n"] * gas.m)
     u_slip1 = mfp * g_x * L / (2 * nu)
     assert 0.5 * u_slip1 < slip < 2.5 * u_slip1, (slip, u_slip1)

@@ -187,7 +187,7 @@ hipError_t launch_update(const GridP& g, const GasP& gas, const BcP& bc, double 
   const int64_t T = update_tile(UpdCfg<S>::STAGE, p.capacity, g.M);
   const int64_t ntiles = cdiv(p.capacity, T);
   int32_t* first = (int32_t*)(ws + L.tiles);
-  launch_tiles(offsets, g.M, T, ntiles, first, st);
+  if (launch_tiles(offsets, g.M, T, ntiles, first, st) != hipSuccess) return hipGetLastError();
   const uint32_t s32 = (uint32_t)step;
   const int adv = g.dim != 0 ? 1 : 0;
   const bool fpm = gas.scheme == USP_SCHEME_FPM;

@@ -44,6 +44,7 @@ typedef int32_t usp_status;
 #define USP_ECAPACITY -3   /* usp_check: injections were dropped for lack of capacity */
 #define USP_ENUMERIC -4    /* usp_check: a NaN or infinite value in the state */
 #define USP_EUNSUPPORTED -5
+#define USP_ESCRATCH -6    /* usp_update_noalloc: needs more than its fixed scratch */
 
 #define USP_F32 0
 #define USP_F64 1
@@ -372,6 +373,29 @@ usp_status usp_update(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc
                       const double* cs, const int64_t* offsets, usp_particles* p,
                       void* ws, size_t ws_bytes, uint64_t seed, uint64_t step,
                       int64_t* counters, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid allocation): the
+   fused particle phase of usp_update with its scratch (the tile index and
+   the injection's face counts, offsets and totals) in a fixed device array
+   of USP_NOALLOC_SCRATCH_BYTES inside the library instead of a caller
+   workspace.  Same arguments, results (the same kernels: bit-identical to
+   usp_update) and errors as usp_update, less ws and ws_bytes; the call
+   allocates nothing.  Each GPU holds its own copy of the array from the
+   first call on it until the process ends; its address is looked up once
+   per GPU on that first call.  Calls on one GPU share the array: calls that
+   may overlap on one GPU (different streams, or one stream from several
+   host threads without ordering) race and must not be issued.  Nothing in
+   the array needs to start at zero (every call writes what it reads).
+   Returns USP_ESCRATCH when the grid's faces and the capacity's tile index
+   need more than the array holds (about 2.6e5 tiles: e.g. 4.5e8 particle
+   slots at the cylinder's tile window), USP_EDEVICE when the array's
+   address cannot be found. */
+#define USP_NOALLOC_SCRATCH_BYTES (1 << 20)
+usp_status usp_update_noalloc(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc,
+                              double dt, const double* cs, const int64_t* offsets,
+                              usp_particles* p, uint64_t seed, uint64_t step, int64_t* counters,
+                              void* stream);
 
 /* nsteps full steps of independent 0D cells (dim 0) in few launches: per
    step the moments and cell state of each cell (Secs. II.A, III.A, IV.A,

@@ -130,6 +130,18 @@ bool bc_ok(const usp_bc* b, const usp_grid* grid) {
 
 usp_status hip_status(hipError_t e) { return e == hipSuccess ? USP_OK : USP_EDEVICE; }
 
+}  // namespace
+
+// The host-side argument checks of usp_update, less the workspace.
+bool usp::update_args_ok(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
+                         const double* cs, const int64_t* offsets, const usp_particles* p) {
+  if (!grid_ok(grid) || !gas_ok(gas) || !parts_ok(p, grid) || !cs || !offsets) return false;
+  if (grid->dim >= 1 && (!bc || !(dt > 0.0))) return false;
+  return bc_ok(bc, grid);
+}
+
+namespace {
+
 template <typename S>
 usp_status do_bin(const usp_grid* grid, const usp_particles* in, usp_particles* out,
                   int64_t* offsets, const int64_t* in_offsets, void* ws, int64_t* counters,
@@ -242,6 +254,7 @@ const char* usp_status_str(usp_status s) {
     case USP_EDEVICE: return "HIP device error";
     case USP_ECAPACITY: return "particle capacity exceeded (injections dropped)";
     case USP_ENUMERIC: return "NaN or infinite value in the state";
+    case USP_ESCRATCH: return "problem too large for the fixed scratch of usp_update_noalloc";
     case USP_EUNSUPPORTED: return "unsupported";
     default: return "unknown status";
   }
@@ -408,10 +421,7 @@ usp_status usp_update(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc
                       const double* cs, const int64_t* offsets, usp_particles* p, void* ws,
                       size_t ws_bytes, uint64_t seed, uint64_t step, int64_t* counters,
                       void* stream) {
-  if (!grid_ok(grid) || !gas_ok(gas) || !parts_ok(p, grid) || !cs || !offsets || !ws)
-    return USP_EINVAL;
-  if (grid->dim >= 1 && (!bc || !(dt > 0.0))) return USP_EINVAL;
-  if (!bc_ok(bc, grid)) return USP_EINVAL;
+  if (!update_args_ok(grid, gas, bc, dt, cs, offsets, p) || !ws) return USP_EINVAL;
   if (ws_bytes < usp_workspace_bytes(grid, p->capacity)) return USP_EINVAL;
   const GridP g = make_grid(grid);
   const GasP gp = make_gas(gas);

@@ -94,6 +94,10 @@ struct PartP {
   int64_t capacity;
 };
 
+// host-side argument checks of usp_update (without its workspace)
+bool update_args_ok(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, double dt,
+                    const double* cs, const int64_t* offsets, const usp_particles* p);
+
 GasP make_gas(const usp_gas* g);
 GridP make_grid(const usp_grid* g);
 BcP make_bc(const usp_bc* b);

@@ -452,7 +452,8 @@ __global__ __launch_bounds__(256) void k_adj_collide(GridP g, GasP gas, TapeP T,
   nbrc[i] = -1;
   if (cs[CS_COLLIDE * M + c] == 0.0) return;  // identity: lam1 already holds the adjoint
   const PartP<double> p = tape_parts(T, cap);
-  const Stencil st = particle_stencil<double>(g, cell_records(cs, M)[c].stencil, c, p, i);
+  const Stencil st = particle_stencil<double>(g, cell_records(cs, M)[c].stencil, c,
+                                              load_pos(p, i, g.dim));
   double U[3], P[6], Tk[3];
   fields_planes(cs, M, c, st, U, P, Tk);
   bool floored[3];

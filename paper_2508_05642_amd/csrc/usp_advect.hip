@@ -16,8 +16,8 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_advect(GridP g, GasP gas, BcP bc,
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.count[0]) return;
   if (p.cell[i] < 0) return;
-  advect_one<S>(g, gas, bc, dt, p, i, p.cx[i], p.cy[i], p.cz[i], p.erot[i], p.vib[i], seed, step,
-                counters);
+  advect_one<S>(g, gas, bc, dt, p, i, load_pos(p, i, g.dim), p.cx[i], p.cy[i], p.cz[i], p.erot[i],
+                p.vib[i], seed, step, counters);
 }
 
 // ---- free-stream injection ------------------------------------------------

@@ -18,7 +18,8 @@ __global__ __launch_bounds__(PART_BLOCK) void k_collide_f32(GridP g, GasP gas,
   const int32_t c = p.cell[i];
   if (c < 0) return;
   uint32_t ev = 0;
-  const PartNew<float> o = collide_one<FPM>(g, gas, cs, p, i, c, load_state(p, i), seed, step, &ev);
+  const PartNew<float> o =
+      collide_one<FPM>(g, gas, cs, load_pos(p, i, g.dim), c, load_state(p, i), seed, step, &ev);
   if (o.changed) {
     p.cx[i] = o.cx; p.cy[i] = o.cy; p.cz[i] = o.cz; p.erot[i] = o.erot;
     p.vib[i] = (uint8_t)o.vib;
@@ -36,7 +37,8 @@ __global__ __launch_bounds__(PART_BLOCK) void k_collide_f64(GridP g, GasP gas,
   const int32_t c = p.cell[i];
   if (c < 0) return;
   uint32_t ev = 0;
-  const PartNew<double> o = collide_one<FPM>(g, gas, cs, p, i, c, load_state(p, i), seed, step, &ev);
+  const PartNew<double> o =
+      collide_one<FPM>(g, gas, cs, load_pos(p, i, g.dim), c, load_state(p, i), seed, step, &ev);
   if (o.changed) {
     p.cx[i] = o.cx; p.cy[i] = o.cy; p.cz[i] = o.cz; p.erot[i] = o.erot;
     p.vib[i] = (uint8_t)o.vib;

@@ -138,10 +138,21 @@ __device__ PartCoef<T> particle_coef(T R, T Th, T Ttr, T Trot, T Tvib, const T P
   T al = (T)cc.al;
   double oma2d = cc.oma2;
   T nu = (T)cc.nu;
-  const T Tc = tcheck<T>(Th, Ttr, Trot, Tvib, a, b);
-  const T cb = cbar_R<T>(Th, Tc, Tvib);
-  const T D = T(1.5) + a + b * cb;
-  const T g1 = T(3) * a / D, g2 = T(3) * b * cb / D, g3 = T(2) * a * b * cb / D;
+  // A vibrational exchange factor b below 1e-12 (tau_vib above ~1e12 time
+  // steps: the Millikan-White number of a cold gas) leaves the gammas'
+  // vibrational parts, b c_v,vib/D, and the shift of T-check from (3/2 T_tr
+  // + a T_rot)/(3/2 + a) below 1e-7 K for temperatures up to 1e5 K (c_v,vib
+  // <= R, e_vib/R <= T), far under FP32 resolution: they are taken as 0.
+  T g1, g2, g3;
+  if (b < T(1e-12)) {
+    g1 = T(3) * a / (T(1.5) + a);
+    g2 = g3 = T(0);
+  } else {
+    const T Tc = tcheck<T>(Th, Ttr, Trot, Tvib, a, b);
+    const T cb = cbar_R<T>(Th, Tc, Tvib);
+    const T D = T(1.5) + a + b * cb;
+    g1 = T(3) * a / D; g2 = T(3) * b * cb / D; g3 = T(2) * a * b * cb / D;
+  }
   const T Xtr = g1 * (Ttr - Trot) + g2 * (Ttr - Tvib);
   const T Xrot = g1 * (Ttr - Trot) - g3 * (Trot - Tvib);
   const T Xvib = g2 * (Ttr - Tvib) + g3 * (Trot - Tvib);
@@ -212,6 +223,24 @@ __device__ PartCoef<T> particle_coef(T R, T Th, T Ttr, T Trot, T Tvib, const T P
   return r;
 }
 
+// A particle's stored position (x used in 2D, y in 1D and 2D) and id (the
+// key of its random streams), as the update reads them: from the particle
+// arrays, or from a stage that holds them.
+template <typename S>
+struct PartPos {
+  S x, y;
+  uint32_t pid;
+};
+
+template <typename S>
+__device__ __forceinline__ PartPos<S> load_pos(const PartP<S>& p, int64_t i, int dim) {
+  PartPos<S> q;
+  q.x = dim == 2 ? p.x[i] : S(0);
+  q.y = dim >= 1 ? p.y[i] : S(0);
+  q.pid = p.pid[i];
+  return q;
+}
+
 // Stencil of a particle: the quadrant of its position in its cell selects
 // one of the four precomputed stencils (see k_stencil); weights are the
 // offsets from the cell centre over the signed spacing.
@@ -223,7 +252,7 @@ struct Stencil {
 
 template <typename S>
 __device__ __forceinline__ Stencil particle_stencil(const GridP& g, int32_t bits, int32_t c,
-                                                    const PartP<S>& p, int64_t i) {
+                                                    const PartPos<S>& q) {
   Stencil st;
   st.c10 = st.c01 = st.c11 = c;
   st.wx = st.wy = 0.0;
@@ -233,14 +262,14 @@ __device__ __forceinline__ Stencil particle_stencil(const GridP& g, int32_t bits
   const int ci = g.dim == 2 ? c % nx : 0;
   const int cj = g.dim == 2 ? c / nx : c;
   // cell centre with explicitly rounded operations (no contraction)
-  const double dyv = (double)p.y[i] - __dadd_rn(g.y0, __dmul_rn(cj + 0.5, g.dy));
+  const double dyv = (double)q.y - __dadd_rn(g.y0, __dmul_rn(cj + 0.5, g.dy));
   double dxv = 0.0;
-  int q = dyv >= 0.0 ? 2 : 0;
+  int qd = dyv >= 0.0 ? 2 : 0;
   if (g.dim == 2) {
-    dxv = (double)p.x[i] - __dadd_rn(g.x0, __dmul_rn(ci + 0.5, g.dx));
-    q |= dxv >= 0.0 ? 1 : 0;
+    dxv = (double)q.x - __dadd_rn(g.x0, __dmul_rn(ci + 0.5, g.dx));
+    qd |= dxv >= 0.0 ? 1 : 0;
   }
-  const int f = (bits >> (5 * q)) & 31;
+  const int f = (bits >> (5 * qd)) & 31;
   const int tx = (f & 3) == 1 ? 1 : ((f & 3) == 2 ? -1 : 0);
   const int ty = ((f >> 2) & 3) == 1 ? 1 : (((f >> 2) & 3) == 2 ? -1 : 0);
   if (ty) { st.hy = true; st.wy = dyv / (ty * g.dy); st.c01 = (int64_t)(cj + ty) * nx + ci; }
@@ -309,11 +338,9 @@ __device__ __forceinline__ PartNew<S> load_state(const PartP<S>& p, int64_t i) {
 // Draws and the velocity (eq. update_ci), rotational (eq. update_erot) and
 // vibrational (eq. update_evib) updates of particle i.
 template <typename S, typename T>
-__device__ __forceinline__ void update_particle(const PartP<S>& p, int64_t i, const PartNew<S>& in,
-                                                const T U[3],
+__device__ __forceinline__ void update_particle(uint32_t id, const PartNew<S>& in, const T U[3],
                                                 const PartCoef<T>& pc, T R, uint64_t seed,
                                                 uint32_t step, uint32_t* ev, PartNew<S>* o) {
-  const uint32_t id = p.pid[i];
   const U4 w0 = philox(id, step, TAG_COLLIDE, 0u, seed);
   const U4 w1 = philox(id, step, TAG_COLLIDE, 1u, seed);
   T G1, G2, G3, G4;
@@ -371,7 +398,7 @@ constexpr int FPM_MAX_JUMPS = 4096;
 template <typename S>
 __device__ __forceinline__ PartNew<S> collide_fpm(const GridP& g, const GasP& gas,
                                                  const double* __restrict__ cs,
-                                                 const PartP<S>& p, int64_t i, int32_t c,
+                                                 const PartPos<S>& pq, int32_t c,
                                                  const PartNew<S>& in, uint64_t seed,
                                                  uint32_t step, uint32_t* evp) {
 #pragma clang fp contract(off)
@@ -407,7 +434,7 @@ __device__ __forceinline__ PartNew<S> collide_fpm(const GridP& g, const GasP& ga
   }
   if (Trot_rel < 0.0) { Trot_rel = 0.0; ev |= 1u << USP_CNT_TREL_CLAMP; }
   if (mrel < 0.0) { mrel = 0.0; ev |= 1u << USP_CNT_TREL_CLAMP; }
-  const uint32_t id = p.pid[i];
+  const uint32_t id = pq.pid;
   const U4 w0 = philox(id, step, TAG_COLLIDE, 0u, seed);
   {
     // the draws and the update in the state precision (the decisions
@@ -464,11 +491,11 @@ __device__ __forceinline__ PartNew<S> collide_fpm(const GridP& g, const GasP& ga
 template <bool FPM>
 __device__ __forceinline__ PartNew<float> collide_f32(const GridP& g, const GasP& gas,
                                                      const double* __restrict__ cs,
-                                                     const PartP<float>& p, int64_t i, int32_t c,
+                                                     const PartPos<float>& q, int32_t c,
                                                      const PartNew<float>& in, uint64_t seed,
                                                      uint32_t step, uint32_t* evp, bool* esc) {
   *esc = false;
-  if constexpr (FPM) return collide_fpm<float>(g, gas, cs, p, i, c, in, seed, step, evp);
+  if constexpr (FPM) return collide_fpm<float>(g, gas, cs, q, c, in, seed, step, evp);
   PartNew<float> o;
   o.changed = false;
   const int64_t M = g.M;
@@ -478,7 +505,7 @@ __device__ __forceinline__ PartNew<float> collide_f32(const GridP& g, const GasP
   const float4 q5 = r4[4];  // a, b, al, nu
   const CellRec& own = rec[c];
   if (own.collide == 0) return o;
-  const Stencil st = particle_stencil<float>(g, __float_as_int(q4.w), c, p, i);
+  const Stencil st = particle_stencil<float>(g, __float_as_int(q4.w), c, q);
   // fields of the stencil cells
   float f00[12], f10[12], f01[12], f11[12];
   auto load12 = [&](int64_t cc, float* o) {
@@ -521,7 +548,7 @@ __device__ __forceinline__ PartNew<float> collide_f32(const GridP& g, const GasP
     return o;
   }
   note_coef_events(pc, &ev);
-  if (!pc.skip) update_particle<float, float>(p, i, in, U, pc, (float)gas.R, seed, step, &ev, &o);
+  if (!pc.skip) update_particle<float, float>(q.pid, in, U, pc, (float)gas.R, seed, step, &ev, &o);
   *evp |= ev;
   return o;
 }
@@ -533,13 +560,13 @@ __device__ __forceinline__ PartNew<float> collide_f32(const GridP& g, const GasP
 // the first pass).
 __device__ __forceinline__ PartNew<float> collide_esc(const GridP& g, const GasP& gas,
                                                      const double* __restrict__ cs,
-                                                     const PartP<float>& p, int64_t i, int32_t c,
+                                                     const PartPos<float>& q, int32_t c,
                                                      const PartNew<float>& in, uint64_t seed,
                                                      uint32_t step, uint32_t* evp) {
   PartNew<float> o;
   o.changed = false;
   const int64_t M = g.M;
-  const Stencil st = particle_stencil<float>(g, cell_records(cs, M)[c].stencil, c, p, i);
+  const Stencil st = particle_stencil<float>(g, cell_records(cs, M)[c].stencil, c, q);
   double Ud[3], Pd[6], Td[3];
   fields_planes(cs, M, c, st, Ud, Pd, Td);
   const CellCoef cd = coef_planes(cs, M, c);
@@ -554,7 +581,7 @@ __device__ __forceinline__ PartNew<float> collide_esc(const GridP& g, const GasP
   uint32_t ev = 0;
   note_coef_events(pc, &ev);
   const float U[3] = {(float)Ud[0], (float)Ud[1], (float)Ud[2]};
-  if (!pc.skip) update_particle<float, float>(p, i, in, U, pc, (float)gas.R, seed, step, &ev, &o);
+  if (!pc.skip) update_particle<float, float>(q.pid, in, U, pc, (float)gas.R, seed, step, &ev, &o);
   *evp |= ev;
   return o;
 }
@@ -563,12 +590,12 @@ __device__ __forceinline__ PartNew<float> collide_esc(const GridP& g, const GasP
 template <bool FPM>
 __device__ __forceinline__ PartNew<float> collide_one(const GridP& g, const GasP& gas,
                                                      const double* __restrict__ cs,
-                                                     const PartP<float>& p, int64_t i, int32_t c,
+                                                     const PartPos<float>& q, int32_t c,
                                                      const PartNew<float>& in, uint64_t seed,
                                                      uint32_t step, uint32_t* evp) {
   bool esc;
-  PartNew<float> o = collide_f32<FPM>(g, gas, cs, p, i, c, in, seed, step, evp, &esc);
-  if (esc) o = collide_esc(g, gas, cs, p, i, c, in, seed, step, evp);
+  PartNew<float> o = collide_f32<FPM>(g, gas, cs, q, c, in, seed, step, evp, &esc);
+  if (esc) o = collide_esc(g, gas, cs, q, c, in, seed, step, evp);
   return o;
 }
 
@@ -576,22 +603,21 @@ __device__ __forceinline__ PartNew<float> collide_one(const GridP& g, const GasP
 template <bool FPM>
 __device__ __forceinline__ PartNew<double> collide_one(const GridP& g, const GasP& gas,
                                                       const double* __restrict__ cs,
-                                                      const PartP<double>& p, int64_t i,
-                                                      int32_t c, const PartNew<double>& in,
-                                                      uint64_t seed, uint32_t step,
-                                                      uint32_t* evp) {
-  if constexpr (FPM) return collide_fpm<double>(g, gas, cs, p, i, c, in, seed, step, evp);
+                                                      const PartPos<double>& q, int32_t c,
+                                                      const PartNew<double>& in, uint64_t seed,
+                                                      uint32_t step, uint32_t* evp) {
+  if constexpr (FPM) return collide_fpm<double>(g, gas, cs, q, c, in, seed, step, evp);
   PartNew<double> o;
   o.changed = false;
   const int64_t M = g.M;
   if (cs[CS_COLLIDE * M + c] == 0.0) return o;
-  const Stencil st = particle_stencil<double>(g, cell_records(cs, M)[c].stencil, c, p, i);
+  const Stencil st = particle_stencil<double>(g, cell_records(cs, M)[c].stencil, c, q);
   double U[3], P[6], Tk[3];
   uint32_t ev = fields_planes(cs, M, c, st, U, P, Tk) ? (1u << USP_CNT_INTERP_CLAMP) : 0u;
   const CellCoef cc = coef_planes(cs, M, c);
   const PartCoef<double> pc = particle_coef<double>(gas.R, gas.theta, Tk[0], Tk[1], Tk[2], P, cc);
   note_coef_events(pc, &ev);
-  if (!pc.skip) update_particle<double, double>(p, i, in, U, pc, gas.R, seed, step, &ev, &o);
+  if (!pc.skip) update_particle<double, double>(q.pid, in, U, pc, gas.R, seed, step, &ev, &o);
   *evp |= ev;
   return o;
 }
@@ -866,16 +892,20 @@ __device__ __forceinline__ void surf_record(const GridP& g, const BcP& bc, int s
   atomicAdd(a + USP_SURF_QVIB, (unsigned long long)(long long)(lvi - lvo));
 }
 
-template <typename S, typename CNT>
+// q holds the particle's stored position and id; with WPOS they are also
+// written to slot i (a caller whose arrays do not hold them yet), the
+// position of a deleted particle unchanged.
+template <typename S, bool WPOS = false, typename CNT>
 __device__ __forceinline__ void advect_one(const GridP& g, const GasP& gas, const BcP& bc,
-                                           double dt, const PartP<S>& p, int64_t i, S cx0, S cy0,
-                                           S cz0, S er0, int lv0, uint64_t seed, uint32_t step,
+                                           double dt, const PartP<S>& p, int64_t i,
+                                           const PartPos<S>& q, S cx0, S cy0, S cz0, S er0,
+                                           int lv0, uint64_t seed, uint32_t step,
                                            CNT counters) {
   // body-force kick, rounded to storage as the state is, then the flight
   double cx = (double)(S)((double)cx0 + bc.g[0] * dt);
   double cy = (double)(S)((double)cy0 + bc.g[1] * dt);
   double cz = (double)(S)((double)cz0 + bc.g[2] * dt);
-  double x = g.dim == 2 ? (double)p.x[i] : 0.0, y = (double)p.y[i];
+  double x = g.dim == 2 ? (double)q.x : 0.0, y = (double)q.y;
   double er = (double)er0;
   int lv = lv0;
   const double xlo = (double)(S)g.x0, xhi = (double)edge<S>(g.x0, g.dx, g.nx);
@@ -884,7 +914,8 @@ __device__ __forceinline__ void advect_one(const GridP& g, const GasP& gas, cons
   int bounces = 0, events = 0;
   bool deleted = false;
   uint32_t ev = 0;
-  const uint32_t id = p.pid[i];
+  const uint32_t id = q.pid;
+  if (WPOS) p.pid[i] = id;
   for (;;) {
     double th = INFINITY;
     int side = -1;
@@ -972,6 +1003,10 @@ __device__ __forceinline__ void advect_one(const GridP& g, const GasP& gas, cons
     // a deleted particle keeps its position and its values before the flight
     p.cell[i] = -1;
     p.cx[i] = cx0; p.cy[i] = cy0; p.cz[i] = cz0; p.erot[i] = er0; p.vib[i] = (uint8_t)lv0;
+    if (WPOS) {
+      if (g.dim == 2) p.x[i] = q.x;
+      p.y[i] = q.y;
+    }
     ev |= 1u << USP_CNT_DELETED;
   } else {
     S xs = S(0);

@@ -45,30 +45,30 @@ __device__ __forceinline__ Stage<S> global_stage(const PartP<S>& p) {
 // state has a single pass.
 template <bool FPM>
 __device__ __forceinline__ PartNew<float> update_first(const GridP& g, const GasP& gas,
-                                                      const double* cs, const PartP<float>& p,
-                                                      int64_t i, int32_t c,
-                                                      const PartNew<float>& in, uint64_t seed,
-                                                      uint32_t step, uint32_t* ev, bool* esc) {
-  return collide_f32<FPM>(g, gas, cs, p, i, c, in, seed, step, ev, esc);
+                                                      const double* cs, const PartPos<float>& q,
+                                                      int32_t c, const PartNew<float>& in,
+                                                      uint64_t seed, uint32_t step, uint32_t* ev,
+                                                      bool* esc) {
+  return collide_f32<FPM>(g, gas, cs, q, c, in, seed, step, ev, esc);
 }
 template <bool FPM>
 __device__ __forceinline__ PartNew<double> update_first(const GridP& g, const GasP& gas,
-                                                       const double* cs, const PartP<double>& p,
-                                                       int64_t i, int32_t c,
-                                                       const PartNew<double>& in, uint64_t seed,
-                                                       uint32_t step, uint32_t* ev, bool* esc) {
+                                                       const double* cs, const PartPos<double>& q,
+                                                       int32_t c, const PartNew<double>& in,
+                                                       uint64_t seed, uint32_t step, uint32_t* ev,
+                                                       bool* esc) {
   *esc = false;
-  return collide_one<FPM>(g, gas, cs, p, i, c, in, seed, step, ev);
+  return collide_one<FPM>(g, gas, cs, q, c, in, seed, step, ev);
 }
 __device__ __forceinline__ PartNew<float> update_second(const GridP& g, const GasP& gas,
-                                                       const double* cs, const PartP<float>& p,
-                                                       int64_t i, int32_t c,
-                                                       const PartNew<float>& in, uint64_t seed,
-                                                       uint32_t step, uint32_t* ev) {
-  return collide_esc(g, gas, cs, p, i, c, in, seed, step, ev);
+                                                       const double* cs, const PartPos<float>& q,
+                                                       int32_t c, const PartNew<float>& in,
+                                                       uint64_t seed, uint32_t step,
+                                                       uint32_t* ev) {
+  return collide_esc(g, gas, cs, q, c, in, seed, step, ev);
 }
 __device__ __forceinline__ PartNew<double> update_second(const GridP&, const GasP&, const double*,
-                                                        const PartP<double>&, int64_t, int32_t,
+                                                        const PartPos<double>&, int32_t,
                                                         const PartNew<double>&, uint64_t,
                                                         uint32_t, uint32_t*) {
   PartNew<double> o;
@@ -104,7 +104,8 @@ __device__ __forceinline__ void tile_update(const GridP& g, const GasP& gas,
       GridP gl = g;
       const double* csl = cs;
       asm volatile("" : "+s"(csl), "+s"(gl.M));
-      if (c >= 0) o = update_first<FPM>(gl, gas, csl, p, i, c, in, seed, step, &ev, &esc);
+      if (c >= 0)
+        o = update_first<FPM>(gl, gas, csl, load_pos(p, i, g.dim), c, in, seed, step, &ev, &esc);
       if (esc) esc_list[atomicAdd(nesc, 1)] = (uint16_t)(i - cb);
       else if (o.changed) dst.store(i, o);
       else if (!SAME) dst.store(i, in);
@@ -116,7 +117,8 @@ __device__ __forceinline__ void tile_update(const GridP& g, const GasP& gas,
       const int64_t i = cb + esc_list[k];
       const PartNew<S> in = src.load(i);
       uint32_t ev = 0;
-      const PartNew<S> o = update_second(g, gas, cs, p, i, p.cell[i], in, seed, step, &ev);
+      const PartNew<S> o = update_second(g, gas, cs, load_pos(p, i, g.dim), p.cell[i], in, seed,
+                                         step, &ev);
       if (o.changed) dst.store(i, o);
       else if (!SAME) dst.store(i, in);
       flush_events(counters, ev);

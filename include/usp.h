@@ -461,8 +461,11 @@ usp_status usp_check(const usp_grid* grid, const usp_particles* p, const double*
    floor (Sec. III.B), the Cholesky test (a particle whose test fails keeps
    its post-collision state as a constant, Sec. III.A.3), the clamp of
    T_rot^rel, the skips of the conservation scalings, and every boundary
-   event of the flight (the particle keeps its post-flight state as a
-   constant).  The outputs, for a run of K steps, area = volume[0]/dy:
+   event of the flight (a particle that meets a wall keeps its re-emitted
+   velocity, energy and level as constants; its position after the flight
+   follows the time of its first hit, the flights between walls after it
+   keeping their durations).  The outputs, for a run of K steps, area =
+   volume[0]/dy:
      J0 = w_mdot * sum over steps of sum_i c_x,i at the start of the step,
      J1 = w_tau * sum over steps of sum over particles whose flight meets a
           boundary of (c_x after the kick - c_x after the flight),

@@ -9,8 +9,9 @@ outcome held fixed at the values the run took:
 - the vibrational levels after the collision (Sec. III.A.2 jumps) and after
   the conservation picks (Sec. IV.C);
 - every boundary event of the free flight: a particle whose flight meets a
-  wall keeps its post-flight state (the re-emitted velocity, energy, level
-  and position) as a constant;
+  wall keeps its re-emitted velocity, energy and level as constants, and
+  its position after the flight follows the time of its first wall hit
+  (the flights between walls after it keep their recorded durations);
 - every branch: the stencil of each particle (Sec. III.B), the 5% floor of
   the interpolated temperatures, the Cholesky test (a particle whose test
   fails keeps its post-collision state as a constant, Sec. III.A.3), the
@@ -370,7 +371,22 @@ class Path:
             ev = dk["event"]
             cf = _t(np.stack([fl["cx"], fl["cy"], fl["cz"]], 1))
             tau = tau + torch.where(ev, ck[:, 0] - cf[:, 0], torch.zeros_like(ck[:, 0])).sum()
-            y = torch.where(ev, _t(fl["y"]), y + ck[:, 1] * dt)
+            # a particle whose flight meets a wall leaves with the re-emitted
+            # velocity, energy and level (constants of the path); its position
+            # after the flight follows the first hit time t1 = (y_wall,1 - y)/c_y:
+            # y_f = y_wall,last + c_y,f (dt - t_between - t1), with t_between
+            # (the flights between the walls) fixed at its recorded value
+            cfy = cf[:, 1]
+            yw1 = torch.where(ck[:, 1] < 0, torch.full_like(y, ylo), torch.full_like(y, yhi))
+            ywl = torch.where(cfy > 0, torch.full_like(y, ylo), torch.full_like(y, yhi))
+            cky = torch.where(ev, ck[:, 1], torch.ones_like(y))
+            if record:
+                with torch.no_grad():
+                    t1r = (yw1 - y) / cky
+                    tlr = dt - (_t(fl["y"]) - ywl) / torch.where(ev, cfy, torch.ones_like(cfy))
+                    dk["t_between"] = torch.where(ev, tlr - t1r, torch.zeros_like(t1r))
+            yhit = ywl + cfy * (dt - dk["t_between"] - (yw1 - y) / cky)
+            y = torch.where(ev, yhit, y + ck[:, 1] * dt)
             c = torch.where(ev[:, None], cf, ck)
             e = torch.where(ev, _t(fl["erot"]), e2)
             if check:

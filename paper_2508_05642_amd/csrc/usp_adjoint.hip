@@ -37,7 +37,7 @@ namespace usp {
 // ---- tape and scratch layouts ---------------------------------------------
 struct TapeLayout {
   size_t perm, y, cx, cy, cz, erot, vib, cell, pid, ccx, ccy, ccz, cerot, kcx, kcy, kcz, kerot,
-      kvib, offsets, cs, total;
+      kvib, fcy, offsets, cs, total;
 };
 
 static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -52,6 +52,7 @@ static TapeLayout tape_layout(int64_t M, int64_t cap) {
   t.vib = take((size_t)cap); t.cell = take((size_t)cap * 4); t.pid = take((size_t)cap * 4);
   t.ccx = take(d); t.ccy = take(d); t.ccz = take(d); t.cerot = take(d);
   t.kcx = take(d); t.kcy = take(d); t.kcz = take(d); t.kerot = take(d); t.kvib = take((size_t)cap);
+  t.fcy = take(d);
   t.offsets = take((size_t)(M + 1) * 8);
   t.cs = take(cellstate_bytes(M));
   t.total = o;
@@ -100,6 +101,7 @@ struct TapeP {
   const double *ccx, *ccy, *ccz, *cerot;
   const double *kcx, *kcy, *kcz, *kerot;
   const uint8_t* kvib;
+  const double* fcy;  // y velocity after the flight
   const int64_t* offsets;
   const double* cs;
 };
@@ -116,6 +118,7 @@ static TapeP tape_ptrs(const char* base, const TapeLayout& t) {
   p.kcx = (const double*)(base + t.kcx); p.kcy = (const double*)(base + t.kcy);
   p.kcz = (const double*)(base + t.kcz); p.kerot = (const double*)(base + t.kerot);
   p.kvib = (const uint8_t*)(base + t.kvib);
+  p.fcy = (const double*)(base + t.fcy);
   p.offsets = (const int64_t*)(base + t.offsets);
   p.cs = (const double*)(base + t.cs);
   return p;
@@ -200,7 +203,12 @@ static hipError_t step_taped(const GridP& g, const GasP& gas, const BcP& bc, dou
   copy_d(tape + T.kerot, out.erot, d, st, &ce);
   copy_d(tape + T.kvib, out.vib, (size_t)cap, st, &ce);
   if (ce != hipSuccess) return ce;
-  return launch_advect<double>(g, gas, bc, dt, out, seed, step, ws, L, counters, st);
+  if ((e = launch_advect<double>(g, gas, bc, dt, out, seed, step, ws, L, counters, st)) != hipSuccess)
+    return e;
+  // the y velocity after the flight, for the hit-time derivative of the
+  // particles that met a wall (1D: no particle is created or removed)
+  copy_d(tape + T.fcy, out.cy, d, st, &ce);
+  return ce;
 }
 
 // ---- shared pieces of the reverse -------------------------------------------
@@ -335,11 +343,21 @@ __global__ __launch_bounds__(256) void k_adj_flight_conserve(GridP g, GasP gas, 
   if (N == 0) return;
   const double* cs = T.cs;
   const bool coll = cs[CS_COLLIDE * M + c] != 0.0;
-  // adjoint of the post-conservation state (o, component) of particle i
+  // adjoint of the post-conservation state (o, component) of particle i.
+  // A particle whose flight meets a wall leaves with the re-emitted
+  // velocity, energy and level (constants of the path); its position after
+  // the flight is y_wall,last + c_y,f (dt - t_between - t_1), with t_1 =
+  // (y_wall,1 - y)/c_y the first hit time, c_y the velocity after the kick
+  // and c_y,f the final one: d y_f/d y = c_y,f/c_y, d y_f/d c_y = c_y,f
+  // t_1/c_y.
+  const double ylo = (double)g.y0, yhi = (double)edge<double>(g.y0, g.dy, g.ny);
   auto post = [&](int64_t i, int o, double lc[3], double* le, double* ly) {
     const double ck[3] = {T.kcx[i] + bc.g[0] * dt, T.kcy[i] + bc.g[1] * dt, T.kcz[i] + bc.g[2] * dt};
     if (flight_event_1d(g, T.y[i], ck[1], dt)) {
-      lc[0] = o == 1 ? w_tau : 0.0; lc[1] = 0.0; lc[2] = 0.0; *le = 0.0; *ly = 0.0;
+      const double lyf = lam_at(const_cast<double*>(lam_in), o, LY, cap, i);
+      const double r = T.fcy[i] / ck[1];
+      const double t1 = ((ck[1] < 0.0 ? ylo : yhi) - T.y[i]) / ck[1];
+      lc[0] = o == 1 ? w_tau : 0.0; lc[1] = lyf * r * t1; lc[2] = 0.0; *le = 0.0; *ly = lyf * r;
       return;
     }
     const double lyv = lam_at(const_cast<double*>(lam_in), o, LY, cap, i);

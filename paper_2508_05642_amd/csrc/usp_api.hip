@@ -79,6 +79,9 @@ WsLayout ws_layout(int64_t M, int64_t capacity, int nfaces) {
   L.face_off = o; o = align256(o + sizeof(int64_t) * (size_t)(nfaces + 1));
   L.misc = o; o = align256(o + sizeof(int64_t) * 8);
   L.tiles = o; o = align256(o + sizeof(int32_t) * (size_t)(cdiv(capacity, UPDATE_TILE_MIN) + 2));
+  L.chunk_off = o; o = align256(o + sizeof(int64_t) * (size_t)(M + 1));
+  L.chunk_part = o; o = align256(o + sizeof(double) * BIG_PARTS * (size_t)chunks_max(capacity, M));
+  L.cons_scal = o; o = align256(o + CONS_SCALAR_BYTES * (size_t)M);
   L.total = o;
   return L;
 }
@@ -168,7 +171,8 @@ usp_status do_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, d
   // Cells far larger than the fused particle phase's LDS stage (mean slots
   // per cell above it) would give whole cells to single workgroups: such
   // grids run the separate phase kernels, which spread every particle over
-  // the chip and give the same bits, after a copying bin.
+  // the chip, after a copying bin, with the moments and the conservation's
+  // sums split over chunks of each cell.
   const int stage = sizeof(S) == 4 ? UPDATE_STAGE_F32 : UPDATE_STAGE_F64;
   const bool big_cells = cdiv(cap, g.M) > stage;
   for (int32_t s = 0; s < nsteps; ++s) {
@@ -184,13 +188,16 @@ usp_status do_step(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc, d
         *p = *p_alt;
         *p_alt = tmp;
       }
+      // the per-cell reductions split over chunks of each cell
       const PartP<S> q = make_parts<S>(p);
-      if ((e = launch_moments<S>(g, q, offsets, mom, st)) != hipSuccess) return USP_EDEVICE;
+      if ((e = launch_moments_split<S>(g, q, offsets, mom, w, L, st)) != hipSuccess)
+        return USP_EDEVICE;
       if ((e = launch_reconstruct(g, gp, mom, dt, dt_cell, cs, counters, st)) != hipSuccess)
         return USP_EDEVICE;
       if ((e = launch_collide<S>(g, gp, cs, offsets, q, seed, sn, counters, st)) != hipSuccess)
         return USP_EDEVICE;
-      if ((e = launch_conserve<S>(g, gp, cs, offsets, q, seed, sn, counters, st)) != hipSuccess)
+      if ((e = launch_conserve_split<S>(g, gp, cs, offsets, q, seed, sn, w, L, counters, st)) !=
+          hipSuccess)
         return USP_EDEVICE;
       if (g.dim != 0 &&
           (e = launch_advect<S>(g, gp, bp, dt, q, seed, sn, w, L, counters, st)) != hipSuccess)

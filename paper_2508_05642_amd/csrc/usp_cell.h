@@ -47,6 +47,9 @@ __device__ __forceinline__ void mom_add(const MomIn<PS>& a, double r0, double r1
 
 constexpr int MOM_LANES = 16;
 
+__device__ __forceinline__ void moments_from_sums(const double s[20], int64_t N, double r0,
+                                                  double r1, double r2, double v[NMOM]);
+
 // The NMOM moments of the particles [o0, o1) (array indices) on one row of
 // 16 lanes (sub = lane in the row; all 16 lanes call); every lane of the
 // row returns the same v.  With G, slot i is the particle perm[i] of the
@@ -85,6 +88,14 @@ __device__ __forceinline__ void row_moments(const PS* cx, const PS* cy, const PS
   for (; i < o1; i += MOM_LANES) mom_add(mom_load<PS>(cx, cy, cz, er, vb, at(i)), r0, r1, r2, s);
 #pragma unroll
   for (int k = 0; k < 20; ++k) s[k] = row16_sum(s[k]);
+  moments_from_sums(s, N, r0, r1, r2, v);
+}
+
+// The NMOM moments of N particles from their 20 sums shifted by (r0, r1,
+// r2) (the first particle's velocity): the sums of d, d_i d_j, |d|^2 d_i,
+// e, d_i e, I, d_i I of mom_add.
+__device__ __forceinline__ void moments_from_sums(const double s[20], int64_t N, double r0,
+                                                  double r1, double r2, double v[NMOM]) {
   if (N == 0) {
 #pragma unroll
     for (int k = 0; k < NMOM; ++k) v[k] = 0.0;

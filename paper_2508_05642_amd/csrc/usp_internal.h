@@ -106,8 +106,18 @@ template <typename S> PartP<S> make_parts(const usp_particles* p);
 // workspace layout (byte offsets into the caller's scratch buffer)
 struct WsLayout {
   size_t key, perm, blocksums, t9, cell_i32, old_off, far_off, far, face_cnt, face_off, misc,
-      tiles, total;
+      tiles, chunk_off, chunk_part, cons_scal, total;
 };
+// Cells split into chunks for the per-cell reductions (grids whose cells
+// are far larger than a workgroup's share): slots per chunk, partial sums
+// per chunk, bytes of a cell's conservation scalars, and the most chunks a
+// binned state of `capacity` slots in M cells can have.
+constexpr int BIG_CHUNK = 512;
+constexpr int BIG_PARTS = 20;
+constexpr size_t CONS_SCALAR_BYTES = 80;
+inline int64_t chunks_max(int64_t capacity, int64_t M) {
+  return (capacity + BIG_CHUNK - 1) / BIG_CHUNK + M;
+}
 // LDS stage of the fused particle phase, in particle slots (FP32 / FP64
 // state), and the smallest tile window (the tile index array is sized for it)
 constexpr int UPDATE_STAGE_F32 = 2048;
@@ -131,6 +141,17 @@ template <typename S>
 hipError_t launch_collide(const GridP& g, const GasP& gas, const double* cs, const int64_t* offsets,
                           const PartP<S>& p, uint64_t seed, uint64_t step, int64_t* counters,
                           hipStream_t st);
+// The moments and the conservation with every cell split into chunks of
+// BIG_CHUNK slots (same quantities, partial sums combined in chunk order;
+// the conservation reuses the chunk index of the moments).
+template <typename S>
+hipError_t launch_moments_split(const GridP& g, const PartP<S>& p, const int64_t* offsets,
+                                double* mom, char* ws, const WsLayout& L, hipStream_t st);
+template <typename S>
+hipError_t launch_conserve_split(const GridP& g, const GasP& gas, const double* cs,
+                                 const int64_t* offsets, const PartP<S>& p, uint64_t seed,
+                                 uint64_t step, char* ws, const WsLayout& L, int64_t* counters,
+                                 hipStream_t st);
 template <typename S>
 hipError_t launch_conserve(const GridP& g, const GasP& gas, const double* cs,
                            const int64_t* offsets, const PartP<S>& p, uint64_t seed, uint64_t step,

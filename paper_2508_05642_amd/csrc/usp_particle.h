@@ -721,26 +721,27 @@ __device__ int wave_picks(uint8_t* lv, int64_t N, int64_t Id, int64_t* SI_io, ui
   return moved;
 }
 
-// Conservation of one cell by one wave (Sec. IV.C).  The cell's particles
-// are [o0, o1); their post-collision values sit at vx[i - base] etc.
-// (LDS or global).  The vibrational picks run on `lv`, the cell's levels
-// (LDS or global); if `copy` is set, vx's levels are first copied to lv and
-// copied back after the picks.
-template <typename S, typename PS>
-__device__ __forceinline__ void conserve_cell(const GasP& gas, const double* __restrict__ cs,
-                                              int64_t M, int64_t c, int64_t o0, int64_t o1,
-                                              PS* vcx, PS* vcy, PS* vcz, PS* verot, uint8_t* vvib,
-                                              int64_t base, uint8_t* lv, bool copy,
-                                              uint64_t seed, uint32_t step, int64_t* counters) {
-  const int lane = threadIdx.x & 63;
-  const int64_t N = o1 - o0;
-  // the cell's values, wave-uniform, all requested before the first pass
-  const double Un[3] = {cs[CS_UX * M + c], cs[CS_UY * M + c], cs[CS_UZ * M + c]};
-  const double evib_t = cs[CS_EVIB_NEW * M + c], erot_t = cs[CS_EROT_NEW * M + c];
-  const double E0 = cs[CS_ETR * M + c] + cs[CS_EROT * M + c] + cs[CS_EVIB * M + c];
-  double s[6] = {0, 0, 0, 0, 0, 0};
-  int lmax = 0;
-  for (int64_t i = o0 + lane; i < o1; i += 64) {
+// The per-cell quantities of the conservation of Sec. IV.C, computed from
+// the cell's post-collision sums and applied to each particle afterwards.
+struct ConsScalars {
+  double Un[3];   // U^n, the velocity scaling's target mean
+  double Us[3];   // U*, the post-collision mean
+  double frot;    // rotational factor (0: no rotational scaling)
+  double sc;      // velocity factor (0: no velocity scaling)
+  int moved;      // a level was changed by the picks
+};
+
+// Post-collision sums of the particles [i0, i1) taken by one lane (i0 =
+// its first index, stride `stride`): s = (sum C_x, C_y, C_z, |C|^2 with C =
+// c - U^n, sum e_rot, sum I) and the largest level; vx[i - base] etc. (LDS
+// or global).  With copy, the levels are also copied to lv[i - o0].
+template <typename PS>
+__device__ __forceinline__ void cons_sums(const double Un[3], int64_t i0, int64_t i1,
+                                          int64_t stride, const PS* vcx, const PS* vcy,
+                                          const PS* vcz, const PS* verot, const uint8_t* vvib,
+                                          int64_t base, uint8_t* lv, int64_t o0, bool copy,
+                                          double s[6], int* lmax) {
+  for (int64_t i = i0; i < i1; i += stride) {
     const int64_t j = i - base;
     const double d0 = (double)vcx[j] - Un[0], d1 = (double)vcy[j] - Un[1],
                  d2 = (double)vcz[j] - Un[2];
@@ -749,12 +750,27 @@ __device__ __forceinline__ void conserve_cell(const GasP& gas, const double* __r
     s[4] += (double)verot[j];
     const uint8_t v = vvib[j];
     s[5] += (double)v;
-    lmax = v > lmax ? v : lmax;
+    *lmax = v > *lmax ? v : *lmax;
     if (copy) lv[i - o0] = v;
   }
-#pragma unroll
-  for (int k = 0; k < 6; ++k) s[k] = wave_sum(s[k]);
-  wave_sync_lds();
+}
+
+// The conservation of cell c from its wave-reduced sums s (uniform on the
+// wave) and largest level lmax: (i) the vibrational correction, |I_delta|
+// single-level moves by wave_picks on the cell's levels lv, (ii) the
+// rotational factor to the cell target, (iii) the velocity factor about U*
+// toward U^n that restores momentum and total energy with the energies
+// actually reached.  Called by a whole wave; the result is uniform.
+__device__ __forceinline__ ConsScalars cons_scalars(const GasP& gas, const double* __restrict__ cs,
+                                                    int64_t M, int64_t c, int64_t N,
+                                                    const double s[6], int lmax, uint8_t* lv,
+                                                    uint64_t seed, uint32_t step,
+                                                    int64_t* counters) {
+  const int lane = threadIdx.x & 63;
+  ConsScalars r;
+  r.Un[0] = cs[CS_UX * M + c]; r.Un[1] = cs[CS_UY * M + c]; r.Un[2] = cs[CS_UZ * M + c];
+  const double evib_t = cs[CS_EVIB_NEW * M + c], erot_t = cs[CS_EROT_NEW * M + c];
+  const double E0 = cs[CS_ETR * M + c] + cs[CS_EROT * M + c] + cs[CS_EVIB * M + c];
   const double Nd = (double)N;
   const double m1[3] = {s[0] / Nd, s[1] / Nd, s[2] / Nd};
   const double RTh = gas.R * gas.theta;
@@ -769,9 +785,9 @@ __device__ __forceinline__ void conserve_cell(const GasP& gas, const double* __r
   // no level can reach VIB_MAX through these increments
   const int64_t need0 = Id0 > 0 ? Id0 : 0;
   const bool low = !__ballot((int64_t)lmax + need0 >= VIB_MAX);
-  const int moved = wave_picks(lv, N, Id0, &SI, (uint32_t)c, step, seed, low, counters);
+  r.moved = wave_picks(lv, N, Id0, &SI, (uint32_t)c, step, seed, low, counters);
   // the cell scalars, the same on every lane (wave-uniform inputs)
-  double frot = 0.0, sc = 0.0;
+  r.frot = 0.0; r.sc = 0.0;
   const double etr_s = 0.5 * (s[3] / Nd - (m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2]));
   // (ii) rotational scaling to the cell target
   const double erot_s = s[4] / Nd;
@@ -780,7 +796,7 @@ __device__ __forceinline__ void conserve_cell(const GasP& gas, const double* __r
   if (fpm) {
     // the sampled rotational energies stand
   } else if (erot_s > 0.0 && erot_t > 0.0) {
-    frot = erot_t / erot_s;
+    r.frot = erot_t / erot_s;
     erot_a = erot_t;
   } else {
     ++skips;
@@ -788,21 +804,53 @@ __device__ __forceinline__ void conserve_cell(const GasP& gas, const double* __r
   // (iii) velocity scaling about U*, toward U^n (momentum and energy)
   const double evib_a = (double)SI * RTh / Nd;
   const double s2 = (E0 - erot_a - evib_a) / etr_s;
-  if (etr_s > 0.0 && s2 > 0.0) sc = sqrt(s2);
+  if (etr_s > 0.0 && s2 > 0.0) r.sc = sqrt(s2);
   else ++skips;
   if (lane == 0)
     for (int k = 0; k < skips; ++k) count_event(counters, USP_CNT_CONS_SKIP);
+  r.Us[0] = r.Un[0] + m1[0]; r.Us[1] = r.Un[1] + m1[1]; r.Us[2] = r.Un[2] + m1[2];
+  return r;
+}
+
+// The conservation's scalings of particle i (vx[i - base] etc.).
+template <typename S, typename PS>
+__device__ __forceinline__ void cons_apply(const ConsScalars& r, int64_t j, PS* vcx, PS* vcy,
+                                           PS* vcz, PS* verot) {
+  if (r.frot > 0.0) verot[j] = (S)((double)verot[j] * r.frot);
+  if (r.sc > 0.0) {
+    vcx[j] = (S)(r.Un[0] + r.sc * ((double)vcx[j] - r.Us[0]));
+    vcy[j] = (S)(r.Un[1] + r.sc * ((double)vcy[j] - r.Us[1]));
+    vcz[j] = (S)(r.Un[2] + r.sc * ((double)vcz[j] - r.Us[2]));
+  }
+}
+
+// Conservation of one cell by one wave (Sec. IV.C).  The cell's particles
+// are [o0, o1); their post-collision values sit at vx[i - base] etc.
+// (LDS or global).  The vibrational picks run on `lv`, the cell's levels
+// (LDS or global); if `copy` is set, vx's levels are first copied to lv and
+// copied back after the picks.
+template <typename S, typename PS>
+__device__ __forceinline__ void conserve_cell(const GasP& gas, const double* __restrict__ cs,
+                                              int64_t M, int64_t c, int64_t o0, int64_t o1,
+                                              PS* vcx, PS* vcy, PS* vcz, PS* verot, uint8_t* vvib,
+                                              int64_t base, uint8_t* lv, bool copy,
+                                              uint64_t seed, uint32_t step, int64_t* counters) {
+  const int lane = threadIdx.x & 63;
+  const int64_t N = o1 - o0;
+  // the cell's mean velocity, wave-uniform, requested before the first pass
+  const double Un[3] = {cs[CS_UX * M + c], cs[CS_UY * M + c], cs[CS_UZ * M + c]};
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  int lmax = 0;
+  cons_sums<PS>(Un, o0 + lane, o1, 64, vcx, vcy, vcz, verot, vvib, base, lv, o0, copy, s, &lmax);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s[k] = wave_sum(s[k]);
   wave_sync_lds();
-  const double Us0 = Un[0] + m1[0], Us1 = Un[1] + m1[1], Us2 = Un[2] + m1[2];
+  const ConsScalars r = cons_scalars(gas, cs, M, c, N, s, lmax, lv, seed, step, counters);
+  wave_sync_lds();
   for (int64_t i = o0 + lane; i < o1; i += 64) {
     const int64_t j = i - base;
-    if (copy && moved) vvib[j] = lv[i - o0];
-    if (frot > 0.0) verot[j] = (S)((double)verot[j] * frot);
-    if (sc > 0.0) {
-      vcx[j] = (S)(Un[0] + sc * ((double)vcx[j] - Us0));
-      vcy[j] = (S)(Un[1] + sc * ((double)vcy[j] - Us1));
-      vcz[j] = (S)(Un[2] + sc * ((double)vcz[j] - Us2));
-    }
+    if (copy && r.moved) vvib[j] = lv[i - o0];
+    cons_apply<S, PS>(r, j, vcx, vcy, vcz, verot);
   }
 }
 

@@ -68,6 +68,26 @@ typedef int32_t usp_status;
 #define USP_SCHEME_USP 0
 #define USP_SCHEME_FPM 1
 
+/* reading switches of the USP-FPM particle update (the defaults are the
+   reading the paper's flow chart of Sec. IV.D gives; the first-order FPM
+   scheme ignores both):
+   gamma_scope -- the temperatures and Pi that enter the gamma coefficients,
+     T-check, the relaxation temperatures (eqs. T_tr_USP, T_rot_USP,
+     T_vib_USP), the diffusion tensor (eq. D_tr) and its positivity refit
+     are interpolated to each particle (USP_GAMMA_PARTICLE: the chain runs
+     per particle, after the interpolation) or are the cell's own
+     (USP_GAMMA_CELL: the chain runs once per cell, in FP64, inside
+     usp_reconstruct; the mean velocity U is still interpolated);
+   alpha_sign -- of the two roots of eq. alpha_USP_positivity_2 after a
+     refit, the one whose Prandtl number (eq. alpha_USP_positivity_3) is
+     closer to the cell's (USP_ALPHA_SIGN_PR; ties: +) or the one with the
+     sign of the cell's alpha = cbrt(r3) (USP_ALPHA_SIGN_KEEP; alpha = 0
+     counts as +). */
+#define USP_GAMMA_PARTICLE 0
+#define USP_GAMMA_CELL 1
+#define USP_ALPHA_SIGN_PR 0
+#define USP_ALPHA_SIGN_KEEP 1
+
 /* boundary kinds, per domain side */
 #define USP_BC_PERIODIC 0
 #define USP_BC_DIFFUSE 1     /* isothermal wall, full accommodation */
@@ -125,6 +145,8 @@ typedef struct {
   int32_t pr_model;
   double Pr_const;
   int32_t scheme;    /* USP_SCHEME_USP or USP_SCHEME_FPM */
+  int32_t gamma_scope; /* USP_GAMMA_PARTICLE or USP_GAMMA_CELL */
+  int32_t alpha_sign;  /* USP_ALPHA_SIGN_PR or USP_ALPHA_SIGN_KEEP */
 } usp_gas;
 
 /* Uniform Cartesian grid (the uniform grid of Sec. III.B).  volume and flags
@@ -213,8 +235,10 @@ typedef struct {
    (1/2)<C^2 C>, q_rot(3) = <C eps_rot>, <C I>(3) (times R theta = q_vib). */
 #define USP_NMOM 21
 /* Cell-state buffer: USP_NCS FP64 planes (names: usp_cs_name(k)) followed
-   by one packed 128-byte record per cell that the particle update reads;
-   usp_cellstate_bytes() gives its size. */
+   by one packed 128-byte record per cell that the particle update reads
+   and one 96-byte record per cell of the coefficients the particle update
+   takes from the cell under USP_GAMMA_CELL; usp_cellstate_bytes() gives
+   its size. */
 #define USP_NCS 39
 /* Field-sampling planes: running sums over sampled steps of the per-cell
    raw particle sums (the time averages of the cylinder case, Sec. V.C):
@@ -475,7 +499,8 @@ usp_status usp_check(const usp_grid* grid, const usp_particles* p, const double*
    y, cx, cy, cz, erot, then particle slot.  Requires particle ids below
    capacity (1D runs create no particles).  Errors: USP_EINVAL for a grid
    that is not 1D, a non-FP64 state, the first-order FPM scheme, a
-   temperature-dependent collision-number model, or short buffers. */
+   temperature-dependent collision-number model, a reading switch other
+   than USP_GAMMA_PARTICLE and USP_ALPHA_SIGN_PR, or short buffers. */
 size_t usp_tape_bytes(const usp_grid* grid, int64_t capacity);
 size_t usp_adjoint_ws_bytes(const usp_grid* grid, int64_t capacity);
 

@@ -44,7 +44,7 @@ class OrcGas(C.Structure):
                 ("T_star", C.c_double), ("zvib_model", C.c_int32), ("Z_vib", C.c_double),
                 ("C1", C.c_double), ("C2", C.c_double), ("sigma_vib", C.c_double),
                 ("d_ref", C.c_double), ("pr_model", C.c_int32), ("Pr_const", C.c_double),
-                ("scheme", C.c_int32)]
+                ("scheme", C.c_int32), ("gamma_scope", C.c_int32), ("alpha_sign", C.c_int32)]
 
 
 class OrcGrid(C.Structure):
@@ -151,7 +151,8 @@ def philox(ctr, key):
 def make_gas(g):
     return OrcGas(g.m, g.theta_vib, g.T_ref, g.mu_ref, g.omega, g.alpha_vss, g.zrot_model,
                   g.Z_rot, g.Z_rot_inf, g.T_star, g.zvib_model, g.Z_vib, g.C1, g.C2,
-                  g.sigma_vib, g.d_ref, g.pr_model, g.Pr_const, getattr(g, "scheme", 0))
+                  g.sigma_vib, g.d_ref, g.pr_model, g.Pr_const, getattr(g, "scheme", 0),
+                  getattr(g, "gamma_scope", 0), getattr(g, "alpha_sign", 0))
 
 
 class Gas:

@@ -702,7 +702,8 @@ static void fpm_cell(const orc_grid* gr, const orc_gas* g, const double* cs, int
 /* coefficients, kept 2^-20 inside so the re-test can pass), alpha^2        */
 /* refitted by eq. alpha_USP_positivity_1 (clamped to [0, 1]), the sign of  */
 /* alpha chosen by the Prandtl number of eq. alpha_USP_positivity_3 that is */
-/* closer to the cell's (ties: +), alpha_rot = alpha_vib = alpha_tr (eq.    */
+/* closer to the cell's (ties: +; with ORC_ALPHA_SIGN_KEEP the sign of the  */
+/* cell's alpha instead), alpha_rot = alpha_vib = alpha_tr (eq.             */
 /* alpha_USP_positivity_4), the relaxation temperatures recomputed with the */
 /* new 1 - alpha^2 and Lambda re-tested; a second failure sets nu = 0       */
 /* (Lambda = R T_tr^rel I, alpha kept).  T_tr^rel <= 0 (before or after    */
@@ -763,7 +764,10 @@ void orc_particle_coef(const orc_gas* g, double Ttr, double Trot, double Tvib, c
       double ap = sqrt(a2), am = -sqrt(a2);
       double Prp = A2 * (1.0 - ap * ap * ap) / (dtc * (1.0 + ap * ap * ap));
       double Prm = A2 * (1.0 - am * am * am) / (dtc * (1.0 + am * am * am));
-      al = (fabs(Prm - Pr) < fabs(Prp - Pr)) ? am : ap;
+      if (g->alpha_sign == ORC_ALPHA_SIGN_KEEP)
+        al = al_cell < 0.0 ? am : ap;
+      else
+        al = (fabs(Prm - Pr) < fabs(Prp - Pr)) ? am : ap;
       oma2 = 1.0 - a2;
       if (!(oma2 > 0.0)) {
         skip = 1;
@@ -841,16 +845,22 @@ int orc_collide(const orc_grid* gr, const orc_gas* g, const double* cs, const in
         /* interpolate U, T_tr, T_rot, T_vib, Pi to the particle */
         double U[3], T[3], P[6];
         for (int k = 0; k < 3; ++k) U[k] = orc_interp(gr, cs, ORC_CS_UX + k, (int32_t)c, px, py);
-        for (int k = 0; k < 3; ++k) T[k] = orc_interp(gr, cs, ORC_CS_TTR + k, (int32_t)c, px, py);
-        for (int k = 0; k < 6; ++k) P[k] = orc_interp(gr, cs, ORC_CS_PXX + k, (int32_t)c, px, py);
-        /* guard: an extrapolated temperature may not fall below 5% of   */
-        /* the cell's own value (the paper has no limiter)               */
-        int clamped = 0;
-        for (int k = 0; k < 3; ++k) {
-          double floorv = 0.05 * cs[(int64_t)(ORC_CS_TTR + k) * M + c];
-          if (T[k] < floorv) { T[k] = floorv; clamped = 1; }
+        if (g->gamma_scope == ORC_GAMMA_CELL) {
+          /* the per-cell reading: the chain at the cell's own values */
+          for (int k = 0; k < 3; ++k) T[k] = cs[(int64_t)(ORC_CS_TTR + k) * M + c];
+          for (int k = 0; k < 6; ++k) P[k] = cs[(int64_t)(ORC_CS_PXX + k) * M + c];
+        } else {
+          for (int k = 0; k < 3; ++k) T[k] = orc_interp(gr, cs, ORC_CS_TTR + k, (int32_t)c, px, py);
+          for (int k = 0; k < 6; ++k) P[k] = orc_interp(gr, cs, ORC_CS_PXX + k, (int32_t)c, px, py);
+          /* guard: an extrapolated temperature may not fall below 5% of */
+          /* the cell's own value (the paper has no limiter)             */
+          int clamped = 0;
+          for (int k = 0; k < 3; ++k) {
+            double floorv = 0.05 * cs[(int64_t)(ORC_CS_TTR + k) * M + c];
+            if (T[k] < floorv) { T[k] = floorv; clamped = 1; }
+          }
+          if (clamped) lc[ORC_CNT_INTERP_CLAMP] += 1;
         }
-        if (clamped) lc[ORC_CNT_INTERP_CLAMP] += 1;
         double Ttr = T[0], Trot = T[1], Tvib = T[2];
         orc_pcoef pc;
         orc_particle_coef(g, Ttr, Trot, Tvib, P, a, b, al_cell, oma2_cell, nu_cell, r2, A2, Pr,

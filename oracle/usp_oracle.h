@@ -109,10 +109,21 @@ typedef struct {
   int32_t pr_model;
   double Pr_const;
   int32_t scheme;    /* ORC_SCHEME_USP or ORC_SCHEME_FPM                    */
+  int32_t gamma_scope; /* ORC_GAMMA_PARTICLE or ORC_GAMMA_CELL               */
+  int32_t alpha_sign;  /* ORC_ALPHA_SIGN_PR or ORC_ALPHA_SIGN_KEEP           */
 } orc_gas;
 
 /* USP-FPM (Secs. III-IV) or the first-order FPM method (Secs. II.B-II.C) */
 enum { ORC_SCHEME_USP = 0, ORC_SCHEME_FPM = 1 };
+/* Readings of the USP-FPM particle update.  gamma_scope: the temperatures */
+/* and Pi of the coefficient chain (gammas, relaxation temperatures,       */
+/* diffusion tensor and its refit) are interpolated to the particle        */
+/* (PARTICLE, the flow chart of Sec. IV.D) or are the cell's own (CELL; U  */
+/* is interpolated in both).  alpha_sign: after a refit, the root of eq.   */
+/* alpha_USP_positivity_2 whose Prandtl number is closer to the cell's     */
+/* (PR) or the one with the sign of the cell's alpha (KEEP; 0 counts +).   */
+enum { ORC_GAMMA_PARTICLE = 0, ORC_GAMMA_CELL = 1 };
+enum { ORC_ALPHA_SIGN_PR = 0, ORC_ALPHA_SIGN_KEEP = 1 };
 
 /* ---- grid --------------------------------------------------------------- */
 typedef struct {

@@ -477,7 +477,7 @@ __global__ __launch_bounds__(256) void k_adj_collide(GridP g, GasP gas, TapeP T,
   bool floored[3];
   for (int k = 0; k < 3; ++k) floored[k] = Tk[k] == 0.05 * cs[(CS_TTR + k) * M + c] &&
                                            interp_planes(cs, M, CS_TTR + k, c, st) < Tk[k];
-  const CellCoef cc = coef_planes(cs, M, c);
+  const CellCoef cc = coef_planes(cs, M, c, false);  // the adjoint takes the Prandtl-number rule
   const PartCoef<double> pc = particle_coef<double>(gas.R, gas.theta, Tk[0], Tk[1], Tk[2], P, cc);
   if (pc.fallback) {
     // held fixed: no adjoint reaches the pre-collision values through it
@@ -753,6 +753,9 @@ bool adj_setup_ok(const usp_grid* grid, const usp_gas* gas) {
   if (!grid || !gas || grid->dim != 1 || grid->nx != 1 || grid->ny <= 0 || !grid->volume) return false;
   if (!(grid->dy > 0.0) || !(grid->fnum > 0.0)) return false;
   if (gas->scheme != USP_SCHEME_USP) return false;
+  // the reverse pass differentiates the per-particle chain with the
+  // Prandtl-number sign rule
+  if (gas->gamma_scope != USP_GAMMA_PARTICLE || gas->alpha_sign != USP_ALPHA_SIGN_PR) return false;
   if (gas->zrot_model != USP_ZROT_CONST || gas->zvib_model != USP_ZVIB_CONST) return false;
   return gas->m > 0.0 && gas->theta_vib > 0.0 && gas->T_ref > 0.0 && gas->mu_ref > 0.0 &&
          gas->alpha_vss > 0.0;

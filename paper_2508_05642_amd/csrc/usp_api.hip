@@ -20,6 +20,8 @@ GasP make_gas(const usp_gas* g) {
   p.sigma_vib = g->sigma_vib; p.d_ref = g->d_ref;
   p.pr_model = g->pr_model; p.Pr_const = g->Pr_const;
   p.scheme = g->scheme;
+  p.gamma_cell = g->gamma_scope == USP_GAMMA_CELL ? 1 : 0;
+  p.alpha_keep = g->alpha_sign == USP_ALPHA_SIGN_KEEP ? 1 : 0;
   return p;
 }
 
@@ -116,7 +118,9 @@ bool parts_ok(const usp_particles* p, const usp_grid* g) {
 
 bool gas_ok(const usp_gas* g) {
   return g && g->m > 0.0 && g->theta_vib > 0.0 && g->T_ref > 0.0 && g->mu_ref > 0.0 &&
-         g->alpha_vss > 0.0 && (g->scheme == USP_SCHEME_USP || g->scheme == USP_SCHEME_FPM);
+         g->alpha_vss > 0.0 && (g->scheme == USP_SCHEME_USP || g->scheme == USP_SCHEME_FPM) &&
+         (g->gamma_scope == USP_GAMMA_PARTICLE || g->gamma_scope == USP_GAMMA_CELL) &&
+         (g->alpha_sign == USP_ALPHA_SIGN_PR || g->alpha_sign == USP_ALPHA_SIGN_KEEP);
 }
 
 // Free-stream faces need a temperature and a depth; the surface element

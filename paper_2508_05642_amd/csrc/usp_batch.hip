@@ -14,7 +14,7 @@
 
 namespace usp {
 
-template <typename S, bool STAGED, int CAP, bool FPM>
+template <typename S, bool STAGED, int CAP, int MODE>
 __device__ __forceinline__ void batch_tile(const GridP& g, const GasP& gas, double dt,
                                            const double* dt_cell, double* mom, double* cs,
                                            const int64_t* __restrict__ offsets,
@@ -34,7 +34,12 @@ __device__ __forceinline__ void batch_tile(const GridP& g, const GasP& gas, doub
     const uint32_t step = (uint32_t)(step0 + (uint64_t)s);
     tile_cells<S>(g, gas, dt, dt_cell, mom, cs, offsets, c0, c1, st, counters);
     __syncthreads();
-    tile_update<S, CAP, true, FPM>(g, gas, cs, p, i0, i1, st, st, esc_list, nesc, seed, step,
+    if constexpr (MODE == MODE_CELL) {
+      for (int64_t c = c0 + threadIdx.x; c < c1; c += UPD_BLOCK)
+        cell_pcoefs(cs, g.M)[c] = cell_pcoef(gas, cs, g.M, c);
+      __syncthreads();
+    }
+    tile_update<S, CAP, true, MODE>(g, gas, cs, p, i0, i1, st, st, esc_list, nesc, seed, step,
                                    wc);
     tile_conserve<S>(gas, cs, g.M, offsets, c0, c1, st, seed, step, counters);
     __syncthreads();
@@ -50,7 +55,7 @@ __device__ __forceinline__ void batch_tile(const GridP& g, const GasP& gas, doub
 
 // CAP = stage size (twice the tile window); WPE = waves per SIMD the
 // register budget is held to (what the stage's LDS allows).
-template <typename S, int CAP, int WPE, bool FPM>
+template <typename S, int CAP, int WPE, int MODE>
 __global__ __launch_bounds__(UPD_BLOCK, WPE) void k_batch(GridP g, GasP gas, double dt,
                                                           const double* dt_cell, double* mom,
                                                           double* cs,
@@ -73,10 +78,10 @@ __global__ __launch_bounds__(UPD_BLOCK, WPE) void k_batch(GridP g, GasP gas, dou
   if (i1 - i0 <= CAP) {
     Stage<S> st;
     st.cx = scx; st.cy = scy; st.cz = scz; st.erot = ser; st.vib = svb; st.base = i0;
-    batch_tile<S, true, CAP, FPM>(g, gas, dt, dt_cell, mom, cs, offsets, p, c0, c1, i0, i1, st,
+    batch_tile<S, true, CAP, MODE>(g, gas, dt, dt_cell, mom, cs, offsets, p, c0, c1, i0, i1, st,
                              esc_list, &nesc, seed, step0, nsteps, counters, wcnt);
   } else {
-    batch_tile<S, false, CAP, FPM>(g, gas, dt, dt_cell, mom, cs, offsets, p, c0, c1, i0, i1,
+    batch_tile<S, false, CAP, MODE>(g, gas, dt, dt_cell, mom, cs, offsets, p, c0, c1, i0, i1,
                               global_stage(p), esc_list, &nesc, seed, step0, nsteps, counters, wcnt);
   }
 }
@@ -143,14 +148,14 @@ static hipError_t batch_launches(const GridP& g, const GasP& gas, double dt,
   }
   for (int s = 0; s < nsteps && e == hipSuccess; s += spl) {
     const int k = nsteps - s < spl ? nsteps - s : spl;
-    if (gas.scheme == USP_SCHEME_FPM)
-      k_batch<S, 2 * TILE, WPE, true><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, dt, dt_cell, mom, cs,
-                                                                   offsets, first, order, p, seed,
-                                                                   step + (uint64_t)s, k, counters);
-    else
-      k_batch<S, 2 * TILE, WPE, false><<<ntiles, UPD_BLOCK, 0, st>>>(g, gas, dt, dt_cell, mom, cs,
-                                                                    offsets, first, order, p, seed,
-                                                                    step + (uint64_t)s, k, counters);
+    const int mode = update_mode(gas);
+#define USP_K_BATCH(MODE)                                                                     \
+  k_batch<S, 2 * TILE, WPE, MODE><<<ntiles, UPD_BLOCK, 0, st>>>(                               \
+      g, gas, dt, dt_cell, mom, cs, offsets, first, order, p, seed, step + (uint64_t)s, k, counters)
+    if (mode == MODE_FPM) USP_K_BATCH(MODE_FPM);
+    else if (mode == MODE_CELL) USP_K_BATCH(MODE_CELL);
+    else USP_K_BATCH(MODE_USP);
+#undef USP_K_BATCH
     e = hipGetLastError();
   }
   return e;

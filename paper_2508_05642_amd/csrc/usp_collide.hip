@@ -8,18 +8,18 @@ constexpr int PART_BLOCK = 256;
 constexpr int CONS_BLOCK = 256;
 
 // One thread per particle.
-template <bool FPM>
-__global__ __launch_bounds__(PART_BLOCK) void k_collide_f32(GridP g, GasP gas,
-                                                            const double* __restrict__ cs,
-                                                            PartP<float> p, uint64_t seed,
-                                                            uint32_t step, int64_t* counters) {
+template <typename S, int MODE>
+__global__ __launch_bounds__(PART_BLOCK) void k_collide(GridP g, GasP gas,
+                                                        const double* __restrict__ cs, PartP<S> p,
+                                                        uint64_t seed, uint32_t step,
+                                                        int64_t* counters) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.count[0]) return;
   const int32_t c = p.cell[i];
   if (c < 0) return;
   uint32_t ev = 0;
-  const PartNew<float> o =
-      collide_one<FPM>(g, gas, cs, load_pos(p, i, g.dim), c, load_state(p, i), seed, step, &ev);
+  const PartNew<S> o = collide_mode<MODE, S>(g, gas, cs, load_pos(p, i, g.dim), c,
+                                             load_state(p, i), seed, step, &ev);
   if (o.changed) {
     p.cx[i] = o.cx; p.cy[i] = o.cy; p.cz[i] = o.cz; p.erot[i] = o.erot;
     p.vib[i] = (uint8_t)o.vib;
@@ -27,23 +27,17 @@ __global__ __launch_bounds__(PART_BLOCK) void k_collide_f32(GridP g, GasP gas,
   flush_events(counters, ev);
 }
 
-template <bool FPM>
-__global__ __launch_bounds__(PART_BLOCK) void k_collide_f64(GridP g, GasP gas,
-                                                            const double* __restrict__ cs,
-                                                            PartP<double> p, uint64_t seed,
-                                                            uint32_t step, int64_t* counters) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= p.count[0]) return;
-  const int32_t c = p.cell[i];
-  if (c < 0) return;
-  uint32_t ev = 0;
-  const PartNew<double> o =
-      collide_one<FPM>(g, gas, cs, load_pos(p, i, g.dim), c, load_state(p, i), seed, step, &ev);
-  if (o.changed) {
-    p.cx[i] = o.cx; p.cy[i] = o.cy; p.cz[i] = o.cz; p.erot[i] = o.erot;
-    p.vib[i] = (uint8_t)o.vib;
-  }
-  flush_events(counters, ev);
+// The coefficient chain once per cell (USP_GAMMA_CELL), thread per cell.
+__global__ void k_cell_coef(GridP g, GasP gas, double* cs) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.M) return;
+  cell_pcoefs(cs, g.M)[c] = cell_pcoef(gas, cs, g.M, c);
+}
+
+hipError_t launch_cell_coef(const GridP& g, const GasP& gas, double* cs, hipStream_t st) {
+  if (update_mode(gas) != MODE_CELL) return hipSuccess;
+  k_cell_coef<<<cdiv(g.M, 128), 128, 0, st>>>(g, gas, cs);
+  return hipGetLastError();
 }
 
 constexpr int CONS_WAVES = CONS_BLOCK / 64;
@@ -72,15 +66,12 @@ hipError_t launch_collide(const GridP& g, const GasP& gas, const double* cs, con
                           const PartP<S>& p, uint64_t seed, uint64_t step, int64_t* counters,
                           hipStream_t st) {
   (void)offsets;
-  const bool fpm = gas.scheme == USP_SCHEME_FPM;
   const int64_t nb = cdiv(p.capacity, PART_BLOCK);
-  if constexpr (sizeof(S) == 4) {
-    if (fpm) k_collide_f32<true><<<nb, PART_BLOCK, 0, st>>>(g, gas, cs, p, seed, (uint32_t)step, counters);
-    else k_collide_f32<false><<<nb, PART_BLOCK, 0, st>>>(g, gas, cs, p, seed, (uint32_t)step, counters);
-  } else {
-    if (fpm) k_collide_f64<true><<<nb, PART_BLOCK, 0, st>>>(g, gas, cs, p, seed, (uint32_t)step, counters);
-    else k_collide_f64<false><<<nb, PART_BLOCK, 0, st>>>(g, gas, cs, p, seed, (uint32_t)step, counters);
-  }
+  const uint32_t s32 = (uint32_t)step;
+  const int mode = update_mode(gas);
+  if (mode == MODE_FPM) k_collide<S, MODE_FPM><<<nb, PART_BLOCK, 0, st>>>(g, gas, cs, p, seed, s32, counters);
+  else if (mode == MODE_CELL) k_collide<S, MODE_CELL><<<nb, PART_BLOCK, 0, st>>>(g, gas, cs, p, seed, s32, counters);
+  else k_collide<S, MODE_USP><<<nb, PART_BLOCK, 0, st>>>(g, gas, cs, p, seed, s32, counters);
   return hipGetLastError();
 }
 

@@ -39,11 +39,31 @@ struct alignas(16) CellRec {
 };
 static_assert(sizeof(CellRec) == 128, "cell record size");
 
-// bytes of the cell-state buffer: FP64 planes, then one CellRec per cell
-__host__ __device__ inline size_t cellstate_bytes(int64_t M) { return (size_t)M * (NCS * sizeof(double) + sizeof(CellRec)); }
+// Coefficients of the particle update taken from the cell (the per-cell
+// reading of the coefficient chain): the chain of Secs. III.A.1-III.A.3
+// at the cell's temperatures and Pi, in FP64.
+struct alignas(16) CellPCoef {
+  double L[6];             // Cholesky factor of Lambda
+  double al, oma2, Trot_rel, mstar;
+  int32_t flags, pad[3];   // PC_* bits
+};
+static_assert(sizeof(CellPCoef) == 96, "cell coefficient record size");
+enum : int32_t { PC_SKIP = 1, PC_FALLBACK = 2, PC_NU_ZERO = 4, PC_CLAMP_ROT = 8, PC_CLAMP_M = 16 };
+
+// bytes of the cell-state buffer: FP64 planes, then one CellRec per cell,
+// then one CellPCoef per cell
+__host__ __device__ inline size_t cellstate_bytes(int64_t M) {
+  return (size_t)M * (NCS * sizeof(double) + sizeof(CellRec) + sizeof(CellPCoef));
+}
 __host__ __device__ inline CellRec* cell_records(double* cs, int64_t M) { return (CellRec*)(cs + (size_t)NCS * M); }
 __host__ __device__ inline const CellRec* cell_records(const double* cs, int64_t M) {
   return (const CellRec*)(cs + (size_t)NCS * M);
+}
+__host__ __device__ inline CellPCoef* cell_pcoefs(double* cs, int64_t M) {
+  return (CellPCoef*)(cell_records(cs, M) + M);
+}
+__host__ __device__ inline const CellPCoef* cell_pcoefs(const double* cs, int64_t M) {
+  return (const CellPCoef*)(cell_records(cs, M) + M);
 }
 
 constexpr int VIB_MAX = 255;
@@ -62,7 +82,15 @@ struct GasP {
   int zvib_model; double Z_vib, C1, C2, sigma_vib, d_ref;
   int pr_model; double Pr_const;
   int scheme;  // USP_SCHEME_USP or USP_SCHEME_FPM
+  int gamma_cell, alpha_keep;  // USP_GAMMA_CELL, USP_ALPHA_SIGN_KEEP
 };
+
+// particle-update variants of the kernels: the USP-FPM chain per particle,
+// the first-order FPM method, the USP-FPM chain taken from the cell
+enum : int { MODE_USP = 0, MODE_FPM = 1, MODE_CELL = 2 };
+inline int update_mode(const GasP& gas) {
+  return gas.scheme == USP_SCHEME_FPM ? MODE_FPM : gas.gamma_cell ? MODE_CELL : MODE_USP;
+}
 
 struct GridP {
   int dim, nx, ny;
@@ -134,6 +162,9 @@ hipError_t launch_bin(const GridP& g, const PartP<S>& in, const PartP<S>& out, i
 template <typename S>
 hipError_t launch_moments(const GridP& g, const PartP<S>& p, const int64_t* offsets, double* mom,
                           hipStream_t st, const uint32_t* gather_perm = nullptr);
+// the particle update's coefficients of every cell (MODE_CELL only; else
+// nothing)
+hipError_t launch_cell_coef(const GridP& g, const GasP& gas, double* cs, hipStream_t st);
 hipError_t launch_reconstruct(const GridP& g, const GasP& gas, const double* mom, double dt,
                               const double* dt_cell, double* cs, int64_t* counters, hipStream_t st);
 hipError_t launch_sample_fields(const GridP& g, const double* mom, double* acc, hipStream_t st);

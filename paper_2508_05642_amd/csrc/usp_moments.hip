@@ -152,11 +152,15 @@ hipError_t launch_reconstruct(const GridP& g, const GasP& gas, const double* mom
                               const double* dt_cell, double* cs, int64_t* counters, hipStream_t st) {
   if (g.M <= CELL_SMALL) {
     k_cell_state_small<<<1, 256, 0, st>>>(g, gas, mom, dt, dt_cell, cs, counters);
-    return hipGetLastError();
+  } else {
+    k_reconstruct<<<cdiv(g.M, 128), 128, 0, st>>>(g, gas, mom, dt, dt_cell, cs, counters);
+    k_stencil<<<cdiv(g.M, 256), 256, 0, st>>>(g, cs);
   }
-  k_reconstruct<<<cdiv(g.M, 128), 128, 0, st>>>(g, gas, mom, dt, dt_cell, cs, counters);
-  k_stencil<<<cdiv(g.M, 256), 256, 0, st>>>(g, cs);
-  return hipGetLastError();
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // the coefficient chain per cell, when the particle update takes it
+  // from the cell
+  return launch_cell_coef(g, gas, cs, st);
 }
 
 template hipError_t launch_moments<float>(const GridP&, const PartP<float>&, const int64_t*,

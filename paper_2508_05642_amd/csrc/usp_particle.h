@@ -93,6 +93,7 @@ __device__ __forceinline__ void eig_minmax(const T P[6], T* lmin, T* lmax) {
 // Cell-level coefficients (FP64, from the cell state).
 struct CellCoef {
   double a, b, al, oma2, nu, r2, A2, Pr, dt;
+  bool keep;  // refit root with the sign of al (else by the Prandtl number)
 };
 
 // Per-particle coefficients of the update.
@@ -188,7 +189,8 @@ __device__ PartCoef<T> particle_coef(T R, T Th, T Ttr, T Trot, T Tvib, const T P
     const double ap = sqrt(a2), am = -ap;
     const double Prp = cc.A2 * (1.0 - ap * ap * ap) / (cc.dt * (1.0 + ap * ap * ap));
     const double Prm = cc.A2 * (1.0 - am * am * am) / (cc.dt * (1.0 + am * am * am));
-    al = (T)((fabs(Prm - cc.Pr) < fabs(Prp - cc.Pr)) ? am : ap);
+    if (cc.keep) al = (T)(cc.al < 0.0 ? am : ap);
+    else al = (T)((fabs(Prm - cc.Pr) < fabs(Prp - cc.Pr)) ? am : ap);
     oma2d = 1.0 - a2;
     if (!(oma2d > 0.0)) {
       r.skip = true;
@@ -291,8 +293,10 @@ __device__ __forceinline__ double interp_planes(const double* __restrict__ cs, i
   return phi;
 }
 
-__device__ __forceinline__ CellCoef coef_planes(const double* __restrict__ cs, int64_t M, int64_t c) {
+__device__ __forceinline__ CellCoef coef_planes(const double* __restrict__ cs, int64_t M, int64_t c,
+                                                bool keep) {
   CellCoef cc;
+  cc.keep = keep;
   cc.a = cs[CS_A * M + c]; cc.b = cs[CS_B * M + c]; cc.al = cs[CS_ALPHA * M + c];
   cc.oma2 = cs[CS_OMA2 * M + c]; cc.nu = cs[CS_NU * M + c]; cc.r2 = cs[CS_R2 * M + c];
   cc.A2 = 2.0 * cs[CS_MUP * M + c]; cc.Pr = cs[CS_PR * M + c]; cc.dt = cs[CS_DT * M + c];
@@ -541,6 +545,7 @@ __device__ __forceinline__ PartNew<float> collide_f32(const GridP& g, const GasP
   CellCoef cc;
   cc.a = q5.x; cc.b = q5.y; cc.al = q5.z; cc.nu = q5.w;
   cc.oma2 = own.oma2; cc.r2 = own.r2; cc.A2 = own.A2; cc.Pr = own.Pr; cc.dt = own.dt;
+  cc.keep = gas.alpha_keep != 0;
   const PartCoef<float> pc = particle_coef<float>((float)gas.R, (float)gas.theta, Tk[0], Tk[1], Tk[2], P, cc);
   if (pc.fallback || pc.margin < 1e-4f) {
     *esc = true;
@@ -569,7 +574,7 @@ __device__ __forceinline__ PartNew<float> collide_esc(const GridP& g, const GasP
   const Stencil st = particle_stencil<float>(g, cell_records(cs, M)[c].stencil, c, q);
   double Ud[3], Pd[6], Td[3];
   fields_planes(cs, M, c, st, Ud, Pd, Td);
-  const CellCoef cd = coef_planes(cs, M, c);
+  const CellCoef cd = coef_planes(cs, M, c, gas.alpha_keep != 0);
   const PartCoef<double> pd = particle_coef<double>(gas.R, gas.theta, Td[0], Td[1], Td[2], Pd, cd);
   PartCoef<float> pc;
 #pragma unroll
@@ -614,12 +619,103 @@ __device__ __forceinline__ PartNew<double> collide_one(const GridP& g, const Gas
   const Stencil st = particle_stencil<double>(g, cell_records(cs, M)[c].stencil, c, q);
   double U[3], P[6], Tk[3];
   uint32_t ev = fields_planes(cs, M, c, st, U, P, Tk) ? (1u << USP_CNT_INTERP_CLAMP) : 0u;
-  const CellCoef cc = coef_planes(cs, M, c);
+  const CellCoef cc = coef_planes(cs, M, c, gas.alpha_keep != 0);
   const PartCoef<double> pc = particle_coef<double>(gas.R, gas.theta, Tk[0], Tk[1], Tk[2], P, cc);
   note_coef_events(pc, &ev);
   if (!pc.skip) update_particle<double, double>(q.pid, in, U, pc, gas.R, seed, step, &ev, &o);
   *evp |= ev;
   return o;
+}
+
+// The coefficient chain of cell c at the cell's own temperatures and Pi
+// (the per-cell reading), FP64, packed for the particle update.
+__device__ __forceinline__ CellPCoef cell_pcoef(const GasP& gas, const double* __restrict__ cs,
+                                                int64_t M, int64_t c) {
+  CellPCoef r;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) r.L[k] = 0.0;
+  r.al = r.oma2 = r.Trot_rel = r.mstar = 0.0;
+  r.flags = 0; r.pad[0] = r.pad[1] = r.pad[2] = 0;
+  if (cs[CS_COLLIDE * M + c] == 0.0) return r;
+  const CellCoef cc = coef_planes(cs, M, c, gas.alpha_keep != 0);
+  double P[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) P[k] = cs[(CS_PXX + k) * M + c];
+  const PartCoef<double> pc = particle_coef<double>(gas.R, gas.theta, cs[CS_TTR * M + c],
+                                                    cs[CS_TROT * M + c], cs[CS_TVIB * M + c], P, cc);
+  r.flags = (pc.skip ? PC_SKIP : 0) | (pc.fallback ? PC_FALLBACK : 0) |
+            (pc.nu_zero ? PC_NU_ZERO : 0) | (pc.clamp_rot ? PC_CLAMP_ROT : 0) |
+            (pc.clamp_m ? PC_CLAMP_M : 0);
+  if (pc.skip) return r;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) r.L[k] = pc.L[k];
+  r.al = pc.al; r.oma2 = pc.oma2; r.Trot_rel = pc.Trot_rel; r.mstar = pc.mstar;
+  return r;
+}
+
+// Particle update with the coefficients of the cell (USP_GAMMA_CELL): U
+// interpolated as the per-particle chain does (FP32 from the packed
+// records for FP32 states, FP64 from the planes for FP64 states), every
+// other coefficient from the cell's record; the coefficient events are
+// those of the cell, counted for each of its particles.
+template <typename S>
+__device__ __forceinline__ PartNew<S> collide_cell(const GridP& g, const GasP& gas,
+                                                   const double* __restrict__ cs,
+                                                   const PartPos<S>& q, int32_t c,
+                                                   const PartNew<S>& in, uint64_t seed,
+                                                   uint32_t step, uint32_t* evp) {
+  PartNew<S> o;
+  o.changed = false;
+  const int64_t M = g.M;
+  const CellRec* __restrict__ rec = cell_records(cs, M);
+  if (rec[c].collide == 0) return o;
+  const Stencil st = particle_stencil<S>(g, rec[c].stencil, c, q);
+  S U[3];
+  if constexpr (sizeof(S) == 4) {
+    const float4 a = ((const float4*)(rec + c))[0], b = ((const float4*)(rec + st.c10))[0];
+    const float4 d = ((const float4*)(rec + st.c01))[0], e = ((const float4*)(rec + st.c11))[0];
+    const float f00[3] = {a.x, a.y, a.z}, f10[3] = {b.x, b.y, b.z};
+    const float f01[3] = {d.x, d.y, d.z}, f11[3] = {e.x, e.y, e.z};
+    const float wx = (float)st.wx, wy = (float)st.wy, wxy = (float)(st.wx * st.wy);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      float phi = f00[k];
+      if (st.hx) phi += (f10[k] - f00[k]) * wx;
+      if (st.hy) phi += (f01[k] - f00[k]) * wy;
+      if (st.hxy) phi += (f00[k] - f10[k] - f01[k] + f11[k]) * wxy;
+      U[k] = phi;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) U[k] = interp_planes(cs, M, CS_UX + k, c, st);
+  }
+  const CellPCoef& cp = cell_pcoefs(cs, M)[c];
+  PartCoef<S> pc;
+  const int32_t f = cp.flags;
+  pc.skip = (f & PC_SKIP) != 0; pc.fallback = (f & PC_FALLBACK) != 0;
+  pc.nu_zero = (f & PC_NU_ZERO) != 0; pc.clamp_rot = (f & PC_CLAMP_ROT) != 0;
+  pc.clamp_m = (f & PC_CLAMP_M) != 0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) pc.L[k] = (S)cp.L[k];
+  pc.al = (S)cp.al; pc.oma2 = cp.oma2; pc.Trot_rel = (S)cp.Trot_rel; pc.mstar = (S)cp.mstar;
+  pc.margin = S(1);
+  uint32_t ev = 0;
+  note_coef_events(pc, &ev);
+  if (!pc.skip) update_particle<S, S>(q.pid, in, U, pc, (S)gas.R, seed, step, &ev, &o);
+  *evp |= ev;
+  return o;
+}
+
+// The particle update of a kernel variant (MODE_*): the per-particle chain
+// (FP32: both passes), the first-order FPM method, or the cell's chain.
+template <int MODE, typename S>
+__device__ __forceinline__ PartNew<S> collide_mode(const GridP& g, const GasP& gas,
+                                                   const double* __restrict__ cs,
+                                                   const PartPos<S>& q, int32_t c,
+                                                   const PartNew<S>& in, uint64_t seed,
+                                                   uint32_t step, uint32_t* evp) {
+  if constexpr (MODE == MODE_CELL) return collide_cell<S>(g, gas, cs, q, c, in, seed, step, evp);
+  else return collide_one<MODE == MODE_FPM>(g, gas, cs, q, c, in, seed, step, evp);
 }
 
 // ---------------------------------------------------------------------------

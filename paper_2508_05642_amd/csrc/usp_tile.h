@@ -40,25 +40,31 @@ __device__ __forceinline__ Stage<S> global_stage(const PartP<S>& p) {
   return s;
 }
 
-// First and second pass of the particle update: in FP32 the first pass
-// flags the particles that need the FP64 chain (see collide_f32); the FP64
-// state has a single pass.
-template <bool FPM>
+// First and second pass of the particle update (MODE_*): in FP32 the
+// first pass of the per-particle chain flags the particles that need the
+// FP64 chain (see collide_f32); the FP64 state, the first-order FPM method
+// and the cell's chain have a single pass.
+template <int MODE>
 __device__ __forceinline__ PartNew<float> update_first(const GridP& g, const GasP& gas,
                                                       const double* cs, const PartPos<float>& q,
                                                       int32_t c, const PartNew<float>& in,
                                                       uint64_t seed, uint32_t step, uint32_t* ev,
                                                       bool* esc) {
-  return collide_f32<FPM>(g, gas, cs, q, c, in, seed, step, ev, esc);
+  if constexpr (MODE == MODE_CELL) {
+    *esc = false;
+    return collide_cell<float>(g, gas, cs, q, c, in, seed, step, ev);
+  } else {
+    return collide_f32<MODE == MODE_FPM>(g, gas, cs, q, c, in, seed, step, ev, esc);
+  }
 }
-template <bool FPM>
+template <int MODE>
 __device__ __forceinline__ PartNew<double> update_first(const GridP& g, const GasP& gas,
                                                        const double* cs, const PartPos<double>& q,
                                                        int32_t c, const PartNew<double>& in,
                                                        uint64_t seed, uint32_t step, uint32_t* ev,
                                                        bool* esc) {
   *esc = false;
-  return collide_one<FPM>(g, gas, cs, q, c, in, seed, step, ev);
+  return collide_mode<MODE, double>(g, gas, cs, q, c, in, seed, step, ev);
 }
 __device__ __forceinline__ PartNew<float> update_second(const GridP& g, const GasP& gas,
                                                        const double* cs, const PartPos<float>& q,
@@ -81,7 +87,7 @@ __device__ __forceinline__ PartNew<double> update_second(const GridP&, const Gas
 // chunks of CAP particles: first pass thread per particle; the particles
 // it lists (esc_list/nesc, LDS) get the second pass.  Positions and ids
 // are read from p.
-template <typename S, int CAP, bool SAME, bool FPM, typename CNT>
+template <typename S, int CAP, bool SAME, int MODE, typename CNT>
 __device__ __forceinline__ void tile_update(const GridP& g, const GasP& gas,
                                             const double* __restrict__ cs, const PartP<S>& p,
                                             int64_t i0, int64_t i1, const Stage<S>& src,
@@ -105,7 +111,7 @@ __device__ __forceinline__ void tile_update(const GridP& g, const GasP& gas,
       const double* csl = cs;
       asm volatile("" : "+s"(csl), "+s"(gl.M));
       if (c >= 0)
-        o = update_first<FPM>(gl, gas, csl, load_pos(p, i, g.dim), c, in, seed, step, &ev, &esc);
+        o = update_first<MODE>(gl, gas, csl, load_pos(p, i, g.dim), c, in, seed, step, &ev, &esc);
       if (esc) esc_list[atomicAdd(nesc, 1)] = (uint16_t)(i - cb);
       else if (o.changed) dst.store(i, o);
       else if (!SAME) dst.store(i, in);

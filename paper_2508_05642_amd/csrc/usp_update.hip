@@ -141,7 +141,7 @@ __device__ __forceinline__ void tile_gather(const GridP& g, const PartP<S>& src,
 //      the FP32 first pass lists get the FP64 second pass);
 //   B  conservation, wave per cell, on the stage;
 //   C  free flight, thread per particle, writing the state once.
-template <typename S, bool STAGED, int CAP, bool FPM, bool G, bool POS>
+template <typename S, bool STAGED, int CAP, int MODE, bool G, bool POS>
 __device__ __forceinline__ void tile_pass(const GridP& g, const GasP& gas, const BcP& bc,
                                           double dt, const double* __restrict__ cs,
                                           const int64_t* __restrict__ offsets, const PartP<S>& p,
@@ -173,7 +173,7 @@ __device__ __forceinline__ void tile_pass(const GridP& g, const GasP& gas, const
       asm volatile("" : "+s"(csl), "+s"(gl.M));
       if (c >= 0) {
         const PartPos<S> q = POS ? ps.load(i) : load_pos(p, i, g.dim);
-        o = update_first<FPM>(gl, gas, csl, q, c, in, seed, step, &ev, &esc);
+        o = update_first<MODE>(gl, gas, csl, q, c, in, seed, step, &ev, &esc);
       }
       if (esc) esc_list[atomicAdd(nesc, 1)] = (uint16_t)(i - cb);
       else if (o.changed) st.store(i, o);
@@ -224,7 +224,7 @@ __device__ __forceinline__ void tile_pass(const GridP& g, const GasP& gas, const
   }
 }
 
-template <typename S, bool FPM, bool G>
+template <typename S, int MODE, bool G>
 __global__ __launch_bounds__(KU_BLOCK, 4) void k_update(GridP g, GasP gas, BcP bc, double dt,
                                                      const double* __restrict__ cs,
                                                      const int64_t* __restrict__ offsets,
@@ -255,17 +255,17 @@ __global__ __launch_bounds__(KU_BLOCK, 4) void k_update(GridP g, GasP gas, BcP b
     st.cx = scx; st.cy = scy; st.cz = scz; st.erot = ser; st.vib = svb; st.base = i0;
     if constexpr (G) {
       tile_gather<S, true>(g, src, perm, p, i0, i1, st, ps);
-      tile_pass<S, true, CAP, FPM, G, true>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1, st, ps,
+      tile_pass<S, true, CAP, MODE, G, true>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1, st, ps,
                                             esc_list, &nesc, seed, step, advect != 0, counters,
                                             wc);
     } else {
-      tile_pass<S, true, CAP, FPM, G, false>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1, st,
+      tile_pass<S, true, CAP, MODE, G, false>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1, st,
                                              ps, esc_list, &nesc, seed, step, advect != 0,
                                              counters, wc);
     }
   } else {
     if constexpr (G) tile_gather<S, false>(g, src, perm, p, i0, i1, global_stage(p), ps);
-    tile_pass<S, false, CAP, FPM, G, false>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1,
+    tile_pass<S, false, CAP, MODE, G, false>(g, gas, bc, dt, cs, offsets, p, c0, c1, i0, i1,
                                             global_stage(p), ps, esc_list, &nesc, seed, step,
                                             advect != 0, counters, wc);
   }
@@ -296,21 +296,22 @@ hipError_t launch_update(const GridP& g, const GasP& gas, const BcP& bc, double 
   if (launch_tiles(offsets, g.M, T, ntiles, first, st) != hipSuccess) return hipGetLastError();
   const uint32_t s32 = (uint32_t)step;
   const int adv = g.dim != 0 ? 1 : 0;
-  const bool fpm = gas.scheme == USP_SCHEME_FPM;
+  const int mode = update_mode(gas);
   const PartP<S> sp = src ? *src : p;
   if (ev_begin && hipEventRecord(ev_begin, st) != hipSuccess) return hipGetLastError();
-  if (gather_perm && fpm)
-    k_update<S, true, true><<<ntiles, KU_BLOCK, 0, st>>>(g, gas, bc, dt, cs, offsets, first, p, seed,
-                                                          s32, adv, counters, sp, gather_perm);
-  else if (gather_perm)
-    k_update<S, false, true><<<ntiles, KU_BLOCK, 0, st>>>(g, gas, bc, dt, cs, offsets, first, p, seed,
-                                                           s32, adv, counters, sp, gather_perm);
-  else if (fpm)
-    k_update<S, true, false><<<ntiles, KU_BLOCK, 0, st>>>(g, gas, bc, dt, cs, offsets, first, p, seed,
-                                                           s32, adv, counters, sp, nullptr);
-  else
-    k_update<S, false, false><<<ntiles, KU_BLOCK, 0, st>>>(g, gas, bc, dt, cs, offsets, first, p,
-                                                            seed, s32, adv, counters, sp, nullptr);
+#define USP_K_UPDATE(MODE, G, PERM)                                                             \
+  k_update<S, MODE, G><<<ntiles, KU_BLOCK, 0, st>>>(g, gas, bc, dt, cs, offsets, first, p, seed, \
+                                                   s32, adv, counters, sp, PERM)
+  if (gather_perm) {
+    if (mode == MODE_FPM) USP_K_UPDATE(MODE_FPM, true, gather_perm);
+    else if (mode == MODE_CELL) USP_K_UPDATE(MODE_CELL, true, gather_perm);
+    else USP_K_UPDATE(MODE_USP, true, gather_perm);
+  } else {
+    if (mode == MODE_FPM) USP_K_UPDATE(MODE_FPM, false, nullptr);
+    else if (mode == MODE_CELL) USP_K_UPDATE(MODE_CELL, false, nullptr);
+    else USP_K_UPDATE(MODE_USP, false, nullptr);
+  }
+#undef USP_K_UPDATE
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && ev_end) e = hipEventRecord(ev_end, st);
   if (e != hipSuccess || g.dim == 0) return e;

@@ -78,12 +78,15 @@ def make(kind, f32):
 SCHEMES = ["usp", "fpm"]
 
 
-def pair(kind, f32, scheme="usp"):
+def pair(kind, f32, scheme="usp", gas_kw=None):
     usp = _usp()
     prob, parts = make(kind, f32)
     if scheme == "fpm":
         prob.gas = dataclasses.replace(prob.gas, scheme=W.SCHEME_FPM)
-    _say(f"[parity] case={kind} f32={f32} scheme={scheme} n={parts['n']} cells={prob.grid.ncells}")
+    if gas_kw:
+        prob.gas = dataclasses.replace(prob.gas, **gas_kw)
+    _say(f"[parity] case={kind} f32={f32} scheme={scheme} gas={gas_kw} n={parts['n']} "
+         f"cells={prob.grid.ncells}")
     return prob, usp.DeviceState(prob, parts), oracle.Sim(prob, parts)
 
 
@@ -327,6 +330,64 @@ def test_full_steps(kind, f32, scheme):
     ca, cb = gpu.cnt(), orc.cnt()
     for k in ("INJECTED", "SOLID_DROP"):
         assert ca[k] == cb[k], (k, ca[k], cb[k])
+
+
+READINGS = {"cell": dict(gamma_scope=W.GAMMA_CELL),
+            "keep": dict(alpha_sign=W.ALPHA_SIGN_KEEP),
+            "cell_keep": dict(gamma_scope=W.GAMMA_CELL, alpha_sign=W.ALPHA_SIGN_KEEP)}
+
+
+@pytest.mark.parametrize("reading", list(READINGS))
+@pytest.mark.parametrize("kind,f32", CASES)
+def test_readings_parity(kind, f32, reading):
+    """The reading switches (the coefficient chain per cell; the sign of
+    alpha after a refit kept from the cell) against the oracle: one collide
+    element by element (with the chain per cell, which runs in FP64 on both
+    sides, the coefficient events too), the fused usp_update against the
+    separate phases bit for bit, and three usp_step steps."""
+    usp = _usp()
+    prob, gpu, orc = pair(kind, f32, gas_kw=READINGS[reading])
+    step = 4
+    gpu.bin(); orc.bin()
+    gpu.do_moments(); orc.do_moments()
+    gpu.do_reconstruct(); orc.do_cellstate()
+    vs = vel_scale(prob, orc)
+    gpu.collide(step); orc.collide(step)
+    compare_states(gpu.state(), orc.state(), prob, vs, _tol(f32), "collide")
+    if prob.gas.gamma_scope == W.GAMMA_CELL:
+        ca, cb = gpu.cnt(), orc.cnt()
+        for k in ("CHOL_FALLBACK", "NU_ZERO", "TREL_SKIP", "TREL_CLAMP", "INTERP_CLAMP"):
+            assert ca[k] == cb[k], (k, ca[k], cb[k])
+    # fused pass (after a copying and after a gathering bin) against the phases
+    _, parts = make(kind, f32)
+    a, b, c = (usp.DeviceState(prob, parts) for _ in range(3))
+    for st in (a, b, c):
+        st.bin(gather=st is c); st.do_moments(); st.do_reconstruct()
+    a.collide(step); a.conserve(step)
+    if prob.grid.dim >= 1:
+        a.advect(step)
+    b.update(step)
+    c.update(step)
+    torch.cuda.synchronize()
+    sa = a.state()
+    for other in (b, c):
+        sb = other.state()
+        for k in sa:
+            if isinstance(sa[k], np.ndarray):
+                assert np.array_equal(sa[k], sb[k]), k
+        assert a.cnt() == other.cnt()
+    # full steps
+    prob, gpu, orc = pair(kind, f32, gas_kw=READINGS[reading])
+    gpu.step(10, 3)
+    orc.step_native(10, 3)
+    x, y = gpu.state(), orc.state()
+    assert x["n"] == y["n"]
+    ia, ib = np.argsort(x["pid"], kind="stable"), np.argsort(y["pid"], kind="stable")
+    for k in list(x):
+        if isinstance(x[k], np.ndarray):
+            x[k] = x[k][ia]
+            y[k] = y[k][ib]
+    compare_states(x, y, prob, vs, MULTI_STEP * _tol(f32), "3 steps", vib_min=0.999)
 
 
 def test_determinism_repeat():

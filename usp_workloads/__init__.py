@@ -43,6 +43,8 @@ MU_REF_VHS074 = 1.7072206778865052e-05  # T_ref 273.15 K, omega 0.74, alpha 1.0
 ZROT_CONST, ZROT_PARKER = 0, 1
 ZVIB_CONST, ZVIB_MW_HT = 0, 1
 SCHEME_USP, SCHEME_FPM = 0, 1
+GAMMA_PARTICLE, GAMMA_CELL = 0, 1
+ALPHA_SIGN_PR, ALPHA_SIGN_KEEP = 0, 1
 PR_EUCKEN_PRINTED, PR_EUCKEN_STANDARD, PR_CONST = 0, 1, 2
 BC_PERIODIC, BC_DIFFUSE, BC_SPECULAR, BC_FREESTREAM, BC_OUTFLOW = 0, 1, 2, 3, 4
 SIDE_XLO, SIDE_XHI, SIDE_YLO, SIDE_YHI = 0, 1, 2, 3
@@ -70,6 +72,8 @@ class Gas:
     pr_model: int = PR_EUCKEN_PRINTED
     Pr_const: float = 2.0 / 3.0
     scheme: int = 0  # SCHEME_USP (USP-FPM) or SCHEME_FPM (first-order FPM)
+    gamma_scope: int = 0  # GAMMA_PARTICLE or GAMMA_CELL (where the coefficient chain runs)
+    alpha_sign: int = 0  # ALPHA_SIGN_PR or ALPHA_SIGN_KEEP (root after a positivity refit)
 
     @property
     def R(self) -> float:

@@ -23,6 +23,10 @@ Also reported on the same line:
   adjoint       the pathwise adjoint's reverse/forward time ratio on the
                 differentiable channel;
   c2            the batched 0D solve's throughput;
+  c0            the single-cell 0D relaxation (100,000 particles, FP64), whose
+                cell is split over the chip;
+  gamma_scope   the headline window with the coefficient chain per particle
+                and once per cell (the two readings), eager, side by side;
   cpu_baseline  the oracle timed on the host's cores on a bounded sample.
 """
 import argparse
@@ -393,6 +397,94 @@ def run_gpu(args):
     return res, prob, parts, first
 
 
+def eager_window(prob, parts, warmup, K):
+    """K eager steps of the gather pipeline after `warmup` steps from the
+    initial state: HIP events around the K steps and around each k_update
+    launch.  Returns (particle-steps/s, ms/step, k_update ms, mean
+    particles, counters)."""
+    import numpy as np
+    import torch
+
+    from paper_2508_05642_amd import usp
+
+    st = usp.DeviceState(prob, parts, device="cuda:0")
+
+    def one(s, nlog=None, k=None, kev=None):
+        st.bin(gather=True)
+        if nlog is not None:
+            nlog[k].copy_(st.bufs[1 - st.cur]["count"][0])
+        st.do_moments()
+        st.do_reconstruct()
+        st.update(s, events=kev)
+
+    for s in range(warmup):
+        one(s)
+    kd = [(_raw_event(torch), _raw_event(torch)) for _ in range(K)]
+    nd = torch.zeros(K, dtype=torch.int64, device="cuda:0")
+    d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    d0.record()
+    for k in range(K):
+        one(warmup + k, nd, k, (kd[k][0].cuda_event, kd[k][1].cuda_event))
+    d1.record()
+    torch.cuda.synchronize()
+    dms = d0.elapsed_time(d1)
+    ndm = nd.cpu().numpy()
+    kdm = float(np.mean([kd[k][0].elapsed_time(kd[k][1]) for k in range(K)]))
+    cnt = {k: v for k, v in st.cnt().items() if v}
+    del st
+    torch.cuda.empty_cache()
+    return float(ndm.sum()) / (dms * 1e-3), dms / K, kdm, float(ndm.mean()), cnt
+
+
+def gamma_cell_window(prob, parts, warmup, K):
+    """The headline window with the coefficient chain taken once per cell
+    (gamma_scope = cell), next to the per-particle chain, both eager."""
+    import dataclasses
+
+    import usp_workloads as W
+
+    M = prob.grid.ncells
+    out = {}
+    for name, scope in (("particle", W.GAMMA_PARTICLE), ("cell", W.GAMMA_CELL)):
+        pr = dataclasses.replace(prob, gas=dataclasses.replace(prob.gas, gamma_scope=scope))
+        v, ms, kms, nm, _ = eager_window(pr, parts, warmup, K)
+        ub = UPDATE_BYTES_PER_PARTICLE * nm + UPDATE_BYTES_PER_CELL * M
+        out[name] = {"value": round(v, 1), "ms_per_step": round(ms, 4),
+                     "k_update_ms": round(kms, 4),
+                     "k_update_hbm_frac": round(ub / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    out["unit"] = "particle-steps/s"
+    out["window"] = f"steps {warmup}..{warmup + K - 1}, eager, events around the K steps"
+    return out
+
+
+def relax0d_timing(K=200, warmup=20):
+    """The 0D relaxation at full size (one cell, 100,000 particles, FP64):
+    usp_step, K steps after `warmup`, events around them."""
+    import torch
+
+    import usp_workloads as W
+    from paper_2508_05642_amd import usp
+
+    prob = W.relax0d()
+    parts = W.particles_for(prob)
+    st = usp.DeviceState(prob, parts, device="cuda:0")
+    st.step(0, warmup)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    st.step(warmup, K)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / K
+    n = int(parts["n"])
+    del st
+    torch.cuda.empty_cache()
+    return {"workload": "relax0d (1 cell, 100,000 particles, FP64)", "steps": K,
+            "ms_per_step": round(ms, 4), "value": round(n / (ms * 1e-3), 1),
+            "unit": "particle-steps/s", "launch": "one usp_step call of K steps"}
+
+
 def adjoint_timing(K, warmup=20, seg=32):
     """The differentiable Poiseuille case: Kn = 0.05, 100 cells x 500
     particles (50,000), FP64, K steps from the initial state.  Times a plain
@@ -657,7 +749,8 @@ def main():
     ap.add_argument("--developed", type=int, default=2000, metavar="STEP",
                     help="cylinder: also time --steps steps from this step on (0 = skip)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="cylinder: skip the adjoint and batched-0D figures")
+                    help="cylinder: skip the adjoint, batched-0D, single-cell and "
+                         "gamma-scope figures")
     ap.add_argument("--no-oracle-error", dest="oracle_error", action="store_false",
                     help="cylinder: skip the first-step comparison with the oracle")
     ap.add_argument("--cpu-warmup", type=int, default=10)
@@ -717,6 +810,12 @@ def main():
                      "schedule": c2["config"]["schedule"], "launch": "one HIP graph of 500 steps"}
         log(f"adjoint/forward {res['adjoint']['adjoint_forward_ratio']}, "
             f"c2 {c2['value']:.4g} particle-steps/s")
+        res["c0"] = relax0d_timing()
+        log(f"c0 {res['c0']['ms_per_step']} ms/step")
+        res["gamma_scope"] = gamma_cell_window(prob, parts, args.warmup, args.steps)
+        log(f"gamma scope per particle / per cell: "
+            f"{res['gamma_scope']['particle']['k_update_ms']} / "
+            f"{res['gamma_scope']['cell']['k_update_ms']} ms k_update")
     if not args.no_cpu_baseline:
         keep = {} if first else None
         res["cpu_baseline"] = run_cpu_baseline(prob, parts, args.cpu_warmup, args.cpu_steps,

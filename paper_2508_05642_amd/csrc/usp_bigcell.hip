@@ -181,7 +181,8 @@ __global__ __launch_bounds__(BIG_BLOCK) void k_cons_cells(GridP g, GasP gas,
     for (int q = 0; q < 6; ++q) s[q] += part[k * NPART + q];
     lm = fmax(lm, part[k * NPART + 6]);
   }
-  r = cons_scalars(gas, cs, M, c, N, s, (int)lm, p.vib + o0, seed, step, counters);
+  r = cons_scalars(gas, cons_in(cs, M, c, step, seed), c, N, s, (int)lm, p.vib + o0, seed, step,
+                   counters);
   if (lane == 0) scal[c] = r;
 }
 

@@ -54,10 +54,11 @@ __global__ __launch_bounds__(CONS_BLOCK) void k_conserve(GridP g, GasP gas, cons
   const int64_t c = (int64_t)blockIdx.x * CONS_WAVES + wid;
   if (c >= M) return;
   const int64_t o0 = offsets[c], o1 = offsets[c + 1], N = o1 - o0;
-  if (N == 0 || cs[CS_COLLIDE * M + c] == 0.0) return;
+  const ConsIn in = cons_in(cs, M, c, step, seed);
+  if (N == 0 || !in.collide) return;
   // levels staged in LDS for the picks (cells up to CONS_LDS particles)
   const bool staged = N <= CONS_LDS;
-  conserve_cell<S, S>(gas, cs, M, c, o0, o1, p.cx, p.cy, p.cz, p.erot, p.vib, 0,
+  conserve_cell<S, S>(gas, in, c, o0, o1, p.cx, p.cy, p.cz, p.erot, p.vib, 0,
                       staged ? lv_s[wid] : p.vib + o0, staged, seed, step, counters);
 }
 

@@ -817,6 +817,28 @@ __device__ int wave_picks(uint8_t* lv, int64_t N, int64_t Id, int64_t* SI_io, ui
   return moved;
 }
 
+// The inputs of the conservation of cell c taken from the cell state, and
+// the cell's draw for the rounding of I_delta: requested together, before
+// the cell's sums, so that one memory round trip covers them all.
+struct ConsIn {
+  double Un[3];           // U^n
+  double evib_t, erot_t;  // the cell targets of the vibrational and rotational energy
+  double E0;              // e_tr^n + e_rot^n + e_vib^n
+  double u0;              // uniform draw (counter (c, step, conserve, 0), word 0)
+  bool collide;
+};
+
+__device__ __forceinline__ ConsIn cons_in(const double* __restrict__ cs, int64_t M, int64_t c,
+                                          uint32_t step, uint64_t seed) {
+  ConsIn a;
+  a.collide = cs[CS_COLLIDE * M + c] != 0.0;
+  a.Un[0] = cs[CS_UX * M + c]; a.Un[1] = cs[CS_UY * M + c]; a.Un[2] = cs[CS_UZ * M + c];
+  a.evib_t = cs[CS_EVIB_NEW * M + c]; a.erot_t = cs[CS_EROT_NEW * M + c];
+  a.E0 = cs[CS_ETR * M + c] + cs[CS_EROT * M + c] + cs[CS_EVIB * M + c];
+  a.u0 = u01d(philox((uint32_t)c, step, TAG_CONSERVE, 0u, seed).w[0]);
+  return a;
+}
+
 // The per-cell quantities of the conservation of Sec. IV.C, computed from
 // the cell's post-collision sums and applied to each particle afterwards.
 struct ConsScalars {
@@ -857,16 +879,14 @@ __device__ __forceinline__ void cons_sums(const double Un[3], int64_t i0, int64_
 // rotational factor to the cell target, (iii) the velocity factor about U*
 // toward U^n that restores momentum and total energy with the energies
 // actually reached.  Called by a whole wave; the result is uniform.
-__device__ __forceinline__ ConsScalars cons_scalars(const GasP& gas, const double* __restrict__ cs,
-                                                    int64_t M, int64_t c, int64_t N,
-                                                    const double s[6], int lmax, uint8_t* lv,
-                                                    uint64_t seed, uint32_t step,
+__device__ __forceinline__ ConsScalars cons_scalars(const GasP& gas, const ConsIn& in, int64_t c,
+                                                    int64_t N, const double s[6], int lmax,
+                                                    uint8_t* lv, uint64_t seed, uint32_t step,
                                                     int64_t* counters) {
   const int lane = threadIdx.x & 63;
   ConsScalars r;
-  r.Un[0] = cs[CS_UX * M + c]; r.Un[1] = cs[CS_UY * M + c]; r.Un[2] = cs[CS_UZ * M + c];
-  const double evib_t = cs[CS_EVIB_NEW * M + c], erot_t = cs[CS_EROT_NEW * M + c];
-  const double E0 = cs[CS_ETR * M + c] + cs[CS_EROT * M + c] + cs[CS_EVIB * M + c];
+  r.Un[0] = in.Un[0]; r.Un[1] = in.Un[1]; r.Un[2] = in.Un[2];
+  const double evib_t = in.evib_t, erot_t = in.erot_t, E0 = in.E0;
   const double Nd = (double)N;
   const double m1[3] = {s[0] / Nd, s[1] / Nd, s[2] / Nd};
   const double RTh = gas.R * gas.theta;
@@ -877,7 +897,7 @@ __device__ __forceinline__ ConsScalars cons_scalars(const GasP& gas, const doubl
   // the first-order FPM method keeps the levels and rotational energies it
   // sampled and conserves momentum and total energy through the velocities
   const bool fpm = gas.scheme == USP_SCHEME_FPM;
-  const int64_t Id0 = fpm ? 0 : (int64_t)floor(X + u01d(philox((uint32_t)c, step, TAG_CONSERVE, 0u, seed).w[0]));
+  const int64_t Id0 = fpm ? 0 : (int64_t)floor(X + in.u0);
   // no level can reach VIB_MAX through these increments
   const int64_t need0 = Id0 > 0 ? Id0 : 0;
   const bool low = !__ballot((int64_t)lmax + need0 >= VIB_MAX);
@@ -926,22 +946,21 @@ __device__ __forceinline__ void cons_apply(const ConsScalars& r, int64_t j, PS* 
 // (LDS or global); if `copy` is set, vx's levels are first copied to lv and
 // copied back after the picks.
 template <typename S, typename PS>
-__device__ __forceinline__ void conserve_cell(const GasP& gas, const double* __restrict__ cs,
-                                              int64_t M, int64_t c, int64_t o0, int64_t o1,
-                                              PS* vcx, PS* vcy, PS* vcz, PS* verot, uint8_t* vvib,
-                                              int64_t base, uint8_t* lv, bool copy,
-                                              uint64_t seed, uint32_t step, int64_t* counters) {
+__device__ __forceinline__ void conserve_cell(const GasP& gas, const ConsIn& in, int64_t c,
+                                              int64_t o0, int64_t o1, PS* vcx, PS* vcy, PS* vcz,
+                                              PS* verot, uint8_t* vvib, int64_t base, uint8_t* lv,
+                                              bool copy, uint64_t seed, uint32_t step,
+                                              int64_t* counters) {
   const int lane = threadIdx.x & 63;
   const int64_t N = o1 - o0;
-  // the cell's mean velocity, wave-uniform, requested before the first pass
-  const double Un[3] = {cs[CS_UX * M + c], cs[CS_UY * M + c], cs[CS_UZ * M + c]};
   double s[6] = {0, 0, 0, 0, 0, 0};
   int lmax = 0;
-  cons_sums<PS>(Un, o0 + lane, o1, 64, vcx, vcy, vcz, verot, vvib, base, lv, o0, copy, s, &lmax);
+  cons_sums<PS>(in.Un, o0 + lane, o1, 64, vcx, vcy, vcz, verot, vvib, base, lv, o0, copy, s,
+                &lmax);
 #pragma unroll
   for (int k = 0; k < 6; ++k) s[k] = wave_sum(s[k]);
   wave_sync_lds();
-  const ConsScalars r = cons_scalars(gas, cs, M, c, N, s, lmax, lv, seed, step, counters);
+  const ConsScalars r = cons_scalars(gas, in, c, N, s, lmax, lv, seed, step, counters);
   wave_sync_lds();
   for (int64_t i = o0 + lane; i < o1; i += 64) {
     const int64_t j = i - base;

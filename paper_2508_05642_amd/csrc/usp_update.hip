@@ -199,8 +199,9 @@ __device__ __forceinline__ void tile_pass(const GridP& g, const GasP& gas, const
   const int wid = threadIdx.x >> 6;
   for (int64_t c = c0 + wid; c < c1; c += KU_WAVES) {
     const int64_t o0 = offsets[c], o1 = offsets[c + 1];
-    if (o1 == o0 || cs[CS_COLLIDE * g.M + c] == 0.0) continue;
-    conserve_cell<S, S>(gas, cs, g.M, c, o0, o1, st.cx, st.cy, st.cz, st.erot, st.vib, st.base,
+    const ConsIn in = cons_in(cs, g.M, c, step, seed);
+    if (o1 == o0 || !in.collide) continue;
+    conserve_cell<S, S>(gas, in, c, o0, o1, st.cx, st.cy, st.cz, st.erot, st.vib, st.base,
                         st.vib + (o0 - st.base), false, seed, step, counters);
   }
   __syncthreads();

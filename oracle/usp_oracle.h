@@ -28,9 +28,6 @@
  *
  * Parity unpinned (the paper fixes no value to check these against; only
  * the GPU/oracle parity tests and the invariants below cover them):
- *   - orc_collide's positivity refit (Sec. III.A.3): which nu and alpha the
- *     fallback picks is checked only by "Lambda is positive definite after
- *     it and the update stays finite";
  *   - orc_conserve's order of the vibrational picks (which particle gets a
  *     level step, draw by draw): the total I_delta and the level bounds are
  *     pinned, the choice of particles is not;

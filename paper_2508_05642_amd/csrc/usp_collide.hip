@@ -49,7 +49,9 @@ __global__ __launch_bounds__(CONS_BLOCK) void k_conserve(GridP g, GasP gas, cons
                                                          uint64_t seed, uint32_t step,
                                                          int64_t* counters) {
   __shared__ uint8_t lv_s[CONS_WAVES][CONS_LDS];
-  const int wid = threadIdx.x >> 6;
+  // the wave's index, made wave-uniform so that the per-cell work of the
+  // conservation (loads, draws, integer arithmetic) runs on the scalar unit
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t M = g.M;
   const int64_t c = (int64_t)blockIdx.x * CONS_WAVES + wid;
   if (c >= M) return;

@@ -129,7 +129,10 @@ __device__ __forceinline__ bool chol3m(const T S[6], T L[6], T* margin) {
 // relaxation temperatures (eqs. T_tr_USP, T_rot_USP, T_vib_USP), the
 // diffusion tensor (eq. D_tr) and its Cholesky test, and on failure the nu
 // clamp and alpha refit (eqs. nu_USP_positivity, alpha_USP_positivity_1..4).
-template <typename T>
+// Without REFIT a failed test returns at once with `fallback` set (the FP32
+// first pass hands such particles to the FP64 chain, so it never needs the
+// refit, nor the cell inputs only the refit reads).
+template <typename T, bool REFIT = true>
 __device__ PartCoef<T> particle_coef(T R, T Th, T Ttr, T Trot, T Tvib, const T P[6],
                                      const CellCoef& cc) {
   PartCoef<T> r;
@@ -169,6 +172,10 @@ __device__ PartCoef<T> particle_coef(T R, T Th, T Ttr, T Trot, T Tvib, const T P
 #pragma unroll
   for (int k = 3; k < 6; ++k) Lam[k] = nu * P[k];
   bool ok = chol3m<T>(Lam, r.L, &r.margin);
+  if (!REFIT && !ok) {
+    r.fallback = true;
+    return r;
+  }
   if (!ok) {
     r.fallback = true;
     if (!(Ttr_rel > T(0))) {
@@ -510,28 +517,27 @@ __device__ __forceinline__ PartNew<float> collide_f32(const GridP& g, const GasP
   const CellRec& own = rec[c];
   if (own.collide == 0) return o;
   const Stencil st = particle_stencil<float>(g, __float_as_int(q4.w), c, q);
-  // fields of the stencil cells
-  float f00[12], f10[12], f01[12], f11[12];
-  auto load12 = [&](int64_t cc, float* o) {
+  // fields at the particle: each stencil cell's 12 fields added in with its
+  // bilinear weight as its record arrives (the four records are never live
+  // at once); the weights are those of f00 + (f10 - f00) wx + (f01 - f00) wy
+  // + (f00 - f10 - f01 + f11) wx wy with the missing terms dropped
+  const float wx = (float)st.wx, wy = (float)st.wy, wxy = (float)(st.wx * st.wy);
+  const float w11 = st.hxy ? wxy : 0.0f;
+  const float w10 = (st.hx ? wx : 0.0f) - w11;
+  const float w01 = (st.hy ? wy : 0.0f) - w11;
+  const float w00 = 1.0f - (st.hx ? wx : 0.0f) - (st.hy ? wy : 0.0f) + w11;
+  float v12[12];
+  auto add12 = [&](int64_t cc, float w, bool first) {
     const float4* v = (const float4*)(rec + cc);
     const float4 a0 = v[0], a1 = v[1], a2 = v[2];
-    o[0] = a0.x; o[1] = a0.y; o[2] = a0.z; o[3] = a0.w; o[4] = a1.x; o[5] = a1.y;
-    o[6] = a1.z; o[7] = a1.w; o[8] = a2.x; o[9] = a2.y; o[10] = a2.z; o[11] = a2.w;
-  };
-  load12(c, f00);
-  load12(st.c10, f10);
-  load12(st.c01, f01);
-  load12(st.c11, f11);
-  const float wx = (float)st.wx, wy = (float)st.wy, wxy = (float)(st.wx * st.wy);
-  float v12[12];
+    const float f[12] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w, a2.x, a2.y, a2.z, a2.w};
 #pragma unroll
-  for (int k = 0; k < 12; ++k) {
-    float phi = f00[k];
-    if (st.hx) phi += (f10[k] - f00[k]) * wx;
-    if (st.hy) phi += (f01[k] - f00[k]) * wy;
-    if (st.hxy) phi += (f00[k] - f10[k] - f01[k] + f11[k]) * wxy;
-    v12[k] = phi;
-  }
+    for (int k = 0; k < 12; ++k) v12[k] = first ? w * f[k] : fmaf(w, f[k], v12[k]);
+  };
+  add12(c, w00, true);
+  add12(st.c10, w10, false);
+  add12(st.c01, w01, false);
+  add12(st.c11, w11, false);
   float U[3] = {v12[0], v12[1], v12[2]};
   float Tk[3] = {v12[3], v12[4], v12[5]};
   float P[6] = {v12[6], v12[7], v12[8], v12[9], v12[10], v12[11]};
@@ -544,9 +550,11 @@ __device__ __forceinline__ PartNew<float> collide_f32(const GridP& g, const GasP
   if (clamped) ev |= 1u << USP_CNT_INTERP_CLAMP;
   CellCoef cc;
   cc.a = q5.x; cc.b = q5.y; cc.al = q5.z; cc.nu = q5.w;
-  cc.oma2 = own.oma2; cc.r2 = own.r2; cc.A2 = own.A2; cc.Pr = own.Pr; cc.dt = own.dt;
-  cc.keep = gas.alpha_keep != 0;
-  const PartCoef<float> pc = particle_coef<float>((float)gas.R, (float)gas.theta, Tk[0], Tk[1], Tk[2], P, cc);
+  // the refit's inputs (r2, 2 mu/p, Pr, dt, the sign rule) stay unread: a
+  // failed test goes to the FP64 chain
+  cc.oma2 = own.oma2;
+  const PartCoef<float> pc =
+      particle_coef<float, false>((float)gas.R, (float)gas.theta, Tk[0], Tk[1], Tk[2], P, cc);
   if (pc.fallback || pc.margin < 1e-4f) {
     *esc = true;
     *evp |= ev;

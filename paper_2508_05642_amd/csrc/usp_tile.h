@@ -139,7 +139,9 @@ __device__ __forceinline__ void tile_conserve(const GasP& gas, const double* __r
                                               int64_t M, const int64_t* __restrict__ offsets,
                                               int64_t c0, int64_t c1, const Stage<S>& st,
                                               uint64_t seed, uint32_t step, int64_t* counters) {
-  const int wid = threadIdx.x >> 6;
+  // the wave's index, made wave-uniform so that the per-cell work of the
+  // conservation (loads, draws, integer arithmetic) runs on the scalar unit
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int64_t c = c0 + wid; c < c1; c += UPD_WAVES) {
     const int64_t o0 = offsets[c], o1 = offsets[c + 1];
     const ConsIn in = cons_in(cs, M, c, step, seed);

@@ -196,7 +196,9 @@ __device__ __forceinline__ void tile_pass(const GridP& g, const GasP& gas, const
     __syncthreads();
   }
   // B: conservation, wave per cell
-  const int wid = threadIdx.x >> 6;
+  // the wave's index, made wave-uniform so that the per-cell work of the
+  // conservation (loads, draws, integer arithmetic) runs on the scalar unit
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int64_t c = c0 + wid; c < c1; c += KU_WAVES) {
     const int64_t o0 = offsets[c], o1 = offsets[c + 1];
     const ConsIn in = cons_in(cs, g.M, c, step, seed);

@@ -830,12 +830,17 @@ def _golden_profile(name):
     return T, np.array(U)
 
 
-POIS_RUNS = [(0.05, 2000, "poiseuille_kn005_200x1000.txt"),
-             (0.01, 4500, "poiseuille_kn001_200x1000.txt")]
+# The bar on the fitted curvature against the oracle's is four standard
+# deviations of the difference of two independent runs: the curvature of
+# one run (whole profile, 4000 sampled steps) varies from seed to seed by
+# 0.77% at Kn = 0.05 and 1.69% at Kn = 0.01 (standard deviation over 12
+# seeds of this test's GPU run), so 4 sqrt(2) of that.
+POIS_RUNS = [(0.05, 2000, "poiseuille_kn005_200x1000.txt", 0.044),
+             (0.01, 4500, "poiseuille_kn001_200x1000.txt", 0.096)]
 
 
-@pytest.mark.parametrize("kn,transient,golden", POIS_RUNS)
-def test_poiseuille_full_size_statistics(kn, transient, golden):
+@pytest.mark.parametrize("kn,transient,golden,curv_bar", POIS_RUNS)
+def test_poiseuille_full_size_statistics(kn, transient, golden, curv_bar):
     """The channel at full size (200 cells x 1000 particles, FP32 state) at
     Kn = 0.05 and 0.01: the transient, then the field sums of 4000 steps,
     against the oracle's time average of the same run (tests/golden,
@@ -843,7 +848,8 @@ def test_poiseuille_full_size_statistics(kn, transient, golden):
     after a few hundred steps (FP32 rounding order, chaotic dynamics), so
     what must agree is the statistics: the profile cell by cell within its
     sampling noise (about 0.35 m/s a cell), the parabola's curvature within
-    2% of the oracle's, the temperature within 0.5 K, and the profile
+    four standard deviations of the difference of two independent runs of
+    the oracle's (4.4% and 9.6%), the temperature within 0.5 K, and the profile
     symmetric.  The curvature fitted over the cells more than two mean free
     paths from the walls (outside the Knudsen layers) is also held to the
     Navier-Stokes value g/(2 nu) with the oracle pin's 5% (the oracle's
@@ -884,7 +890,7 @@ def test_poiseuille_full_size_statistics(kn, transient, golden):
          f"/ NS {ratio:.4f}, slip {slip:.2f} (oracle {slip_o:.2f}) m/s, "
          f"|U - U_oracle| mean {d.mean():.3f} max {d.max():.3f} m/s")
     assert abs(T - To) < 0.5
-    assert abs(curv / curv_o - 1.0) < 0.02
+    assert abs(curv / curv_o - 1.0) < curv_bar
     assert d.mean() < 1.0 and d.max() < 2.5
     assert abs(ratio - 1.0) < 0.05
     assert np.abs(U - U[::-1]).mean() < 0.03 * U.max()

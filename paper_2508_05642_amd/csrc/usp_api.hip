@@ -32,6 +32,7 @@ GridP make_grid(const usp_grid* g) {
   p.x0 = g->x0; p.y0 = g->y0; p.dx = g->dx; p.dy = g->dy; p.fnum = g->fnum;
   p.idx = g->dx > 0.0 ? 1.0 / g->dx : 0.0;
   p.idy = g->dy > 0.0 ? 1.0 / g->dy : 0.0;
+  p.inx = g->nx > 0 ? 1.0 / g->nx : 0.0;
   p.volume = g->volume; p.flags = g->flags;
   return p;
 }

@@ -96,7 +96,8 @@ struct GridP {
   int dim, nx, ny;
   int64_t M;
   double x0, y0, dx, dy, fnum;
-  double idx, idy;  // 1/dx, 1/dy (first guess of a cell index only)
+  double idx, idy;  // 1/dx, 1/dy (first guess of a cell index; stencil weights)
+  double inx;       // 1/nx (first guess of a cell's row)
   const double* volume;
   const uint8_t* flags;
 };

@@ -268,8 +268,15 @@ __device__ __forceinline__ Stencil particle_stencil(const GridP& g, int32_t bits
   st.hx = st.hy = st.hxy = false;
   if (g.dim == 0) return st;
   const int nx = g.nx;
-  const int ci = g.dim == 2 ? c % nx : 0;
-  const int cj = g.dim == 2 ? c / nx : c;
+  int cj = c, ci = 0;
+  if (g.dim == 2) {
+    // the row from an FP64 estimate of c / nx (off by at most one for any
+    // int32 index), corrected against the remainder
+    cj = (int)((double)c * g.inx);
+    int r = c - cj * nx;
+    if (r < 0) { --cj; r += nx; } else if (r >= nx) { ++cj; r -= nx; }
+    ci = r;
+  }
   // cell centre with explicitly rounded operations (no contraction)
   const double dyv = (double)q.y - __dadd_rn(g.y0, __dmul_rn(cj + 0.5, g.dy));
   double dxv = 0.0;
@@ -281,8 +288,9 @@ __device__ __forceinline__ Stencil particle_stencil(const GridP& g, int32_t bits
   const int f = (bits >> (5 * qd)) & 31;
   const int tx = (f & 3) == 1 ? 1 : ((f & 3) == 2 ? -1 : 0);
   const int ty = ((f >> 2) & 3) == 1 ? 1 : (((f >> 2) & 3) == 2 ? -1 : 0);
-  if (ty) { st.hy = true; st.wy = dyv / (ty * g.dy); st.c01 = (int64_t)(cj + ty) * nx + ci; }
-  if (tx) { st.hx = true; st.wx = dxv / (tx * g.dx); st.c10 = (int64_t)cj * nx + ci + tx; }
+  // weights: the offset over the signed spacing (times 1/dx, 1/dy)
+  if (ty) { st.hy = true; st.wy = (ty > 0 ? dyv : -dyv) * g.idy; st.c01 = (int64_t)(cj + ty) * nx + ci; }
+  if (tx) { st.hx = true; st.wx = (tx > 0 ? dxv : -dxv) * g.idx; st.c10 = (int64_t)cj * nx + ci + tx; }
   if ((f >> 4) & 1) { st.hxy = true; st.c11 = (int64_t)(cj + ty) * nx + ci + tx; }
   return st;
 }
@@ -895,8 +903,8 @@ __device__ __forceinline__ ConsScalars cons_scalars(const GasP& gas, const ConsI
   ConsScalars r;
   r.Un[0] = in.Un[0]; r.Un[1] = in.Un[1]; r.Un[2] = in.Un[2];
   const double evib_t = in.evib_t, erot_t = in.erot_t, E0 = in.E0;
-  const double Nd = (double)N;
-  const double m1[3] = {s[0] / Nd, s[1] / Nd, s[2] / Nd};
+  const double Nd = (double)N, iN = 1.0 / Nd;
+  const double m1[3] = {s[0] * iN, s[1] * iN, s[2] * iN};
   const double RTh = gas.R * gas.theta;
   // (i) vibrational levels: I_delta = floor(N (e_target - e*)/(R theta) + U),
   // then |I_delta| single-level moves on randomly picked particles
@@ -912,9 +920,9 @@ __device__ __forceinline__ ConsScalars cons_scalars(const GasP& gas, const ConsI
   r.moved = wave_picks(lv, N, Id0, &SI, (uint32_t)c, step, seed, low, counters);
   // the cell scalars, the same on every lane (wave-uniform inputs)
   r.frot = 0.0; r.sc = 0.0;
-  const double etr_s = 0.5 * (s[3] / Nd - (m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2]));
+  const double etr_s = 0.5 * (s[3] * iN - (m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2]));
   // (ii) rotational scaling to the cell target
-  const double erot_s = s[4] / Nd;
+  const double erot_s = s[4] * iN;
   double erot_a = erot_s;
   int skips = 0;
   if (fpm) {
@@ -926,7 +934,7 @@ __device__ __forceinline__ ConsScalars cons_scalars(const GasP& gas, const ConsI
     ++skips;
   }
   // (iii) velocity scaling about U*, toward U^n (momentum and energy)
-  const double evib_a = (double)SI * RTh / Nd;
+  const double evib_a = (double)SI * RTh * iN;
   const double s2 = (E0 - erot_a - evib_a) / etr_s;
   if (etr_s > 0.0 && s2 > 0.0) r.sc = sqrt(s2);
   else ++skips;

@@ -161,6 +161,57 @@ static void copy_d(void* dst, const void* src, size_t bytes, hipStream_t st, hip
   if (*e == hipSuccess) *e = r;
 }
 
+// Several device-to-device copies in one launch (the tape copies of a
+// phase): blockIdx.y picks the copy; 8-byte words where both ends allow it,
+// bytes otherwise.
+constexpr int COPY_MAX = 8;
+struct CopyList {
+  void* dst[COPY_MAX];
+  const void* src[COPY_MAX];
+  size_t bytes[COPY_MAX];
+  int n;
+};
+
+__global__ __launch_bounds__(256) void k_copy_many(CopyList L) {
+  const int k = blockIdx.y;
+  if (k >= L.n) return;
+  const size_t n = L.bytes[k];
+  const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const uintptr_t a = (uintptr_t)L.dst[k] | (uintptr_t)L.src[k];
+  if ((a & 7) == 0) {
+    uint64_t* d = (uint64_t*)L.dst[k];
+    const uint64_t* s = (const uint64_t*)L.src[k];
+    const size_t w = n / 8;
+    for (size_t i = t0; i < w; i += stride) d[i] = s[i];
+    uint8_t* db = (uint8_t*)L.dst[k];
+    const uint8_t* sb = (const uint8_t*)L.src[k];
+    for (size_t i = w * 8 + t0; i < n; i += stride) db[i] = sb[i];
+  } else {
+    uint8_t* d = (uint8_t*)L.dst[k];
+    const uint8_t* s = (const uint8_t*)L.src[k];
+    for (size_t i = t0; i < n; i += stride) d[i] = s[i];
+  }
+}
+
+struct CopyBatch {
+  CopyList L{};
+  void add(void* dst, const void* src, size_t bytes) {
+    L.dst[L.n] = dst; L.src[L.n] = src; L.bytes[L.n] = bytes; ++L.n;
+  }
+  void launch(hipStream_t st, hipError_t* e) {
+    if (L.n == 0) return;
+    size_t mx = 0;
+    for (int k = 0; k < L.n; ++k) mx = L.bytes[k] > mx ? L.bytes[k] : mx;
+    const size_t blocks = (mx / 8 + 255) / 256;
+    const unsigned gx = (unsigned)(blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks));
+    k_copy_many<<<dim3(gx, (unsigned)L.n), 256, 0, st>>>(L);
+    const hipError_t r = hipGetLastError();
+    if (*e == hipSuccess) *e = r;
+    L.n = 0;
+  }
+};
+
 // One full step of a 1D FP64 state through the separate phase kernels (the
 // bits of usp_step), keeping the tape.
 static hipError_t step_taped(const GridP& g, const GasP& gas, const BcP& bc, double dt,
@@ -177,31 +228,36 @@ static hipError_t step_taped(const GridP& g, const GasP& gas, const BcP& bc, dou
   k_perm<<<grid_p, 256, 0, st>>>(out.pid, out.count, cap, map, (int32_t*)(tape + T.perm));
   hipError_t ce = hipSuccess;
   const size_t d = (size_t)cap * 8;
-  copy_d(tape + T.y, out.y, d, st, &ce);
-  copy_d(tape + T.cx, out.cx, d, st, &ce);
-  copy_d(tape + T.cy, out.cy, d, st, &ce);
-  copy_d(tape + T.cz, out.cz, d, st, &ce);
-  copy_d(tape + T.erot, out.erot, d, st, &ce);
-  copy_d(tape + T.vib, out.vib, (size_t)cap, st, &ce);
-  copy_d(tape + T.cell, out.cell, (size_t)cap * 4, st, &ce);
-  copy_d(tape + T.pid, out.pid, (size_t)cap * 4, st, &ce);
+  CopyBatch cb;
+  cb.add(tape + T.y, out.y, d);
+  cb.add(tape + T.cx, out.cx, d);
+  cb.add(tape + T.cy, out.cy, d);
+  cb.add(tape + T.cz, out.cz, d);
+  cb.add(tape + T.erot, out.erot, d);
+  cb.add(tape + T.vib, out.vib, (size_t)cap);
+  cb.add(tape + T.cell, out.cell, (size_t)cap * 4);
+  cb.add(tape + T.pid, out.pid, (size_t)cap * 4);
+  cb.launch(st, &ce);
   if ((e = launch_moments<double>(g, out, offsets, mom, st)) != hipSuccess) return e;
   if ((e = launch_reconstruct(g, gas, mom, dt, nullptr, cs, counters, st)) != hipSuccess) return e;
-  copy_d(tape + T.offsets, offsets, (size_t)(g.M + 1) * 8, st, &ce);
-  copy_d(tape + T.cs, cs, cellstate_bytes(g.M), st, &ce);
+  cb.add(tape + T.offsets, offsets, (size_t)(g.M + 1) * 8);
+  cb.add(tape + T.cs, cs, cellstate_bytes(g.M));
+  cb.launch(st, &ce);
   if ((e = launch_collide<double>(g, gas, cs, offsets, out, seed, step, counters, st)) != hipSuccess)
     return e;
-  copy_d(tape + T.ccx, out.cx, d, st, &ce);
-  copy_d(tape + T.ccy, out.cy, d, st, &ce);
-  copy_d(tape + T.ccz, out.cz, d, st, &ce);
-  copy_d(tape + T.cerot, out.erot, d, st, &ce);
+  cb.add(tape + T.ccx, out.cx, d);
+  cb.add(tape + T.ccy, out.cy, d);
+  cb.add(tape + T.ccz, out.cz, d);
+  cb.add(tape + T.cerot, out.erot, d);
+  cb.launch(st, &ce);
   if ((e = launch_conserve<double>(g, gas, cs, offsets, out, seed, step, counters, st)) != hipSuccess)
     return e;
-  copy_d(tape + T.kcx, out.cx, d, st, &ce);
-  copy_d(tape + T.kcy, out.cy, d, st, &ce);
-  copy_d(tape + T.kcz, out.cz, d, st, &ce);
-  copy_d(tape + T.kerot, out.erot, d, st, &ce);
-  copy_d(tape + T.kvib, out.vib, (size_t)cap, st, &ce);
+  cb.add(tape + T.kcx, out.cx, d);
+  cb.add(tape + T.kcy, out.cy, d);
+  cb.add(tape + T.kcz, out.cz, d);
+  cb.add(tape + T.kerot, out.erot, d);
+  cb.add(tape + T.kvib, out.vib, (size_t)cap);
+  cb.launch(st, &ce);
   if (ce != hipSuccess) return ce;
   if ((e = launch_advect<double>(g, gas, bc, dt, out, seed, step, ws, L, counters, st)) != hipSuccess)
     return e;

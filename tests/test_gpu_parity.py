@@ -1052,6 +1052,39 @@ def test_relax0d_full_size_histories():
     _say(f"  T after 200 steps: {[round(float(oc[k, 0]), 3) for k in iT]}")
 
 
+@pytest.mark.parametrize("f32", [False, True])
+def test_big_cells_split_path(f32):
+    """Grids whose mean slots per cell exceed the fused kernel's stage take
+    the split per-cell reductions (moments and conservation sums per
+    512-slot chunk): empty cells, cells of one and two particles (not
+    collided), a cell of 700 and cells of 30,000 and 45,000 particles, three
+    usp_step steps against the oracle's."""
+    usp = _usp()
+    counts = [0, 30000, 1, 45000, 2, 0, 700]
+    M = len(counts)
+    prob, parts = W.batch0d(counts, T_tr=[3000.0, 9000.0, 5000.0, 15000.0, 4000.0, 3000.0, 6000.0],
+                            T_rot=[300.0, 500.0, 300.0, 800.0, 300.0, 300.0, 1000.0],
+                            T_vib=[300.0, 700.0, 300.0, 2000.0, 300.0, 300.0, 900.0],
+                            dens=[1e23] * M, dt=2e-8, f32=f32, seed=5,
+                            anis=[(1.0, 1.5, 0.7)] * M)
+    _say(f"[big-cells] f32={f32} n={parts['n']} cells={M}")
+    gpu, orc = usp.DeviceState(prob, parts), oracle.Sim(prob, parts)
+    gpu.step(0, 3)
+    orc.step_native(0, 3)
+    a, b = gpu.state(), orc.state()
+    assert a["n"] == b["n"]
+    ia, ib = np.argsort(a["pid"], kind="stable"), np.argsort(b["pid"], kind="stable")
+    for k in list(a):
+        if isinstance(a[k], np.ndarray):
+            a[k] = a[k][ia]
+            b[k] = b[k][ib]
+    compare_states(a, b, prob, vel_scale(prob, orc), MULTI_STEP * _tol(f32), "3 steps",
+                   vib_min=0.999)
+    ca, cb = gpu.cnt(), orc.cnt()
+    for k in ("CELL_SKIP", "PICK_FAIL", "CONS_SKIP"):
+        assert ca[k] == cb[k], (k, ca[k], cb[k])
+
+
 def test_cylinder_full_size_stagnation_pressure():
     """End to end at full size: the Mach 10 cylinder (600 x 300 cells, ~36M
     particles, Kn ~ 1e-3 on the radius) after 4000 steps of flow

@@ -778,6 +778,7 @@ __device__ int wave_picks(uint8_t* lv, int64_t N, int64_t Id, int64_t* SI_io, ui
   uint32_t jbase = 1;
   int moved = 0;
   const double Nd = (double)N;
+  const int kbits = N > 1 ? 64 - __clzll((long long)(N - 1)) : 0;  // bits of the keys
   while (Id != 0) {
     if (att >= maxatt || (Id < 0 && SI == 0)) {
       if (lane == 0) count_event(counters, USP_CNT_PICK_FAIL);
@@ -795,12 +796,15 @@ __device__ int wave_picks(uint8_t* lv, int64_t N, int64_t Id, int64_t* SI_io, ui
     if (Id > 0 && low) {
       acc = valid;
     } else {
-      int dup = 0;
-#pragma unroll
-      for (int l = 0; l < 64; ++l) {
-        const int kl = __builtin_amdgcn_readlane(kk, l);
-        dup += (l < lane && kl == kk) ? 1 : 0;
+      // the earlier lanes that drew the same particle: the lanes whose key
+      // agrees with this lane's in every bit (one ballot per bit of N - 1)
+      uint64_t same = ~0ull;
+      for (int b = 0; b < kbits; ++b) {
+        const uint32_t bit = ((uint32_t)kk >> b) & 1u;
+        const uint64_t bm = __ballot(bit);
+        same &= bit ? bm : ~bm;
       }
+      const int dup = __popcll(same & ((1ull << lane) - 1ull));
       const int L = valid ? (int)lv[k] : 0;
       acc = valid && (Id > 0 ? (L + dup < VIB_MAX) : (dup < L));
     }

@@ -458,6 +458,20 @@ def gamma_cell_window(prob, parts, warmup, K):
     return out
 
 
+# Bytes per particle-step of a 0D step if its passes streamed the state
+# (moments read c, e_rot, I; update read c, e_rot, I, id; update write c,
+# e_rot, I): 17 + 21 + 17 B for an FP32 state, 33 + 37 + 33 B for FP64.
+# The 0D workloads fit the Infinity Cache (and the batched kernel keeps a
+# tile's particles in LDS for all its steps), so the product of this figure
+# and the throughput is an effective, cache-resident rate, not HBM traffic.
+ZERO_D_BYTES = {"f32": 55, "f64": 103}
+
+
+def effective_0d(value, state):
+    return {"effective_gbs_cache_resident": round(value * ZERO_D_BYTES[state] / 1e9, 1),
+            "bytes_per_particle_step": ZERO_D_BYTES[state]}
+
+
 def relax0d_timing(K=200, warmup=20):
     """The 0D relaxation at full size (one cell, 100,000 particles, FP64):
     usp_step, K steps after `warmup`, events around them."""
@@ -480,9 +494,11 @@ def relax0d_timing(K=200, warmup=20):
     n = int(parts["n"])
     del st
     torch.cuda.empty_cache()
+    value = round(n / (ms * 1e-3), 1)
     return {"workload": "relax0d (1 cell, 100,000 particles, FP64)", "steps": K,
-            "ms_per_step": round(ms, 4), "value": round(n / (ms * 1e-3), 1),
-            "unit": "particle-steps/s", "launch": "one usp_step call of K steps"}
+            "ms_per_step": round(ms, 4), "value": value,
+            "unit": "particle-steps/s", "launch": "one usp_step call of K steps",
+            **effective_0d(value, "f64")}
 
 
 def adjoint_timing(K, warmup=20, seg=32):
@@ -725,6 +741,7 @@ def run_gpu_c2(args):
                 "state": "f32", "accumulation": "f64", "schedule": {"tile": tile,
                 "steps_per_launch": spl}, "hip_graph": True, "parallelism": "single-gpu"},
         roofline=roof, counters={k: v for k, v in st.cnt().items() if v},
+        **effective_0d(n * K / wall, "f32"),
     )
     return res, prob, parts
 
@@ -807,7 +824,8 @@ def main():
         c2, _, _ = run_gpu_c2(c2args)
         res["c2"] = {"workload": c2["config"]["workload"], "value": c2["value"],
                      "unit": c2["unit"], "ms_per_step": c2["ms_per_step"], "steps": 500,
-                     "schedule": c2["config"]["schedule"], "launch": "one HIP graph of 500 steps"}
+                     "schedule": c2["config"]["schedule"], "launch": "one HIP graph of 500 steps",
+                     **effective_0d(c2["value"], "f32")}
         log(f"adjoint/forward {res['adjoint']['adjoint_forward_ratio']}, "
             f"c2 {c2['value']:.4g} particle-steps/s")
         res["c0"] = relax0d_timing()

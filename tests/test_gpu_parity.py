@@ -1117,7 +1117,10 @@ def test_cylinder_full_size_stagnation_pressure():
     front = co["theta_deg"] < 40.0
     newton = cpmax * np.cos(th[front]) ** 2
     _say(f"  C_p {np.round(co['C_p'][front], 3)} vs {np.round(newton, 3)}, "
-         f"C_D {co['drag'] / (0.5 * rho * U * U * 2 * bc.cyl_r):.3f}")
+         f"C_D {co['drag'] / (0.5 * rho * U * U * 2 * bc.cyl_r):.3f}, "
+         f"capacity drops {st.cnt()['CAPACITY']}")
+    # a full state would drop the injections of the top boundary first
+    assert st.cnt()["CAPACITY"] == 0
     assert np.all(np.abs(co["C_p"][front] / newton - 1.0) < 0.04)
 
 
@@ -1125,40 +1128,58 @@ def test_cylinder_reduced_wall_statistics():
     """Wall sampling of a developed flow against the oracle: the scale-0.25
     Mach 10 cylinder (the full grid's 1-mm cells, ~2.25M particles, FP32
     state), 1000 steps of flow development, then the surface sums of 2000
-    steps in 36 body elements, against the oracle's sums of the same run
-    (tests/golden, written by make_cylinder_wall_sums.py).  The two
-    trajectories part early, so the statistics must agree: the drag and the
-    body-integrated pressure within 1%, the integrated shear and heat load
-    within 3%, and the pressure coefficient element by element over the
-    front (Theta < 60 degrees) within 6%.  Single elements' shear and heat
-    flux are noisier than that and are not compared one by one."""
+    steps in 36 body elements, against the oracle's sums of the seed-99 run
+    (tests/golden, written by make_cylinder_wall_sums.py).  The trajectories
+    part early, so statistics are compared, taking on the GPU the median of
+    five seeds (99..103): over 15 seeds one GPU run's integrated heat load
+    spreads by 1.5% (sd) and its shear by 0.7%, and about one seed in 15
+    starts with a burst of p_B clamps in the stagnation region (steps
+    ~700-1000) that leaves a vibrationally hotter wake and a heat load 6%
+    low over the sampled steps; the median of five is such a run with
+    probability ~1%.  Bars: drag and body-integrated pressure within 1%,
+    integrated shear within 3% and heat load within 5% (about 3 sd of the
+    median against one oracle run), and the pressure coefficient element by
+    element over the front (Theta < 60 degrees) within 6%.  Single
+    elements' shear and heat flux are noisier than that and are not
+    compared one by one.  No run may drop an injection for lack of
+    capacity."""
     usp = _usp()
     from paper_2508_05642_amd import sampling
-    prob = W.cylinder(scale=0.25, f32=True)
-    parts = W.particles_for(prob)
     transient, sampled, nb = 1000, 2000, 36
-    _say(f"[cylinder-wall] n={parts['n']} cells={prob.grid.ncells}")
-    st = usp.DeviceState(prob, parts)
-    st.step(0, transient)
-    st.enable_sampling(nb)
-    st.step(transient, sampled)
     rows = [line.split() for line in open(os.path.join(GOLD, "cylinder_s025_wall_sums.txt"))
             if not line.startswith("#") and line.strip()]
     so = np.array(rows, dtype=np.int64)
-    g, gas, bc = prob.grid, prob.gas, prob.bc
-    rho, U = prob.notes["n"] * gas.m, prob.notes["U"]
-    co = {}
-    for who, surf in (("gpu", st.surface_sums()), ("oracle", so)):
-        fl = sampling.surface_fluxes(surf, g, bc, nb, gas.m, g.fnum, gas.theta_vib,
+    runs = []
+    for seed in (99, 100, 101, 102, 103):
+        prob = W.cylinder(scale=0.25, f32=True, seed=seed)
+        parts = W.particles_for(prob)
+        _say(f"[cylinder-wall] seed={seed} n={parts['n']} cells={prob.grid.ncells}")
+        st = usp.DeviceState(prob, parts)
+        st.step(0, transient)
+        st.enable_sampling(nb)
+        st.step(transient, sampled)
+        g, gas, bc = prob.grid, prob.gas, prob.bc
+        rho, U = prob.notes["n"] * gas.m, prob.notes["U"]
+        fl = sampling.surface_fluxes(st.surface_sums(), g, bc, nb, gas.m, g.fnum, gas.theta_vib,
                                      sampled * prob.dt)
-        co[who] = sampling.cylinder_coefficients(fl, rho, U)
-    a, b = co["gpu"], co["oracle"]
+        runs.append(sampling.cylinder_coefficients(fl, rho, U))
+        _say(f"  drag {runs[-1]['drag']:.3f} N/m; sum C_p {runs[-1]['C_p'].sum():.3f}, "
+             f"C_f {runs[-1]['C_f'].sum():.4f}, C_h {runs[-1]['C_h'].sum():.4f}; "
+             f"capacity drops {st.cnt()['CAPACITY']}")
+        assert st.cnt()["CAPACITY"] == 0
+        del st
+    fl = sampling.surface_fluxes(so, g, bc, nb, gas.m, g.fnum, gas.theta_vib, sampled * prob.dt)
+    b = sampling.cylinder_coefficients(fl, rho, U)
+    med = lambda f: np.median(np.stack([f(r) for r in runs]), axis=0)
+    drag, cp, cf, ch = (med(lambda r: r["drag"]), med(lambda r: r["C_p"].sum()),
+                        med(lambda r: r["C_f"].sum()), med(lambda r: r["C_h"].sum()))
+    cp_el = med(lambda r: r["C_p"])
+    _say(f"  median: drag {drag:.3f} (oracle {b['drag']:.3f}) N/m; sum C_p {cp:.3f} "
+         f"({b['C_p'].sum():.3f}), C_f {cf:.4f} ({b['C_f'].sum():.4f}), "
+         f"C_h {ch:.4f} ({b['C_h'].sum():.4f})")
     front = b["theta_deg"] < 60.0
-    _say(f"  drag {a['drag']:.3f} (oracle {b['drag']:.3f}) N/m; sum C_p {a['C_p'].sum():.3f} "
-         f"({b['C_p'].sum():.3f}), C_f {a['C_f'].sum():.4f} ({b['C_f'].sum():.4f}), "
-         f"C_h {a['C_h'].sum():.4f} ({b['C_h'].sum():.4f})")
-    assert abs(a["drag"] / b["drag"] - 1.0) < 0.01
-    assert abs(a["C_p"].sum() / b["C_p"].sum() - 1.0) < 0.01
-    assert abs(a["C_f"].sum() / b["C_f"].sum() - 1.0) < 0.03
-    assert abs(a["C_h"].sum() / b["C_h"].sum() - 1.0) < 0.03
-    assert np.all(np.abs(a["C_p"][front] / b["C_p"][front] - 1.0) < 0.06)
+    assert abs(drag / b["drag"] - 1.0) < 0.01
+    assert abs(cp / b["C_p"].sum() - 1.0) < 0.01
+    assert abs(cf / b["C_f"].sum() - 1.0) < 0.03
+    assert abs(ch / b["C_h"].sum() - 1.0) < 0.05
+    assert np.all(np.abs(cp_el[front] / b["C_p"][front] - 1.0) < 0.06)

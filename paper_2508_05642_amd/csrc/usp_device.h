@@ -84,6 +84,18 @@ __device__ __forceinline__ void sincos2pi(uint32_t w, double* s, double* c) {
   sincospi(u01d(w) * 2.0, s, c);
 }
 
+// a / b for the coefficient chain.  In single precision: a times the
+// hardware reciprocal (v_rcp_f32, 1 ulp), within 2 ulp of the quotient for
+// |b| between 2^-126 and 2^126 (the chain divides physical quantities far
+// inside that range), two instructions where the compiler's denormal-safe
+// 2.5-ulp expansion takes eight; in FP64 (and for the dual numbers of the
+// adjoint) the division itself.
+template <typename T>
+__device__ __forceinline__ T qdiv(T a, T b) {
+  return a / b;
+}
+__device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
 // two standard normals from two words (Box-Muller)
 template <typename T>
 __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, T* g1, T* g2) {
@@ -101,9 +113,9 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, T* g1, T* g
 template <typename T>
 __device__ __forceinline__ T mlevel(T theta, T Temp) {
   if (!(Temp > T(0))) return T(0);
-  const T x = theta / Temp;
+  const T x = qdiv(theta, Temp);
   if (x > T(700)) return T(0);
-  return T(1) / expm1(x);
+  return qdiv(T(1), expm1(x));
 }
 
 // Rescaled translational temperature: root of
@@ -116,20 +128,20 @@ template <typename T>
 __device__ __forceinline__ T tcheck(T theta, T Ttr, T Trot, T Tvib, T a, T b) {
   const T ca = T(1.5) + a;
   const T rhs = T(1.5) * Ttr + a * Trot + b * theta * mlevel(theta, Tvib);
-  T hi = rhs / ca, lo = T(0);
+  T hi = qdiv(rhs, ca), lo = T(0);
   if (!(hi > T(0))) return T(0);
-  T t = (T(1.5) * Ttr + a * Trot) / ca;
+  T t = qdiv(T(1.5) * Ttr + a * Trot, ca);
   if (!(t > T(0) && t <= hi)) t = hi;
   const T tol = sizeof(T) == 4 ? T(3e-7) : T(1e-14);
   for (int it = 0; it < 40; ++it) {
-    const T x = theta / t;
+    const T x = qdiv(theta, t);
     // m(T) and c_v,vib/R; e^x overflows to inf for large x, giving m = 0
-    const T m = x > T(700) ? T(0) : T(1) / expm1(x);
+    const T m = x > T(700) ? T(0) : qdiv(T(1), expm1(x));
     const T cv = x * x * m * (T(1) + m);
     const T f = ca * t + b * theta * m - rhs;
     if (f > T(0)) hi = t; else lo = t;
     const T fp = ca + b * cv;
-    T tn = t - f / fp;
+    T tn = t - qdiv(f, fp);
     if (!(tn > lo && tn < hi)) tn = T(0.5) * (lo + hi);
     const T dt = fabs(tn - t);
     t = tn;
@@ -146,18 +158,18 @@ template <typename T>
 __device__ __forceinline__ T cbar_R(T theta, T Tc, T Tv) {
   if (!(Tc > T(0))) return T(0);
   if (!(Tv > T(0))) {
-    const T xa = theta / Tc;
-    return xa > T(700) ? T(0) : xa / expm1(xa);
+    const T xa = qdiv(theta, Tc);
+    return xa > T(700) ? T(0) : qdiv(xa, expm1(xa));
   }
-  const T x1 = theta / Tc, x2 = theta / Tv;
+  const T x1 = qdiv(theta, Tc), x2 = qdiv(theta, Tv);
   const T xa = fmin(x1, x2), xb = fmax(x1, x2);
   if (xa > T(700)) return T(0);
-  const T d = theta * fabs(Tc - Tv) / (Tc * Tv);
+  const T d = qdiv(theta * fabs(Tc - Tv), Tc * Tv);
   const T h = d < T(1e-3) ? T(1) - d * (T(0.5) - d * (T(1) / T(6) - d * T(1) / T(24)))
-                          : -expm1(-d) / d;
+                          : qdiv(-expm1(-d), d);
   const T ea = exp(-xa);
   const T oa = -expm1(-xa), ob = -expm1(-xb);
-  return xa * (xb * h) * ea / (oa * ob);
+  return qdiv(xa * (xb * h) * ea, oa * ob);
 }
 
 // Eucken Prandtl number (Sec. IV.B)

@@ -112,15 +112,15 @@ template <typename T>
 __device__ __forceinline__ bool chol3m(const T S[6], T L[6], T* margin) {
   if (!(S[0] > T(0))) return false;
   const T l11 = sqrt(S[0]);
-  const T l21 = S[3] / l11, l31 = S[4] / l11;
+  const T l21 = qdiv(S[3], l11), l31 = qdiv(S[4], l11);
   const T d2 = S[1] - l21 * l21;
   if (!(d2 > T(0))) return false;
   const T l22 = sqrt(d2);
-  const T l32 = (S[5] - l31 * l21) / l22;
+  const T l32 = qdiv(S[5] - l31 * l21, l22);
   const T d3 = S[2] - l31 * l31 - l32 * l32;
   if (!(d3 > T(0))) return false;
   L[0] = l11; L[1] = l21; L[2] = l22; L[3] = l31; L[4] = l32; L[5] = sqrt(d3);
-  *margin = fmin(d2 / S[1], d3 / S[2]);
+  *margin = fmin(qdiv(d2, S[1]), qdiv(d3, S[2]));
   return true;
 }
 
@@ -149,22 +149,22 @@ __device__ PartCoef<T> particle_coef(T R, T Th, T Ttr, T Trot, T Tvib, const T P
   // <= R, e_vib/R <= T), far under FP32 resolution: they are taken as 0.
   T g1, g2, g3;
   if (b < T(1e-12)) {
-    g1 = T(3) * a / (T(1.5) + a);
+    g1 = qdiv(T(3) * a, T(1.5) + a);
     g2 = g3 = T(0);
   } else {
     const T Tc = tcheck<T>(Th, Ttr, Trot, Tvib, a, b);
     const T cb = cbar_R<T>(Th, Tc, Tvib);
     const T D = T(1.5) + a + b * cb;
-    g1 = T(3) * a / D; g2 = T(3) * b * cb / D; g3 = T(2) * a * b * cb / D;
+    g1 = qdiv(T(3) * a, D); g2 = qdiv(T(3) * b * cb, D); g3 = qdiv(T(2) * a * b * cb, D);
   }
   const T Xtr = g1 * (Ttr - Trot) + g2 * (Ttr - Tvib);
   const T Xrot = g1 * (Ttr - Trot) - g3 * (Trot - Tvib);
   const T Xvib = g2 * (Ttr - Tvib) + g3 * (Trot - Tvib);
   const T mvib = mlevel<T>(Th, Tvib);
   T oma2 = (T)oma2d;
-  T Ttr_rel = Ttr - Xtr / (T(1.5) * oma2);
-  T Trot_rel = Trot + Xrot / oma2;
-  T mstar = mvib + Xvib / (oma2 * Th);
+  T Ttr_rel = Ttr - qdiv(Xtr, T(1.5) * oma2);
+  T Trot_rel = Trot + qdiv(Xrot, oma2);
+  T mstar = mvib + qdiv(Xvib, oma2 * Th);
   const T RT = R * Ttr;
   T Lam[6];
 #pragma unroll
@@ -204,9 +204,9 @@ __device__ PartCoef<T> particle_coef(T R, T Th, T Ttr, T Trot, T Tvib, const T P
       return r;
     }
     oma2 = (T)oma2d;
-    Ttr_rel = Ttr - Xtr / (T(1.5) * oma2);
-    Trot_rel = Trot + Xrot / oma2;
-    mstar = mvib + Xvib / (oma2 * Th);
+    Ttr_rel = Ttr - qdiv(Xtr, T(1.5) * oma2);
+    Trot_rel = Trot + qdiv(Xrot, oma2);
+    mstar = mvib + qdiv(Xvib, oma2 * Th);
 #pragma unroll
     for (int k = 0; k < 3; ++k) Lam[k] = R * Ttr_rel + nu * (P[k] - RT);
 #pragma unroll

@@ -1132,11 +1132,11 @@ def test_cylinder_reduced_wall_statistics():
     (tests/golden, written by make_cylinder_wall_sums.py).  The trajectories
     part early, so statistics are compared, taking on the GPU the median of
     five seeds (99..103): over 15 seeds one GPU run's integrated heat load
-    spreads by 1.5% (sd) and its shear by 0.7%, and about one seed in 15
-    starts with a burst of p_B clamps in the stagnation region (steps
-    ~700-1000) that leaves a vibrationally hotter wake and a heat load 6%
-    low over the sampled steps; the median of five is such a run with
-    probability ~1%.  Bars: drag and body-integrated pressure within 1%,
+    spreads by 1.5% (sd) and its shear by 0.7%, and some runs (1 in 5 to 1
+    in 15 seeds, in FP64 as in FP32) have a burst of p_B clamps in the
+    stagnation region that leaves a vibrationally hotter wake and a heat
+    load ~6% low over the sampled steps; the median is such a run only when
+    three of the five are.  Bars: drag and body-integrated pressure within 1%,
     integrated shear within 3% and heat load within 5% (about 3 sd of the
     median against one oracle run), and the pressure coefficient element by
     element over the front (Theta < 60 degrees) within 6%.  Single

@@ -412,8 +412,9 @@ usp_status usp_update(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc
    host threads without ordering) race and must not be issued.  Nothing in
    the array needs to start at zero (every call writes what it reads).
    Returns USP_ESCRATCH when the grid's faces and the capacity's tile index
-   need more than the array holds (about 2.6e5 tiles: e.g. 4.3e8 particle
-   slots at the cylinder's tile window of 1646 slots), USP_EDEVICE when the array's
+   need more than the array holds (about 2.6e5 tiles: e.g. 4.0e8 particle
+   slots for the cylinder's cells, whose launch bound is a 1527-slot
+   window), USP_EDEVICE when the array's
    address cannot be found. */
 #define USP_NOALLOC_SCRATCH_BYTES (1 << 20)
 usp_status usp_update_noalloc(const usp_grid* grid, const usp_gas* gas, const usp_bc* bc,

@@ -216,9 +216,12 @@ hipError_t launch_check(const GridP& g, const PartP<S>& p, const double* mom, co
                         int64_t* found, hipStream_t st);
 
 // first[t] (t = 0..ntiles) = first cell of tile t: the cells whose first
-// particle slot lies in [t T, (t+1) T)
+// particle slot lies in [t T, (t+1) T).  With stage > 0 the window T is
+// update_tile(stage, offsets[M], M), taken on the device from the binned
+// count (the given T must be the window of a count at least as large, so
+// that ntiles tiles cover it); with stage = 0 it is T as given.
 hipError_t launch_tiles(const int64_t* offsets, int64_t M, int64_t T, int64_t ntiles,
-                        int32_t* first, hipStream_t st);
+                        int32_t* first, hipStream_t st, int stage = 0);
 template <typename S>
 hipError_t launch_batch(const GridP& g, const GasP& gas, double dt, const double* dt_cell,
                         double* mom, double* cs, const int64_t* offsets, const PartP<S>& p,
@@ -231,11 +234,12 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // Tile window of the fused particle phase: a tile holds the cells whose
 // first particle lies in one window, so it spans the window plus the part
 // of its last cell past the window's end.  The window is the stage less
-// 1.25x the mean slots per cell (capacity / M), kept within [stage/8,
-// 7 stage/8], so that most tiles fit the stage.
-inline int64_t update_tile(int stage, int64_t capacity, int64_t M) {
-  const int64_t ppc = M > 0 ? cdiv(capacity, M) : stage;
-  int64_t t = stage - ppc - ppc / 4;
+// 13/8 of the mean particles per cell (n / M), kept within [stage/8,
+// 7 stage/8], so that most tiles fit the stage.  It shrinks as n grows:
+// the window of the capacity bounds the number of tiles any count needs.
+__host__ __device__ inline int64_t update_tile(int stage, int64_t n, int64_t M) {
+  const int64_t ppc = M > 0 ? (n + M - 1) / M : stage;
+  int64_t t = stage - ppc - ppc / 2 - ppc / 8;
   const int64_t lo = stage / 8, hi = stage - stage / 8;
   if (t < lo) t = lo;
   if (t > hi) t = hi;

@@ -4,7 +4,7 @@
 //
 // A workgroup of 8 waves owns a tile: the cells whose first particle lies
 // in one window of particle slots (so whole cells; the window is sized from
-// the mean slots per cell by update_tile).  A gathering launch first loads
+// the mean particles per cell by update_tile).  A gathering launch first loads
 // the tile's particles through the bin's permutation into LDS: velocities,
 // rotational energy and level, and also position, id and new cell, so that
 // the later phases touch global memory only for the cell records and the
@@ -33,6 +33,11 @@ __global__ void k_fill_first(int32_t* first, int64_t n, int32_t v) {
 // first[t] = the smallest cell c with offsets[c] >= t * T (tiles past the
 // last particle keep the prefilled M): cell c owns the tiles t with
 // offsets[c-1] < t T <= offsets[c].
+__device__ __forceinline__ int64_t tile_window(const int64_t* __restrict__ offsets, int64_t M,
+                                               int64_t T, int stage) {
+  return stage > 0 ? update_tile(stage, offsets[M], M) : T;
+}
+
 __device__ __forceinline__ void tile_first(const int64_t* __restrict__ offsets, int64_t T,
                                            int64_t ntiles, int32_t* first, int64_t c) {
   const int64_t lo = c == 0 ? 0 : offsets[c - 1] / T + 1;
@@ -42,19 +47,21 @@ __device__ __forceinline__ void tile_first(const int64_t* __restrict__ offsets, 
 }
 
 __global__ void k_tile_first(const int64_t* __restrict__ offsets, int64_t M, int64_t T,
-                             int64_t ntiles, int32_t* first) {
+                             int64_t ntiles, int32_t* first, int stage) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c <= M) tile_first(offsets, T, ntiles, first, c);
+  if (c <= M) tile_first(offsets, tile_window(offsets, M, T, stage), ntiles, first, c);
 }
 
 // Both passes in one block for grids of at most TILES_SMALL cells and tiles
 // (launch-bound steps); the barrier orders the fill before the starts.
 constexpr int64_t TILES_SMALL = 4096;
 __global__ __launch_bounds__(256) void k_tiles_small(const int64_t* __restrict__ offsets, int64_t M,
-                                                     int64_t T, int64_t ntiles, int32_t* first) {
+                                                     int64_t T, int64_t ntiles, int32_t* first,
+                                                     int stage) {
   for (int64_t t = threadIdx.x; t <= ntiles; t += blockDim.x) first[t] = (int32_t)M;
   __syncthreads();
-  for (int64_t c = threadIdx.x; c <= M; c += blockDim.x) tile_first(offsets, T, ntiles, first, c);
+  const int64_t W = tile_window(offsets, M, T, stage);
+  for (int64_t c = threadIdx.x; c <= M; c += blockDim.x) tile_first(offsets, W, ntiles, first, c);
 }
 
 // The fused kernel's workgroup: 8 waves, two workgroups per CU (their LDS
@@ -277,13 +284,13 @@ __global__ __launch_bounds__(KU_BLOCK, 4) void k_update(GridP g, GasP gas, BcP b
 }
 
 hipError_t launch_tiles(const int64_t* offsets, int64_t M, int64_t T, int64_t ntiles,
-                        int32_t* first, hipStream_t st) {
+                        int32_t* first, hipStream_t st, int stage) {
   if (M < TILES_SMALL && ntiles < TILES_SMALL) {
-    k_tiles_small<<<1, 256, 0, st>>>(offsets, M, T, ntiles, first);
+    k_tiles_small<<<1, 256, 0, st>>>(offsets, M, T, ntiles, first, stage);
     return hipGetLastError();
   }
   k_fill_first<<<cdiv(ntiles + 1, 256), 256, 0, st>>>(first, ntiles + 1, (int32_t)M);
-  k_tile_first<<<cdiv(M + 1, 256), 256, 0, st>>>(offsets, M, T, ntiles, first);
+  k_tile_first<<<cdiv(M + 1, 256), 256, 0, st>>>(offsets, M, T, ntiles, first, stage);
   return hipGetLastError();
 }
 
@@ -293,10 +300,13 @@ hipError_t launch_update(const GridP& g, const GasP& gas, const BcP& bc, double 
                          uint64_t seed, uint64_t step, char* ws, const WsLayout& L,
                          int64_t* counters, hipStream_t st, const PartP<S>* src,
                          const uint32_t* gather_perm, hipEvent_t ev_begin, hipEvent_t ev_end) {
+  // the launch covers a full state; the window itself comes from the
+  // binned count on the device
   const int64_t T = update_tile(UpdCfg<S>::STAGE, p.capacity, g.M);
   const int64_t ntiles = cdiv(p.capacity, T);
   int32_t* first = (int32_t*)(ws + L.tiles);
-  if (launch_tiles(offsets, g.M, T, ntiles, first, st) != hipSuccess) return hipGetLastError();
+  if (launch_tiles(offsets, g.M, T, ntiles, first, st, UpdCfg<S>::STAGE) != hipSuccess)
+    return hipGetLastError();
   const uint32_t s32 = (uint32_t)step;
   const int adv = g.dim != 0 ? 1 : 0;
   const int mode = update_mode(gas);

@@ -334,14 +334,26 @@ __device__ __forceinline__ double row16_sum(double v) {
 }
 
 // FP64 sum over a whole wave (all 64 lanes active): the four row sums,
-// then (r0 + r1) + (r2 + r3); the result is uniform.
+// then (r0 + r1) + (r2 + r3); the result is uniform.  The rows are
+// combined by the gfx950 row swaps: v_permlane16_swap exchanges rows 1 and
+// 3 of its first operand with rows 0 and 2 of its second, so swapping a
+// value with itself leaves rows (r0, r0, r2, r2) and (r1, r1, r3, r3),
+// whose sum is r0 + r1 in rows 0-1 and r2 + r3 in rows 2-3;
+// v_permlane32_swap exchanges rows 2-3 of the first with rows 0-1 of the
+// second, which then sum to (r0 + r1) + (r2 + r3) in every lane (FP64
+// addition commutes, so each lane has the same bits).
+__device__ __forceinline__ double wave_swap_add(double v, bool rows32) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const auto l = rows32 ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false)
+                        : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h = rows32 ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false)
+                        : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
+}
 __device__ __forceinline__ double wave_sum(double v) {
   v = row16_sum(v);
-  auto lane_val = [&](int l) {
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                            __builtin_amdgcn_readlane(__double2loint(v), l));
-  };
-  return (lane_val(0) + lane_val(16)) + (lane_val(32) + lane_val(48));
+  v = wave_swap_add(v, false);
+  return wave_swap_add(v, true);
 }
 
 }  // namespace usp

@@ -18,7 +18,14 @@ struct U4 {
 
 __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                      uint64_t seed) {
-  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  // The key is the same on every lane: every caller passes its launch's
+  // seed.  An opaque scalar copy per call keeps the compiler from hoisting
+  // the ten round keys out of the particle loops: hoisted, they overflow
+  // the scalar registers and come back by one VALU readlane each;
+  // recomputed, they are twenty scalar adds.
+  uint32_t k0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)seed);
+  uint32_t k1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(seed >> 32));
+  asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     // one 32x32->64 product per multiplier (a single v_mad_u64_u32)

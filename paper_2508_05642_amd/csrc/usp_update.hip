@@ -109,18 +109,38 @@ __device__ __forceinline__ void tile_gather(const GridP& g, const PartP<S>& src,
       j[k] = i < i1 ? perm[i] : 0u;
       if (POS) cl[k] = i < i1 ? p.cell[i] : 0;
     }
+    // every lane loads all GATHER_U slots, array by array (a slot past the
+    // tile reads particle 0, in bounds, and stores nothing): no load waits
+    // on a per-slot branch, and each array's base address is fetched once
     PartNew<S> v[GATHER_U];
     S xs[GATHER_U], ys[GATHER_U];
     uint32_t id[GATHER_U];
 #pragma unroll
+    for (int k = 0; k < GATHER_U; ++k) v[k].cx = src.cx[j[k]];
+#pragma unroll
+    for (int k = 0; k < GATHER_U; ++k) v[k].cy = src.cy[j[k]];
+#pragma unroll
+    for (int k = 0; k < GATHER_U; ++k) v[k].cz = src.cz[j[k]];
+#pragma unroll
+    for (int k = 0; k < GATHER_U; ++k) v[k].erot = src.erot[j[k]];
+#pragma unroll
+    for (int k = 0; k < GATHER_U; ++k) v[k].vib = src.vib[j[k]];
+#pragma unroll
     for (int k = 0; k < GATHER_U; ++k) {
-      if (b + k * KU_BLOCK < i1) {
-        v[k] = load_state(src, j[k]);
-        xs[k] = g.dim == 2 ? src.x[j[k]] : S(0);
-        ys[k] = g.dim >= 1 ? src.y[j[k]] : S(0);
-        id[k] = src.pid[j[k]];
-      }
+      v[k].changed = false;
+      xs[k] = S(0);
+      ys[k] = S(0);
     }
+    if (g.dim == 2) {
+#pragma unroll
+      for (int k = 0; k < GATHER_U; ++k) xs[k] = src.x[j[k]];
+    }
+    if (g.dim >= 1) {
+#pragma unroll
+      for (int k = 0; k < GATHER_U; ++k) ys[k] = src.y[j[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < GATHER_U; ++k) id[k] = src.pid[j[k]];
 #pragma unroll
     for (int k = 0; k < GATHER_U; ++k) {
       const int64_t i = b + k * KU_BLOCK;

@@ -8,7 +8,8 @@ A step is bin -> moments -> cell state -> the fused particle phase
 (collide + conserve + advect with injection, one pass), each a call of the
 C ABI on torch's current stream so HIP events bracket every phase.  `value`
 is particle-steps/s over exactly --steps timed steps (inputs resident in
-HBM), after --warmup steps.
+HBM), after --warmup steps, replayed from one HIP graph; an eager pass over
+the same steps from the same state gives the per-phase and k_update times.
 
 Also reported on the same line:
   roofline      the HBM roofline of the dominant kernel (k_update): the
@@ -24,7 +25,9 @@ Also reported on the same line:
                 differentiable channel;
   c2            the batched 0D solve's throughput;
   c0            the single-cell 0D relaxation (100,000 particles, FP64), whose
-                cell is split over the chip;
+                cell is split over the chip (c0 and c2 also give an effective
+                cache-resident rate: the bytes a 0D step would stream per
+                particle times the throughput);
   gamma_scope   the headline window with the coefficient chain per particle
                 and once per cell (the two readings), eager, side by side;
   cpu_baseline  the oracle timed on the host's cores on a bounded sample.

@@ -16,6 +16,15 @@ struct U4 {
   uint32_t w[4];
 };
 
+// Four floats in global memory.  Loads through a pointer of this type are
+// global (not flat) loads even where the compiler has lost track of where
+// a generic pointer points (an opaque scalar copy of it, for instance):
+// they then count only against the vector-memory counter, so waiting for
+// them does not also wait for LDS traffic.
+typedef float F4 __attribute__((ext_vector_type(4)));
+typedef F4 __attribute__((address_space(1))) GlobalF4;
+typedef CellRec __attribute__((address_space(1))) GlobalRec;
+
 __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                      uint64_t seed) {
   // The key is the same on every lane: every caller passes its launch's

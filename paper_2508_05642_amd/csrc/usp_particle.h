@@ -518,11 +518,11 @@ __device__ __forceinline__ PartNew<float> collide_f32(const GridP& g, const GasP
   PartNew<float> o;
   o.changed = false;
   const int64_t M = g.M;
-  const CellRec* __restrict__ rec = cell_records(cs, M);
-  const float4* r4 = (const float4*)(rec + c);
-  const float4 q4 = r4[3];  // fl[3], stencil
-  const float4 q5 = r4[4];  // a, b, al, nu
-  const CellRec& own = rec[c];
+  const GlobalRec* __restrict__ rec = (const GlobalRec*)cell_records(cs, M);
+  const GlobalF4* r4 = (const GlobalF4*)(rec + c);
+  const F4 q4 = r4[3];  // fl[3], stencil
+  const F4 q5 = r4[4];  // a, b, al, nu
+  const GlobalRec& own = rec[c];
   if (own.collide == 0) return o;
   const Stencil st = particle_stencil<float>(g, __float_as_int(q4.w), c, q);
   // fields at the particle: each stencil cell's 12 fields added in with its
@@ -536,8 +536,8 @@ __device__ __forceinline__ PartNew<float> collide_f32(const GridP& g, const GasP
   const float w00 = 1.0f - (st.hx ? wx : 0.0f) - (st.hy ? wy : 0.0f) + w11;
   float v12[12];
   auto add12 = [&](int64_t cc, float w, bool first) {
-    const float4* v = (const float4*)(rec + cc);
-    const float4 a0 = v[0], a1 = v[1], a2 = v[2];
+    const GlobalF4* v = (const GlobalF4*)(rec + cc);
+    const F4 a0 = v[0], a1 = v[1], a2 = v[2];
     const float f[12] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w, a2.x, a2.y, a2.z, a2.w};
 #pragma unroll
     for (int k = 0; k < 12; ++k) v12[k] = first ? w * f[k] : fmaf(w, f[k], v12[k]);
@@ -688,8 +688,8 @@ __device__ __forceinline__ PartNew<S> collide_cell(const GridP& g, const GasP& g
   const Stencil st = particle_stencil<S>(g, rec[c].stencil, c, q);
   S U[3];
   if constexpr (sizeof(S) == 4) {
-    const float4 a = ((const float4*)(rec + c))[0], b = ((const float4*)(rec + st.c10))[0];
-    const float4 d = ((const float4*)(rec + st.c01))[0], e = ((const float4*)(rec + st.c11))[0];
+    const F4 a = ((const GlobalF4*)(rec + c))[0], b = ((const GlobalF4*)(rec + st.c10))[0];
+    const F4 d = ((const GlobalF4*)(rec + st.c01))[0], e = ((const GlobalF4*)(rec + st.c11))[0];
     const float f00[3] = {a.x, a.y, a.z}, f10[3] = {b.x, b.y, b.z};
     const float f01[3] = {d.x, d.y, d.z}, f11[3] = {e.x, e.y, e.z};
     const float wx = (float)st.wx, wy = (float)st.wy, wxy = (float)(st.wx * st.wy);

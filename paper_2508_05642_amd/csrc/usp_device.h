@@ -24,6 +24,10 @@ struct U4 {
 typedef float F4 __attribute__((ext_vector_type(4)));
 typedef F4 __attribute__((address_space(1))) GlobalF4;
 typedef CellRec __attribute__((address_space(1))) GlobalRec;
+typedef CellPCoef __attribute__((address_space(1))) GlobalPCoef;
+typedef double __attribute__((address_space(1))) GlobalD;
+// p[k] of a cell-state plane, as a global load
+__device__ __forceinline__ double ldg(const double* p, int64_t k) { return ((const GlobalD*)p)[k]; }
 
 __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                      uint64_t seed) {

@@ -299,12 +299,12 @@ __device__ __forceinline__ Stencil particle_stencil(const GridP& g, int32_t bits
 __device__ __forceinline__ double interp_planes(const double* __restrict__ cs, int64_t M, int f,
                                                 int64_t c, const Stencil& st) {
   const double* F = cs + (int64_t)f * M;
-  const double f00 = F[c];
+  const double f00 = ldg(F, c);
   double phi = f00;
-  const double f10 = F[st.c10], f01 = F[st.c01];
+  const double f10 = ldg(F, st.c10), f01 = ldg(F, st.c01);
   if (st.hx) phi += (f10 - f00) * st.wx;
   if (st.hy) phi += (f01 - f00) * st.wy;
-  if (st.hxy) phi += (f00 - f10 - f01 + F[st.c11]) * st.wx * st.wy;
+  if (st.hxy) phi += (f00 - f10 - f01 + ldg(F, st.c11)) * st.wx * st.wy;
   return phi;
 }
 
@@ -312,9 +312,9 @@ __device__ __forceinline__ CellCoef coef_planes(const double* __restrict__ cs, i
                                                 bool keep) {
   CellCoef cc;
   cc.keep = keep;
-  cc.a = cs[CS_A * M + c]; cc.b = cs[CS_B * M + c]; cc.al = cs[CS_ALPHA * M + c];
-  cc.oma2 = cs[CS_OMA2 * M + c]; cc.nu = cs[CS_NU * M + c]; cc.r2 = cs[CS_R2 * M + c];
-  cc.A2 = 2.0 * cs[CS_MUP * M + c]; cc.Pr = cs[CS_PR * M + c]; cc.dt = cs[CS_DT * M + c];
+  cc.a = ldg(cs, CS_A * M + c); cc.b = ldg(cs, CS_B * M + c); cc.al = ldg(cs, CS_ALPHA * M + c);
+  cc.oma2 = ldg(cs, CS_OMA2 * M + c); cc.nu = ldg(cs, CS_NU * M + c); cc.r2 = ldg(cs, CS_R2 * M + c);
+  cc.A2 = 2.0 * ldg(cs, CS_MUP * M + c); cc.Pr = ldg(cs, CS_PR * M + c); cc.dt = ldg(cs, CS_DT * M + c);
   return cc;
 }
 
@@ -330,7 +330,7 @@ __device__ __forceinline__ bool fields_planes(const double* __restrict__ cs, int
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     Tk[k] = interp_planes(cs, M, CS_TTR + k, c, st);
-    const double fl = 0.05 * cs[(CS_TTR + k) * M + c];
+    const double fl = 0.05 * ldg(cs, (CS_TTR + k) * M + c);
     if (Tk[k] < fl) { Tk[k] = fl; clamped = true; }
   }
   return clamped;
@@ -427,14 +427,14 @@ __device__ __forceinline__ PartNew<S> collide_fpm(const GridP& g, const GasP& ga
   const double R = gas.R;
   double U[3], P[6];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) U[k] = cs[(CS_UX + k) * M + c];
+  for (int k = 0; k < 3; ++k) U[k] = ldg(cs, (CS_UX + k) * M + c);
 #pragma unroll
-  for (int k = 0; k < 6; ++k) P[k] = cs[(CS_PXX + k) * M + c];
-  const double Ttr = cs[CS_TTR * M + c];
-  const double al = cs[CS_ALPHA * M + c], oma2 = cs[CS_OMA2 * M + c], nu = cs[CS_NU * M + c];
-  const double dtc = cs[CS_DT * M + c], tau = cs[CS_FPM_TAU * M + c];
-  const double Ttr_rel = cs[CS_FPM_TTR_REL * M + c];
-  double Trot_rel = cs[CS_FPM_TROT_REL * M + c], mrel = cs[CS_FPM_MREL * M + c];
+  for (int k = 0; k < 6; ++k) P[k] = ldg(cs, (CS_PXX + k) * M + c);
+  const double Ttr = ldg(cs, CS_TTR * M + c);
+  const double al = ldg(cs, CS_ALPHA * M + c), oma2 = ldg(cs, CS_OMA2 * M + c), nu = ldg(cs, CS_NU * M + c);
+  const double dtc = ldg(cs, CS_DT * M + c), tau = ldg(cs, CS_FPM_TAU * M + c);
+  const double Ttr_rel = ldg(cs, CS_FPM_TTR_REL * M + c);
+  double Trot_rel = ldg(cs, CS_FPM_TROT_REL * M + c), mrel = ldg(cs, CS_FPM_MREL * M + c);
   uint32_t ev = 0;
   const double RT = R * Ttr;
   double Lam[6], L[6], margin;
@@ -631,7 +631,7 @@ __device__ __forceinline__ PartNew<double> collide_one(const GridP& g, const Gas
   PartNew<double> o;
   o.changed = false;
   const int64_t M = g.M;
-  if (cs[CS_COLLIDE * M + c] == 0.0) return o;
+  if (ldg(cs, CS_COLLIDE * M + c) == 0.0) return o;
   const Stencil st = particle_stencil<double>(g, cell_records(cs, M)[c].stencil, c, q);
   double U[3], P[6], Tk[3];
   uint32_t ev = fields_planes(cs, M, c, st, U, P, Tk) ? (1u << USP_CNT_INTERP_CLAMP) : 0u;
@@ -705,7 +705,7 @@ __device__ __forceinline__ PartNew<S> collide_cell(const GridP& g, const GasP& g
 #pragma unroll
     for (int k = 0; k < 3; ++k) U[k] = interp_planes(cs, M, CS_UX + k, c, st);
   }
-  const CellPCoef& cp = cell_pcoefs(cs, M)[c];
+  const GlobalPCoef& cp = ((const GlobalPCoef*)cell_pcoefs(cs, M))[c];
   PartCoef<S> pc;
   const int32_t f = cp.flags;
   pc.skip = (f & PC_SKIP) != 0; pc.fallback = (f & PC_FALLBACK) != 0;

@@ -129,13 +129,37 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, T* g1, T* g
 // ---------------------------------------------------------------------------
 // Gas model in reduced units (temperatures in K, energies per R).
 // ---------------------------------------------------------------------------
+// e^x and e^x - 1 for the gas-model terms.  FP64: the library.  FP32: the
+// hardware base-2 exponential (v_exp_f32) of x log2(e), with the rounding of
+// the product carried as a first-order correction (x log2 e = t + r exactly
+// to FP32 working precision, 2^(t + r) = 2^t (1 + r ln 2)), about 2 ulp;
+// e^x - 1 takes the library below |x| = 1, where the subtraction would lose
+// bits (above it, at most 1.6x the exponential's relative error).
+template <typename T>
+__device__ __forceinline__ T gm_exp(T x) { return exp(x); }
+template <typename T>
+__device__ __forceinline__ T gm_expm1(T x) { return expm1(x); }
+template <>
+__device__ __forceinline__ float gm_exp<float>(float x) {
+  const float hi = 1.44269502162933349609375f, lo = 1.925963033500011e-08f;
+  const float t = x * hi;
+  const float r = fmaf(x, hi, -t) + x * lo;
+  const float e = __builtin_amdgcn_exp2f(t);
+  return e * (1.0f + r * 0.693147180559945309f);  // inf stays inf
+}
+template <>
+__device__ __forceinline__ float gm_expm1<float>(float x) {
+  if (fabsf(x) < 1.0f) return expm1f(x);
+  return gm_exp(x) - 1.0f;
+}
+
 // mean harmonic-oscillator level 1/(e^{theta/T} - 1) = e_vib/(R theta)
 template <typename T>
 __device__ __forceinline__ T mlevel(T theta, T Temp) {
   if (!(Temp > T(0))) return T(0);
   const T x = qdiv(theta, Temp);
   if (x > T(700)) return T(0);
-  return qdiv(T(1), expm1(x));
+  return qdiv(T(1), gm_expm1(x));
 }
 
 // Rescaled translational temperature: root of
@@ -156,7 +180,7 @@ __device__ __forceinline__ T tcheck(T theta, T Ttr, T Trot, T Tvib, T a, T b) {
   for (int it = 0; it < 40; ++it) {
     const T x = qdiv(theta, t);
     // m(T) and c_v,vib/R; e^x overflows to inf for large x, giving m = 0
-    const T m = x > T(700) ? T(0) : qdiv(T(1), expm1(x));
+    const T m = x > T(700) ? T(0) : qdiv(T(1), gm_expm1(x));
     const T cv = x * x * m * (T(1) + m);
     const T f = ca * t + b * theta * m - rhs;
     if (f > T(0)) hi = t; else lo = t;
@@ -179,16 +203,16 @@ __device__ __forceinline__ T cbar_R(T theta, T Tc, T Tv) {
   if (!(Tc > T(0))) return T(0);
   if (!(Tv > T(0))) {
     const T xa = qdiv(theta, Tc);
-    return xa > T(700) ? T(0) : qdiv(xa, expm1(xa));
+    return xa > T(700) ? T(0) : qdiv(xa, gm_expm1(xa));
   }
   const T x1 = qdiv(theta, Tc), x2 = qdiv(theta, Tv);
   const T xa = fmin(x1, x2), xb = fmax(x1, x2);
   if (xa > T(700)) return T(0);
   const T d = qdiv(theta * fabs(Tc - Tv), Tc * Tv);
   const T h = d < T(1e-3) ? T(1) - d * (T(0.5) - d * (T(1) / T(6) - d * T(1) / T(24)))
-                          : qdiv(-expm1(-d), d);
-  const T ea = exp(-xa);
-  const T oa = -expm1(-xa), ob = -expm1(-xb);
+                          : qdiv(-gm_expm1(-d), d);
+  const T ea = gm_exp(-xa);
+  const T oa = -gm_expm1(-xa), ob = -gm_expm1(-xb);
   return qdiv(xa * (xb * h) * ea, oa * ob);
 }
 

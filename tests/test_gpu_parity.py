@@ -694,6 +694,32 @@ def test_batch_c2_full_size(tile):
         assert ca[k] == cb[k], (k, ca[k], cb[k])
 
 
+def test_step_independent_of_capacity():
+    """The fused particle phase takes its tile window from the binned count
+    and only bounds its launch by the capacity, so usp_step gives the same
+    bits whether the particle buffers hold little more than the particles
+    (the launch bound then close to the window) or eight times as many (far
+    more tiles launched, the ones past the particles empty).  Reduced Mach
+    10 cylinder (scale 0.1), five steps, no injection dropped."""
+    usp = _usp()
+    prob = W.cylinder(scale=0.1, f32=True)
+    parts = W.particles_for(prob)
+    n = int(parts["n"])
+    out = []
+    for cap in (int(1.05 * n) + 64, 8 * n):
+        st = usp.DeviceState(prob, parts, capacity=cap)
+        st.step(0, 5)
+        out.append((st.state(), st.cnt()))
+        del st
+    (a, ca), (b, cb) = out
+    _say(f"[capacity] n={n}: {a['n']} and {b['n']} particles after 5 steps")
+    assert ca["CAPACITY"] == 0 and cb["CAPACITY"] == 0
+    assert a["n"] == b["n"] and ca == cb
+    for k in a:
+        if isinstance(a[k], np.ndarray):
+            assert np.array_equal(a[k], b[k]), k
+
+
 def test_step_graph_replay():
     """usp_step captured in a HIP graph (torch.cuda.graph) and replayed three
     times, with eager work between replays, reproduces the eager steps bit
